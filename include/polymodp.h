@@ -1,0 +1,137 @@
+/*
+ * polymodp.h -- C ABI of libpolymodp: dense univariate polynomial arithmetic
+ * over the prime field Z/pZ on AMD Instinct MI355X (gfx950).
+ *
+ * The operations are the ones whose many-core algorithms the paper "A
+ * Many-core Machine Model for Designing Algorithms with Minimum Parallelism
+ * Overheads" (Haque, Moreno Maza, Xie) studies: the plain product (Sec. 5),
+ * Euclidean division (Sec. 3) and the Euclidean gcd (Sec. 6).
+ *
+ * Conventions for every entry point
+ *  - A polynomial is an array of uint32 coefficients indexed by exponent; its
+ *    length is its number of terms (degree + 1). High zero coefficients in
+ *    inputs are allowed and ignored; the zero polynomial has length 0.
+ *    Outputs are normalised: their reported length ends at a non-zero
+ *    coefficient.
+ *  - Coefficient and output arrays are DEVICE pointers (memory of the
+ *    current HIP device). Length and status pointers named d_* are device
+ *    pointers too; the other int64_t* outputs are host pointers.
+ *  - p must be a prime with 2 <= p < 2^30, and every input coefficient must
+ *    be a canonical residue in [0, p).
+ *  - `stream` is a hipStream_t (NULL = the default stream). Work is enqueued
+ *    on it in order; synchronous entry points wait for it before returning.
+ *  - Ownership: the caller owns every buffer. Inputs are read only. Outputs
+ *    must not overlap inputs. Scratch memory belongs to the library (one pool
+ *    per device and stream, grown on demand and kept until pm_release).
+ *  - Errors: checks that need no device access (null pointers, negative
+ *    lengths, capacities smaller than the given lengths require, a modulus
+ *    that is not a prime below 2^30) are made before anything is enqueued.
+ *    Checks that need the data (coefficients >= p, a zero divisor, a
+ *    capacity below what the true degrees require) are made on the device:
+ *    synchronous calls return them, asynchronous calls write them to
+ *    d_status. Nothing is thrown across the ABI. pm_last_error() describes
+ *    the last failure of the calling thread.
+ */
+#ifndef POLYMODP_H
+#define POLYMODP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pm_status;
+enum {
+    PM_OK = 0,
+    PM_EINVAL = -1,    /* null pointer, negative length, capacity too small */
+    PM_EMODULUS = -2,  /* p not prime, or p >= 2^30                          */
+    PM_ERANGE = -3,    /* an input coefficient is >= p                       */
+    PM_EDIVZERO = -4,  /* division by the zero polynomial                    */
+    PM_ENOMEM = -5,    /* device memory for scratch could not be allocated   */
+    PM_EDEVICE = -6    /* a HIP runtime error or a broken device invariant   */
+};
+
+/*
+ * Product f = a * b (Sec. 5, plain multiplication: every coefficient of a
+ * is multiplied with every coefficient of b and the products of equal degree
+ * are added), f_k = sum_i a_i b_{k-i} mod p.
+ *   a, na / b, nb : inputs (device), lengths >= 0
+ *   f, f_cap      : output (device), f_cap >= na + nb - 1 when na, nb > 0
+ *   nf            : host; normalised length of f (0 if a or b is zero)
+ * f[0 .. na+nb-2] is written in full; entries past *nf are zero.
+ */
+pm_status poly_mul_modp(const uint32_t *a, int64_t na, const uint32_t *b, int64_t nb, uint32_t p,
+                        uint32_t *f, int64_t f_cap, int64_t *nf, void *stream);
+
+/*
+ * Asynchronous product: same computation, nothing waits for the device and
+ * nothing is allocated when the plan's scratch is already in the pool (a
+ * plan with a single b-chunk needs none). d_nf (int64) and d_status (int32)
+ * are device pointers written by the launch. Safe to capture in a hipGraph
+ * once the same sizes ran once outside capture.
+ */
+pm_status poly_mul_modp_async(const uint32_t *a, int64_t na, const uint32_t *b, int64_t nb, uint32_t p,
+                              uint32_t *f, int64_t f_cap, int64_t *d_nf, int32_t *d_status, void *stream);
+
+/*
+ * Euclidean division (Sec. 3, problem statement): the unique q, r with
+ * a = q*b + r and deg r < deg b, for b != 0.
+ *   q, q_cap : quotient (device); needs deg a - deg b + 1 words (0 when
+ *              deg a < deg b); q_cap >= na - nb + 1 is checked on the host
+ *              when nb > 0, the true requirement on the device
+ *   r, r_cap : remainder (device); needs deg b words, or deg a + 1 when
+ *              deg a < deg b
+ *   nq, nr   : host; normalised lengths
+ * Returns PM_EDIVZERO when b is the zero polynomial.
+ */
+pm_status poly_divrem_modp(const uint32_t *a, int64_t na, const uint32_t *b, int64_t nb, uint32_t p,
+                           uint32_t *q, int64_t q_cap, int64_t *nq, uint32_t *r, int64_t r_cap, int64_t *nr,
+                           void *stream);
+
+/*
+ * Greatest common divisor by the Euclidean remainder sequence (Sec. 6),
+ * returned monic; gcd(a, 0) = a made monic, gcd(0, 0) = 0.
+ *   g, g_cap : output (device); needs deg gcd + 1 words, at most
+ *              max(deg a, deg b) + 1 (checked on the device)
+ *   ng       : host; length of g
+ */
+pm_status poly_gcd_modp(const uint32_t *a, int64_t na, const uint32_t *b, int64_t nb, uint32_t p,
+                        uint32_t *g, int64_t g_cap, int64_t *ng, void *stream);
+
+/* Statistics of the last poly_gcd_modp call on this thread. */
+typedef struct {
+    int64_t steps;    /* Euclidean division steps                        */
+    int64_t updates;  /* coefficient updates, (deg divisor + 1) per step */
+    int64_t chunks;   /* fused chunks, one grid barrier each             */
+} pm_gcd_stats;
+void pm_last_gcd_stats(pm_gcd_stats *out);
+
+/*
+ * Tuning (the paper's program parameter s).
+ *   mul_s   : b-coefficients per thread-block in the product (0 = default)
+ *   mul_r   : outputs per thread in the product (1,2,4,8,16,32; 0 = default)
+ *   div_s   : division steps fused per pass in the quotient (1..64; 0 = 64)
+ *   gcd_s   : Euclidean steps fused per chunk (1..256; 0 = 64)
+ * The settings are per process and apply to later calls.
+ */
+typedef struct {
+    int32_t mul_s;
+    int32_t mul_r;
+    int32_t div_s;
+    int32_t gcd_s;
+} pm_params;
+pm_status pm_set_params(const pm_params *params);
+void pm_get_params(pm_params *params);
+
+/* Frees the scratch pool of every device and stream. */
+void pm_release(void);
+
+/* Thread-local description of the last non-OK status. */
+const char *pm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* POLYMODP_H */

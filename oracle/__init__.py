@@ -54,6 +54,9 @@ def lib():
         L.orc_inv.restype = ctypes.c_uint32
         L.orc_mul.argtypes = [_u32p, ctypes.c_int64, _u32p, ctypes.c_int64, ctypes.c_uint32, _u32p]
         L.orc_mul.restype = ctypes.c_int64
+        L.orc_mul_coeff.argtypes = [_u32p, ctypes.c_int64, _u32p, ctypes.c_int64, ctypes.c_uint32,
+                                    ctypes.c_int64]
+        L.orc_mul_coeff.restype = ctypes.c_uint32
         L.orc_divrem.argtypes = [_u32p, ctypes.c_int64, _u32p, ctypes.c_int64, ctypes.c_uint32,
                                  _u32p, _i64p, _u32p, _i64p]
         L.orc_divrem.restype = ctypes.c_int
@@ -90,6 +93,12 @@ def mul(a, b, p: int) -> np.ndarray:
     f = np.zeros(max(a.size + b.size - 1, 1), dtype=np.uint32)
     nf = lib().orc_mul(_ptr(a), a.size, _ptr(b), b.size, p, _ptr(f))
     return f[:nf].copy()
+
+
+def mul_coeff(a, b, p: int, k: int) -> int:
+    """f_k of the product a*b (no normalisation of the inputs)."""
+    a, b = _arr(a), _arr(b)
+    return int(lib().orc_mul_coeff(_ptr(a), a.size, _ptr(b), b.size, p, k))
 
 
 def divrem(a, b, p: int):

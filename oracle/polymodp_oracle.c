@@ -82,6 +82,21 @@ int64_t orc_mul(const uint32_t *a, int64_t na, const uint32_t *b, int64_t nb,
     return trimmed(f, nf);
 }
 
+/* One coefficient of the product, f_k, by the same definition as orc_mul
+ * (for spot checks of products too large to form here). */
+uint32_t orc_mul_coeff(const uint32_t *a, int64_t na, const uint32_t *b, int64_t nb,
+                       uint32_t p, int64_t k)
+{
+    if (na <= 0 || nb <= 0 || k < 0 || k > na + nb - 2)
+        return 0;
+    int64_t lo = k - (nb - 1) > 0 ? k - (nb - 1) : 0;
+    int64_t hi = k < na - 1 ? k : na - 1;
+    u128 acc = 0;
+    for (int64_t i = lo; i <= hi; i++)
+        acc += (u128)((uint64_t)a[i] * (uint64_t)b[k - i]);
+    return (uint32_t)(acc % p);
+}
+
 /* Statistics of one long division or one remainder sequence. */
 typedef struct {
     int64_t steps;    /* division steps (one quotient coefficient each)   */

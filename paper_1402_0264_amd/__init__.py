@@ -1,0 +1,206 @@
+"""Dense univariate polynomial arithmetic over Z/pZ on AMD MI355X (gfx950).
+
+Python binding of libpolymodp (C ABI in include/polymodp.h): argument
+marshalling only. Every step of the computation runs in the library's HIP
+kernels; PyTorch provides device memory and streams. There is no CPU
+fallback: if the library is not built, loading it raises.
+
+Polynomials are torch tensors of dtype int32 or uint32 on a ROCm device,
+holding uint32 coefficient bit patterns (index = exponent). Results come
+back as int32 tensors of the same bit patterns; ``to_numpy`` views them as
+numpy uint32.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libpolymodp.so")
+HEADER = os.path.join(os.path.dirname(PKG), "include", "polymodp.h")
+
+PM_OK, PM_EINVAL, PM_EMODULUS, PM_ERANGE, PM_EDIVZERO, PM_ENOMEM, PM_EDEVICE = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "PM_OK", -1: "PM_EINVAL", -2: "PM_EMODULUS", -3: "PM_ERANGE", -4: "PM_EDIVZERO",
+                -5: "PM_ENOMEM", -6: "PM_EDEVICE"}
+
+
+class PolyModPError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), message))
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("mul_s", ctypes.c_int32), ("mul_r", ctypes.c_int32),
+                ("div_s", ctypes.c_int32), ("gcd_s", ctypes.c_int32)]
+
+
+class GcdStats(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int64), ("updates", ctypes.c_int64), ("chunks", ctypes.c_int64)]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i64p = ctypes.POINTER(ctypes.c_int64)
+
+
+def lib() -> ctypes.CDLL:
+    """Load libpolymodp.so; raises when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libpolymodp.so is not built; run `python -m paper_1402_0264_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    L.poly_mul_modp.argtypes = [_vp, _i64, _vp, _i64, ctypes.c_uint32, _vp, _i64, _i64p, _vp]
+    L.poly_mul_modp.restype = ctypes.c_int32
+    L.poly_mul_modp_async.argtypes = [_vp, _i64, _vp, _i64, ctypes.c_uint32, _vp, _i64, _vp, _vp, _vp]
+    L.poly_mul_modp_async.restype = ctypes.c_int32
+    L.poly_divrem_modp.argtypes = [_vp, _i64, _vp, _i64, ctypes.c_uint32, _vp, _i64, _i64p, _vp, _i64,
+                                   _i64p, _vp]
+    L.poly_divrem_modp.restype = ctypes.c_int32
+    L.poly_gcd_modp.argtypes = [_vp, _i64, _vp, _i64, ctypes.c_uint32, _vp, _i64, _i64p, _vp]
+    L.poly_gcd_modp.restype = ctypes.c_int32
+    L.pm_last_gcd_stats.argtypes = [ctypes.POINTER(GcdStats)]
+    L.pm_last_gcd_stats.restype = None
+    L.pm_set_params.argtypes = [ctypes.POINTER(Params)]
+    L.pm_set_params.restype = ctypes.c_int32
+    L.pm_get_params.argtypes = [ctypes.POINTER(Params)]
+    L.pm_get_params.restype = None
+    L.pm_release.argtypes = []
+    L.pm_release.restype = None
+    L.pm_last_error.argtypes = []
+    L.pm_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def declared_symbols() -> list:
+    """Function names declared in include/polymodp.h."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b([a-z_][a-z0-9_]*)\s*\(", text)) - {"if", "sizeof"})
+
+
+def _check(st: int):
+    if st != PM_OK:
+        raise PolyModPError(st, lib().pm_last_error().decode(errors="replace"))
+
+
+def last_error() -> str:
+    return lib().pm_last_error().decode(errors="replace")
+
+
+# ----------------------------------------------------------------- torch glue
+def _torch():
+    import torch
+    return torch
+
+
+def _dev_ptr(t) -> int:
+    return t.data_ptr() if t.numel() else 0
+
+
+def _as_u32_tensor(x, device=None):
+    torch = _torch()
+    if isinstance(x, torch.Tensor):
+        if x.dtype == torch.uint32:
+            x = x.view(torch.int32)
+        if x.dtype != torch.int32:
+            raise TypeError("coefficient tensors must be int32 or uint32")
+        if not x.is_cuda:
+            raise ValueError("coefficient tensors must live on the GPU")
+        return x.contiguous()
+    import numpy as np
+    arr = np.ascontiguousarray(np.asarray(x, dtype=np.uint32)).view(np.int32)
+    return torch.from_numpy(arr.copy()).to(device or "cuda")
+
+
+def to_device(x, device=None):
+    """numpy/list of uint32 coefficients -> int32 tensor on the GPU."""
+    return _as_u32_tensor(x, device)
+
+
+def to_numpy(t):
+    """int32 coefficient tensor -> numpy uint32 array."""
+    import numpy as np
+    return t.detach().cpu().numpy().view(np.uint32).copy()
+
+
+def _stream_handle(stream=None) -> int:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def mul(a, b, p: int, stream=None):
+    """Product a*b mod p; returns an int32 tensor of length deg a + deg b + 1."""
+    torch = _torch()
+    a, b = _as_u32_tensor(a), _as_u32_tensor(b, None)
+    na, nb = a.numel(), b.numel()
+    n = na + nb - 1 if na and nb else 0
+    f = torch.empty(max(n, 1), dtype=torch.int32, device=a.device if na else b.device)
+    nf = ctypes.c_int64(0)
+    _check(lib().poly_mul_modp(_dev_ptr(a), na, _dev_ptr(b), nb, p, f.data_ptr(), n, ctypes.byref(nf),
+                               _stream_handle(stream)))
+    return f[:nf.value]
+
+
+def mul_async(a, b, p: int, f, d_nf, d_status, stream=None):
+    """Enqueue f = a*b; d_nf (int64, 1 element) and d_status (int32,
+    1 element) are device tensors written by the launch."""
+    a, b = _as_u32_tensor(a), _as_u32_tensor(b)
+    _check(lib().poly_mul_modp_async(_dev_ptr(a), a.numel(), _dev_ptr(b), b.numel(), p, f.data_ptr(),
+                                     f.numel(), d_nf.data_ptr(), d_status.data_ptr(), _stream_handle(stream)))
+
+
+def divrem(a, b, p: int, stream=None):
+    """(q, r) with a = q*b + r, deg r < deg b."""
+    torch = _torch()
+    a, b = _as_u32_tensor(a), _as_u32_tensor(b)
+    na, nb = a.numel(), b.numel()
+    qcap = max(na - nb + 1, 0) if nb else 0
+    qcap = max(qcap, na)  # the true quotient may be longer when b has high zeros
+    rcap = max(nb, na, 1)
+    dev = a.device if na else b.device
+    q = torch.empty(max(qcap, 1), dtype=torch.int32, device=dev)
+    r = torch.empty(rcap, dtype=torch.int32, device=dev)
+    nq, nr = ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(lib().poly_divrem_modp(_dev_ptr(a), na, _dev_ptr(b), nb, p, q.data_ptr(), qcap, ctypes.byref(nq),
+                                  r.data_ptr(), rcap, ctypes.byref(nr), _stream_handle(stream)))
+    return q[:nq.value], r[:nr.value]
+
+
+def gcd(a, b, p: int, stream=None):
+    """Monic gcd(a, b) mod p."""
+    torch = _torch()
+    a, b = _as_u32_tensor(a), _as_u32_tensor(b)
+    na, nb = a.numel(), b.numel()
+    cap = max(na, nb, 1)
+    g = torch.empty(cap, dtype=torch.int32, device=a.device if na else b.device)
+    ng = ctypes.c_int64(0)
+    _check(lib().poly_gcd_modp(_dev_ptr(a), na, _dev_ptr(b), nb, p, g.data_ptr(), cap, ctypes.byref(ng),
+                               _stream_handle(stream)))
+    return g[:ng.value]
+
+
+def last_gcd_stats() -> dict:
+    st = GcdStats()
+    lib().pm_last_gcd_stats(ctypes.byref(st))
+    return {"steps": st.steps, "updates": st.updates, "chunks": st.chunks}
+
+
+def set_params(mul_s: int = 0, mul_r: int = 0, div_s: int = 0, gcd_s: int = 0):
+    _check(lib().pm_set_params(ctypes.byref(Params(mul_s, mul_r, div_s, gcd_s))))
+
+
+def get_params() -> dict:
+    pp = Params()
+    lib().pm_get_params(ctypes.byref(pp))
+    return {"mul_s": pp.mul_s, "mul_r": pp.mul_r, "div_s": pp.div_s, "gcd_s": pp.gcd_s}
+
+
+def release():
+    lib().pm_release()

@@ -1,0 +1,373 @@
+// capi.cpp -- the extern "C" entry points of libpolymodp (include/polymodp.h):
+// argument checks, per-prime constants, the scratch pool and the sequencing
+// of the kernel launches in mul.hip, divrem.hip and gcd.hip.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <utility>
+
+#include "../../include/polymodp.h"
+#include "internal.hpp"
+
+namespace {
+
+thread_local char g_err[512] = "";
+thread_local pm_gcd_stats g_gcd_stats = {0, 0, 0};
+
+pm_status fail(pm_status st, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+pm_status hip_fail(hipError_t e, const char* what) {
+    return fail(PM_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                          \
+    do {                                             \
+        hipError_t e_ = (expr);                      \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+// ------------------------------------------------------------ prime field
+uint64_t mulmod_host(uint64_t a, uint64_t b, uint64_t m) { return (unsigned __int128)a * b % m; }
+
+uint64_t powmod_host(uint64_t a, uint64_t e, uint64_t m) {
+    uint64_t r = 1 % m;
+    a %= m;
+    while (e) {
+        if (e & 1) r = mulmod_host(r, a, m);
+        a = mulmod_host(a, a, m);
+        e >>= 1;
+    }
+    return r;
+}
+
+// Deterministic Miller-Rabin for 32-bit n (bases 2, 7, 61 suffice).
+bool is_prime_u32(uint32_t n) {
+    if (n < 2) return false;
+    for (uint32_t sp : {2u, 3u, 5u, 7u, 11u, 13u, 61u})
+        if (n % sp == 0) return n == sp;
+    uint32_t d = n - 1;
+    int r = 0;
+    while ((d & 1) == 0) { d >>= 1; r++; }
+    for (uint32_t a : {2u, 7u, 61u}) {
+        uint64_t x = powmod_host(a, d, n);
+        if (x == 1 || x == n - 1) continue;
+        bool comp = true;
+        for (int i = 1; i < r; i++) {
+            x = mulmod_host(x, x, n);
+            if (x == n - 1) { comp = false; break; }
+        }
+        if (comp) return false;
+    }
+    return true;
+}
+
+std::mutex g_field_mu;
+std::map<uint32_t, pm::Field> g_fields;
+
+pm_status field_for(uint32_t p, pm::Field* out) {
+    if (p < 2 || p >= (1u << 30)) return fail(PM_EMODULUS, "modulus %u is outside [2, 2^30)", p);
+    std::lock_guard<std::mutex> lk(g_field_mu);
+    auto it = g_fields.find(p);
+    if (it != g_fields.end()) { *out = it->second; return PM_OK; }
+    if (!is_prime_u32(p)) return fail(PM_EMODULUS, "modulus %u is not prime", p);
+    pm::Field F{};
+    F.p = p;
+    F.c32 = (uint32_t)((1ULL << 32) % p);
+    // -p^{-1} mod 2^32 by Newton iteration (p odd); p = 2 never uses REDC
+    uint32_t inv = 1;
+    if (p & 1) {
+        inv = p;
+        for (int i = 0; i < 5; i++) inv *= 2u - p * inv;
+    }
+    F.pinv_neg = (uint32_t)(0u - inv);
+    F.mu = ~0ULL / p;
+    // after a fold the accumulator is below (2^32-1)*c32 + 2^32; each further
+    // product is at most (p-1)^2
+    unsigned __int128 after = (unsigned __int128)0xFFFFFFFFull * F.c32 + 0xFFFFFFFFull;
+    unsigned __int128 room = ((unsigned __int128)1 << 64) - 1 - after;
+    unsigned __int128 sq = (unsigned __int128)(p - 1) * (p - 1);
+    unsigned __int128 fe = sq ? room / sq : ((unsigned __int128)1 << 30);
+    F.fold_every = fe > (1u << 30) ? (1u << 30) : (uint32_t)fe;
+    g_fields[p] = F;
+    *out = F;
+    return PM_OK;
+}
+
+// REDC needs an odd modulus; for p = 2 the gcd kernel would not be exact.
+bool redc_ok(uint32_t p) { return (p & 1) != 0; }
+
+// ------------------------------------------------------------ parameters
+std::mutex g_param_mu;
+pm_params g_params = {0, 0, 0, 0};
+
+pm_params params_now() {
+    std::lock_guard<std::mutex> lk(g_param_mu);
+    return g_params;
+}
+
+// ------------------------------------------------------------ scratch pool
+struct Pool {
+    pm::CallInfo* d_info = nullptr;  // device
+    pm::CallInfo* h_info = nullptr;  // pinned host
+    uint32_t* words = nullptr;       // device scratch
+    int64_t cap = 0;
+};
+
+std::mutex g_pool_mu;
+std::map<std::pair<int, hipStream_t>, Pool> g_pools;
+
+pm_status pool_get(hipStream_t stream, int64_t words, Pool** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    Pool& P = g_pools[{dev, stream}];
+    if (!P.d_info) {
+        HIP_TRY(hipMalloc((void**)&P.d_info, sizeof(pm::CallInfo)), "hipMalloc(info)");
+        HIP_TRY(hipMemset(P.d_info, 0, sizeof(pm::CallInfo)), "hipMemset(info)");
+        HIP_TRY(hipHostMalloc((void**)&P.h_info, sizeof(pm::CallInfo), hipHostMallocDefault), "hipHostMalloc");
+    }
+    if (words > P.cap) {
+        if (P.words) {
+            HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
+            HIP_TRY(hipFree(P.words), "hipFree");
+            P.words = nullptr;
+            P.cap = 0;
+        }
+        int64_t want = words + words / 4 + 1024;
+        if (hipMalloc((void**)&P.words, (size_t)want * sizeof(uint32_t)) != hipSuccess) {
+            P.words = nullptr;
+            return fail(PM_ENOMEM, "cannot allocate %lld scratch words", (long long)want);
+        }
+        P.cap = want;
+    }
+    *out = &P;
+    return PM_OK;
+}
+
+pm_status read_info(Pool* P, hipStream_t stream) {
+    HIP_TRY(hipMemcpyAsync(P->h_info, P->d_info, sizeof(pm::CallInfo), hipMemcpyDeviceToHost, stream),
+            "hipMemcpyAsync(info)");
+    HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    return PM_OK;
+}
+
+int num_cus() {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        hipDeviceProp_t pr;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&pr, dev) == hipSuccess)
+            cus = pr.multiProcessorCount;
+        if (cus <= 0) cus = 256;
+    }
+    return cus;
+}
+
+pm::MulPlan mul_plan(int64_t na, int64_t nb) {
+    pm::MulPlan plan = pm::mul_default_plan(na, nb, num_cus());
+    pm_params pp = params_now();
+    if (pp.mul_r > 0) plan.r = pp.mul_r;
+    if (pp.mul_s > 0) plan.kc = pp.mul_s;
+    if (plan.kc < plan.r) plan.kc = plan.r;
+    return plan;
+}
+
+const char* status_text(pm_status st) {
+    switch (st) {
+        case PM_ERANGE: return "an input coefficient is not below p";
+        case PM_EDIVZERO: return "division by the zero polynomial";
+        case PM_EINVAL: return "output capacity below what the result needs";
+        case PM_EDEVICE: return "device invariant broken";
+        default: return "error";
+    }
+}
+
+bool bad_len(const void* ptr, int64_t n) { return n < 0 || (n > 0 && ptr == nullptr); }
+
+// Ordered larger-first for the product kernel: the longer operand is staged
+// in LDS windows, the shorter one is walked step by step.
+void order_operands(const uint32_t*& a, int64_t& na, const uint32_t*& b, int64_t& nb) {
+    if (nb > na) {
+        std::swap(a, b);
+        std::swap(na, nb);
+    }
+}
+
+pm_status mul_enqueue(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, const pm::Field& F,
+                      uint32_t* f, int64_t* d_nf, int32_t* d_status, hipStream_t stream) {
+    order_operands(a, na, b, nb);
+    pm::MulPlan plan = mul_plan(na, nb);
+    int64_t words = pm::mul_scratch_words(na, nb, plan);
+    Pool* P = nullptr;
+    uint32_t* M = nullptr;
+    if (words > 0) {
+        pm_status st = pool_get(stream, words, &P);
+        if (st) return st;
+        M = P->words;
+    }
+    HIP_TRY(pm::mul_launch(a, na, b, nb, F, f, plan, M, d_nf, d_status, nullptr, -1, stream), "mul launch");
+    return PM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pm_last_error(void) { return g_err; }
+
+void pm_last_gcd_stats(pm_gcd_stats* out) {
+    if (out) *out = g_gcd_stats;
+}
+
+pm_status pm_set_params(const pm_params* params) {
+    if (!params) return fail(PM_EINVAL, "null params");
+    const pm_params& q = *params;
+    if (q.mul_r != 0 && q.mul_r != 1 && q.mul_r != 2 && q.mul_r != 4 && q.mul_r != 8 && q.mul_r != 16 &&
+        q.mul_r != 32)
+        return fail(PM_EINVAL, "mul_r must be 0, 1, 2, 4, 8, 16 or 32");
+    if (q.mul_s < 0 || q.mul_s > 16384) return fail(PM_EINVAL, "mul_s must be in [0, 16384]");
+    if (q.div_s < 0 || q.div_s > 64) return fail(PM_EINVAL, "div_s must be in [0, 64]");
+    if (q.gcd_s < 0 || q.gcd_s > 256) return fail(PM_EINVAL, "gcd_s must be in [0, 256]");
+    std::lock_guard<std::mutex> lk(g_param_mu);
+    g_params = q;
+    return PM_OK;
+}
+
+void pm_get_params(pm_params* params) {
+    if (params) *params = params_now();
+}
+
+void pm_release(void) {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    for (auto& kv : g_pools) {
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        (void)hipSetDevice(kv.first.first);
+        (void)hipStreamSynchronize(kv.first.second);
+        if (kv.second.words) (void)hipFree(kv.second.words);
+        if (kv.second.d_info) (void)hipFree(kv.second.d_info);
+        if (kv.second.h_info) (void)hipHostFree(kv.second.h_info);
+        (void)hipSetDevice(cur);
+    }
+    g_pools.clear();
+}
+
+pm_status poly_mul_modp_async(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, uint32_t p,
+                              uint32_t* f, int64_t f_cap, int64_t* d_nf, int32_t* d_status, void* stream) {
+    if (bad_len(a, na) || bad_len(b, nb)) return fail(PM_EINVAL, "null input or negative length");
+    int64_t need = (na > 0 && nb > 0) ? na + nb - 1 : 0;
+    if (need > 0 && (f == nullptr || f_cap < need))
+        return fail(PM_EINVAL, "f_cap %lld < na + nb - 1 = %lld", (long long)f_cap, (long long)need);
+    pm::Field F;
+    pm_status st = field_for(p, &F);
+    if (st) return st;
+    return mul_enqueue(a, na, b, nb, F, f, d_nf, d_status, (hipStream_t)stream);
+}
+
+pm_status poly_mul_modp(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, uint32_t p, uint32_t* f,
+                        int64_t f_cap, int64_t* nf, void* stream) {
+    if (!nf) return fail(PM_EINVAL, "null nf");
+    if (bad_len(a, na) || bad_len(b, nb)) return fail(PM_EINVAL, "null input or negative length");
+    int64_t need = (na > 0 && nb > 0) ? na + nb - 1 : 0;
+    if (need > 0 && (f == nullptr || f_cap < need))
+        return fail(PM_EINVAL, "f_cap %lld < na + nb - 1 = %lld", (long long)f_cap, (long long)need);
+    pm::Field F;
+    pm_status st = field_for(p, &F);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    Pool* P = nullptr;
+    if ((st = pool_get(s, 0, &P))) return st;
+    if ((st = mul_enqueue(a, na, b, nb, F, f, &P->d_info->n0, &P->d_info->status, s))) return st;
+    if ((st = read_info(P, s))) return st;
+    *nf = P->h_info->n0;
+    if (P->h_info->status) return fail(P->h_info->status, "%s", status_text(P->h_info->status));
+    return PM_OK;
+}
+
+pm_status poly_divrem_modp(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, uint32_t p, uint32_t* q,
+                           int64_t q_cap, int64_t* nq, uint32_t* r, int64_t r_cap, int64_t* nr, void* stream) {
+    if (!nq || !nr) return fail(PM_EINVAL, "null nq or nr");
+    if (bad_len(a, na) || bad_len(b, nb)) return fail(PM_EINVAL, "null input or negative length");
+    if (q_cap < 0 || r_cap < 0 || (q_cap > 0 && !q) || (r_cap > 0 && !r))
+        return fail(PM_EINVAL, "bad output buffer");
+    if (nb == 0) return fail(PM_EDIVZERO, "division by the zero polynomial");
+    if (na - nb + 1 > q_cap) return fail(PM_EINVAL, "q_cap %lld < na - nb + 1", (long long)q_cap);
+    pm::Field F;
+    pm_status st = field_for(p, &F);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    Pool* P = nullptr;
+    if ((st = pool_get(s, pm::divrem_head_words(na), &P))) return st;
+    pm_params pp = params_now();
+    HIP_TRY(pm::divrem_head_launch(a, na, b, nb, F, q, q_cap, r_cap, P->words, P->d_info,
+                                   pp.div_s > 0 ? pp.div_s : 64, s),
+            "divrem head launch");
+    if ((st = read_info(P, s))) return st;
+    const pm::CallInfo I = *P->h_info;
+    if (I.status) return fail(I.status, "%s", status_text(I.status));
+    const int64_t da = I.deg_a, db = I.deg_b;
+    if (da < db) {  // q = 0, r = a
+        if (da >= 0)
+            HIP_TRY(hipMemcpyAsync(r, a, (size_t)(da + 1) * 4, hipMemcpyDeviceToDevice, s), "copy r");
+        HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+        *nq = 0;
+        *nr = da + 1;
+        return PM_OK;
+    }
+    const int64_t mu = da - db + 1;
+    *nq = mu;
+    if (db == 0) {
+        HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+        *nr = 0;
+        return PM_OK;
+    }
+    // r_k = a_k - (q*b)_k for k < deg b
+    const uint32_t *x = b, *y = q;
+    int64_t nx = db + 1, ny = mu;
+    order_operands(x, nx, y, ny);
+    pm::MulPlan plan = mul_plan(nx, ny);
+    int64_t words = pm::mul_scratch_words(nx, ny, plan);
+    if ((st = pool_get(s, words, &P))) return st;
+    HIP_TRY(pm::mul_launch(x, nx, y, ny, F, r, plan, P->words, nullptr, nullptr, a, db, s), "remainder launch");
+    HIP_TRY(pm::trim_launch(r, db, P->d_info, s), "trim launch");
+    if ((st = read_info(P, s))) return st;
+    *nr = P->h_info->n1;
+    return PM_OK;
+}
+
+pm_status poly_gcd_modp(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, uint32_t p, uint32_t* g,
+                        int64_t g_cap, int64_t* ng, void* stream) {
+    if (!ng) return fail(PM_EINVAL, "null ng");
+    if (bad_len(a, na) || bad_len(b, nb)) return fail(PM_EINVAL, "null input or negative length");
+    if (g_cap < 0 || (g_cap > 0 && !g)) return fail(PM_EINVAL, "bad output buffer");
+    pm::Field F;
+    pm_status st = field_for(p, &F);
+    if (st) return st;
+    if (!redc_ok(p)) return fail(PM_EMODULUS, "p = 2 is not supported by the gcd");
+    hipStream_t s = (hipStream_t)stream;
+    g_gcd_stats = pm_gcd_stats{0, 0, 0};
+    int64_t n = na > nb ? na : nb;
+    pm_params pp = params_now();
+    pm::GcdPlan plan = pm::gcd_default_plan(n > 0 ? n : 1, num_cus(), pp.gcd_s);
+    Pool* P = nullptr;
+    if ((st = pool_get(s, pm::gcd_scratch_words(n, plan), &P))) return st;
+    HIP_TRY(pm::gcd_launch(a, na, b, nb, F, g, g_cap, P->words, P->d_info, plan, s), "gcd launch");
+    if ((st = read_info(P, s))) return st;
+    const pm::CallInfo I = *P->h_info;
+    g_gcd_stats = pm_gcd_stats{I.steps, I.updates, I.chunks};
+    if (I.status) return fail(I.status, "%s", status_text(I.status));
+    *ng = I.n0;
+    return PM_OK;
+}
+
+}  // extern "C"

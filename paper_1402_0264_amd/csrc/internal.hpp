@@ -1,0 +1,79 @@
+// internal.hpp -- host-side interfaces between the C ABI (capi.cpp) and the
+// kernel launchers (mul.hip, divrem.hip, gcd.hip, batch.hip, serve.cpp).
+// Not installed; the public interface is include/polymodp.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "common.hpp"
+
+namespace pm {
+
+// ------------------------------------------------------------------ product
+// Tiling of one product f = a*b (Sec. 5). The b operand is cut into chunks
+// of `kc` coefficients (the paper's s: b-coefficients handled per
+// thread-block); each thread-block owns `r` * 256 consecutive outputs of one
+// chunk and each thread `r` consecutive outputs. With more than one chunk the
+// per-chunk partial sums go to the array M (one row of n_a + kc - 1 residues
+// per chunk, as in the paper's multiplication phase) and a second kernel adds
+// the rows (the addition phase).
+struct MulPlan {
+    int r;        // outputs per thread: 1, 2, 4, 8, 16 or 32
+    int64_t kc;   // b-coefficients per chunk (multiple of r)
+};
+
+constexpr int MUL_THREADS = 256;
+
+// Scratch words (uint32) needed for the partial-sum rows of a plan.
+int64_t mul_scratch_words(int64_t na, int64_t nb, const MulPlan& plan);
+
+// Default plan for a product of the given sizes on this device.
+MulPlan mul_default_plan(int64_t na, int64_t nb, int num_cus);
+
+// Enqueue f = a*b (f has room for na+nb-1 words). When out_len or
+// out_status is non-null one extra thread-block validates the inputs and
+// writes the normalised length of f and the status there. `M` is scratch of mul_scratch_words words
+// (may be null when the plan has one chunk). `sub_from` (optional, for the
+// division remainder) switches the epilogue to f[k] = sub_from[k] - (a*b)[k]
+// for k < out_limit, and limits the outputs to k < out_limit.
+hipError_t mul_launch(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb,
+                      const Field& F, uint32_t* f, const MulPlan& plan, uint32_t* M,
+                      int64_t* out_len, int32_t* out_status, const uint32_t* sub_from,
+                      int64_t out_limit, hipStream_t stream);
+
+// ----------------------------------------------------------------- division
+// Euclidean division (Sec. 3) runs in two launches around one host read of
+// the degrees: divrem_head_launch validates the inputs, finds deg a and
+// deg b, and computes the whole quotient from the heads of a and b (the
+// division steps, s at a time); the remainder r = a - q*b restricted to
+// exponents below deg b is then one product launch with a subtracting
+// epilogue (mul_launch with sub_from = a), and trim_launch finds its length.
+constexpr int DIV_THREADS = 256;
+// Scratch words for the head of a (deg a - deg b + 1 words at most).
+inline int64_t divrem_head_words(int64_t na) { return na > 0 ? na : 1; }
+hipError_t divrem_head_launch(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb,
+                              const Field& F, uint32_t* q, int64_t q_cap, int64_t r_cap,
+                              uint32_t* head, CallInfo* info, int s, hipStream_t stream);
+// info->n1 = 1 + (largest k < n with r[k] != 0), or 0.
+hipError_t trim_launch(const uint32_t* r, int64_t n, CallInfo* info, hipStream_t stream);
+// Degrees and range check only (info->deg_a, deg_b, status).
+hipError_t degrees_launch(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb,
+                          const Field& F, CallInfo* info, hipStream_t stream);
+
+// ---------------------------------------------------------------------- gcd
+struct GcdPlan {
+    int groups;      // cooperating thread-blocks (1 = single block)
+    int slice;       // coefficient positions owned by each block
+    int head;        // head length (multiple of 64)
+    int s;           // max Euclidean division steps per fused chunk
+};
+constexpr int GCD_THREADS = 256;
+GcdPlan gcd_default_plan(int64_t n, int num_cus, int s);
+int64_t gcd_scratch_words(int64_t n, const GcdPlan& plan);
+hipError_t gcd_launch(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb,
+                      const Field& F, uint32_t* g, int64_t g_cap, uint32_t* scratch,
+                      CallInfo* info, const GcdPlan& plan, hipStream_t stream);
+
+}  // namespace pm

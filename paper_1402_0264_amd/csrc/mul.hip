@@ -1,0 +1,299 @@
+// mul.hip -- plain (schoolbook) product of dense polynomials over Z/pZ on
+// gfx950 (Sec. 5: multiplication phase and addition phase).
+//
+// f_k = sum_i a_i * b_{k-i}. The paper's long multiplication cuts b into
+// chunks of s coefficients; each thread-block multiplies one chunk of b by a
+// window of a and writes partial sums into rows of an array M, and an
+// addition phase adds the rows. Here:
+//
+//  * a thread-block owns T = 256*R consecutive outputs of one b-chunk of kc
+//    coefficients (kc is the paper's s); each thread owns R consecutive
+//    outputs and keeps R exact 64-bit sums in registers;
+//  * the a window (T + kc - 1 words, the paper's s*l + s - 1) is staged once
+//    from HBM into LDS with a padded layout, so that at every step the 64
+//    lanes of a wave read 64 distinct banks;
+//  * at step j each thread needs one new a value (its window slides by one)
+//    and the uniform b_j, which the compiler keeps in scalar registers, so a
+//    step is one LDS read plus R v_mad_u64_u32 multiply-adds;
+//  * sums are folded every FOLD steps (fold(), one more multiply-add) and
+//    reduced to canonical residues once at the end;
+//  * with more than one chunk, residues go to row c of M (length
+//    n_a + kc - 1, output k = c*kc + x) and mul_reduce_kernel adds the rows,
+//    one output per thread, reading M coalesced.
+#include "internal.hpp"
+
+namespace pm {
+namespace {
+
+struct MulArgs {
+    const uint32_t* a;
+    const uint32_t* b;
+    uint32_t* out;             // f (one chunk) or M (several chunks)
+    const uint32_t* sub_from;  // optional: out = sub_from - a*b
+    int64_t na, nb;
+    int64_t kc;                // b-coefficients per chunk
+    int64_t nchunks;
+    int64_t rowlen;            // na + kc - 1
+    int64_t tiles;             // thread-blocks per chunk
+    int64_t out_limit;         // outputs k < out_limit are written (one chunk)
+    Field F;
+    int64_t* out_len;          // optional: normalised length of f
+    int32_t* out_status;       // optional: validation status
+};
+
+// Padded LDS address of window index x >= 0: lanes reading x = t*R + c
+// (fixed c) are R+1 words apart, an odd stride, so no two share a bank.
+template <int R>
+__host__ __device__ __forceinline__ int lds_addr(int x) {
+    return R > 1 ? x + x / R : x;
+}
+
+// Validation block: range check of every coefficient and the normalised
+// length of the product.
+__device__ void mul_aux_block(const MulArgs& A) {
+    __shared__ int64_t s_deg[2];
+    __shared__ int s_bad;
+    if (threadIdx.x == 0) s_bad = 0;
+    __syncthreads();
+    int bad = 0;
+    for (int64_t i = threadIdx.x; i < A.na; i += blockDim.x) bad |= A.a[i] >= A.F.p;
+    for (int64_t i = threadIdx.x; i < A.nb; i += blockDim.x) bad |= A.b[i] >= A.F.p;
+    if (bad) atomicOr(&s_bad, 1);
+    const int wave = threadIdx.x >> 6;
+    if (wave < 2) {
+        int64_t d = top_nonzero_wave(wave == 0 ? A.a : A.b, wave == 0 ? A.na : A.nb);
+        if ((threadIdx.x & 63) == 0) s_deg[wave] = d;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t da = s_deg[0], db = s_deg[1];
+        if (A.out_len) *A.out_len = (da >= 0 && db >= 0) ? da + db + 1 : 0;
+        if (A.out_status) *A.out_status = s_bad ? -3 /* PM_ERANGE */ : 0;
+    }
+}
+
+template <int R, int FOLD>
+__global__ __launch_bounds__(MUL_THREADS) void mul_tile_kernel(MulArgs A) {
+    extern __shared__ uint32_t lds[];
+    const int64_t work = A.nchunks * A.tiles;
+    if ((int64_t)blockIdx.x >= work) {
+        mul_aux_block(A);
+        return;
+    }
+    const int tid = threadIdx.x;
+    const int64_t c = blockIdx.x / A.tiles;
+    const int64_t tile = blockIdx.x - c * A.tiles;
+    const int64_t j0 = c * A.kc;
+    constexpr int T = MUL_THREADS * R;
+    constexpr int PAD = R > 1 ? R + 1 : 1;  // padded words per group of R
+    const int64_t x0 = tile * T;  // first row offset of the tile (output k = j0 + x)
+    // steps of this chunk, rounded up to whole blocks of R (b reads as 0 past nb)
+    const int64_t left = A.nb - j0;
+    const int steps = (int)(((left < A.kc ? left : A.kc) + R - 1) / R * R);
+
+    // Stage the a window: index w <-> a[x0 - steps + w], w = 0 .. T + steps - 1
+    // (w = 0 is one spare word below the window so the last prefetch stays in
+    // bounds), then the b chunk (zero past nb).
+    const int W = T + steps;
+    const int64_t abase = x0 - steps;
+    for (int w = tid; w < W; w += MUL_THREADS) {
+        int64_t i = abase + w;
+        uint32_t v = (i >= 0 && i < A.na) ? A.a[i] : 0u;
+        lds[lds_addr<R>(w)] = v;
+    }
+    const int lb = (lds_addr<R>(W) + 7) & ~3;  // b chunk, 16-byte aligned
+    for (int j = tid; j < steps; j += MUL_THREADS) lds[lb + j] = j < left ? A.b[j0 + j] : 0u;
+    __syncthreads();
+
+    // Thread window at step jj: w = tid*R + steps + u with u = r - jj; the
+    // value of offset u lives in ring[u mod R]. For w = R*g + e (0 <= e < R)
+    // the padded address is PAD*g + e, so the load of step v of a block is a
+    // constant offset from one address per block.
+    uint32_t ring[R];
+    uint64_t acc[R];
+    {
+        const int g0 = PAD * (tid + steps / R);
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            ring[r] = lds[g0 + r];
+            acc[r] = 0;
+        }
+    }
+    const uint32_t c32 = A.F.c32;
+    const int nblk = steps / R;
+    constexpr int BPF = FOLD >= R ? FOLD / R : 1;  // blocks between folds
+    int blk = 0;
+    while (blk < nblk) {
+        const int stop = blk + BPF < nblk ? blk + BPF : nblk;
+        for (; blk < stop; blk++) {
+            uint32_t bv[R];
+#pragma unroll
+            for (int v = 0; v < R; v++) bv[v] = lds[lb + blk * R + v];
+            const int gb = PAD * (tid + (nblk - blk - 1));
+#pragma unroll
+            for (int v = 0; v < R; v++) {
+                // next window value (offset u = -(blk*R+v) - 1) replaces the
+                // slot that acc[R-1] consumes in this step
+                const uint32_t nxt = lds[gb + (R - 1 - v)];
+#pragma unroll
+                for (int r = 0; r < R; r++) {
+                    const int slot = ((r - v) % R + R) % R;
+                    acc[r] = (uint64_t)ring[slot] * bv[v] + acc[r];
+                }
+                ring[(R - 1 - v) % R] = nxt;
+                if (FOLD < R && (v + 1) % FOLD == 0) {
+#pragma unroll
+                    for (int r = 0; r < R; r++) acc[r] = fold(acc[r], c32);
+                }
+            }
+        }
+        if (FOLD >= R) {
+#pragma unroll
+            for (int r = 0; r < R; r++) acc[r] = fold(acc[r], c32);
+        }
+    }
+
+    // Epilogue: canonical residues, then either a row of M or f itself.
+    const int64_t xt = x0 + (int64_t)tid * R;
+    if (A.nchunks > 1) {
+        uint32_t* row = A.out + c * A.rowlen;
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            int64_t x = xt + r;
+            if (x < A.rowlen) row[x] = reduce64(acc[r], A.F);
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            int64_t k = xt + r;
+            if (k < A.out_limit) {
+                uint32_t v = reduce64(acc[r], A.F);
+                A.out[k] = A.sub_from ? submod(A.sub_from[k], v, A.F.p) : v;
+            }
+        }
+    }
+}
+
+// Addition phase: f_k = sum over chunks c of M[c][k - c*kc].
+__global__ __launch_bounds__(256) void mul_reduce_kernel(const uint32_t* M, int64_t rowlen, int64_t kc,
+                                                         int64_t nchunks, uint32_t* f, int64_t out_limit,
+                                                         const uint32_t* sub_from, Field F) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= out_limit) return;
+    int64_t c_hi = k / kc;
+    if (c_hi > nchunks - 1) c_hi = nchunks - 1;
+    int64_t c_lo = k - rowlen + 1;
+    c_lo = c_lo <= 0 ? 0 : (c_lo + kc - 1) / kc;
+    uint64_t s = 0;
+    for (int64_t c = c_lo; c <= c_hi; c++) s += M[c * rowlen + (k - c * kc)];
+    uint32_t v = reduce64(s, F);
+    f[k] = sub_from ? submod(sub_from[k], v, F.p) : v;
+}
+
+// LDS bytes of one thread-block for R outputs per thread and kc steps.
+int64_t tile_lds_bytes(int R, int64_t kc) {
+    int64_t W = (int64_t)MUL_THREADS * R + kc;
+    int64_t padded = R > 1 ? W + W / R : W;
+    return (padded + 8 + kc) * (int64_t)sizeof(uint32_t);
+}
+
+// Chunk length actually used: a multiple of R, at most nb rounded up, and
+// small enough for the tile to fit in LDS.
+int64_t effective_kc(const MulPlan& plan, int64_t nb) {
+    const int R = plan.r;
+    int64_t kc = (plan.kc + R - 1) / R * R;
+    const int64_t full = (nb + R - 1) / R * R;
+    if (kc >= full) kc = full;
+    while (kc > R && tile_lds_bytes(R, kc) > 160 * 1024) kc = (kc / 2 + R - 1) / R * R;
+    return kc;
+}
+
+template <int R, int FOLD>
+hipError_t launch_tile(const MulArgs& A, int64_t grid, hipStream_t stream) {
+    size_t lds = (size_t)tile_lds_bytes(R, A.kc);
+    hipLaunchKernelGGL((mul_tile_kernel<R, FOLD>), dim3((unsigned)grid), dim3(MUL_THREADS), lds, stream, A);
+    return hipGetLastError();
+}
+
+template <int R>
+hipError_t launch_fold(const MulArgs& A, int64_t grid, hipStream_t stream) {
+    uint32_t fe = A.F.fold_every;
+    if (fe >= 128) return launch_tile<R, 128>(A, grid, stream);
+    if (fe >= 64) return launch_tile<R, 64>(A, grid, stream);
+    if (fe >= 32) return launch_tile<R, 32>(A, grid, stream);
+    if (fe >= 16) return launch_tile<R, 16>(A, grid, stream);
+    return launch_tile<R, 8>(A, grid, stream);
+}
+
+}  // namespace
+
+int64_t mul_scratch_words(int64_t na, int64_t nb, const MulPlan& plan) {
+    if (na <= 0 || nb <= 0) return 0;
+    int64_t kc = effective_kc(plan, nb);
+    if (kc >= nb) return 0;
+    int64_t nchunks = (nb + kc - 1) / kc;
+    return nchunks * (na + kc - 1);
+}
+
+MulPlan mul_default_plan(int64_t na, int64_t nb, int num_cus) {
+    MulPlan best{1, 64};
+    if (na <= 0 || nb <= 0) return best;
+    const int64_t target = 4LL * num_cus;
+    static const int Rs[] = {16, 8, 4, 2, 1};
+    static const int64_t KCs[] = {2048, 1024, 512, 256, 128, 64, 32};
+    for (int R : Rs) {
+        if ((int64_t)MUL_THREADS * R > 2 * (na + nb)) continue;
+        for (int64_t kc : KCs) {
+            if (kc % R) continue;
+            int64_t k = kc < nb ? kc : (nb + R - 1) / R * R;
+            int64_t nch = (nb + k - 1) / k;
+            int64_t tiles = (na + k - 1 + MUL_THREADS * R - 1) / (MUL_THREADS * R);
+            if (nch * tiles >= target) return MulPlan{R, kc};
+        }
+    }
+    // small products: as much parallelism as the sizes allow
+    return MulPlan{1, 32};
+}
+
+hipError_t mul_launch(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, const Field& F,
+                      uint32_t* f, const MulPlan& plan, uint32_t* M, int64_t* out_len, int32_t* out_status,
+                      const uint32_t* sub_from, int64_t out_limit, hipStream_t stream) {
+    MulArgs A{};
+    A.a = a; A.b = b; A.F = F; A.na = na; A.nb = nb; A.sub_from = sub_from;
+    A.out_len = out_len; A.out_status = out_status;
+    const bool aux = out_len || out_status;
+    const int R = plan.r;
+    int64_t nf = (na > 0 && nb > 0) ? na + nb - 1 : 0;
+    if (out_limit >= 0 && out_limit < nf) nf = out_limit;
+    A.out_limit = nf;
+    if (nf == 0) {
+        if (!aux) return hipSuccess;
+        A.nchunks = 0; A.tiles = 0; A.kc = R; A.rowlen = 0; A.out = f;
+        hipLaunchKernelGGL((mul_tile_kernel<1, 8>), dim3(1), dim3(MUL_THREADS), 8, stream, A);
+        return hipGetLastError();
+    }
+    const int64_t kc = effective_kc(plan, nb);
+    A.kc = kc;
+    A.nchunks = (nb + kc - 1) / kc;
+    A.rowlen = na + kc - 1;
+    A.tiles = (A.rowlen + MUL_THREADS * R - 1) / (MUL_THREADS * R);
+    A.out = A.nchunks > 1 ? M : f;
+    int64_t grid = A.nchunks * A.tiles + (aux ? 1 : 0);
+    hipError_t e;
+    switch (R) {
+        case 1: e = launch_fold<1>(A, grid, stream); break;
+        case 2: e = launch_fold<2>(A, grid, stream); break;
+        case 4: e = launch_fold<4>(A, grid, stream); break;
+        case 8: e = launch_fold<8>(A, grid, stream); break;
+        case 16: e = launch_fold<16>(A, grid, stream); break;
+        case 32: e = launch_fold<32>(A, grid, stream); break;
+        default: return hipErrorInvalidValue;
+    }
+    if (e != hipSuccess || A.nchunks == 1) return e;
+    int64_t blocks = (nf + 255) / 256;
+    hipLaunchKernelGGL(mul_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, M, A.rowlen, kc,
+                       A.nchunks, f, nf, sub_from, F);
+    return hipGetLastError();
+}
+
+}  // namespace pm

@@ -1,0 +1,252 @@
+"""Bit-exact parity of the HIP library (through its C ABI) with the CPU
+oracle, on seeded inputs: ragged sizes spanning several tiles, every prime
+of the workloads plus tiny primes, the full-size workloads (sampled outputs
+or size-independent properties where the oracle would be too slow), the
+degenerate cases, and invariance under the tuning parameter s."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1402_0264_amd as pm
+from paper_1402_0264_amd import gen
+from tests import checkers as ck
+
+pytestmark = pytest.mark.gpu
+
+PRIMES = [gen.P_A, gen.P_B, gen.P_C]
+TINY_ODD = [3, 5, 7, 65521]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    pm.lib()
+    pm.set_params()
+    yield
+    pm.set_params()
+
+
+def dev(x):
+    return pm.to_device(x)
+
+
+def host(t):
+    return pm.to_numpy(t)
+
+
+def rnd(st, n, p):
+    return st.uniform_poly(n - 1, p) if n > 0 else np.zeros(0, dtype=np.uint32)
+
+
+def same(x, y):
+    return np.array_equal(np.asarray(x, dtype=np.uint32), np.asarray(y, dtype=np.uint32))
+
+
+# ----------------------------------------------------------------- product
+MUL_SIZES = [(1, 1), (1, 7), (7, 1), (2, 2), (63, 65), (100, 3), (257, 1000), (2048, 2048), (5000, 123),
+             (4099, 4097), (12289, 700)]
+
+
+@pytest.mark.parametrize("p", PRIMES + TINY_ODD + [2])
+def test_mul_matches_oracle(p):
+    st = gen.Stream(101 + p % 997)
+    for na, nb in MUL_SIZES:
+        a, b = rnd(st, na, p), rnd(st, nb, p)
+        f = host(pm.mul(dev(a), dev(b), p))
+        assert same(f, oracle.mul(a, b, p)), (p, na, nb)
+
+
+@pytest.mark.parametrize("r,s", [(1, 1), (2, 2), (4, 4), (8, 8), (16, 16), (4, 2048), (16, 512), (32, 64),
+                                 (32, 4096), (1, 3), (8, 100)])
+def test_mul_invariant_under_s(r, s):
+    p = gen.P_B  # smallest fold interval
+    st = gen.Stream(102)
+    a, b = rnd(st, 3001, p), rnd(st, 2500, p)
+    want = oracle.mul(a, b, p)
+    pm.set_params(mul_r=r, mul_s=s)
+    try:
+        f = host(pm.mul(dev(a), dev(b), p))
+    finally:
+        pm.set_params()
+    assert same(f, want)
+
+
+def test_mul_product_2048():
+    a, b = gen.product_2048()
+    f = host(pm.mul(dev(a), dev(b), gen.P_A))
+    assert f.size == 4095
+    assert same(f, oracle.mul(a, b, gen.P_A))
+
+
+def test_mul_product_65536_sampled():
+    """Full size: outputs sampled one by one against the oracle's
+    definition, plus the evaluation identity at random points."""
+    a, b = gen.product_65536()
+    p = gen.P_A
+    f = host(pm.mul(dev(a), dev(b), p))
+    assert f.size == 131071
+    st = gen.Stream(103)
+    ks = [0, 1, 2, 4095, 4096, 65534, 65535, 65536, 131069, 131070] + [st.uniform_int(0, 131070) for _ in range(54)]
+    for k in ks:
+        assert int(f[k]) == oracle.mul_coeff(a, b, p, k), k
+    for _ in range(3):
+        x = st.uniform_int(0, p - 1)
+        assert ck.horner(f, x, p) == ck.horner(a, x, p) * ck.horner(b, x, p) % p
+
+
+def test_mul_edge_cases():
+    p = gen.P_A
+    z = np.zeros(0, dtype=np.uint32)
+    st = gen.Stream(104)
+    a = rnd(st, 40, p)
+    assert pm.mul(dev(a), dev(z), p).numel() == 0
+    assert pm.mul(dev(z), dev(a), p).numel() == 0
+    a_hz = np.concatenate([a, np.zeros(13, dtype=np.uint32)])   # high zeros are ignored
+    b = rnd(st, 17, p)
+    b_hz = np.concatenate([b, np.zeros(300, dtype=np.uint32)])
+    f = host(pm.mul(dev(a_hz), dev(b_hz), p))
+    assert same(f, oracle.mul(a, b, p))
+    assert same(host(pm.mul(dev(np.zeros(5, dtype=np.uint32)), dev(b), p)), [])
+    bad = a.copy(); bad[3] = p
+    with pytest.raises(pm.PolyModPError) as e:
+        pm.mul(dev(bad), dev(b), p)
+    assert e.value.status == pm.PM_ERANGE
+
+
+def test_mul_async_writes_device_results():
+    import torch
+    p = gen.P_C
+    st = gen.Stream(105)
+    a, b = rnd(st, 1500, p), rnd(st, 900, p)
+    f = torch.zeros(2399, dtype=torch.int32, device="cuda")
+    d_nf = torch.full((1,), -1, dtype=torch.int64, device="cuda")
+    d_st = torch.full((1,), 99, dtype=torch.int32, device="cuda")
+    pm.mul_async(dev(a), dev(b), p, f, d_nf, d_st)
+    torch.cuda.synchronize()
+    assert int(d_nf.item()) == 2399 and int(d_st.item()) == 0
+    assert same(host(f), oracle.mul(a, b, p))
+
+
+# ---------------------------------------------------------------- division
+DIV_SIZES = [(1, 1), (10, 1), (10, 3), (100, 99), (500, 17), (300, 300), (3, 10), (2049, 2048), (5000, 200),
+             (20000, 64), (1000, 999), (700, 2)]
+
+
+@pytest.mark.parametrize("p", PRIMES + TINY_ODD + [2])
+def test_divrem_matches_oracle(p):
+    st = gen.Stream(201 + p % 997)
+    for na, nb in DIV_SIZES:
+        a, b = rnd(st, na, p), rnd(st, nb, p)
+        q, r = pm.divrem(dev(a), dev(b), p)
+        wq, wr = oracle.divrem(a, b, p)
+        assert same(host(q), wq) and same(host(r), wr), (p, na, nb)
+
+
+@pytest.mark.parametrize("s", [1, 2, 5, 16, 64])
+def test_divrem_invariant_under_s(s):
+    p = gen.P_A
+    st = gen.Stream(202)
+    a, b = rnd(st, 3000, p), rnd(st, 1100, p)
+    wq, wr = oracle.divrem(a, b, p)
+    pm.set_params(div_s=s)
+    try:
+        q, r = pm.divrem(dev(a), dev(b), p)
+    finally:
+        pm.set_params()
+    assert same(host(q), wq) and same(host(r), wr)
+
+
+def test_divrem_gcd_workload():
+    pl = gen.gcd_32768()
+    p = pl.p
+    a = oracle.mul(pl.g, pl.u, p)
+    b = oracle.mul(pl.g, pl.v, p)
+    q, r = pm.divrem(dev(a), dev(b), p)
+    wq, wr = oracle.divrem(a, b, p)
+    assert host(q).size == 2
+    assert same(host(q), wq) and same(host(r), wr)
+
+
+def test_divrem_edge_cases():
+    p = gen.P_B
+    st = gen.Stream(203)
+    a, b = rnd(st, 50, p), rnd(st, 9, p)
+    z = np.zeros(4, dtype=np.uint32)
+    with pytest.raises(pm.PolyModPError) as e:
+        pm.divrem(dev(a), dev(z), p)
+    assert e.value.status == pm.PM_EDIVZERO
+    for x, y in [(a, b), (b, a), (np.zeros(0, dtype=np.uint32), b), (a, a), (a, np.array([7], dtype=np.uint32)),
+                 (np.concatenate([a, np.zeros(5, dtype=np.uint32)]), np.concatenate([b, np.zeros(50, dtype=np.uint32)]))]:
+        q, r = pm.divrem(dev(x), dev(y), p)
+        wq, wr = oracle.divrem(x, y, p)
+        assert same(host(q), wq) and same(host(r), wr)
+    bad = b.copy(); bad[0] = p + 5
+    with pytest.raises(pm.PolyModPError) as e:
+        pm.divrem(dev(a), dev(bad), p)
+    assert e.value.status == pm.PM_ERANGE
+
+
+# --------------------------------------------------------------------- gcd
+GCD_CASES = [(5, 3, 0), (40, 40, 3), (100, 60, 20), (60, 100, 59), (200, 199, 50), (300, 300, 0),
+             (1000, 999, 10), (2500, 2400, 700), (5000, 4999, 1234), (3000, 10, 2), (700, 1, 0)]
+
+
+@pytest.mark.parametrize("p", PRIMES + TINY_ODD)
+def test_gcd_matches_oracle(p):
+    st = gen.Stream(301 + p % 997)
+    for da, db, dg in GCD_CASES:
+        pl = gen.planted_gcd(da, db, dg, p, st)
+        a, b = oracle.mul(pl.g, pl.u, p), oracle.mul(pl.g, pl.v, p)
+        g = host(pm.gcd(dev(a), dev(b), p))
+        assert same(g, oracle.gcd(a, b, p)), (p, da, db, dg)
+
+
+@pytest.mark.parametrize("s", [1, 2, 7, 31, 64, 128, 256])
+def test_gcd_invariant_under_s(s):
+    p = gen.P_C
+    st = gen.Stream(302)
+    pl = gen.planted_gcd(3000, 2999, 300, p, st)
+    a, b = oracle.mul(pl.g, pl.u, p), oracle.mul(pl.g, pl.v, p)
+    want = oracle.gcd(a, b, p)
+    pm.set_params(gcd_s=s)
+    try:
+        g = host(pm.gcd(dev(a), dev(b), p))
+    finally:
+        pm.set_params()
+    assert same(g, want)
+
+
+def test_gcd_workload_32768():
+    pl = gen.gcd_32768()
+    p = pl.p
+    a = oracle.mul(pl.g, pl.u, p)
+    b = oracle.mul(pl.g, pl.v, p)
+    g = host(pm.gcd(dev(a), dev(b), p))
+    want, degs, stats = oracle.gcd(a, b, p, with_info=True)
+    assert same(g, want) and same(g, pl.g)
+    got = pm.last_gcd_stats()
+    assert got["steps"] == stats.steps and got["updates"] == stats.updates
+
+
+def test_gcd_edge_cases():
+    p = gen.P_A
+    st = gen.Stream(303)
+    a, b = rnd(st, 30, p), rnd(st, 12, p)
+    z = np.zeros(0, dtype=np.uint32)
+    cases = [(z, z), (a, z), (z, a), (a, a), (a, np.array([9], dtype=np.uint32)), (a, b),
+             (np.concatenate([a, np.zeros(9, dtype=np.uint32)]), np.zeros(3, dtype=np.uint32))]
+    h = rnd(st, 8, p)
+    ab = oracle.mul(a, h, p)
+    cases.append((ab, a))   # a | ab
+    for x, y in cases:
+        g = host(pm.gcd(dev(x), dev(y), p))
+        assert same(g, oracle.gcd(x, y, p))
+    for i, j in [(12, 18), (97, 13), (64, 48)]:   # gcd(X^i - 1, X^j - 1) = X^gcd(i,j) - 1
+        x = np.zeros(i + 1, dtype=np.uint32); x[0] = p - 1; x[i] = 1
+        y = np.zeros(j + 1, dtype=np.uint32); y[0] = p - 1; y[j] = 1
+        assert same(host(pm.gcd(dev(x), dev(y), p)), oracle.gcd(x, y, p))
+    bad = a.copy(); bad[-1] = p
+    with pytest.raises(pm.PolyModPError) as e:
+        pm.gcd(dev(bad), dev(b), p)
+    assert e.value.status == pm.PM_ERANGE

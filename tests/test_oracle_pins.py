@@ -56,6 +56,18 @@ def test_mul_product_2048_seeded(orc):
     assert ck.trim(f) == ck.ntt_mul(a, b, gen.P_A)
 
 
+def test_mul_single_coefficient(orc):
+    p = gen.P_B
+    st = gen.Stream(16)
+    a, b = rnd(st, 300, p), rnd(st, 77, p)
+    f = orc.mul(a, b, p)
+    for k in [0, 1, 76, 77, 150, 299, 375, 376, 400, -1]:
+        want = int(f[k]) if 0 <= k < f.size else 0
+        assert orc.mul_coeff(a, b, p, k) == want
+        if 0 <= k < f.size:
+            assert want == sum(int(a[i]) * int(b[k - i]) for i in range(max(0, k - 76), min(k, 299) + 1)) % p
+
+
 @pytest.mark.parametrize("p", [gen.P_A, 7])
 def test_mul_sympy(orc, p):
     st = gen.Stream(14)
