@@ -99,6 +99,36 @@ pm_status poly_divrem_modp(const uint32_t *a, int64_t na, const uint32_t *b, int
 pm_status poly_gcd_modp(const uint32_t *a, int64_t na, const uint32_t *b, int64_t nb, uint32_t p,
                         uint32_t *g, int64_t g_cap, int64_t *ng, void *stream);
 
+/*
+ * Many independent gcds in one launch (one thread-block per instance, both
+ * polynomials resident in LDS for the whole remainder sequence). Items may
+ * mix degrees and primes; each needs max(na, nb) <= PM_GCD_BATCH_MAX.
+ *   items   : host array of `count` descriptors; a, b, g are device pointers
+ *   results : host array of `count` results, filled when the call returns
+ * Host checks (per item: prime, lengths, pointers) fail the whole call
+ * before any device work; device checks are reported per item in
+ * results[i].status. Synchronous.
+ */
+#define PM_GCD_BATCH_MAX 17408
+typedef struct {
+    const uint32_t *a;
+    int64_t na;
+    const uint32_t *b;
+    int64_t nb;
+    uint32_t p;
+    uint32_t *g;
+    int64_t g_cap;
+} pm_gcd_item;
+typedef struct {
+    int64_t ng;       /* length of the monic gcd                          */
+    int64_t steps;    /* Euclidean division steps                         */
+    int64_t updates;  /* coefficient updates, (deg divisor + 1) per step  */
+    int64_t chunks;   /* fused chunks                                     */
+    int32_t status;   /* PM_OK or the item's device-side error            */
+    int32_t done;     /* 1 once the item finished                         */
+} pm_gcd_result;
+pm_status poly_gcd_modp_batch(const pm_gcd_item *items, int32_t count, pm_gcd_result *results, void *stream);
+
 /* Statistics of the last poly_gcd_modp call on this thread. */
 typedef struct {
     int64_t steps;    /* Euclidean division steps                        */
@@ -123,6 +153,18 @@ typedef struct {
 } pm_params;
 pm_status pm_set_params(const pm_params *params);
 void pm_get_params(pm_params *params);
+
+/*
+ * Kernel timing (diagnostics). While enabled, every kernel launch of the
+ * library is bracketed by two HIP events recorded on its launch stream
+ * (no host synchronisation). pm_timing_read waits for the recorded launches
+ * of the kernel with the given function name (e.g. "mul_tile_kernel",
+ * "mul_reduce_kernel", "gcd_kernel") and returns their count and total
+ * elapsed milliseconds. pm_timing_reset drops the records.
+ */
+void pm_timing_enable(int on);
+pm_status pm_timing_read(const char *kernel, int64_t *launches, double *total_ms);
+void pm_timing_reset(void);
 
 /* Frees the scratch pool of every device and stream. */
 void pm_release(void);

@@ -36,6 +36,19 @@ class Params(ctypes.Structure):
                 ("div_s", ctypes.c_int32), ("gcd_s", ctypes.c_int32)]
 
 
+class GcdItem(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_void_p), ("na", ctypes.c_int64), ("b", ctypes.c_void_p), ("nb", ctypes.c_int64),
+                ("p", ctypes.c_uint32), ("g", ctypes.c_void_p), ("g_cap", ctypes.c_int64)]
+
+
+class GcdResult(ctypes.Structure):
+    _fields_ = [("ng", ctypes.c_int64), ("steps", ctypes.c_int64), ("updates", ctypes.c_int64),
+                ("chunks", ctypes.c_int64), ("status", ctypes.c_int32), ("done", ctypes.c_int32)]
+
+
+GCD_BATCH_MAX = 17408
+
+
 class GcdStats(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int64), ("updates", ctypes.c_int64), ("chunks", ctypes.c_int64)]
 
@@ -63,12 +76,20 @@ def lib() -> ctypes.CDLL:
     L.poly_divrem_modp.restype = ctypes.c_int32
     L.poly_gcd_modp.argtypes = [_vp, _i64, _vp, _i64, ctypes.c_uint32, _vp, _i64, _i64p, _vp]
     L.poly_gcd_modp.restype = ctypes.c_int32
+    L.poly_gcd_modp_batch.argtypes = [ctypes.POINTER(GcdItem), ctypes.c_int32, ctypes.POINTER(GcdResult), _vp]
+    L.poly_gcd_modp_batch.restype = ctypes.c_int32
     L.pm_last_gcd_stats.argtypes = [ctypes.POINTER(GcdStats)]
     L.pm_last_gcd_stats.restype = None
     L.pm_set_params.argtypes = [ctypes.POINTER(Params)]
     L.pm_set_params.restype = ctypes.c_int32
     L.pm_get_params.argtypes = [ctypes.POINTER(Params)]
     L.pm_get_params.restype = None
+    L.pm_timing_enable.argtypes = [ctypes.c_int]
+    L.pm_timing_enable.restype = None
+    L.pm_timing_reset.argtypes = []
+    L.pm_timing_reset.restype = None
+    L.pm_timing_read.argtypes = [ctypes.c_char_p, _i64p, ctypes.POINTER(ctypes.c_double)]
+    L.pm_timing_read.restype = ctypes.c_int32
     L.pm_release.argtypes = []
     L.pm_release.restype = None
     L.pm_last_error.argtypes = []
@@ -186,6 +207,31 @@ def gcd(a, b, p: int, stream=None):
     return g[:ng.value]
 
 
+def gcd_batch(pairs, stream=None):
+    """Monic gcds of many (a, b, p) triples in one launch; returns a list of
+    (g, result dict). Inputs are device tensors (or arrays moved there)."""
+    torch = _torch()
+    n = len(pairs)
+    items = (GcdItem * max(n, 1))()
+    results = (GcdResult * max(n, 1))()
+    keep = []
+    outs = []
+    for i, (a, b, p) in enumerate(pairs):
+        a, b = _as_u32_tensor(a), _as_u32_tensor(b)
+        cap = max(a.numel(), b.numel(), 1)
+        g = torch.empty(cap, dtype=torch.int32, device=a.device if a.numel() else b.device)
+        keep += [a, b]
+        outs.append(g)
+        items[i] = GcdItem(_dev_ptr(a), a.numel(), _dev_ptr(b), b.numel(), p, g.data_ptr(), cap)
+    _check(lib().poly_gcd_modp_batch(items, n, results, _stream_handle(stream)))
+    ret = []
+    for i in range(n):
+        r = results[i]
+        ret.append((outs[i][:r.ng], {"status": r.status, "ng": r.ng, "steps": r.steps, "updates": r.updates,
+                                     "chunks": r.chunks}))
+    return ret
+
+
 def last_gcd_stats() -> dict:
     st = GcdStats()
     lib().pm_last_gcd_stats(ctypes.byref(st))
@@ -200,6 +246,21 @@ def get_params() -> dict:
     pp = Params()
     lib().pm_get_params(ctypes.byref(pp))
     return {"mul_s": pp.mul_s, "mul_r": pp.mul_r, "div_s": pp.div_s, "gcd_s": pp.gcd_s}
+
+
+def timing_enable(on: bool = True):
+    lib().pm_timing_enable(1 if on else 0)
+
+
+def timing_reset():
+    lib().pm_timing_reset()
+
+
+def timing_read(kernel: str):
+    """(launches, total_ms) of the recorded launches of one kernel."""
+    n, ms = ctypes.c_int64(0), ctypes.c_double(0)
+    _check(lib().pm_timing_read(kernel.encode(), ctypes.byref(n), ctypes.byref(ms)))
+    return n.value, ms.value
 
 
 def release():

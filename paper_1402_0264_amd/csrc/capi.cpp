@@ -6,9 +6,12 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <atomic>
 #include <map>
 #include <mutex>
+#include <string>
 #include <utility>
+#include <vector>
 
 #include "../../include/polymodp.h"
 #include "internal.hpp"
@@ -219,9 +222,80 @@ pm_status mul_enqueue(const uint32_t* a, int64_t na, const uint32_t* b, int64_t 
     return PM_OK;
 }
 
+// ------------------------------------------------------------ kernel timing
+std::atomic<int> g_timing_on{0};
+std::mutex g_timing_mu;
+struct TimedLaunch {
+    std::string kernel;
+    hipEvent_t start, stop;
+};
+std::vector<TimedLaunch> g_timed;
+std::vector<hipEvent_t> g_event_pool;
+
+hipEvent_t take_event() {
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    if (!g_event_pool.empty()) {
+        hipEvent_t e = g_event_pool.back();
+        g_event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
 }  // namespace
 
+namespace pm {
+
+TimingScope::TimingScope(const char* kernel, hipStream_t stream) : kernel_(kernel), stream_(stream) {
+    if (!g_timing_on.load(std::memory_order_relaxed)) return;
+    start_ = take_event();
+    if (start_ && hipEventRecord(start_, stream_) != hipSuccess) start_ = nullptr;
+}
+
+TimingScope::~TimingScope() {
+    if (!start_) return;
+    hipEvent_t stop = take_event();
+    if (!stop || hipEventRecord(stop, stream_) != hipSuccess) return;
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    g_timed.push_back(TimedLaunch{kernel_, start_, stop});
+}
+
+}  // namespace pm
+
 extern "C" {
+
+void pm_timing_enable(int on) { g_timing_on.store(on ? 1 : 0); }
+
+void pm_timing_reset(void) {
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    for (auto& t : g_timed) {
+        (void)hipEventSynchronize(t.stop);
+        g_event_pool.push_back(t.start);
+        g_event_pool.push_back(t.stop);
+    }
+    g_timed.clear();
+}
+
+pm_status pm_timing_read(const char* kernel, int64_t* launches, double* total_ms) {
+    if (!kernel || !launches || !total_ms) return fail(PM_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    int64_t n = 0;
+    double ms = 0;
+    for (auto& t : g_timed) {
+        if (t.kernel != kernel) continue;
+        HIP_TRY(hipEventSynchronize(t.stop), "hipEventSynchronize");
+        float x = 0;
+        HIP_TRY(hipEventElapsedTime(&x, t.start, t.stop), "hipEventElapsedTime");
+        n++;
+        ms += x;
+    }
+    *launches = n;
+    *total_ms = ms;
+    return PM_OK;
+}
+
 
 const char* pm_last_error(void) { return g_err; }
 
@@ -345,6 +419,59 @@ pm_status poly_divrem_modp(const uint32_t* a, int64_t na, const uint32_t* b, int
     return PM_OK;
 }
 
+static_assert(sizeof(pm_gcd_result) == sizeof(pm::GcdResult), "result layouts differ");
+
+pm_status poly_gcd_modp_batch(const pm_gcd_item* items, int32_t count, pm_gcd_result* results, void* stream) {
+    if (count < 0 || (count > 0 && (!items || !results))) return fail(PM_EINVAL, "bad item or result array");
+    if (count == 0) return PM_OK;
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<pm::GcdJob> jobs((size_t)count);
+    std::vector<int32_t> small, large;
+    for (int32_t i = 0; i < count; i++) {
+        const pm_gcd_item& it = items[i];
+        if (bad_len(it.a, it.na) || bad_len(it.b, it.nb) || it.g_cap < 0 || (it.g_cap > 0 && !it.g))
+            return fail(PM_EINVAL, "item %d: bad pointer or length", i);
+        int64_t n = it.na > it.nb ? it.na : it.nb;
+        if (n > PM_GCD_BATCH_MAX)
+            return fail(PM_EINVAL, "item %d: %lld terms exceed the batch limit", i, (long long)n);
+        pm::Field F;
+        pm_status st = field_for(it.p, &F);
+        if (st) return st;
+        if (!redc_ok(it.p)) return fail(PM_EMODULUS, "item %d: p = 2 is not supported by the gcd", i);
+        jobs[i] = pm::GcdJob{it.a, it.b, it.na, it.nb, it.g, it.g_cap, nullptr, F};
+        (n <= pm::gcd_batch_cap(0) ? small : large).push_back(i);
+    }
+    // scratch: jobs | order | results
+    const int64_t job_words = ((int64_t)count * (int64_t)sizeof(pm::GcdJob) + 3) / 4;
+    const int64_t res_off = (job_words + count + 3) & ~3LL;
+    const int64_t res_words = ((int64_t)count * (int64_t)sizeof(pm::GcdResult) + 3) / 4;
+    Pool* P = nullptr;
+    pm_status st = pool_get(s, res_off + res_words + 16, &P);
+    if (st) return st;
+    pm::GcdJob* d_jobs = (pm::GcdJob*)P->words;
+    int32_t* d_order = (int32_t*)(P->words + job_words);
+    pm::GcdResult* d_res = (pm::GcdResult*)(P->words + res_off);
+    for (int32_t i = 0; i < count; i++) jobs[i].out = d_res + i;
+    std::vector<int32_t> order;
+    order.insert(order.end(), large.begin(), large.end());
+    order.insert(order.end(), small.begin(), small.end());
+    HIP_TRY(hipMemcpyAsync(d_jobs, jobs.data(), jobs.size() * sizeof(pm::GcdJob), hipMemcpyHostToDevice, s),
+            "copy jobs");
+    HIP_TRY(hipMemcpyAsync(d_order, order.data(), order.size() * sizeof(int32_t), hipMemcpyHostToDevice, s),
+            "copy order");
+    pm_params pp = params_now();
+    const int gs = pp.gcd_s > 0 ? pp.gcd_s : 64;
+    if (!large.empty())
+        HIP_TRY(pm::gcd_batch_launch(d_jobs, d_order, (int)large.size(), 1, gs, s), "gcd batch launch");
+    if (!small.empty())
+        HIP_TRY(pm::gcd_batch_launch(d_jobs, d_order + large.size(), (int)small.size(), 0, gs, s),
+                "gcd batch launch");
+    HIP_TRY(hipMemcpyAsync(results, d_res, (size_t)count * sizeof(pm::GcdResult), hipMemcpyDeviceToHost, s),
+            "copy results");
+    HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+    return PM_OK;
+}
+
 pm_status poly_gcd_modp(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, uint32_t p, uint32_t* g,
                         int64_t g_cap, int64_t* ng, void* stream) {
     if (!ng) return fail(PM_EINVAL, "null ng");
@@ -358,6 +485,17 @@ pm_status poly_gcd_modp(const uint32_t* a, int64_t na, const uint32_t* b, int64_
     g_gcd_stats = pm_gcd_stats{0, 0, 0};
     int64_t n = na > nb ? na : nb;
     pm_params pp = params_now();
+    if (n <= pm::gcd_batch_cap(0)) {
+        // one block holds the whole instance in LDS
+        pm_gcd_item it{a, na, b, nb, p, g, g_cap};
+        pm_gcd_result res{};
+        pm_status st1 = poly_gcd_modp_batch(&it, 1, &res, stream);
+        if (st1) return st1;
+        g_gcd_stats = pm_gcd_stats{res.steps, res.updates, res.chunks};
+        if (res.status) return fail(res.status, "%s", status_text(res.status));
+        *ng = res.ng;
+        return PM_OK;
+    }
     pm::GcdPlan plan = pm::gcd_default_plan(n > 0 ? n : 1, num_cus(), pp.gcd_s);
     Pool* P = nullptr;
     if ((st = pool_get(s, pm::gcd_scratch_words(n, plan), &P))) return st;

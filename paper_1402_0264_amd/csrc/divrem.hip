@@ -136,6 +136,7 @@ __global__ __launch_bounds__(256) void trim_kernel(const uint32_t* r, int64_t n,
 
 hipError_t degrees_launch(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, const Field& F,
                           CallInfo* info, hipStream_t stream) {
+    TimingScope ts("degrees_kernel", stream);
     hipLaunchKernelGGL(degrees_kernel, dim3(1), dim3(256), 0, stream, a, na, b, nb, F, info);
     return hipGetLastError();
 }
@@ -145,12 +146,14 @@ hipError_t divrem_head_launch(const uint32_t* a, int64_t na, const uint32_t* b, 
                               int s, hipStream_t stream) {
     if (s < 1) s = 1;
     if (s > 64) s = 64;
+    TimingScope ts("divrem_head_kernel", stream);
     hipLaunchKernelGGL(divrem_head_kernel, dim3(1), dim3(DIV_THREADS), 0, stream, a, na, b, nb, F, q, q_cap,
                        r_cap, head, info, s);
     return hipGetLastError();
 }
 
 hipError_t trim_launch(const uint32_t* r, int64_t n, CallInfo* info, hipStream_t stream) {
+    TimingScope ts("trim_kernel", stream);
     hipLaunchKernelGGL(trim_kernel, dim3(1), dim3(64), 0, stream, r, n, info);
     return hipGetLastError();
 }

@@ -1,33 +1,28 @@
 // gcd.hip -- Euclidean remainder-sequence gcd of dense polynomials over
 // Z/pZ on gfx950 (Sec. 6: naive and optimized Euclidean algorithm).
 //
-// State: the two current polynomials A and B (the paper's a and b, updated
-// in place by division steps) and their degrees (the paper's st). One
-// division step reduces the operand of higher degree (A on ties, as in the
-// naive Euclidean kernel):  A <- lc(B)*A - lc(A)*X^d*B with d = deg A - deg B.
-// This is the paper's step multiplied by the unit lc(B), so no inverse sits
-// on the dependent chain of steps; the Montgomery reduction used for the
-// combination multiplies by one more unit, 2^-32. Remainders are therefore
-// associates of the paper's, with the same degrees, and the final remainder
-// is made monic with a single inverse.
+// Two kernels share the fused chunk of gcd_core.hpp (heads -> recorded
+// steps -> matrix M -> one independent sum per coefficient):
 //
-// Fusion (the paper's s, Sec. 6.2): every thread-block loads the heads of A
-// and B (their top H coefficients) and one wave runs up to s steps on the
-// heads alone, recording each step's multipliers and shift; a head entry
-// stays exact while everything it depends on was loaded, so the run stops
-// when the next leading coefficient is no longer known. Then each block
-// applies the recorded steps to its own slice of both polynomials, staged in
-// LDS together with a halo below the slice that covers the total shift of
-// the chunk; the top of the slice is exact at the end. Blocks exchange
-// nothing but the slices themselves, through a double buffer in HBM, with
-// one grid barrier per chunk. Every block computes the same step sequence
-// from the same heads, so all of them leave the loop together.
+//  * gcd_multi_kernel, for one large instance: a cooperative persistent
+//    grid; every block owns a slice of coefficient positions of both
+//    polynomials. Each chunk, every block recomputes the same steps and the
+//    same M from the heads (read from HBM/L2), stages its slice plus the
+//    S positions below it, writes the new slice to the other half of a
+//    double buffer, and meets the others at one grid barrier. No other
+//    communication: the heads are the only cross-block state, as the paper's
+//    s-heads are.
+//  * gcd_batch_kernel, for many instances: one block per instance, both
+//    polynomials resident in LDS for the whole remainder sequence; each
+//    chunk computes the new coefficients into registers, then overwrites the
+//    LDS copy after a block barrier.
+//
+// Both end with the last non-zero remainder made monic (one Fermat inverse).
+#include "gcd_core.hpp"
 #include "internal.hpp"
 
 namespace pm {
 namespace {
-
-constexpr int MAXS = 256;  // descriptor slots per chunk
 
 struct GcdArgs {
     const uint32_t* a;
@@ -40,22 +35,7 @@ struct GcdArgs {
     int64_t g_cap;
     Field F;
     CallInfo* info;
-    int groups, slice, head, s, halo;
-};
-
-struct Desc {
-    uint32_t m1;    // multiplier of the reduced operand X (lc of the other)
-    uint32_t m2;    // multiplier of the shifted other operand Y (p - lc X)
-    int32_t d;      // shift: deg X - deg Y
-    int32_t which;  // 0: X = A, 1: X = B
-};
-
-struct ChunkResult {
-    int64_t dA, dB;     // degrees after the chunk (upper bounds when unk*)
-    int64_t upd;        // coefficient updates of the chunk
-    int32_t nsteps;
-    int32_t S;          // total shift
-    int32_t unkA, unkB;
+    int groups, slice, s;
 };
 
 __device__ __forceinline__ void grid_sync(CallInfo* info, unsigned nblocks, unsigned& gen) {
@@ -79,119 +59,33 @@ __device__ __forceinline__ void grid_sync(CallInfo* info, unsigned nblocks, unsi
     }
 }
 
-// Head phase, run by wave 0 (all 64 lanes). hA/hB: LDS arrays of H entries,
-// entry i = coefficient of X^(deg - i).
-__device__ void head_phase(const uint32_t* Acur, const uint32_t* Bcur, int64_t dA, int64_t dB, int H, int s,
-                           int halo, const Field& F, uint32_t* hA, uint32_t* hB, Desc* desc, ChunkResult* out) {
+template <int E>
+__device__ __forceinline__ void load_heads(const uint32_t* A, const uint32_t* B, int64_t dA, int64_t dB,
+                                           uint32_t (&hA)[E], uint32_t (&hB)[E]) {
     const int lane = threadIdx.x & 63;
-    for (int i = lane; i < H; i += 64) {
-        hA[i] = dA - i >= 0 ? Acur[dA - i] : 0u;
-        hB[i] = dB - i >= 0 ? Bcur[dB - i] : 0u;
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    int vA = H, vB = H, S = 0, n = 0, unkA = 0, unkB = 0;
-    int64_t upd = 0;
-    while (n < s) {
-        const bool redA = dA >= dB;
-        uint32_t* X = redA ? hA : hB;
-        uint32_t* Y = redA ? hB : hA;
-        const int64_t dX = redA ? dA : dB, dY = redA ? dB : dA;
-        const int vX = redA ? vA : vB, vY = redA ? vB : vA;
-        const int64_t d64 = dX - dY;
-        if (n > 0 && S + d64 > halo) break;
-        const int d = (int)d64;
-        const uint32_t lcX = X[0], lcY = Y[0];
-        const uint32_t m1 = lcY, m2 = F.p - lcX;
-        const int v = vX < vY ? vX : vY;
-        // combine, keep the new values in registers (at most 4 per lane)
-        uint32_t nv[4];
-        unsigned long long nzm[4];
 #pragma unroll
-        for (int e = 0; e < 4; e++) {
-            const int i = lane + 64 * e;
-            uint32_t x = 0;
-            if (i < H && i < v) x = redc((uint64_t)m1 * X[i] + (uint64_t)m2 * Y[i], F);
-            nv[e] = x;
-            nzm[e] = __ballot(i >= 1 && i < v && x != 0);
-        }
-        if (lane == 0) desc[n] = Desc{m1, m2, d, redA ? 0 : 1};
-        n++;
-        S += d;
-        upd += dY + 1;
-        int delta = -1;
-#pragma unroll
-        for (int e = 0; e < 4; e++)
-            if (delta < 0 && nzm[e]) delta = 64 * e + __builtin_ctzll(nzm[e]);
-        int64_t ndX;
-        int nvX;
-        if (delta > 0) {
-            ndX = dX - delta;
-            nvX = v - delta;
-            // shift the head: X[i] = new[i + delta]
-            __builtin_amdgcn_wave_barrier();
-#pragma unroll
-            for (int e = 0; e < 4; e++) {
-                const int i = lane + 64 * e;
-                if (i < H) X[i] = nv[e];
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            uint32_t sh[4];
-#pragma unroll
-            for (int e = 0; e < 4; e++) {
-                const int i = lane + 64 * e;
-                sh[e] = (i < H && i + delta < H) ? X[i + delta] : 0u;
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll
-            for (int e = 0; e < 4; e++) {
-                const int i = lane + 64 * e;
-                if (i < H) X[i] = sh[e];
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        } else {
-            // every known entry below the old leading one vanished
-            ndX = dX - v;
-            nvX = 0;
-            if (ndX < 0) ndX = -1;
-            else if (redA) unkA = 1;
-            else unkB = 1;
-        }
-        if (redA) { dA = ndX; vA = nvX; } else { dB = ndX; vB = nvX; }
-        if (unkA || unkB || dA < 0 || dB < 0) break;
-    }
-    if (lane == 0) {
-        out->dA = dA;
-        out->dB = dB;
-        out->upd = upd;
-        out->nsteps = n;
-        out->S = S;
-        out->unkA = unkA;
-        out->unkB = unkB;
+    for (int e = 0; e < E; e++) {
+        const int64_t i = lane + 64 * e;
+        hA[e] = dA - i >= 0 ? A[dA - i] : 0u;
+        hB[e] = dB - i >= 0 ? B[dB - i] : 0u;
     }
 }
 
-__global__ __launch_bounds__(GCD_THREADS) void gcd_kernel(GcdArgs G) {
+template <int E>
+__global__ __launch_bounds__(GCD_THREADS) void gcd_multi_kernel(GcdArgs G) {
     extern __shared__ uint32_t smem[];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    const int slice = G.slice, halo = G.halo, H = G.head;
+    const int slice = G.slice;
     const int64_t N = G.N;
     const int64_t lo = (int64_t)blockIdx.x * slice;
     const int64_t hi = lo + slice;
-    uint32_t* la = smem;                       // slice + halo
-    uint32_t* lb = la + slice + halo;          // slice + halo
-    uint32_t* hA = lb + slice + halo;          // H
-    uint32_t* hB = hA + H;                     // H
-    Desc* desc = (Desc*)(hB + H);              // MAXS
-    __shared__ ChunkResult s_res;
+    uint32_t* la = smem;                        // slice + GCD_MAXSHIFT + 1
+    uint32_t* lb = la + slice + GCD_MAXSHIFT + 1;
+    uint32_t* M = lb + slice + GCD_MAXSHIFT + 1;  // 256
+    uint32_t* tmp = M + 256;                    // 64 * E
+    StepDesc* desc = (StepDesc*)(tmp + 64 * E); // GCD_MAXSTEPS
+    __shared__ ChunkOut s_out;
     __shared__ int64_t s_deg[2];
     const Field F = G.F;
     unsigned gen = __hip_atomic_load(&G.info->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -200,7 +94,6 @@ __global__ __launch_bounds__(GCD_THREADS) void gcd_kernel(GcdArgs G) {
     uint32_t* const A1 = G.buf + 2 * N;
     uint32_t* const B1 = G.buf + 3 * N;
 
-    // Stage the inputs into buffer 0 and check the range.
     int bad = 0;
     for (int64_t i = lo + tid; i < hi; i += GCD_THREADS) {
         uint32_t x = i < G.na ? G.a[i] : 0u;
@@ -252,13 +145,19 @@ __global__ __launch_bounds__(GCD_THREADS) void gcd_kernel(GcdArgs G) {
         if (dA < 0 || dB < 0) break;
         if (chunks >= max_chunks) { ok = false; break; }
         chunks++;
-        if (wave == 0) head_phase(Acur, Bcur, dA, dB, H, G.s, halo, F, hA, hB, desc, &s_res);
+        if (wave == 0) {
+            uint32_t hA[E], hB[E];
+            load_heads<E>(Acur, Bcur, dA, dB, hA, hB);
+            int n, big;
+            head_run<E>(hA, hB, dA, dB, G.s, F, desc, &s_out, tmp, n, big);
+            if (!big) build_m(desc, n, F, M);
+        }
         __syncthreads();
-        const ChunkResult res = s_res;
+        const ChunkOut res = s_out;
         const int64_t top = dA > dB ? dA : dB;
         if (lo <= top) {
-            const int S = res.S;
-            if (S <= halo) {
+            if (!res.big) {
+                const int S = res.S;
                 const int64_t base = lo - S;
                 const int len = slice + S;
                 for (int x = tid; x < len; x += GCD_THREADS) {
@@ -267,25 +166,17 @@ __global__ __launch_bounds__(GCD_THREADS) void gcd_kernel(GcdArgs G) {
                     lb[x] = P >= 0 ? Bcur[P] : 0u;
                 }
                 __syncthreads();
-                for (int k = 0; k < res.nsteps; k++) {
-                    const Desc D = desc[k];
-                    uint32_t* X = D.which ? lb : la;
-                    const uint32_t* Y = D.which ? la : lb;
-                    for (int x = tid; x < len; x += GCD_THREADS) {
-                        uint32_t y = x - D.d >= 0 ? Y[x - D.d] : 0u;
-                        X[x] = redc((uint64_t)D.m1 * X[x] + (uint64_t)D.m2 * y, F);
-                    }
-                    __syncthreads();
-                }
                 for (int x = tid; x < slice; x += GCD_THREADS) {
-                    int64_t P = lo + x;
-                    Anext[P] = P <= res.dA ? la[S + x] : 0u;
-                    Bnext[P] = P <= res.dB ? lb[S + x] : 0u;
+                    const int64_t P = lo + x;
+                    uint32_t na_, nb_;
+                    apply_m_at(la, lb, x + S, S, M, F, na_, nb_);
+                    Anext[P] = P <= res.dA ? na_ : 0u;
+                    Bnext[P] = P <= res.dB ? nb_ : 0u;
                 }
             } else {
-                // a single step with a shift beyond the halo: read the other
+                // one step whose shift is beyond the matrix: read the other
                 // operand straight from the chunk-start buffer
-                const Desc D = desc[0];
+                const StepDesc D = desc[0];
                 const uint32_t* Xc = D.which ? Bcur : Acur;
                 const uint32_t* Yc = D.which ? Acur : Bcur;
                 uint32_t* Xn = D.which ? Bnext : Anext;
@@ -293,7 +184,7 @@ __global__ __launch_bounds__(GCD_THREADS) void gcd_kernel(GcdArgs G) {
                 const int64_t bX = D.which ? res.dB : res.dA;
                 const int64_t bY = D.which ? res.dA : res.dB;
                 for (int x = tid; x < slice; x += GCD_THREADS) {
-                    int64_t P = lo + x;
+                    const int64_t P = lo + x;
                     uint32_t y = P - D.d >= 0 ? Yc[P - D.d] : 0u;
                     uint32_t nx = redc((uint64_t)D.m1 * Xc[P] + (uint64_t)D.m2 * y, F);
                     Xn[P] = P <= bX ? nx : 0u;
@@ -331,15 +222,151 @@ __global__ __launch_bounds__(GCD_THREADS) void gcd_kernel(GcdArgs G) {
     }
 }
 
+// ------------------------------------------------------------------ batched
+// One block per instance; A and B live in LDS at offset PADLO so that
+// positions below 0 read as zero.
+constexpr int PADLO = 64;
+
+template <int NT, int PPT, int E>
+__global__ __launch_bounds__(NT) void gcd_batch_kernel(const GcdJob* jobs, const int32_t* order, int njobs,
+                                                       int s, int64_t cap) {
+    extern __shared__ uint32_t smem[];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    if ((int)blockIdx.x >= njobs) return;
+    const int jid = order ? order[blockIdx.x] : (int)blockIdx.x;
+    const GcdJob J = jobs[jid];
+    const Field F = J.F;
+    uint32_t* A = smem + PADLO;                 // cap words (+PADLO zeros below)
+    uint32_t* B = A + cap + PADLO;
+    uint32_t* M = B + cap;                      // 256
+    uint32_t* tmp = M + 256;                    // 64 * E
+    StepDesc* desc = (StepDesc*)(tmp + 64 * E); // GCD_MAXSTEPS
+    __shared__ ChunkOut s_out;
+    __shared__ int64_t s_deg[2];
+
+    const int64_t n = J.na > J.nb ? J.na : J.nb;
+    int bad = n > cap;
+    if (tid < PADLO) { A[tid - PADLO] = 0u; B[tid - PADLO] = 0u; }
+    for (int64_t i = tid; i < cap; i += NT) {
+        uint32_t x = i < J.na ? J.a[i] : 0u;
+        uint32_t y = i < J.nb ? J.b[i] : 0u;
+        bad |= (x >= F.p) | (y >= F.p);
+        A[i] = x;
+        B[i] = y;
+    }
+    bad = __syncthreads_or(bad);
+    if (bad) {
+        if (tid == 0) {
+            J.out->status = n > cap ? -1 : -3;
+            J.out->ng = 0;
+        }
+        return;
+    }
+    if (wave < 2) {
+        int64_t d = top_nonzero_wave(wave == 0 ? A : B, cap);
+        if (lane == 0) s_deg[wave] = d;
+    }
+    __syncthreads();
+    int64_t dA = s_deg[0], dB = s_deg[1];
+    int unkA = 0, unkB = 0;
+    int64_t steps = 0, chunks = 0, updates = 0;
+    const int64_t max_chunks = (dA > 0 ? dA : 0) + (dB > 0 ? dB : 0) + 4;
+    bool ok = true;
+    for (;;) {
+        if (unkA || unkB) {
+            if (wave == 0) {
+                int64_t x = unkA ? top_nonzero_wave(A, dA + 1) : dA;
+                int64_t y = unkB ? top_nonzero_wave(B, dB + 1) : dB;
+                if (lane == 0) { s_deg[0] = x; s_deg[1] = y; }
+            }
+            __syncthreads();
+            dA = s_deg[0];
+            dB = s_deg[1];
+            unkA = unkB = 0;
+            __syncthreads();
+        }
+        if (dA < 0 || dB < 0) break;
+        if (chunks >= max_chunks) { ok = false; break; }
+        chunks++;
+        if (wave == 0) {
+            uint32_t hA[E], hB[E];
+            load_heads<E>(A, B, dA, dB, hA, hB);
+            int nst, big;
+            head_run<E>(hA, hB, dA, dB, s, F, desc, &s_out, tmp, nst, big);
+            if (!big) build_m(desc, nst, F, M);
+        }
+        __syncthreads();
+        const ChunkOut res = s_out;
+        const int top = (int)(dA > dB ? dA : dB);
+        if (!res.big) {
+            uint32_t nA[PPT], nB[PPT];
+#pragma unroll
+            for (int j = 0; j < PPT; j++) {
+                const int P = tid + j * NT;
+                nA[j] = nB[j] = 0u;
+                if (P <= top) apply_m_at(A, B, P, res.S, M, F, nA[j], nB[j]);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < PPT; j++) {
+                const int P = tid + j * NT;
+                if (P <= top) {
+                    A[P] = P <= res.dA ? nA[j] : 0u;
+                    B[P] = P <= res.dB ? nB[j] : 0u;
+                }
+            }
+        } else {
+            const StepDesc D = desc[0];
+            uint32_t* X = D.which ? B : A;
+            const uint32_t* Y = D.which ? A : B;
+            const int64_t bX = D.which ? res.dB : res.dA;
+            // only X changes and Y is only read: in place
+            for (int P = tid; P <= top; P += NT) {
+                uint32_t y = P - D.d >= 0 ? Y[P - D.d] : 0u;
+                uint32_t nx = redc((uint64_t)D.m1 * X[P] + (uint64_t)D.m2 * y, F);
+                X[P] = P <= bX ? nx : 0u;
+            }
+        }
+        __syncthreads();
+        dA = res.dA;
+        dB = res.dB;
+        unkA = res.unkA;
+        unkB = res.unkB;
+        steps += res.nsteps;
+        updates += res.upd;
+    }
+    const uint32_t* R = dA >= 0 ? A : B;
+    const int64_t dR = dA >= 0 ? dA : dB;
+    int status = ok ? 0 : -6;
+    if (status == 0 && dR + 1 > J.g_cap) status = -1;
+    if (status == 0 && dR >= 0) {
+        const uint32_t inv = invmod(R[dR], F);
+        for (int64_t P = tid; P <= dR; P += NT) J.g[P] = mulmod(R[P], inv, F);
+    }
+    if (tid == 0) {
+        J.out->status = status;
+        J.out->ng = status == 0 ? dR + 1 : 0;
+        J.out->steps = steps;
+        J.out->updates = updates;
+        J.out->chunks = chunks;
+        __threadfence_system();
+        __hip_atomic_store(&J.out->done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
+template <int NT, int PPT, int E>
+size_t batch_lds_bytes(int64_t cap) {
+    return (size_t)(2 * (cap + PADLO) + 256 + 64 * E) * sizeof(uint32_t) + GCD_MAXSTEPS * sizeof(StepDesc);
+}
+
 }  // namespace
 
 GcdPlan gcd_default_plan(int64_t n, int num_cus, int s) {
     GcdPlan P{};
-    P.head = 128;
     P.s = s > 0 ? s : 64;
-    if (P.s > MAXS) P.s = MAXS;
-    if (P.head < P.s + 64) P.head = ((P.s + 64) + 63) / 64 * 64;
-    if (P.head > 256) P.head = 256;
+    if (P.s > GCD_MAXSTEPS) P.s = GCD_MAXSTEPS;
+    P.head = P.s <= 96 ? 128 : 256;
     P.slice = 256;
     int64_t groups = (n + P.slice - 1) / P.slice;
     const int64_t max_groups = 2LL * num_cus;
@@ -366,16 +393,52 @@ hipError_t gcd_launch(const uint32_t* a, int64_t na, const uint32_t* b, int64_t 
     A.buf = scratch;
     A.flags = scratch + 4 * A.N;
     A.g = g; A.g_cap = g_cap; A.F = F; A.info = info;
-    A.groups = plan.groups; A.slice = plan.slice; A.head = plan.head; A.s = plan.s;
-    A.halo = plan.s;  // generic chunks shift by about s/2
-    size_t lds = (size_t)(2 * (plan.slice + A.halo) + 2 * plan.head) * sizeof(uint32_t) + MAXS * sizeof(Desc);
+    A.groups = plan.groups; A.slice = plan.slice; A.s = plan.s;
+    const int E = plan.head / 64;
+    size_t lds = (size_t)(2 * (plan.slice + GCD_MAXSHIFT + 1) + 256 + 64 * E) * sizeof(uint32_t) +
+                 GCD_MAXSTEPS * sizeof(StepDesc);
     void* args[] = {&A};
+    const void* fn = E == 2 ? (const void*)gcd_multi_kernel<2> : (const void*)gcd_multi_kernel<4>;
+    TimingScope ts("gcd_multi_kernel", stream);
     if (plan.groups == 1) {
-        hipLaunchKernelGGL(gcd_kernel, dim3(1), dim3(GCD_THREADS), lds, stream, A);
+        if (E == 2) hipLaunchKernelGGL((gcd_multi_kernel<2>), dim3(1), dim3(GCD_THREADS), lds, stream, A);
+        else hipLaunchKernelGGL((gcd_multi_kernel<4>), dim3(1), dim3(GCD_THREADS), lds, stream, A);
         return hipGetLastError();
     }
-    return hipLaunchCooperativeKernel((const void*)gcd_kernel, dim3(plan.groups), dim3(GCD_THREADS), args,
-                                      (unsigned)lds, stream);
+    return hipLaunchCooperativeKernel(fn, dim3(plan.groups), dim3(GCD_THREADS), args, (unsigned)lds, stream);
+}
+
+int64_t gcd_batch_cap(int kind) { return kind == 0 ? 256 * 16 : 1024 * 17; }
+
+hipError_t gcd_batch_launch(const GcdJob* d_jobs, const int32_t* d_order, int njobs, int kind, int s,
+                            hipStream_t stream) {
+    if (njobs <= 0) return hipSuccess;
+    if (s > 96) {
+        if (kind == 0) {
+            size_t lds = batch_lds_bytes<256, 16, 4>(gcd_batch_cap(0));
+            TimingScope ts("gcd_batch_kernel", stream);
+            hipLaunchKernelGGL((gcd_batch_kernel<256, 16, 4>), dim3(njobs), dim3(256), lds, stream, d_jobs, d_order,
+                               njobs, s, gcd_batch_cap(0));
+        } else {
+            size_t lds = batch_lds_bytes<1024, 17, 4>(gcd_batch_cap(1));
+            TimingScope ts("gcd_batch_kernel", stream);
+            hipLaunchKernelGGL((gcd_batch_kernel<1024, 17, 4>), dim3(njobs), dim3(1024), lds, stream, d_jobs,
+                               d_order, njobs, s, gcd_batch_cap(1));
+        }
+    } else {
+        if (kind == 0) {
+            size_t lds = batch_lds_bytes<256, 16, 2>(gcd_batch_cap(0));
+            TimingScope ts("gcd_batch_kernel", stream);
+            hipLaunchKernelGGL((gcd_batch_kernel<256, 16, 2>), dim3(njobs), dim3(256), lds, stream, d_jobs, d_order,
+                               njobs, s, gcd_batch_cap(0));
+        } else {
+            size_t lds = batch_lds_bytes<1024, 17, 2>(gcd_batch_cap(1));
+            TimingScope ts("gcd_batch_kernel", stream);
+            hipLaunchKernelGGL((gcd_batch_kernel<1024, 17, 2>), dim3(njobs), dim3(1024), lds, stream, d_jobs,
+                               d_order, njobs, s, gcd_batch_cap(1));
+        }
+    }
+    return hipGetLastError();
 }
 
 }  // namespace pm

@@ -11,6 +11,22 @@
 
 namespace pm {
 
+// Kernel timing for diagnostics (pm_timing_enable in the C ABI): when on,
+// each launch wrapped in a TimingScope is bracketed by two HIP events on its
+// stream; pm_timing_read sums the elapsed times per kernel name.
+class TimingScope {
+public:
+    TimingScope(const char* kernel, hipStream_t stream);
+    ~TimingScope();
+    TimingScope(const TimingScope&) = delete;
+    TimingScope& operator=(const TimingScope&) = delete;
+
+private:
+    const char* kernel_;
+    hipStream_t stream_;
+    hipEvent_t start_ = nullptr;
+};
+
 // ------------------------------------------------------------------ product
 // Tiling of one product f = a*b (Sec. 5). The b operand is cut into chunks
 // of `kc` coefficients (the paper's s: b-coefficients handled per
@@ -66,9 +82,40 @@ hipError_t degrees_launch(const uint32_t* a, int64_t na, const uint32_t* b, int6
 struct GcdPlan {
     int groups;      // cooperating thread-blocks (1 = single block)
     int slice;       // coefficient positions owned by each block
-    int head;        // head length (multiple of 64)
+    int head;        // head length (128 or 256)
     int s;           // max Euclidean division steps per fused chunk
 };
+
+// Per-instance results of the batched gcd kernel (device or host-mapped
+// memory). `done` is set last, with release order, when the instance ends.
+struct GcdResult {
+    int64_t ng;
+    int64_t steps;
+    int64_t updates;
+    int64_t chunks;
+    int32_t status;
+    int32_t done;
+};
+
+// One instance of the batched gcd: inputs, output and where to report.
+struct GcdJob {
+    const uint32_t* a;
+    const uint32_t* b;
+    int64_t na, nb;
+    uint32_t* g;
+    int64_t g_cap;
+    GcdResult* out;
+    Field F;
+};
+
+// Capacity (max(na, nb)) of the two batched kernel shapes: kind 0 = 256
+// threads, kind 1 = 1024 threads.
+int64_t gcd_batch_cap(int kind);
+// One block for each of the first njobs entries of `order` (job indices
+// into d_jobs; when order is null, block i runs job i). Jobs must fit the
+// capacity of `kind`.
+hipError_t gcd_batch_launch(const GcdJob* d_jobs, const int32_t* d_order, int njobs, int kind, int s,
+                            hipStream_t stream);
 constexpr int GCD_THREADS = 256;
 GcdPlan gcd_default_plan(int64_t n, int num_cus, int s);
 int64_t gcd_scratch_words(int64_t n, const GcdPlan& plan);

@@ -269,6 +269,7 @@ hipError_t mul_launch(const uint32_t* a, int64_t na, const uint32_t* b, int64_t 
     if (nf == 0) {
         if (!aux) return hipSuccess;
         A.nchunks = 0; A.tiles = 0; A.kc = R; A.rowlen = 0; A.out = f;
+        TimingScope ts("mul_tile_kernel", stream);
         hipLaunchKernelGGL((mul_tile_kernel<1, 8>), dim3(1), dim3(MUL_THREADS), 8, stream, A);
         return hipGetLastError();
     }
@@ -280,6 +281,8 @@ hipError_t mul_launch(const uint32_t* a, int64_t na, const uint32_t* b, int64_t 
     A.out = A.nchunks > 1 ? M : f;
     int64_t grid = A.nchunks * A.tiles + (aux ? 1 : 0);
     hipError_t e;
+    {
+    TimingScope ts("mul_tile_kernel", stream);
     switch (R) {
         case 1: e = launch_fold<1>(A, grid, stream); break;
         case 2: e = launch_fold<2>(A, grid, stream); break;
@@ -289,8 +292,10 @@ hipError_t mul_launch(const uint32_t* a, int64_t na, const uint32_t* b, int64_t 
         case 32: e = launch_fold<32>(A, grid, stream); break;
         default: return hipErrorInvalidValue;
     }
+    }
     if (e != hipSuccess || A.nchunks == 1) return e;
     int64_t blocks = (nf + 255) / 256;
+    TimingScope ts("mul_reduce_kernel", stream);
     hipLaunchKernelGGL(mul_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, M, A.rowlen, kc,
                        A.nchunks, f, nf, sub_from, F);
     return hipGetLastError();

@@ -250,3 +250,40 @@ def test_gcd_edge_cases():
     with pytest.raises(pm.PolyModPError) as e:
         pm.gcd(dev(bad), dev(b), p)
     assert e.value.status == pm.PM_ERANGE
+
+
+def test_gcd_batch_mixed_primes_and_degrees():
+    """One launch, one block per instance, both kernel shapes (<= 4096 and
+    up to the batch limit), three primes; each result equals the oracle's
+    and equals the result of the same instance computed alone."""
+    st = gen.Stream(304)
+    pairs, want = [], []
+    for i in range(40):
+        p = gen.PRIMES[st.index(3)]
+        D = st.log_uniform_int(8, 3000) if i < 36 else st.log_uniform_int(4097, 9000)
+        k = st.uniform_int(0, D // 4)
+        pl = gen.planted_gcd(D, D - 1, k, p, st)
+        a, b = oracle.mul(pl.g, pl.u, p), oracle.mul(pl.g, pl.v, p)
+        pairs.append((a, b, p))
+        want.append(oracle.gcd(a, b, p))
+    res = pm.gcd_batch([(dev(a), dev(b), p) for a, b, p in pairs])
+    for (g, info), w in zip(res, want):
+        assert info["status"] == 0
+        assert same(host(g), w)
+    a, b, p = pairs[5]
+    assert same(host(pm.gcd(dev(a), dev(b), p)), want[5])
+
+
+def test_gcd_batch_reports_item_errors():
+    p = gen.P_A
+    st = gen.Stream(305)
+    a, b = rnd(st, 20, p), rnd(st, 10, p)
+    bad = a.copy(); bad[0] = p + 1
+    c, d = rnd(st, 15, gen.P_C), rnd(st, 7, gen.P_C)
+    res = pm.gcd_batch([(dev(a), dev(b), p), (dev(bad), dev(b), p), (dev(c), dev(d), gen.P_C),
+                        (dev(a), dev(b), gen.P_C)])
+    assert res[0][1]["status"] == 0 and same(host(res[0][0]), oracle.gcd(a, b, p))
+    assert res[1][1]["status"] == pm.PM_ERANGE
+    assert res[2][1]["status"] == 0 and same(host(res[2][0]), oracle.gcd(c, d, gen.P_C))
+    # residues of P_A are not all below P_C
+    assert res[3][1]["status"] == (pm.PM_ERANGE if (a >= gen.P_C).any() or (b >= gen.P_C).any() else 0)
