@@ -17,6 +17,10 @@ Beside it, in the same line:
                 against the VALU multiply-add peak of the chip;
   cpu_baseline  the CPU oracle timed on this host on a bounded sample of the
                 same product (single thread);
+  batched_4096  4096 independent products (degrees log-uniform in [32, 8192])
+                in one persistent launch replayed from a captured graph,
+                tile shape from the autotuner, beside the same products as
+                4096 separate calls on the same stream;
   gcd_32768     Euclidean division and remainder-sequence gcd of the degree
                 32768 / 32767 pair with a planted degree-1000 gcd.
 """
@@ -99,6 +103,61 @@ def cpu_baseline(a, b, p: int, seconds: float) -> dict:
                       "%d coefficient products in %.1f s" % (n, terms, el)}
 
 
+def bench_batched(reps: int) -> dict:
+    import torch
+    import paper_1402_0264_amd as pm
+    from paper_1402_0264_amd import gen, tune
+    bt = gen.batch_products()
+    p = bt.p
+    items = [(pm.to_device(a), pm.to_device(b), p) for a, b in zip(bt.a, bt.b)]
+    work = float(sum(a.size * b.size for a, b in zip(bt.a, bt.b)))
+    t = tune.tune_mul_batch(items)
+    batch = pm.MulBatch(items, t["r"], t["kc"])
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        batch.run(stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        batch.run()
+    for _ in range(2):
+        g.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_batch = e0.elapsed_time(e1) / reps
+    # the same products as one call each (the library's own per-call plan)
+    outs = [torch.empty(a.numel() + b.numel() - 1, dtype=torch.int32, device="cuda") for a, b, _ in items]
+    d_nf = torch.zeros(len(items), dtype=torch.int64, device="cuda")
+    d_st = torch.zeros(len(items), dtype=torch.int32, device="cuda")
+
+    def one_by_one():
+        for i, (a, b, _) in enumerate(items):
+            pm.mul_async(a, b, p, outs[i], d_nf[i:i + 1], d_st[i:i + 1])
+
+    one_by_one()
+    torch.cuda.synchronize()
+    e0.record()
+    one_by_one()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_single = e0.elapsed_time(e1)
+    same = all(torch.equal(o, f) for o, f in zip(outs[::97], batch.outputs[::97]))
+    batch.close()
+    return {"workload": "4096 products, degrees log-uniform in [32, 8192], p=469762049",
+            "mulmods": work, "ms": round(ms_batch, 4), "mulmods_per_s": round(work / (ms_batch * 1e-3), 1),
+            "tuned": {"r": t["r"], "kc": t["kc"], "from_cache": t["cached"]},
+            "one_call_per_instance_ms": round(ms_single, 4),
+            "speedup_vs_one_call_per_instance": round(ms_single / ms_batch, 2),
+            "graph_replays": reps, "matches_one_call_results": bool(same)}
+
+
 def bench_gcd(reps: int) -> dict:
     import numpy as np
     import torch
@@ -143,6 +202,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gcd", action="store_true")
     ap.add_argument("--gcd-reps", type=int, default=5)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -162,6 +223,12 @@ def main() -> int:
     f = torch.empty(nf, dtype=torch.int32, device="cuda")
     d_nf = torch.zeros(1, dtype=torch.int64, device="cuda")
     d_st = torch.zeros(1, dtype=torch.int32, device="cuda")
+
+    tuned = None
+    if not args.no_tune:
+        from paper_1402_0264_amd import tune
+        tuned = tune.tune_mul(a, b, p)
+        pm.set_params(mul_r=tuned["r"], mul_s=tuned["kc"])
 
     def step():
         pm.mul_async(a, b, p, f, d_nf, d_st)
@@ -196,7 +263,8 @@ def main() -> int:
         "dtype": "u32",
         "data": "synthetic (seeded uniform residues)",
         "config": {"workload": "product_65536: deg 65535 x deg 65535 over p=469762049",
-                   "params": pm.get_params(), "parallelism": "single GPU"},
+                   "params": pm.get_params(), "tuned": tuned and {"r": tuned["r"], "s": tuned["kc"]},
+                   "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 3),
                      "peak": round(PEAK_MULMOD_PER_S / 1e12, 3), "unit": "Tmulmod/s",
                      "frac": round(achieved / PEAK_MULMOD_PER_S, 4),
@@ -204,6 +272,9 @@ def main() -> int:
                      "kernel": "mul_tile_kernel", "kernel_avg_ms": round(tile_avg_ms, 5),
                      "launches": n_tile, "reduce_avg_ms": round(ms_red / max(n_red, 1), 5)},
     }
+    pm.set_params()
+    if not args.no_batched:
+        out["batched_4096"] = bench_batched(10)
     if not args.no_gcd:
         out["gcd_32768"] = bench_gcd(args.gcd_reps)
     if not args.no_cpu_baseline:

@@ -75,6 +75,40 @@ pm_status poly_mul_modp_async(const uint32_t *a, int64_t na, const uint32_t *b, 
                               uint32_t *f, int64_t f_cap, int64_t *d_nf, int32_t *d_status, void *stream);
 
 /*
+ * Batched products: many independent f_i = a_i * b_i (mixed lengths and
+ * primes) in ONE persistent launch. The work is cut into output tiles of
+ * 256*r coefficients, each summed over the whole of b_i in chunks of kc
+ * coefficients of b (kc is the paper's s); thread-blocks take tiles from a
+ * queue, longest first.
+ *   items  : host array; a, b, f are device pointers, f_cap >= na + nb - 1
+ *   r, kc  : tile shape (r in {4, 8, 16}; kc >= r); 0 = defaults
+ * pm_mul_batch_create checks every item on the host, builds the task
+ * table and uploads it (allocates device memory; not graph-capturable).
+ * pm_mul_batch_run enqueues the batch: no allocation, no host sync, and it
+ * may be captured in a hipGraph and replayed. Item coefficients must be
+ * canonical residues; when d_status (device, count int32) is given, an
+ * extra launch checks them and writes PM_OK or PM_ERANGE per item. f_i is
+ * written in full (na_i + nb_i - 1 words). A batch object must not run on
+ * two streams at once.
+ */
+typedef struct {
+    const uint32_t *a;
+    int64_t na;
+    const uint32_t *b;
+    int64_t nb;
+    uint32_t p;
+    uint32_t *f;
+    int64_t f_cap;
+} pm_mul_item;
+typedef struct pm_mul_batch pm_mul_batch;
+pm_status pm_mul_batch_create(const pm_mul_item *items, int32_t count, int32_t r, int32_t kc,
+                              pm_mul_batch **out);
+pm_status pm_mul_batch_run(pm_mul_batch *batch, int32_t *d_status, void *stream);
+void pm_mul_batch_destroy(pm_mul_batch *batch);
+/* create + run + wait + destroy */
+pm_status poly_mul_modp_batch(const pm_mul_item *items, int32_t count, int32_t *d_status, void *stream);
+
+/*
  * Euclidean division (Sec. 3, problem statement): the unique q, r with
  * a = q*b + r and deg r < deg b, for b != 0.
  *   q, q_cap : quotient (device); needs deg a - deg b + 1 words (0 when

@@ -49,6 +49,11 @@ class GcdResult(ctypes.Structure):
 GCD_BATCH_MAX = 17408
 
 
+class MulItem(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_void_p), ("na", ctypes.c_int64), ("b", ctypes.c_void_p), ("nb", ctypes.c_int64),
+                ("p", ctypes.c_uint32), ("f", ctypes.c_void_p), ("f_cap", ctypes.c_int64)]
+
+
 class GcdStats(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int64), ("updates", ctypes.c_int64), ("chunks", ctypes.c_int64)]
 
@@ -78,6 +83,15 @@ def lib() -> ctypes.CDLL:
     L.poly_gcd_modp.restype = ctypes.c_int32
     L.poly_gcd_modp_batch.argtypes = [ctypes.POINTER(GcdItem), ctypes.c_int32, ctypes.POINTER(GcdResult), _vp]
     L.poly_gcd_modp_batch.restype = ctypes.c_int32
+    L.pm_mul_batch_create.argtypes = [ctypes.POINTER(MulItem), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                      ctypes.POINTER(ctypes.c_void_p)]
+    L.pm_mul_batch_create.restype = ctypes.c_int32
+    L.pm_mul_batch_run.argtypes = [ctypes.c_void_p, _vp, _vp]
+    L.pm_mul_batch_run.restype = ctypes.c_int32
+    L.pm_mul_batch_destroy.argtypes = [ctypes.c_void_p]
+    L.pm_mul_batch_destroy.restype = None
+    L.poly_mul_modp_batch.argtypes = [ctypes.POINTER(MulItem), ctypes.c_int32, _vp, _vp]
+    L.poly_mul_modp_batch.restype = ctypes.c_int32
     L.pm_last_gcd_stats.argtypes = [ctypes.POINTER(GcdStats)]
     L.pm_last_gcd_stats.restype = None
     L.pm_set_params.argtypes = [ctypes.POINTER(Params)]
@@ -205,6 +219,54 @@ def gcd(a, b, p: int, stream=None):
     _check(lib().poly_gcd_modp(_dev_ptr(a), na, _dev_ptr(b), nb, p, g.data_ptr(), cap, ctypes.byref(ng),
                                _stream_handle(stream)))
     return g[:ng.value]
+
+
+class MulBatch:
+    """Prepared batch of products (pm_mul_batch_*). ``items`` is a list of
+    (a, b, p) with a, b device tensors; outputs are allocated here and
+    returned by ``outputs``. ``run`` enqueues one persistent launch (graph
+    capturable)."""
+
+    def __init__(self, items, r: int = 0, kc: int = 0):
+        torch = _torch()
+        self.keep, self.outputs = [], []
+        arr = (MulItem * max(len(items), 1))()
+        for i, (a, b, p) in enumerate(items):
+            a, b = _as_u32_tensor(a), _as_u32_tensor(b)
+            n = a.numel() + b.numel() - 1 if a.numel() and b.numel() else 0
+            f = torch.zeros(max(n, 1), dtype=torch.int32, device=a.device if a.numel() else b.device)
+            self.keep += [a, b]
+            self.outputs.append(f[:n])
+            arr[i] = MulItem(_dev_ptr(a), a.numel(), _dev_ptr(b), b.numel(), p, f.data_ptr(), n)
+        self.count = len(items)
+        self.handle = ctypes.c_void_p()
+        _check(lib().pm_mul_batch_create(arr, self.count, r, kc, ctypes.byref(self.handle)))
+
+    def run(self, d_status=None, stream=None):
+        _check(lib().pm_mul_batch_run(self.handle, d_status.data_ptr() if d_status is not None else None,
+                                      _stream_handle(stream)))
+
+    def close(self):
+        if self.handle:
+            lib().pm_mul_batch_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mul_batch(items, d_status=None, stream=None):
+    """One-shot batched products; returns the list of outputs."""
+    b = MulBatch(items, get_params()["mul_r"] if get_params()["mul_r"] in (4, 8, 16) else 0,
+                 get_params()["mul_s"])
+    b.run(d_status, stream)
+    _torch().cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+    out = b.outputs
+    b.close()
+    return out
 
 
 def gcd_batch(pairs, stream=None):

@@ -16,6 +16,20 @@
 #include "../../include/polymodp.h"
 #include "internal.hpp"
 
+#include <algorithm>
+
+struct pm_mul_batch {
+    int device = 0;
+    int count = 0;
+    int ntasks = 0;
+    int r = 8;
+    int64_t kc = 1024;
+    uint32_t fold_min = 1u << 30;
+    pm::MulItem* d_items = nullptr;
+    pm::MulTask* d_tasks = nullptr;
+    uint32_t* d_counters = nullptr;
+};
+
 namespace {
 
 thread_local char g_err[512] = "";
@@ -346,6 +360,105 @@ pm_status poly_mul_modp_async(const uint32_t* a, int64_t na, const uint32_t* b, 
     pm_status st = field_for(p, &F);
     if (st) return st;
     return mul_enqueue(a, na, b, nb, F, f, d_nf, d_status, (hipStream_t)stream);
+}
+
+void pm_mul_batch_destroy(pm_mul_batch* B) {
+    if (!B) return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(B->device);
+    (void)hipDeviceSynchronize();
+    if (B->d_items) (void)hipFree(B->d_items);
+    if (B->d_tasks) (void)hipFree(B->d_tasks);
+    if (B->d_counters) (void)hipFree(B->d_counters);
+    (void)hipSetDevice(cur);
+    delete B;
+}
+
+pm_status pm_mul_batch_create(const pm_mul_item* items, int32_t count, int32_t r, int32_t kc, pm_mul_batch** out) {
+    if (!out || count < 0 || (count > 0 && !items)) return fail(PM_EINVAL, "bad arguments");
+    if (r == 0) r = 8;
+    if (r != 4 && r != 8 && r != 16) return fail(PM_EINVAL, "r must be 4, 8 or 16");
+    if (kc == 0) kc = 1024;
+    if (kc < r) return fail(PM_EINVAL, "kc must be at least r");
+    std::vector<pm::MulItem> host((size_t)count);
+    std::vector<std::pair<int64_t, pm::MulTask>> tasks;
+    uint32_t fold_min = 1u << 30;
+    const int64_t T = pm::mul_batch_tile(r);
+    for (int32_t i = 0; i < count; i++) {
+        const pm_mul_item& it = items[i];
+        if (bad_len(it.a, it.na) || bad_len(it.b, it.nb)) return fail(PM_EINVAL, "item %d: bad input", i);
+        const int64_t need = (it.na > 0 && it.nb > 0) ? it.na + it.nb - 1 : 0;
+        if (need > 0 && (!it.f || it.f_cap < need)) return fail(PM_EINVAL, "item %d: f_cap < na + nb - 1", i);
+        pm::Field F;
+        pm_status st = field_for(it.p, &F);
+        if (st) return st;
+        fold_min = std::min(fold_min, F.fold_every);
+        const uint32_t *x = it.a, *y = it.b;
+        int64_t nx = it.na, ny = it.nb;
+        order_operands(x, nx, y, ny);
+        host[i] = pm::MulItem{x, y, it.f, nx, ny, F};
+        if (need == 0) continue;
+        const int64_t tiles = (need + T - 1) / T;
+        if (tiles > INT32_MAX) return fail(PM_EINVAL, "item %d too large", i);
+        for (int64_t t = 0; t < tiles; t++) tasks.push_back({T * ny, pm::MulTask{i, (int32_t)t}});
+    }
+    if (tasks.size() > (size_t)INT32_MAX) return fail(PM_EINVAL, "too many tasks");
+    // longest first: a greedy queue then ends with the short tasks
+    std::stable_sort(tasks.begin(), tasks.end(),
+                     [](const std::pair<int64_t, pm::MulTask>& u, const std::pair<int64_t, pm::MulTask>& v) {
+                         return u.first > v.first;
+                     });
+    std::vector<pm::MulTask> tv(tasks.size());
+    for (size_t i = 0; i < tasks.size(); i++) tv[i] = tasks[i].second;
+    pm_mul_batch* B = new pm_mul_batch();
+    (void)hipGetDevice(&B->device);
+    B->count = count;
+    B->ntasks = (int)tv.size();
+    B->r = r;
+    B->kc = pm::mul_batch_kc(r, kc);
+    B->fold_min = fold_min;
+    hipError_t e = hipSuccess;
+    if (count > 0) e = hipMalloc((void**)&B->d_items, host.size() * sizeof(pm::MulItem));
+    if (e == hipSuccess && !tv.empty()) e = hipMalloc((void**)&B->d_tasks, tv.size() * sizeof(pm::MulTask));
+    if (e == hipSuccess) e = hipMalloc((void**)&B->d_counters, 2 * sizeof(uint32_t));
+    if (e != hipSuccess) {
+        pm_mul_batch_destroy(B);
+        return fail(PM_ENOMEM, "batch tables: %s", hipGetErrorString(e));
+    }
+    if (count > 0) e = hipMemcpy(B->d_items, host.data(), host.size() * sizeof(pm::MulItem), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !tv.empty())
+        e = hipMemcpy(B->d_tasks, tv.data(), tv.size() * sizeof(pm::MulTask), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(B->d_counters, 0, 2 * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        pm_mul_batch_destroy(B);
+        return hip_fail(e, "batch upload");
+    }
+    *out = B;
+    return PM_OK;
+}
+
+pm_status pm_mul_batch_run(pm_mul_batch* B, int32_t* d_status, void* stream) {
+    if (!B) return fail(PM_EINVAL, "null batch");
+    hipStream_t s = (hipStream_t)stream;
+    if (d_status) HIP_TRY(pm::mul_batch_check_launch(B->d_items, B->count, d_status, s), "batch check launch");
+    HIP_TRY(pm::mul_batch_launch(B->d_items, B->d_tasks, B->ntasks, B->r, B->kc, B->fold_min, B->d_counters,
+                                 num_cus(), s),
+            "batch launch");
+    return PM_OK;
+}
+
+pm_status poly_mul_modp_batch(const pm_mul_item* items, int32_t count, int32_t* d_status, void* stream) {
+    pm_mul_batch* B = nullptr;
+    pm_params pp = params_now();
+    int r = pp.mul_r == 4 || pp.mul_r == 8 || pp.mul_r == 16 ? pp.mul_r : 0;
+    pm_status st = pm_mul_batch_create(items, count, r, pp.mul_s, &B);
+    if (st) return st;
+    st = pm_mul_batch_run(B, d_status, stream);
+    if (st == PM_OK && hipStreamSynchronize((hipStream_t)stream) != hipSuccess) st = fail(PM_EDEVICE, "sync");
+    pm_mul_batch_destroy(B);
+    return st;
 }
 
 pm_status poly_mul_modp(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, uint32_t p, uint32_t* f,

@@ -83,6 +83,16 @@ __device__ __forceinline__ uint32_t invmod(uint32_t x, const Field& F) {
     return powmod(x, F.p - 2, F);
 }
 
+// Values the whole wave holds identically, moved to scalar registers so that
+// loops and branches on them stay scalar (no exec masking).
+__device__ __forceinline__ int32_t uni(int32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ uint32_t uni(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); }
+__device__ __forceinline__ int64_t uni(int64_t x) {
+    uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+    uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)x >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // Largest index i < n with v[i] != 0, or -1. Called by one whole wave, which
 // scans 64 words at a time from the top; every lane gets the result.
 __device__ inline int64_t top_nonzero_wave(const uint32_t* v, int64_t n) {

@@ -119,7 +119,7 @@ __global__ __launch_bounds__(GCD_THREADS) void gcd_multi_kernel(GcdArgs G) {
         }
         return;
     }
-    int64_t dA = s_deg[0], dB = s_deg[1];
+    int64_t dA = uni(s_deg[0]), dB = uni(s_deg[1]);
     int unkA = 0, unkB = 0;
     int cur = 0;
     int64_t steps = 0, chunks = 0, updates = 0;
@@ -137,8 +137,8 @@ __global__ __launch_bounds__(GCD_THREADS) void gcd_multi_kernel(GcdArgs G) {
                 if (lane == 0) { s_deg[0] = x; s_deg[1] = y; }
             }
             __syncthreads();
-            dA = s_deg[0];
-            dB = s_deg[1];
+            dA = uni(s_deg[0]);
+            dB = uni(s_deg[1]);
             unkA = unkB = 0;
             __syncthreads();
         }
@@ -149,11 +149,19 @@ __global__ __launch_bounds__(GCD_THREADS) void gcd_multi_kernel(GcdArgs G) {
             uint32_t hA[E], hB[E];
             load_heads<E>(Acur, Bcur, dA, dB, hA, hB);
             int n, big;
-            head_run<E>(hA, hB, dA, dB, G.s, F, desc, &s_out, tmp, n, big);
+            head_run<E>(hA, hB, (int)dA, (int)dB, G.s, F, desc, &s_out, n, big);
             if (!big) build_m(desc, n, F, M);
         }
         __syncthreads();
-        const ChunkOut res = s_out;
+        ChunkOut res = s_out;
+        res.dA = uni(res.dA);
+        res.dB = uni(res.dB);
+        res.upd = uni(res.upd);
+        res.nsteps = uni(res.nsteps);
+        res.S = uni(res.S);
+        res.unkA = uni(res.unkA);
+        res.unkB = uni(res.unkB);
+        res.big = uni(res.big);
         const int64_t top = dA > dB ? dA : dB;
         if (lo <= top) {
             if (!res.big) {
@@ -268,7 +276,7 @@ __global__ __launch_bounds__(NT) void gcd_batch_kernel(const GcdJob* jobs, const
         if (lane == 0) s_deg[wave] = d;
     }
     __syncthreads();
-    int64_t dA = s_deg[0], dB = s_deg[1];
+    int64_t dA = uni(s_deg[0]), dB = uni(s_deg[1]);
     int unkA = 0, unkB = 0;
     int64_t steps = 0, chunks = 0, updates = 0;
     const int64_t max_chunks = (dA > 0 ? dA : 0) + (dB > 0 ? dB : 0) + 4;
@@ -281,8 +289,8 @@ __global__ __launch_bounds__(NT) void gcd_batch_kernel(const GcdJob* jobs, const
                 if (lane == 0) { s_deg[0] = x; s_deg[1] = y; }
             }
             __syncthreads();
-            dA = s_deg[0];
-            dB = s_deg[1];
+            dA = uni(s_deg[0]);
+            dB = uni(s_deg[1]);
             unkA = unkB = 0;
             __syncthreads();
         }
@@ -293,11 +301,19 @@ __global__ __launch_bounds__(NT) void gcd_batch_kernel(const GcdJob* jobs, const
             uint32_t hA[E], hB[E];
             load_heads<E>(A, B, dA, dB, hA, hB);
             int nst, big;
-            head_run<E>(hA, hB, dA, dB, s, F, desc, &s_out, tmp, nst, big);
+            head_run<E>(hA, hB, (int)dA, (int)dB, s, F, desc, &s_out, nst, big);
             if (!big) build_m(desc, nst, F, M);
         }
         __syncthreads();
-        const ChunkOut res = s_out;
+        ChunkOut res = s_out;
+        res.dA = uni(res.dA);
+        res.dB = uni(res.dB);
+        res.upd = uni(res.upd);
+        res.nsteps = uni(res.nsteps);
+        res.S = uni(res.S);
+        res.unkA = uni(res.unkA);
+        res.unkB = uni(res.unkB);
+        res.big = uni(res.big);
         const int top = (int)(dA > dB ? dA : dB);
         if (!res.big) {
             uint32_t nA[PPT], nB[PPT];

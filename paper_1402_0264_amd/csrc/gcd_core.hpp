@@ -71,108 +71,95 @@ __device__ __forceinline__ uint32_t lanes_up(uint32_t x, int d) {
     return src < 0 ? 0u : y;
 }
 
-// Shift a strided head down by delta entries: new[i] = old[i + delta]
-// (entries shifted in from beyond the head are 0). `tmp` is 64*E words of
-// LDS private to the calling wave, used only when delta > 1.
+// Shift a strided head down by one entry: new[i] = old[i + 1] (0 enters at
+// the end). Element e of lane l is entry l + 64e.
 template <int E>
-__device__ __forceinline__ void head_shift(uint32_t (&h)[E], int delta, uint32_t* tmp) {
-    const int lane = threadIdx.x & 63;
-    if (delta == 1) {
-#pragma unroll
-        for (int e = 0; e < E; e++) {
-            uint32_t next0 = e + 1 < E ? (uint32_t)__builtin_amdgcn_readlane((int)h[e + 1], 0) : 0u;
-            h[e] = lanes_down1(h[e], next0);
-        }
-        return;
-    }
-#pragma unroll
-    for (int e = 0; e < E; e++) tmp[lane + 64 * e] = h[e];
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+__device__ __forceinline__ void head_shift1(uint32_t (&h)[E]) {
 #pragma unroll
     for (int e = 0; e < E; e++) {
-        int i = lane + 64 * e + delta;
-        h[e] = i < 64 * E ? tmp[i] : 0u;
+        uint32_t next0 = e + 1 < E ? (uint32_t)__builtin_amdgcn_readlane((int)h[e + 1], 0) : 0u;
+        h[e] = lanes_down1(h[e], next0);
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// One reduction of the head X by Y (in registers); returns delta, the drop of
-// deg X (>= 1), or 0 when no non-zero entry is left among the first v.
+// One reduction of the head X by Y (in registers): X <- REDC(m1 X + m2 Y),
+// entries at or beyond v cleared; returns delta, the index of the first
+// non-zero entry after the leading one (the drop of deg X), or 0 when none
+// is left among the first v.
 template <int E>
 __device__ __forceinline__ int head_reduce(uint32_t (&X)[E], const uint32_t (&Y)[E], uint32_t m1, uint32_t m2,
                                            int v, const Field& F) {
     const int lane = threadIdx.x & 63;
-    int delta = 0;
+    unsigned long long m[E];
 #pragma unroll
     for (int e = 0; e < E; e++) {
         const int i = lane + 64 * e;
         uint32_t x = redc((uint64_t)m1 * X[e] + (uint64_t)m2 * Y[e], F);
         x = i < v ? x : 0u;
         X[e] = x;
-        unsigned long long m = __ballot(i >= 1 && x != 0);
-        if (delta == 0 && m) delta = 64 * e + (int)__builtin_ctzll(m);
+        m[e] = __ballot(x != 0);
     }
-    return delta;
+    m[0] &= ~1ull;  // entry 0 is the cancelled leading coefficient
+#pragma unroll
+    for (int e = 0; e < E; e++)
+        if (m[e]) return 64 * e + (int)__builtin_ctzll(m[e]);
+    return 0;
 }
 
 // Head run by one whole wave. hA/hB: the heads (entry i = coefficient of
-// x^(deg - i)), exact for i < 64*E. Records the steps into desc[], returns
-// the chunk summary through *out (lane 0 writes). tmp: 64*E words of LDS.
+// x^(deg - i)), exact for i < 64*E. Records the steps into desc[] (lane 0
+// writes LDS), returns the chunk summary through *out (lane 0 writes) and
+// the step count and big flag in n_out / big_out.
 template <int E>
-__device__ void head_run(uint32_t (&hA)[E], uint32_t (&hB)[E], int64_t dA, int64_t dB, int s, const Field& F,
-                         StepDesc* desc, ChunkOut* out, uint32_t* tmp, int& n_out, int& big_out) {
+__device__ void head_run(uint32_t (&hA)[E], uint32_t (&hB)[E], int dA, int dB, int s, const Field& F,
+                         StepDesc* desc, ChunkOut* out, int& n_out, int& big_out) {
     const int lane = threadIdx.x & 63;
     constexpr int H = 64 * E;
+    dA = uni(dA);
+    dB = uni(dB);
+    s = uni(s);
     int vA = H, vB = H, S = 0, n = 0, unkA = 0, unkB = 0, big = 0;
     int64_t upd = 0;
     while (n < s && dA >= 0 && dB >= 0) {
         const bool redA = dA >= dB;
-        const int64_t d64 = redA ? dA - dB : dB - dA;
-        if (d64 > GCD_MAXSHIFT || S + d64 > GCD_MAXSHIFT) {
+        const int d = redA ? dA - dB : dB - dA;
+        if (S + d > GCD_MAXSHIFT) {
             if (n > 0) break;
             big = 1;  // one step alone, applied directly
         }
-        const int d = (int)(d64 > 0x7fffffff ? 0x7fffffff : d64);
         const uint32_t lcA = (uint32_t)__builtin_amdgcn_readfirstlane((int)hA[0]);
         const uint32_t lcB = (uint32_t)__builtin_amdgcn_readfirstlane((int)hB[0]);
-        int v, delta;
+        const int v = vA < vB ? vA : vB;
         uint32_t m1, m2;
+        int delta;
         if (redA) {
             m1 = lcB;
             m2 = F.p - lcA;
-            v = vA < vB ? vA : vB;
             delta = head_reduce<E>(hA, hB, m1, m2, v, F);
         } else {
             m1 = lcA;
             m2 = F.p - lcB;
-            v = vA < vB ? vA : vB;
             delta = head_reduce<E>(hB, hA, m1, m2, v, F);
         }
         if (lane == 0) desc[n] = StepDesc{m1, m2, d, redA ? 0 : 1};
         n++;
-        S += big ? 0 : d;
+        if (!big) S += d;
         upd += (redA ? dB : dA) + 1;
-        int64_t nd;
-        int nv;
         if (delta > 0) {
-            nd = (redA ? dA : dB) - delta;
-            nv = v - delta;
-            if (redA) head_shift<E>(hA, delta, tmp);
-            else head_shift<E>(hB, delta, tmp);
+            for (int k = 0; k < delta; k++) {
+                if (redA) head_shift1<E>(hA);
+                else head_shift1<E>(hB);
+            }
+            if (redA) { dA -= delta; vA = v - delta; } else { dB -= delta; vB = v - delta; }
         } else {
             // the first v entries vanished: deg X <= old deg - v
-            nd = (redA ? dA : dB) - v;
-            nv = 0;
+            int nd = (redA ? dA : dB) - v;
             if (nd < 0) nd = -1;
             else if (redA) unkA = 1;
             else unkB = 1;
+            if (redA) { dA = nd; vA = 0; } else { dB = nd; vB = 0; }
         }
-        if (redA) { dA = nd; vA = nv; } else { dB = nd; vB = nv; }
-        if (unkA || unkB || big) break;
+        if (unkA | unkB | big) break;
     }
     n_out = n;
     big_out = big;
@@ -190,21 +177,32 @@ __device__ void head_run(uint32_t (&hA)[E], uint32_t (&hB)[E], int64_t dA, int64
 
 // Compose the recorded steps into M (one wave; lane k = coefficient k).
 // Writes M to LDS as 4 rows of 64 words: alpha, beta, gamma, delta.
+// The descriptors are first spread over the lanes (lane j holds step j of
+// each group of 64) so the sequential loop reads them with readlane.
 __device__ __forceinline__ void build_m(const StepDesc* desc, int n, const Field& F, uint32_t* M) {
     const int lane = threadIdx.x & 63;
+    n = uni(n);
     uint32_t al = lane == 0 ? 1u : 0u, be = 0u, ga = 0u, de = lane == 0 ? 1u : 0u;
-    for (int k = 0; k < n; k++) {
-        const StepDesc D = desc[k];
-        if (D.which == 0) {  // (alpha, beta) <- REDC(m1*(alpha, beta) + m2*x^d*(gamma, delta))
-            uint32_t sg = D.d == 0 ? ga : (D.d == 1 ? lanes_up1(ga) : lanes_up(ga, D.d));
-            uint32_t sd = D.d == 0 ? de : (D.d == 1 ? lanes_up1(de) : lanes_up(de, D.d));
-            al = redc((uint64_t)D.m1 * al + (uint64_t)D.m2 * sg, F);
-            be = redc((uint64_t)D.m1 * be + (uint64_t)D.m2 * sd, F);
-        } else {
-            uint32_t sa = D.d == 0 ? al : (D.d == 1 ? lanes_up1(al) : lanes_up(al, D.d));
-            uint32_t sb = D.d == 0 ? be : (D.d == 1 ? lanes_up1(be) : lanes_up(be, D.d));
-            ga = redc((uint64_t)D.m1 * ga + (uint64_t)D.m2 * sa, F);
-            de = redc((uint64_t)D.m1 * de + (uint64_t)D.m2 * sb, F);
+    for (int k0 = 0; k0 < n; k0 += 64) {
+        StepDesc mine = k0 + lane < n ? desc[k0 + lane] : StepDesc{0, 0, 0, 0};
+        const uint32_t dw = (uint32_t)mine.d | ((uint32_t)mine.which << 31);
+        const int kn = n - k0 < 64 ? n - k0 : 64;
+        for (int k = 0; k < kn; k++) {
+            const uint32_t m1 = (uint32_t)__builtin_amdgcn_readlane((int)mine.m1, k);
+            const uint32_t m2 = (uint32_t)__builtin_amdgcn_readlane((int)mine.m2, k);
+            const uint32_t w = (uint32_t)__builtin_amdgcn_readlane((int)dw, k);
+            const int d = (int)(w & 0x7fffffffu);
+            if ((w >> 31) == 0) {  // (alpha, beta) <- REDC(m1*(alpha, beta) + m2*x^d*(gamma, delta))
+                uint32_t sg = d == 0 ? ga : (d == 1 ? lanes_up1(ga) : lanes_up(ga, d));
+                uint32_t sd = d == 0 ? de : (d == 1 ? lanes_up1(de) : lanes_up(de, d));
+                al = redc((uint64_t)m1 * al + (uint64_t)m2 * sg, F);
+                be = redc((uint64_t)m1 * be + (uint64_t)m2 * sd, F);
+            } else {
+                uint32_t sa = d == 0 ? al : (d == 1 ? lanes_up1(al) : lanes_up(al, d));
+                uint32_t sb = d == 0 ? be : (d == 1 ? lanes_up1(be) : lanes_up(be, d));
+                ga = redc((uint64_t)m1 * ga + (uint64_t)m2 * sa, F);
+                de = redc((uint64_t)m1 * de + (uint64_t)m2 * sb, F);
+            }
         }
     }
     M[lane] = al;
@@ -221,6 +219,7 @@ __device__ __forceinline__ void apply_m_at(const uint32_t* la, const uint32_t* l
     uint64_t accA = 0, accB = 0;
     uint32_t cnt = 0;
     const uint32_t half = F.fold_every / 2;
+    S = uni(S);
     for (int k = 0; k <= S; k++) {
         const uint32_t a = la[x - k], b = lb[x - k];
         accA += (uint64_t)M[k] * a;

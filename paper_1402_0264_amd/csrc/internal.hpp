@@ -59,6 +59,28 @@ hipError_t mul_launch(const uint32_t* a, int64_t na, const uint32_t* b, int64_t 
                       int64_t* out_len, int32_t* out_status, const uint32_t* sub_from,
                       int64_t out_limit, hipStream_t stream);
 
+// Batched product: one item per independent product (a is the longer
+// operand), one task per output tile of 256*r outputs.
+struct MulItem {
+    const uint32_t* a;
+    const uint32_t* b;
+    uint32_t* f;
+    int64_t na, nb;
+    Field F;
+};
+struct MulTask {
+    int32_t item;
+    int32_t tile;
+};
+int64_t mul_batch_tile(int r);
+// Chunk length the batched kernel uses for a requested kc.
+int64_t mul_batch_kc(int r, int64_t kc);
+// d_counters: two words, zero before the first launch (the kernel leaves
+// them zero). fold_min: the smallest Field::fold_every over the items.
+hipError_t mul_batch_launch(const MulItem* d_items, const MulTask* d_tasks, int ntasks, int r, int64_t kc,
+                            uint32_t fold_min, uint32_t* d_counters, int num_cus, hipStream_t stream);
+hipError_t mul_batch_check_launch(const MulItem* d_items, int count, int32_t* d_status, hipStream_t stream);
+
 // ----------------------------------------------------------------- division
 // Euclidean division (Sec. 3) runs in two launches around one host read of
 // the degrees: divrem_head_launch validates the inputs, finds deg a and

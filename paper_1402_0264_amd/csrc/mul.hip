@@ -72,24 +72,22 @@ __device__ void mul_aux_block(const MulArgs& A) {
     }
 }
 
+// One b-chunk of one output tile, accumulated into acc[] (exact 64-bit sums,
+// folded every FOLD products). Tile outputs: x0 + tid*R + r relative to the
+// chunk start j0 (output k = j0 + x); the chunk is b[j0 .. j0 + kc) with
+// b beyond nb read as zero; `lds` holds at least tile_lds_bytes(R, kc).
+// Returns with acc folded (below 2^32 p); the caller syncs before reusing
+// the LDS.
 template <int R, int FOLD>
-__global__ __launch_bounds__(MUL_THREADS) void mul_tile_kernel(MulArgs A) {
-    extern __shared__ uint32_t lds[];
-    const int64_t work = A.nchunks * A.tiles;
-    if ((int64_t)blockIdx.x >= work) {
-        mul_aux_block(A);
-        return;
-    }
+__device__ __forceinline__ void tile_chunk(const uint32_t* __restrict__ a, int64_t na, const uint32_t* __restrict__ b,
+                                           int64_t nb, int64_t x0, int64_t j0, int64_t kc, uint32_t c32,
+                                           uint32_t* lds, uint64_t (&acc)[R]) {
     const int tid = threadIdx.x;
-    const int64_t c = blockIdx.x / A.tiles;
-    const int64_t tile = blockIdx.x - c * A.tiles;
-    const int64_t j0 = c * A.kc;
     constexpr int T = MUL_THREADS * R;
     constexpr int PAD = R > 1 ? R + 1 : 1;  // padded words per group of R
-    const int64_t x0 = tile * T;  // first row offset of the tile (output k = j0 + x)
     // steps of this chunk, rounded up to whole blocks of R (b reads as 0 past nb)
-    const int64_t left = A.nb - j0;
-    const int steps = (int)(((left < A.kc ? left : A.kc) + R - 1) / R * R);
+    const int64_t left = nb - j0;
+    const int steps = (int)(((left < kc ? left : kc) + R - 1) / R * R);
 
     // Stage the a window: index w <-> a[x0 - steps + w], w = 0 .. T + steps - 1
     // (w = 0 is one spare word below the window so the last prefetch stays in
@@ -98,11 +96,11 @@ __global__ __launch_bounds__(MUL_THREADS) void mul_tile_kernel(MulArgs A) {
     const int64_t abase = x0 - steps;
     for (int w = tid; w < W; w += MUL_THREADS) {
         int64_t i = abase + w;
-        uint32_t v = (i >= 0 && i < A.na) ? A.a[i] : 0u;
+        uint32_t v = (i >= 0 && i < na) ? a[i] : 0u;
         lds[lds_addr<R>(w)] = v;
     }
     const int lb = (lds_addr<R>(W) + 7) & ~3;  // b chunk, 16-byte aligned
-    for (int j = tid; j < steps; j += MUL_THREADS) lds[lb + j] = j < left ? A.b[j0 + j] : 0u;
+    for (int j = tid; j < steps; j += MUL_THREADS) lds[lb + j] = j < left ? b[j0 + j] : 0u;
     __syncthreads();
 
     // Thread window at step jj: w = tid*R + steps + u with u = r - jj; the
@@ -110,16 +108,11 @@ __global__ __launch_bounds__(MUL_THREADS) void mul_tile_kernel(MulArgs A) {
     // the padded address is PAD*g + e, so the load of step v of a block is a
     // constant offset from one address per block.
     uint32_t ring[R];
-    uint64_t acc[R];
     {
         const int g0 = PAD * (tid + steps / R);
 #pragma unroll
-        for (int r = 0; r < R; r++) {
-            ring[r] = lds[g0 + r];
-            acc[r] = 0;
-        }
+        for (int r = 0; r < R; r++) ring[r] = lds[g0 + r];
     }
-    const uint32_t c32 = A.F.c32;
     const int nblk = steps / R;
     constexpr int BPF = FOLD >= R ? FOLD / R : 1;  // blocks between folds
     int blk = 0;
@@ -152,25 +145,51 @@ __global__ __launch_bounds__(MUL_THREADS) void mul_tile_kernel(MulArgs A) {
             for (int r = 0; r < R; r++) acc[r] = fold(acc[r], c32);
         }
     }
+}
 
-    // Epilogue: canonical residues, then either a row of M or f itself.
-    const int64_t xt = x0 + (int64_t)tid * R;
-    if (A.nchunks > 1) {
-        uint32_t* row = A.out + c * A.rowlen;
+template <int R, int FOLD>
+__global__ __launch_bounds__(MUL_THREADS) void mul_tile_kernel(MulArgs A) {
+    extern __shared__ uint32_t lds[];
+    const int64_t work = A.nchunks * A.tiles;
+    // the last block validates (when asked); the others stride over the
+    // (chunk, tile) work units
+    const int64_t workers = A.out_len || A.out_status ? (int64_t)gridDim.x - 1 : (int64_t)gridDim.x;
+    if ((int64_t)blockIdx.x >= workers) {
+        mul_aux_block(A);
+        return;
+    }
+    const int tid = threadIdx.x;
+    constexpr int T = MUL_THREADS * R;
+    for (int64_t w = blockIdx.x; w < work; w += workers) {
+        const int64_t c = w / A.tiles;
+        const int64_t tile = w - c * A.tiles;
+        const int64_t j0 = c * A.kc;
+        const int64_t x0 = tile * T;  // first row offset of the tile (output k = j0 + x)
+        uint64_t acc[R];
 #pragma unroll
-        for (int r = 0; r < R; r++) {
-            int64_t x = xt + r;
-            if (x < A.rowlen) row[x] = reduce64(acc[r], A.F);
-        }
-    } else {
+        for (int r = 0; r < R; r++) acc[r] = 0;
+        tile_chunk<R, FOLD>(A.a, A.na, A.b, A.nb, x0, j0, A.kc, A.F.c32, lds, acc);
+
+        // Epilogue: canonical residues, then either a row of M or f itself.
+        const int64_t xt = x0 + (int64_t)tid * R;
+        if (A.nchunks > 1) {
+            uint32_t* row = A.out + c * A.rowlen;
 #pragma unroll
-        for (int r = 0; r < R; r++) {
-            int64_t k = xt + r;
-            if (k < A.out_limit) {
-                uint32_t v = reduce64(acc[r], A.F);
-                A.out[k] = A.sub_from ? submod(A.sub_from[k], v, A.F.p) : v;
+            for (int r = 0; r < R; r++) {
+                int64_t x = xt + r;
+                if (x < A.rowlen) row[x] = reduce64(acc[r], A.F);
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; r++) {
+                int64_t k = xt + r;
+                if (k < A.out_limit) {
+                    uint32_t v = reduce64(acc[r], A.F);
+                    A.out[k] = A.sub_from ? submod(A.sub_from[k], v, A.F.p) : v;
+                }
             }
         }
+        __syncthreads();  // the next unit restages the LDS
     }
 }
 
@@ -208,6 +227,96 @@ int64_t effective_kc(const MulPlan& plan, int64_t nb) {
     return kc;
 }
 
+// ------------------------------------------------------------------ batched
+// Persistent product of many independent pairs (one launch): each task is
+// one output tile of T = 256*R outputs of one product, summed over all of b
+// in chunks of kc coefficients with the sums kept in registers (no partial
+// rows). Thread-blocks take tasks from a queue (one atomic counter) in the
+// order of the task table, which the host sorts longest first; the last
+// block to leave resets the counters, so the launch can be replayed (e.g.
+// from a hipGraph) without any memset.
+template <int R, int FOLD>
+__global__ __launch_bounds__(MUL_THREADS) void mul_batch_kernel(const MulItem* __restrict__ items,
+                                                                const MulTask* __restrict__ tasks, int ntasks,
+                                                                int64_t kc, uint32_t* counters) {
+    extern __shared__ uint32_t lds[];
+    __shared__ int s_task;
+    constexpr int T = MUL_THREADS * R;
+    const int tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) s_task = (int)atomicAdd(&counters[0], 1u);
+        __syncthreads();
+        const int t = s_task;
+        __syncthreads();
+        if (t >= ntasks) break;
+        const MulTask tk = tasks[t];
+        const MulItem it = items[tk.item];
+        const int64_t K0 = (int64_t)tk.tile * T;
+        const int64_t nf = it.na + it.nb - 1;
+        const int64_t nchunks = (it.nb + kc - 1) / kc;
+        int64_t c_lo = K0 - it.na + 1;
+        c_lo = c_lo <= 0 ? 0 : c_lo / kc;
+        int64_t c_hi = (K0 + T - 1) / kc;
+        if (c_hi > nchunks - 1) c_hi = nchunks - 1;
+        uint64_t acc[R];
+#pragma unroll
+        for (int r = 0; r < R; r++) acc[r] = 0;
+        for (int64_t c = c_lo; c <= c_hi; c++) {
+            tile_chunk<R, FOLD>(it.a, it.na, it.b, it.nb, K0 - c * kc, c * kc, kc, it.F.c32, lds, acc);
+            __syncthreads();
+        }
+        const int64_t kt = K0 + (int64_t)tid * R;
+#pragma unroll
+        for (int r = 0; r < R; r++)
+            if (kt + r < nf) it.f[kt + r] = reduce64(acc[r], it.F);
+    }
+    if (tid == 0) {
+        if (atomicAdd(&counters[1], 1u) == gridDim.x - 1) {
+            atomicExch(&counters[0], 0u);
+            atomicExch(&counters[1], 0u);
+        }
+    }
+}
+
+// Range check of every coefficient of every item (one block per item).
+__global__ __launch_bounds__(256) void mul_batch_check_kernel(const MulItem* __restrict__ items, int32_t* status) {
+    const MulItem it = items[blockIdx.x];
+    int bad = 0;
+    for (int64_t i = threadIdx.x; i < it.na; i += 256) bad |= it.a[i] >= it.F.p;
+    for (int64_t i = threadIdx.x; i < it.nb; i += 256) bad |= it.b[i] >= it.F.p;
+    bad = __syncthreads_or(bad);
+    if (threadIdx.x == 0) status[blockIdx.x] = bad ? -3 /* PM_ERANGE */ : 0;
+}
+
+template <int R, int FOLD>
+hipError_t launch_batch(const MulItem* items, const MulTask* tasks, int ntasks, int64_t kc, uint32_t* counters,
+                        int grid, hipStream_t stream) {
+    size_t lds = (size_t)tile_lds_bytes(R, kc);
+    hipLaunchKernelGGL((mul_batch_kernel<R, FOLD>), dim3(grid), dim3(MUL_THREADS), lds, stream, items, tasks, ntasks,
+                       kc, counters);
+    return hipGetLastError();
+}
+
+template <int R>
+hipError_t launch_batch_fold(uint32_t fold_min, const MulItem* items, const MulTask* tasks, int ntasks, int64_t kc,
+                             uint32_t* counters, int grid, hipStream_t stream) {
+    if (fold_min >= 128) return launch_batch<R, 128>(items, tasks, ntasks, kc, counters, grid, stream);
+    if (fold_min >= 64) return launch_batch<R, 64>(items, tasks, ntasks, kc, counters, grid, stream);
+    if (fold_min >= 32) return launch_batch<R, 32>(items, tasks, ntasks, kc, counters, grid, stream);
+    if (fold_min >= 16) return launch_batch<R, 16>(items, tasks, ntasks, kc, counters, grid, stream);
+    return launch_batch<R, 8>(items, tasks, ntasks, kc, counters, grid, stream);
+}
+
+template <int R>
+int batch_blocks_per_cu(int64_t kc) {
+    int nb = 0;
+    size_t lds = (size_t)tile_lds_bytes(R, kc);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)mul_batch_kernel<R, 64>, MUL_THREADS, lds) !=
+            hipSuccess || nb < 1)
+        nb = 1;
+    return nb;
+}
+
 template <int R, int FOLD>
 hipError_t launch_tile(const MulArgs& A, int64_t grid, hipStream_t stream) {
     size_t lds = (size_t)tile_lds_bytes(R, A.kc);
@@ -226,6 +335,41 @@ hipError_t launch_fold(const MulArgs& A, int64_t grid, hipStream_t stream) {
 }
 
 }  // namespace
+
+int64_t mul_batch_tile(int r) { return (int64_t)MUL_THREADS * r; }
+
+int64_t mul_batch_kc(int r, int64_t kc) {
+    MulPlan p{r, kc};
+    return effective_kc(p, INT64_C(1) << 40);
+}
+
+hipError_t mul_batch_launch(const MulItem* d_items, const MulTask* d_tasks, int ntasks, int r, int64_t kc,
+                            uint32_t fold_min, uint32_t* d_counters, int num_cus, hipStream_t stream) {
+    if (ntasks <= 0) return hipSuccess;
+    kc = mul_batch_kc(r, kc);
+    int per_cu = 1, grid;
+    switch (r) {
+        case 4: per_cu = batch_blocks_per_cu<4>(kc); break;
+        case 8: per_cu = batch_blocks_per_cu<8>(kc); break;
+        case 16: per_cu = batch_blocks_per_cu<16>(kc); break;
+        default: return hipErrorInvalidValue;
+    }
+    grid = per_cu * num_cus;
+    if (grid > ntasks) grid = ntasks;
+    TimingScope ts("mul_batch_kernel", stream);
+    switch (r) {
+        case 4: return launch_batch_fold<4>(fold_min, d_items, d_tasks, ntasks, kc, d_counters, grid, stream);
+        case 8: return launch_batch_fold<8>(fold_min, d_items, d_tasks, ntasks, kc, d_counters, grid, stream);
+        default: return launch_batch_fold<16>(fold_min, d_items, d_tasks, ntasks, kc, d_counters, grid, stream);
+    }
+}
+
+hipError_t mul_batch_check_launch(const MulItem* d_items, int count, int32_t* d_status, hipStream_t stream) {
+    if (count <= 0) return hipSuccess;
+    TimingScope ts("mul_batch_check_kernel", stream);
+    hipLaunchKernelGGL(mul_batch_check_kernel, dim3(count), dim3(256), 0, stream, d_items, d_status);
+    return hipGetLastError();
+}
 
 int64_t mul_scratch_words(int64_t na, int64_t nb, const MulPlan& plan) {
     if (na <= 0 || nb <= 0) return 0;
@@ -279,7 +423,11 @@ hipError_t mul_launch(const uint32_t* a, int64_t na, const uint32_t* b, int64_t 
     A.rowlen = na + kc - 1;
     A.tiles = (A.rowlen + MUL_THREADS * R - 1) / (MUL_THREADS * R);
     A.out = A.nchunks > 1 ? M : f;
-    int64_t grid = A.nchunks * A.tiles + (aux ? 1 : 0);
+    // at most 2^20 blocks (the runtime counts grid*block work-items in 32
+    // bits); blocks stride over the remaining (chunk, tile) units
+    int64_t units = A.nchunks * A.tiles;
+    if (units > (INT64_C(1) << 20)) units = INT64_C(1) << 20;
+    int64_t grid = units + (aux ? 1 : 0);
     hipError_t e;
     {
     TimingScope ts("mul_tile_kernel", stream);

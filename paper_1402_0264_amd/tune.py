@@ -1,0 +1,142 @@
+"""Autotuner for the product kernels' tile shape.
+
+For the batched product the tunable shape is (r, kc): r outputs per thread
+(a thread-block owns 256*r outputs) and kc coefficients of b staged per
+pass, which is the paper's program parameter s for the product (Sec. 5:
+b-coefficients handled per thread-block). For the single large product the
+same pair picks the split into b-chunks. Each candidate is timed with HIP
+events on the real inputs; the fastest is kept in a JSON cache keyed by a
+workload signature and the device name.
+
+The model of the paper predicts the opposite direction for the product (its
+estimate grows with s, so s should be as small as possible; mmm.py), while
+the paper measured its best s at 4. The tuner's choice is reported beside
+both.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+BATCH_CANDIDATES = [(4, 256), (4, 512), (4, 1024), (8, 256), (8, 512), (8, 1024), (8, 2048),
+                    (16, 256), (16, 512), (16, 1024), (16, 2048)]
+SINGLE_CANDIDATES = [(8, 512), (8, 1024), (8, 2048), (16, 512), (16, 1024), (16, 2048), (16, 4096)]
+
+
+def cache_path() -> str:
+    p = os.environ.get("PM_TUNE_CACHE")
+    if p:
+        return p
+    base = os.environ.get("XDG_CACHE_HOME", os.path.join(os.path.expanduser("~"), ".cache"))
+    return os.path.join(base, "polymodp", "tune.json")
+
+
+def _load() -> dict:
+    try:
+        with open(cache_path()) as fh:
+            return json.load(fh)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(key: str, rec: dict) -> None:
+    d = _load()
+    d[key] = rec
+    path = cache_path()
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + ".tmp%d" % os.getpid()
+        with open(tmp, "w") as fh:
+            json.dump(d, fh, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    except OSError:
+        pass  # a read-only home only costs the cache
+
+
+def _device_name() -> str:
+    import torch
+    return torch.cuda.get_device_properties(torch.cuda.current_device()).name or "gpu"
+
+
+def _time(fn, reps: int) -> float:
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    best = float("inf")
+    for _ in range(reps):
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    return best
+
+
+def batch_signature(items) -> str:
+    """items: list of (a, b, p) with tensor/array a, b."""
+    degs = [(len(a) if not hasattr(a, "numel") else a.numel()) for a, _, _ in items]
+    degs += [(len(b) if not hasattr(b, "numel") else b.numel()) for _, b, _ in items]
+    pbits = sorted({int(p).bit_length() for _, _, p in items})
+    work = sum((a.numel() if hasattr(a, "numel") else len(a)) * (b.numel() if hasattr(b, "numel") else len(b))
+               for a, b, _ in items)
+    return "mul_batch:n%d:deg%d-%d:work%.3g:pbits%s" % (len(items), min(degs), max(degs), work,
+                                                         "-".join(map(str, pbits)))
+
+
+def tune_mul_batch(items, candidates=BATCH_CANDIDATES, reps: int = 3, use_cache: bool = True) -> dict:
+    """Pick (r, kc) for a batch of products (list of (a, b, p) device
+    tensors). Returns {"r", "kc", "ms", "trials", "cached"}."""
+    import paper_1402_0264_amd as pm
+    key = batch_signature(items) + ":" + _device_name()
+    if use_cache:
+        rec = _load().get(key)
+        if rec:
+            rec = dict(rec)
+            rec["cached"] = True
+            return rec
+    trials = []
+    for r, kc in candidates:
+        b = pm.MulBatch(items, r, kc)
+        ms = _time(b.run, reps)
+        b.close()
+        trials.append({"r": r, "kc": kc, "ms": round(ms, 5)})
+    best = min(trials, key=lambda t: t["ms"])
+    rec = {"r": best["r"], "kc": best["kc"], "ms": best["ms"], "trials": trials}
+    _store(key, rec)
+    rec = dict(rec)
+    rec["cached"] = False
+    return rec
+
+
+def tune_mul(a, b, p: int, candidates=SINGLE_CANDIDATES, reps: int = 3, use_cache: bool = True) -> dict:
+    """Pick (mul_r, mul_s) for one product of device tensors a, b."""
+    import torch
+    import paper_1402_0264_amd as pm
+    key = "mul:%d:%d:pbits%d:%s" % (a.numel(), b.numel(), int(p).bit_length(), _device_name())
+    if use_cache:
+        rec = _load().get(key)
+        if rec:
+            rec = dict(rec)
+            rec["cached"] = True
+            return rec
+    n = a.numel() + b.numel() - 1
+    f = torch.empty(n, dtype=torch.int32, device=a.device)
+    d_nf = torch.zeros(1, dtype=torch.int64, device=a.device)
+    d_st = torch.zeros(1, dtype=torch.int32, device=a.device)
+    saved = pm.get_params()
+    trials = []
+    try:
+        for r, kc in candidates:
+            pm.set_params(mul_r=r, mul_s=kc, div_s=saved["div_s"], gcd_s=saved["gcd_s"])
+            ms = _time(lambda: pm.mul_async(a, b, p, f, d_nf, d_st), reps)
+            trials.append({"r": r, "kc": kc, "ms": round(ms, 5)})
+    finally:
+        pm.set_params(**saved)
+    best = min(trials, key=lambda t: t["ms"])
+    rec = {"r": best["r"], "kc": best["kc"], "ms": best["ms"], "trials": trials}
+    _store(key, rec)
+    rec = dict(rec)
+    rec["cached"] = False
+    return rec

@@ -287,3 +287,102 @@ def test_gcd_batch_reports_item_errors():
     assert res[2][1]["status"] == 0 and same(host(res[2][0]), oracle.gcd(c, d, gen.P_C))
     # residues of P_A are not all below P_C
     assert res[3][1]["status"] == (pm.PM_ERANGE if (a >= gen.P_C).any() or (b >= gen.P_C).any() else 0)
+
+
+# ---------------------------------------------------------- batched product
+def _batch_items(count, lo, hi, seed, primes=PRIMES):
+    st = gen.Stream(seed)
+    items = []
+    for _ in range(count):
+        p = primes[st.index(len(primes))]
+        na, nb = st.log_uniform_int(lo, hi), st.log_uniform_int(lo, hi)
+        items.append((st.uniform_poly(na - 1, p), st.uniform_poly(nb - 1, p), p))
+    return items
+
+
+@pytest.mark.parametrize("r,kc", [(0, 0), (4, 64), (8, 1000), (16, 2048), (4, 4)])
+def test_mul_batch_matches_oracle(r, kc):
+    items = _batch_items(150, 1, 3000, 401)
+    b = pm.MulBatch([(dev(a), dev(b_), p) for a, b_, p in items], r, kc)
+    b.run()
+    import torch
+    torch.cuda.synchronize()
+    for (a, b_, p), f in zip(items, b.outputs):
+        assert same(host(f), oracle.mul(a, b_, p))
+    b.close()
+
+
+def test_mul_batch_graph_replay_and_status():
+    import torch
+    items = _batch_items(60, 1, 2000, 402)
+    bad_a = items[7][0].copy(); bad_a[0] = items[7][2]
+    items[7] = (bad_a, items[7][1], items[7][2])
+    b = pm.MulBatch([(dev(a), dev(b_), p) for a, b_, p in items], 8, 256)
+    status = torch.full((len(items),), 77, dtype=torch.int32, device="cuda")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        b.run(status, stream=s)          # once outside capture
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    st = status.cpu().numpy()
+    assert st[7] == pm.PM_ERANGE and (np.delete(st, 7) == 0).all()
+    want = [oracle.mul(a, b_, p) for a, b_, p in items]
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        b.run()
+    for rep in range(3):
+        for f in b.outputs:
+            f.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for i, f in enumerate(b.outputs):
+            if i != 7:
+                assert same(host(f), want[i]), (rep, i)
+    b.close()
+
+
+def test_mul_batch_workload_4096_sampled():
+    """The 4096-product workload: every product checked at one random
+    point (f(x) = a(x) b(x)), 24 products checked in full."""
+    import torch
+    bt = gen.batch_products()
+    p = bt.p
+    b = pm.MulBatch([(dev(a), dev(b_), p) for a, b_ in zip(bt.a, bt.b)])
+    b.run()
+    torch.cuda.synchronize()
+    st = gen.Stream(403)
+    for i, f in enumerate(b.outputs):
+        fh = host(f)
+        x = st.uniform_int(0, p - 1)
+        assert ck.horner(fh, x, p) == ck.horner(bt.a[i], x, p) * ck.horner(bt.b[i], x, p) % p, i
+    for i in range(0, 4096, 171):
+        assert same(host(b.outputs[i]), oracle.mul(bt.a[i], bt.b[i], p)), i
+    b.close()
+
+
+def test_mul_s1_plan_beyond_one_launch_of_blocks():
+    """s = 1 on a 65536 x 8192 product: 8192 b-chunks x 256 tiles exceed
+    2^20 thread-blocks, so the blocks stride over the work; sampled outputs
+    against the oracle, and the same result as s = 512."""
+    import torch
+    p = gen.P_A
+    a, b = gen.mul_pair(65536, 8192, p, seed=gen.SEED_BASE + 60)
+    pm.set_params(mul_r=1, mul_s=1)
+    try:
+        f1 = pm.mul(dev(a), dev(b), p)
+    finally:
+        pm.set_params()
+    torch.cuda.synchronize()
+    fh = host(f1)
+    st = gen.Stream(106)
+    for k in [0, 1, 8190, 8191, 65535, 73726] + [st.uniform_int(0, 73726) for _ in range(20)]:
+        assert int(fh[k]) == oracle.mul_coeff(a, b, p, k), k
+    pm.set_params(mul_r=16, mul_s=512)
+    try:
+        f2 = pm.mul(dev(a), dev(b), p)
+    finally:
+        pm.set_params()
+    assert torch.equal(f1, f2)
+    pm.release()  # drop the 2 GiB partial-sum pool
