@@ -22,7 +22,12 @@ Beside it, in the same line:
                 tile shape from the autotuner, beside the same products as
                 4096 separate calls on the same stream;
   gcd_32768     Euclidean division and remainder-sequence gcd of the degree
-                32768 / 32767 pair with a planted degree-1000 gcd.
+                32768 / 32767 pair with a planted degree-1000 gcd;
+  served        a Poisson stream of 2048 gcd requests (degrees log-uniform
+                in [64, 16384], planted gcd, three primes) through the
+                continuous-batching server: saturated GCDs/s, then p50/p99
+                latency at 0.8 of that rate, beside the same trace served
+                one synchronous call per request (FIFO).
 """
 from __future__ import annotations
 
@@ -158,6 +163,112 @@ def bench_batched(reps: int) -> dict:
             "graph_replays": reps, "matches_one_call_results": bool(same)}
 
 
+def _pct(xs, q):
+    xs = sorted(xs)
+    return xs[max(0, min(len(xs) - 1, int(round(q * len(xs) + 0.5)) - 1))]
+
+
+def served_inputs(count: int):
+    """The served trace's requests as host arrays; a = g*u and b = g*v are
+    formed with the library's batched product."""
+    import torch
+    import paper_1402_0264_amd as pm
+    from paper_1402_0264_amd import gen
+    trace = gen.served_trace(count, rate=1.0)
+    items = []
+    for r in trace:
+        g = pm.to_device(r.factors.g)
+        items.append((g, pm.to_device(r.factors.u), r.p))
+        items.append((g, pm.to_device(r.factors.v), r.p))
+    out = []
+    for lo in range(0, len(items), 1024):
+        b = pm.MulBatch(items[lo:lo + 1024])
+        b.run()
+        torch.cuda.synchronize()
+        out += [pm.to_numpy(f) for f in b.outputs]
+        b.close()
+    reqs = [(out[2 * i], out[2 * i + 1], r.p, r.arrival, r.D, r.k) for i, r in enumerate(trace)]
+    return reqs
+
+
+def run_server_trace(reqs, scale: float):
+    """Submit each request at arrival * scale seconds; returns latencies (ms)
+    and the span from the first arrival to the last completion."""
+    import paper_1402_0264_amd as pm
+    srv = pm.Server()
+    t0 = time.perf_counter()
+    i = done = 0
+    lat = []
+    first = last = None
+    deadline = time.perf_counter() + 600.0
+    while done < len(reqs):
+        now = time.perf_counter() - t0
+        if time.perf_counter() > deadline:
+            raise TimeoutError("served trace did not finish")
+        while i < len(reqs) and reqs[i][3] * scale <= now:
+            a, b, p = reqs[i][0], reqs[i][1], reqs[i][2]
+            srv.submit(a, b, p, tag=i)
+            i += 1
+        for c in srv.poll():
+            if c["status"] != 0:
+                raise RuntimeError("served request %d failed: %d" % (c["tag"], c["status"]))
+            lat.append(c["t_done_ms"] - c["t_submit_ms"])
+            first = c["t_submit_ms"] if first is None else min(first, c["t_submit_ms"])
+            last = c["t_done_ms"] if last is None else max(last, c["t_done_ms"])
+            done += 1
+    srv.close()
+    return lat, (last - first) / 1e3
+
+
+def run_one_call_trace(reqs, scale: float):
+    """The same trace, one synchronous poly_gcd_modp call per request in
+    arrival order (host copy in, gcd, copy out)."""
+    import paper_1402_0264_amd as pm
+    t0 = time.perf_counter()
+    lat = []
+    for a, b, p, arr, _, _ in reqs:
+        t_arr = arr * scale
+        while time.perf_counter() - t0 < t_arr:
+            pass
+        g = pm.gcd(pm.to_device(a), pm.to_device(b), p)
+        pm.to_numpy(g)
+        lat.append((time.perf_counter() - t0 - t_arr) * 1e3)
+    span = time.perf_counter() - t0 - reqs[0][3] * scale
+    return lat, span
+
+
+def bench_served(n_req: int, warm: int, load: float, baseline: bool) -> dict:
+    import torch
+    reqs = served_inputs(n_req + warm)
+    warm_reqs, reqs = reqs[:warm], reqs[warm:]
+    t_first = reqs[0][3]
+    reqs = [(a, b, p, arr - t_first, D, k) for a, b, p, arr, D, k in reqs]
+    run_server_trace(warm_reqs, 0.0)
+    lat_sat, span_sat = run_server_trace(reqs, 0.0)      # everything arrives at once
+    sat = len(reqs) / span_sat
+    mean_gap = reqs[-1][3] / max(len(reqs) - 1, 1)         # of the rate-1 trace
+    rate = load * sat
+    scale = 1.0 / (rate * mean_gap)
+    lat, span = run_server_trace(reqs, scale)
+    out = {"workload": "%d gcd requests, D log-uniform in [64, 16384], deg b = D-1, planted gcd degree "
+                       "uniform in [0, D/4], p in {469762049, 998244353, 167772161}" % len(reqs),
+           "saturated_gcds_per_s": round(sat, 1),
+           "offered_rate_per_s": round(rate, 1), "load": load,
+           "gcds_per_s": round(len(reqs) / span, 1),
+           "p50_ms": round(_pct(lat, 0.50), 3), "p99_ms": round(_pct(lat, 0.99), 3),
+           "max_ms": round(max(lat), 3)}
+    if baseline:
+        run_one_call_trace(warm_reqs[:16], 0.0)
+        lat1, span1 = run_one_call_trace(reqs, scale)
+        out["one_call_per_instance"] = {"gcds_per_s": round(len(reqs) / span1, 1),
+                                        "p50_ms": round(_pct(lat1, 0.50), 3),
+                                        "p99_ms": round(_pct(lat1, 0.99), 3)}
+        out["throughput_ratio"] = round(out["gcds_per_s"] / out["one_call_per_instance"]["gcds_per_s"], 2)
+        out["p99_ratio_one_call_over_served"] = round(out["one_call_per_instance"]["p99_ms"] / out["p99_ms"], 2)
+    torch.cuda.synchronize()
+    return out
+
+
 def bench_gcd(reps: int) -> dict:
     import numpy as np
     import torch
@@ -203,6 +314,9 @@ def main() -> int:
     ap.add_argument("--no-gcd", action="store_true")
     ap.add_argument("--gcd-reps", type=int, default=5)
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--served-requests", type=int, default=2048)
+    ap.add_argument("--no-served-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -277,6 +391,8 @@ def main() -> int:
         out["batched_4096"] = bench_batched(10)
     if not args.no_gcd:
         out["gcd_32768"] = bench_gcd(args.gcd_reps)
+    if not args.no_served:
+        out["served"] = bench_served(args.served_requests, 128, 0.8, not args.no_served_baseline)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(a_np, b_np, p, args.cpu_seconds)
     print(json.dumps(out), flush=True)

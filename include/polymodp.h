@@ -163,6 +163,61 @@ typedef struct {
 } pm_gcd_result;
 pm_status poly_gcd_modp_batch(const pm_gcd_item *items, int32_t count, pm_gcd_result *results, void *stream);
 
+/*
+ * GCD server with continuous batching. Requests of mixed degree (up to
+ * PM_GCD_BATCH_MAX terms) and prime are queued by pm_server_submit (inputs
+ * are copied; the caller may reuse its arrays at once). pm_server_poll
+ * returns the requests that finished since the last poll and admits queued
+ * requests in arrival order while a slot (max_inflight) and room in the
+ * resident-input budget (arena_words) are free; admitted requests are
+ * published to the GPU at once, their inputs staged in pinned memory mapped
+ * into the device's address space.
+ * A persistent worker kernel (one block per CU) runs the published
+ * requests one block each, taking the next one as soon as it finishes, so
+ * requests join and leave the GPU individually. Each request's remainder
+ * sequence stays in its block's LDS until its monic gcd is written to the
+ * caller's host buffer g (done by the time the completion is returned).
+ * The worker stops by itself after an idle period and is relaunched when
+ * work arrives; pm_server_destroy stops it and waits for it.
+ * Not thread-safe: one host thread drives a server. Times are milliseconds
+ * on the server's steady clock.
+ */
+typedef struct pm_server pm_server;
+typedef struct {
+    int32_t max_inflight;  /* requests admitted at once (0 = 1024)             */
+    int32_t streams;       /* unused, 0                                        */
+    int64_t arena_words;   /* budget of resident input words (0 = 32 Mi)       */
+    int32_t s;             /* Euclidean steps fused per chunk (0 = 64)         */
+    int32_t reserved;
+} pm_server_opts;
+typedef struct {
+    const uint32_t *a;     /* host arrays */
+    int64_t na;
+    const uint32_t *b;
+    int64_t nb;
+    uint32_t p;
+    uint32_t *g;           /* host output, g_cap words */
+    int64_t g_cap;
+    uint64_t tag;          /* returned in the completion */
+} pm_gcd_request;
+typedef struct {
+    uint64_t ticket;
+    uint64_t tag;
+    int32_t status;
+    int32_t reserved;
+    int64_t ng;
+    int64_t steps;
+    int64_t updates;
+    double t_submit_ms;    /* pm_server_submit                          */
+    double t_start_ms;     /* admitted and launched                     */
+    double t_done_ms;      /* seen finished by pm_server_poll           */
+} pm_completion;
+pm_status pm_server_create(const pm_server_opts *opts, pm_server **out);
+pm_status pm_server_submit(pm_server *srv, const pm_gcd_request *req, uint64_t *ticket);
+pm_status pm_server_poll(pm_server *srv, pm_completion *out, int32_t max, int32_t *n);
+int64_t pm_server_pending(pm_server *srv);   /* queued + on the device */
+void pm_server_destroy(pm_server *srv);
+
 /* Statistics of the last poly_gcd_modp call on this thread. */
 typedef struct {
     int64_t steps;    /* Euclidean division steps                        */

@@ -54,6 +54,24 @@ class MulItem(ctypes.Structure):
                 ("p", ctypes.c_uint32), ("f", ctypes.c_void_p), ("f_cap", ctypes.c_int64)]
 
 
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("max_inflight", ctypes.c_int32), ("streams", ctypes.c_int32), ("arena_words", ctypes.c_int64),
+                ("s", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class GcdRequest(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_void_p), ("na", ctypes.c_int64), ("b", ctypes.c_void_p), ("nb", ctypes.c_int64),
+                ("p", ctypes.c_uint32), ("g", ctypes.c_void_p), ("g_cap", ctypes.c_int64),
+                ("tag", ctypes.c_uint64)]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_uint64), ("tag", ctypes.c_uint64), ("status", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("ng", ctypes.c_int64), ("steps", ctypes.c_int64),
+                ("updates", ctypes.c_int64), ("t_submit_ms", ctypes.c_double), ("t_start_ms", ctypes.c_double),
+                ("t_done_ms", ctypes.c_double)]
+
+
 class GcdStats(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int64), ("updates", ctypes.c_int64), ("chunks", ctypes.c_int64)]
 
@@ -92,6 +110,17 @@ def lib() -> ctypes.CDLL:
     L.pm_mul_batch_destroy.restype = None
     L.poly_mul_modp_batch.argtypes = [ctypes.POINTER(MulItem), ctypes.c_int32, _vp, _vp]
     L.poly_mul_modp_batch.restype = ctypes.c_int32
+    L.pm_server_create.argtypes = [ctypes.POINTER(ServerOpts), ctypes.POINTER(ctypes.c_void_p)]
+    L.pm_server_create.restype = ctypes.c_int32
+    L.pm_server_submit.argtypes = [ctypes.c_void_p, ctypes.POINTER(GcdRequest), ctypes.POINTER(ctypes.c_uint64)]
+    L.pm_server_submit.restype = ctypes.c_int32
+    L.pm_server_poll.argtypes = [ctypes.c_void_p, ctypes.POINTER(Completion), ctypes.c_int32,
+                                 ctypes.POINTER(ctypes.c_int32)]
+    L.pm_server_poll.restype = ctypes.c_int32
+    L.pm_server_pending.argtypes = [ctypes.c_void_p]
+    L.pm_server_pending.restype = ctypes.c_int64
+    L.pm_server_destroy.argtypes = [ctypes.c_void_p]
+    L.pm_server_destroy.restype = None
     L.pm_last_gcd_stats.argtypes = [ctypes.POINTER(GcdStats)]
     L.pm_last_gcd_stats.restype = None
     L.pm_set_params.argtypes = [ctypes.POINTER(Params)]
@@ -292,6 +321,69 @@ def gcd_batch(pairs, stream=None):
         ret.append((outs[i][:r.ng], {"status": r.status, "ng": r.ng, "steps": r.steps, "updates": r.updates,
                                      "chunks": r.chunks}))
     return ret
+
+
+class Server:
+    """Continuous-batching gcd server (pm_server_*). Inputs and outputs are
+    host numpy arrays; ``submit`` returns a ticket, ``poll`` returns the
+    finished requests as dicts with the monic gcd ``g``."""
+
+    def __init__(self, max_inflight: int = 0, streams: int = 0, arena_words: int = 0, s: int = 0):
+        self.handle = ctypes.c_void_p()
+        _check(lib().pm_server_create(ctypes.byref(ServerOpts(max_inflight, streams, arena_words, s, 0)),
+                                      ctypes.byref(self.handle)))
+        self._out = {}
+        self._buf = (Completion * 512)()
+
+    def submit(self, a, b, p: int, tag: int = 0) -> int:
+        import numpy as np
+        a = np.ascontiguousarray(np.asarray(a, dtype=np.uint32))
+        b = np.ascontiguousarray(np.asarray(b, dtype=np.uint32))
+        g = np.zeros(max(a.size, b.size, 1), dtype=np.uint32)
+        req = GcdRequest(a.ctypes.data if a.size else None, a.size, b.ctypes.data if b.size else None, b.size, p,
+                         g.ctypes.data, g.size, tag)
+        t = ctypes.c_uint64(0)
+        _check(lib().pm_server_submit(self.handle, ctypes.byref(req), ctypes.byref(t)))
+        self._out[t.value] = g
+        return t.value
+
+    def poll(self) -> list:
+        n = ctypes.c_int32(0)
+        _check(lib().pm_server_poll(self.handle, self._buf, len(self._buf), ctypes.byref(n)))
+        done = []
+        for i in range(n.value):
+            c = self._buf[i]
+            g = self._out.pop(c.ticket)
+            done.append({"ticket": c.ticket, "tag": c.tag, "status": c.status, "g": g[:c.ng].copy(),
+                         "steps": c.steps, "updates": c.updates, "t_submit_ms": c.t_submit_ms,
+                         "t_start_ms": c.t_start_ms, "t_done_ms": c.t_done_ms})
+        return done
+
+    def pending(self) -> int:
+        return int(lib().pm_server_pending(self.handle))
+
+    def drain(self, timeout_s: float = 300.0) -> list:
+        """Poll until every submitted request has finished (raises
+        TimeoutError after timeout_s)."""
+        import time
+        out = []
+        t_end = time.monotonic() + timeout_s
+        while self.pending():
+            out += self.poll()
+            if time.monotonic() > t_end:
+                raise TimeoutError("server did not finish its requests in %.0f s" % timeout_s)
+        return out
+
+    def close(self):
+        if self.handle:
+            lib().pm_server_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def last_gcd_stats() -> dict:

@@ -262,6 +262,10 @@ hipEvent_t take_event() {
 
 namespace pm {
 
+pm_status server_field(uint32_t p, Field* out) { return field_for(p, out); }
+pm_status server_fail(pm_status st, const char* msg) { return fail(st, "%s", msg); }
+int server_num_cus() { return num_cus(); }
+
 TimingScope::TimingScope(const char* kernel, hipStream_t stream) : kernel_(kernel), stream_(stream) {
     if (!g_timing_on.load(std::memory_order_relaxed)) return;
     start_ = take_event();
@@ -551,7 +555,7 @@ pm_status poly_gcd_modp_batch(const pm_gcd_item* items, int32_t count, pm_gcd_re
         pm_status st = field_for(it.p, &F);
         if (st) return st;
         if (!redc_ok(it.p)) return fail(PM_EMODULUS, "item %d: p = 2 is not supported by the gcd", i);
-        jobs[i] = pm::GcdJob{it.a, it.b, it.na, it.nb, it.g, it.g_cap, nullptr, F};
+        jobs[i] = pm::GcdJob{it.a, it.b, it.na, it.nb, it.g, it.g_cap, nullptr, F, 0, 0};
         (n <= pm::gcd_batch_cap(0) ? small : large).push_back(i);
     }
     // scratch: jobs | order | results

@@ -235,15 +235,11 @@ __global__ __launch_bounds__(GCD_THREADS) void gcd_multi_kernel(GcdArgs G) {
 // positions below 0 read as zero.
 constexpr int PADLO = 64;
 
+// One whole instance on the calling block (all NT threads).
 template <int NT, int PPT, int E>
-__global__ __launch_bounds__(NT) void gcd_batch_kernel(const GcdJob* jobs, const int32_t* order, int njobs,
-                                                       int s, int64_t cap) {
-    extern __shared__ uint32_t smem[];
+__device__ void gcd_instance(const GcdJob& J, int s, int64_t cap, uint32_t* smem) {
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    if ((int)blockIdx.x >= njobs) return;
-    const int jid = order ? order[blockIdx.x] : (int)blockIdx.x;
-    const GcdJob J = jobs[jid];
     const Field F = J.F;
     uint32_t* A = smem + PADLO;                 // cap words (+PADLO zeros below)
     uint32_t* B = A + cap + PADLO;
@@ -256,18 +252,30 @@ __global__ __launch_bounds__(NT) void gcd_batch_kernel(const GcdJob* jobs, const
     const int64_t n = J.na > J.nb ? J.na : J.nb;
     int bad = n > cap;
     if (tid < PADLO) { A[tid - PADLO] = 0u; B[tid - PADLO] = 0u; }
-    for (int64_t i = tid; i < cap; i += NT) {
-        uint32_t x = i < J.na ? J.a[i] : 0u;
-        uint32_t y = i < J.nb ? J.b[i] : 0u;
-        bad |= (x >= F.p) | (y >= F.p);
-        A[i] = x;
-        B[i] = y;
+    if (J.fresh) {
+        for (int64_t i = tid; i < cap; i += NT) {
+            uint32_t x = i < J.na ? __hip_atomic_load(J.a + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) : 0u;
+            uint32_t y = i < J.nb ? __hip_atomic_load(J.b + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) : 0u;
+            bad |= (x >= F.p) | (y >= F.p);
+            A[i] = x;
+            B[i] = y;
+        }
+    } else {
+        for (int64_t i = tid; i < cap; i += NT) {
+            uint32_t x = i < J.na ? J.a[i] : 0u;
+            uint32_t y = i < J.nb ? J.b[i] : 0u;
+            bad |= (x >= F.p) | (y >= F.p);
+            A[i] = x;
+            B[i] = y;
+        }
     }
     bad = __syncthreads_or(bad);
     if (bad) {
         if (tid == 0) {
             J.out->status = n > cap ? -1 : -3;
             J.out->ng = 0;
+            __threadfence_system();
+            __hip_atomic_store(&J.out->done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
         }
         return;
     }
@@ -360,6 +368,10 @@ __global__ __launch_bounds__(NT) void gcd_batch_kernel(const GcdJob* jobs, const
         const uint32_t inv = invmod(R[dR], F);
         for (int64_t P = tid; P <= dR; P += NT) J.g[P] = mulmod(R[P], inv, F);
     }
+    // g may live in host memory (the server's completion buffers): every
+    // thread's stores are made visible before `done` is raised
+    __threadfence_system();
+    __syncthreads();
     if (tid == 0) {
         J.out->status = status;
         J.out->ng = status == 0 ? dR + 1 : 0;
@@ -368,6 +380,66 @@ __global__ __launch_bounds__(NT) void gcd_batch_kernel(const GcdJob* jobs, const
         J.out->chunks = chunks;
         __threadfence_system();
         __hip_atomic_store(&J.out->done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
+template <int NT, int PPT, int E>
+__global__ __launch_bounds__(NT) void gcd_batch_kernel(const GcdJob* jobs, const int32_t* order, int njobs,
+                                                       int s, int64_t cap) {
+    extern __shared__ uint32_t smem[];
+    if ((int)blockIdx.x >= njobs) return;
+    const int jid = order ? order[blockIdx.x] : (int)blockIdx.x;
+    const GcdJob J = jobs[jid];
+    gcd_instance<NT, PPT, E>(J, s, cap, smem);
+}
+
+// Persistent worker for the server: each block claims the next published
+// job (head < tail) and runs it, until `stop` is raised with nothing left,
+// or nothing was published for `idle_ticks` of the constant-rate wall clock
+// (the host relaunches the worker when new work arrives after that).
+template <int NT, int PPT, int E>
+__global__ __launch_bounds__(NT) void gcd_worker_kernel(const GcdJob* jobs, const uint32_t* order, uint32_t order_cap,
+                                                        const uint32_t* tail, const uint32_t* stop, uint32_t* head,
+                                                        int s, int64_t cap, uint64_t idle_ticks) {
+    extern __shared__ uint32_t smem[];
+    __shared__ int64_t s_job;
+    __shared__ GcdJob s_J;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            int64_t got = -1;
+            uint64_t idle_from = wall_clock64();
+            for (;;) {
+                const uint32_t t = __hip_atomic_load(tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+                uint32_t h = __hip_atomic_load(head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (h < t) {
+                    if (atomicCAS(head, h, h + 1) == h) { got = h; break; }
+                    continue;
+                }
+                if (__hip_atomic_load(stop, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM)) break;
+                if (wall_clock64() - idle_from > idle_ticks) break;
+                __builtin_amdgcn_s_sleep(64);
+            }
+            s_job = got;
+        }
+        __syncthreads();
+        const int64_t job = s_job;
+        __syncthreads();
+        if (job < 0) break;
+        // the order ring and the job table live in host memory written by
+        // the host after this kernel started: one thread reads them past
+        // the caches and shares them
+        if (threadIdx.x == 0) {
+            const uint32_t slot =
+                __hip_atomic_load(order + (job & (order_cap - 1)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            const uint64_t* src = (const uint64_t*)(jobs + slot);
+            uint64_t* dst = (uint64_t*)&s_J;
+            for (int w = 0; w < (int)(sizeof(GcdJob) / 8); w++)
+                dst[w] = __hip_atomic_load(src + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+        __syncthreads();
+        const GcdJob J = s_J;
+        gcd_instance<NT, PPT, E>(J, s, cap, smem);
+        __syncthreads();
     }
 }
 
@@ -425,6 +497,24 @@ hipError_t gcd_launch(const uint32_t* a, int64_t na, const uint32_t* b, int64_t 
 }
 
 int64_t gcd_batch_cap(int kind) { return kind == 0 ? 256 * 16 : 1024 * 17; }
+
+hipError_t gcd_worker_launch(const GcdJob* jobs, const uint32_t* order, uint32_t order_cap, const uint32_t* tail,
+                             const uint32_t* stop, uint32_t* head, int s, int blocks, double idle_seconds,
+                             hipStream_t stream) {
+    const int64_t cap = gcd_batch_cap(1);
+    int dev = 0, khz = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0) khz = 100000;
+    const uint64_t ticks = (uint64_t)(idle_seconds * 1e3 * khz);
+    size_t lds = s > 96 ? batch_lds_bytes<1024, 17, 4>(cap) : batch_lds_bytes<1024, 17, 2>(cap);
+    if (s > 96)
+        hipLaunchKernelGGL((gcd_worker_kernel<1024, 17, 4>), dim3(blocks), dim3(1024), lds, stream, jobs, order,
+                           order_cap, tail, stop, head, s, cap, ticks);
+    else
+        hipLaunchKernelGGL((gcd_worker_kernel<1024, 17, 2>), dim3(blocks), dim3(1024), lds, stream, jobs, order,
+                           order_cap, tail, stop, head, s, cap, ticks);
+    return hipGetLastError();
+}
 
 hipError_t gcd_batch_launch(const GcdJob* d_jobs, const int32_t* d_order, int njobs, int kind, int s,
                             hipStream_t stream) {

@@ -128,6 +128,10 @@ struct GcdJob {
     int64_t g_cap;
     GcdResult* out;
     Field F;
+    // 1 when a and b were written by another agent (a copy engine) after
+    // the running kernel started: they are then read past the caches
+    int32_t fresh;
+    int32_t pad;
 };
 
 // Capacity (max(na, nb)) of the two batched kernel shapes: kind 0 = 256
@@ -138,6 +142,14 @@ int64_t gcd_batch_cap(int kind);
 // capacity of `kind`.
 hipError_t gcd_batch_launch(const GcdJob* d_jobs, const int32_t* d_order, int njobs, int kind, int s,
                             hipStream_t stream);
+// Persistent worker (1024 threads, capacity gcd_batch_cap(1)): blocks claim
+// sequence numbers h < *tail from *head and run jobs[order[h % order_cap]]
+// (order_cap a power of two). tail, stop, order and jobs live in pinned host
+// memory written by the host; head in device memory, zero at first. Exits
+// when stop is raised with nothing left, or after idle_seconds without work.
+hipError_t gcd_worker_launch(const GcdJob* jobs, const uint32_t* order, uint32_t order_cap, const uint32_t* tail,
+                             const uint32_t* stop, uint32_t* head, int s, int blocks, double idle_seconds,
+                             hipStream_t stream);
 constexpr int GCD_THREADS = 256;
 GcdPlan gcd_default_plan(int64_t n, int num_cus, int s);
 int64_t gcd_scratch_words(int64_t n, const GcdPlan& plan);

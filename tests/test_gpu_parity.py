@@ -386,3 +386,65 @@ def test_mul_s1_plan_beyond_one_launch_of_blocks():
         pm.set_params()
     assert torch.equal(f1, f2)
     pm.release()  # drop the 2 GiB partial-sum pool
+
+
+# ------------------------------------------------------------------ server
+def _served_requests(count, seed, lo=8, hi=6000):
+    st = gen.Stream(seed)
+    reqs = []
+    for _ in range(count):
+        p = gen.PRIMES[st.index(3)]
+        D = st.log_uniform_int(lo, hi)
+        k = st.uniform_int(0, D // 4)
+        pl = gen.planted_gcd(D, D - 1, k, p, st)
+        reqs.append((oracle.mul(pl.g, pl.u, p), oracle.mul(pl.g, pl.v, p), p))
+    return reqs
+
+
+def test_server_results_same_alone_and_in_the_mix():
+    reqs = _served_requests(48, 501) + _served_requests(3, 502, lo=5000, hi=16000)
+    want = [oracle.gcd(a, b, p) for a, b, p in reqs]
+    srv = pm.Server()
+    tickets = {}
+    done = {}
+    # submit in three waves while polling, so later requests join a GPU
+    # that is already working on earlier ones
+    for w in range(3):
+        for i in range(w, len(reqs), 3):
+            a, b, p = reqs[i]
+            tickets[srv.submit(a, b, p, tag=i)] = i
+        for c in srv.poll():
+            done[c["tag"]] = c
+    for c in srv.drain():
+        done[c["tag"]] = c
+    assert len(done) == len(reqs)
+    for i, w in enumerate(want):
+        assert done[i]["status"] == 0 and same(done[i]["g"], w), i
+    srv.close()
+    # alone: a fresh server, one request at a time
+    for i in [0, 7, len(reqs) - 1]:
+        solo = pm.Server()
+        solo.submit(*reqs[i], tag=i)
+        c = solo.drain()[0]
+        assert same(c["g"], done[i]["g"]) and c["steps"] == done[i]["steps"]
+        solo.close()
+
+
+def test_server_admission_waits_for_memory_and_slots():
+    reqs = _served_requests(20, 503, lo=500, hi=3000)
+    srv = pm.Server(max_inflight=3, arena_words=8192)  # at most a few resident at once
+    for i, (a, b, p) in enumerate(reqs):
+        srv.submit(a, b, p, tag=i)
+    out = srv.drain()
+    assert sorted(c["tag"] for c in out) == list(range(20))
+    for c in out:
+        a, b, p = reqs[c["tag"]]
+        assert c["status"] == 0 and same(c["g"], oracle.gcd(a, b, p))
+    big = np.ones(9000, dtype=np.uint32)
+    with pytest.raises(pm.PolyModPError) as e:
+        srv.submit(big, big, gen.P_A)
+    assert e.value.status == pm.PM_ENOMEM
+    with pytest.raises(pm.PolyModPError) as e:
+        srv.submit(big[:5], big[:3], 91)
+    assert e.value.status == pm.PM_EMODULUS
+    srv.close()
