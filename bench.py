@@ -318,6 +318,8 @@ def main() -> int:
     ap.add_argument("--served-requests", type=int, default=2048)
     ap.add_argument("--no-served-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--mul-r", type=int, default=0, help="force the product's outputs per thread (skips tuning)")
+    ap.add_argument("--mul-s", type=int, default=0, help="force the product's b-chunk s (skips tuning)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -339,7 +341,9 @@ def main() -> int:
     d_st = torch.zeros(1, dtype=torch.int32, device="cuda")
 
     tuned = None
-    if not args.no_tune:
+    if args.mul_r or args.mul_s:
+        pm.set_params(mul_r=args.mul_r, mul_s=args.mul_s)
+    elif not args.no_tune:
         from paper_1402_0264_amd import tune
         tuned = tune.tune_mul(a, b, p)
         pm.set_params(mul_r=tuned["r"], mul_s=tuned["kc"])
