@@ -322,8 +322,8 @@ def main() -> int:
     ap.add_argument("--mul-s", type=int, default=0, help="force the product's b-chunk s (skips tuning)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see the sharding paragraph of DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path; "
+              "run with --gpus 1", file=sys.stderr)
         return 2
 
     import torch
