@@ -11,10 +11,13 @@ product (all kernels of the call), timed with events on the launch stream
 over K steps after W warm-up steps.
 
 Beside it, in the same line:
-  roofline      the dominant kernel (mul_tile_kernel): algorithmic
-                multiply-adds per launch over its average duration (HIP
-                events around each launch on its stream, same timed steps),
-                against the VALU multiply-add peak of the chip;
+  roofline      the dominant kernel of the engine that ran (matrix cores:
+                mulx_kernel, 16 int8 digit products per coefficient product,
+                against the dense int8 MFMA peak; VALU tiles: mul_tile_kernel,
+                one 32x32->64-bit multiply-add per coefficient product,
+                against the VALU multiply-add peak): algorithmic operations
+                per launch over its average duration (HIP events around each
+                launch on its stream, same timed steps);
   cpu_baseline  the CPU oracle timed on this host on a bounded sample of the
                 same product (single thread);
   batched_4096  4096 independent products (degrees log-uniform in [32, 8192])
@@ -46,28 +49,44 @@ METRIC = "mulmods/s in plain poly multiply; batched GCDs/s + p99 vs one-call-per
 # VALU peak for one exact 32x32->64-bit multiply-add per lane per clock
 # (v_mad_u64_u32 issues at the full rate on gfx950): 256 CUs x 64 lanes x 2.4 GHz.
 PEAK_MULMOD_PER_S = 256 * 64 * 2.4e9
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_product_65536.json")
+# Published dense int8 matrix-core peak of MI355X (operations: 2 per multiply-add).
+PEAK_INT8_OPS_PER_S = 5.0e15
+# int8 digit products per coefficient product on the matrix cores (4 x 4 digits)
+DIGIT_PRODUCTS = 16
+KERNEL_SOURCES = {"mulx_kernel": ("mul_mfma.hip", "common.hpp", "internal.hpp"),
+                  "mul_tile_kernel": ("mul.hip", "common.hpp", "internal.hpp")}
 
 
-def source_digest() -> str:
+def traffic_file(kernel: str) -> str:
+    return os.path.join(ROOT, "profiles", "traffic_%s_product_65536.json" % kernel)
+
+
+def source_digest(kernel: str) -> str:
     h = hashlib.sha256()
-    for f in ("mul.hip", "common.hpp"):
+    for f in KERNEL_SOURCES[kernel]:
         with open(os.path.join(ROOT, "paper_1402_0264_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def traffic_for(launch_bytes_alg: float):
-    """HBM bytes per launch of mul_tile_kernel from the committed counter
-    summary, or None when the kernel source changed since it was taken."""
+def traffic_for(kernel: str):
+    """HBM bytes per launch of the kernel from the committed counter
+    summary, or None when its source changed since the counters were taken."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(traffic_file(kernel)) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
-    if rec.get("source_digest") != source_digest():
+    if rec.get("kernel") != kernel or rec.get("source_digest") != source_digest(kernel):
         return None
     return rec.get("bytes_per_launch")
+
+
+def tune_summary(rec: dict) -> dict:
+    out = {"engine": rec["engine"], "ms": rec["ms"], "cached": rec.get("cached", False)}
+    if rec["engine"] == "valu":
+        out.update({"r": rec["r"], "s": rec["kc"]})
+    return out
 
 
 def time_steps(fn, steps: int, warmup: int):
@@ -320,6 +339,8 @@ def main() -> int:
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--mul-r", type=int, default=0, help="force the product's outputs per thread (skips tuning)")
     ap.add_argument("--mul-s", type=int, default=0, help="force the product's b-chunk s (skips tuning)")
+    ap.add_argument("--engine", choices=("auto", "mfma", "valu"), default="auto",
+                    help="product engine (auto: the autotuner's pick)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path; "
@@ -341,12 +362,18 @@ def main() -> int:
     d_st = torch.zeros(1, dtype=torch.int32, device="cuda")
 
     tuned = None
-    if args.mul_r or args.mul_s:
-        pm.set_params(mul_r=args.mul_r, mul_s=args.mul_s)
+    if args.engine == "valu" or args.mul_r or args.mul_s:
+        pm.set_params(mul_r=args.mul_r, mul_s=args.mul_s, mul_engine=pm.MUL_VALU)
+    elif args.engine == "mfma":
+        pm.set_params(mul_engine=pm.MUL_MFMA)
     elif not args.no_tune:
         from paper_1402_0264_amd import tune
         tuned = tune.tune_mul(a, b, p)
-        pm.set_params(mul_r=tuned["r"], mul_s=tuned["kc"])
+        pm.set_params(**tune.params_of(tuned))
+    mfma = pm.get_params()["mul_engine"] == pm.MUL_MFMA or (
+        pm.get_params()["mul_engine"] == pm.MUL_AUTO and not (pm.get_params()["mul_r"] or pm.get_params()["mul_s"]))
+    kernel = "mulx_kernel" if mfma else "mul_tile_kernel"
+    reduce_kernel = "mulx_reduce_kernel" if mfma else "mul_reduce_kernel"
 
     def step():
         pm.mul_async(a, b, p, f, d_nf, d_st)
@@ -358,8 +385,9 @@ def main() -> int:
     pm.timing_enable(True)
     ms = time_steps(step, args.steps, 0)
     pm.timing_enable(False)
-    n_tile, ms_tile = pm.timing_read("mul_tile_kernel")
-    n_red, ms_red = pm.timing_read("mul_reduce_kernel")
+    n_tile, ms_tile = pm.timing_read(kernel)
+    n_red, ms_red = pm.timing_read(reduce_kernel)
+    assert n_tile == args.steps, "the product did not run %s once per step" % kernel
     pm.timing_reset()
     assert int(d_st.item()) == 0 and int(d_nf.item()) == nf, "product failed its device checks"
     work = float(a_np.size) * float(b_np.size)
@@ -367,6 +395,18 @@ def main() -> int:
     value = work / (ms_per_step * 1e-3)
     tile_avg_ms = ms_tile / max(n_tile, 1)
     achieved = work / (tile_avg_ms * 1e-3)
+    if mfma:
+        ops = 2.0 * DIGIT_PRODUCTS * work
+        roof = {"bound": "mfma", "achieved": round(ops / (tile_avg_ms * 1e-3) / 1e12, 1),
+                "peak": round(PEAK_INT8_OPS_PER_S / 1e12, 1), "unit": "TOP/s",
+                "frac": round(ops / (tile_avg_ms * 1e-3) / PEAK_INT8_OPS_PER_S, 4)}
+    else:
+        roof = {"bound": "alu", "achieved": round(achieved / 1e12, 3),
+                "peak": round(PEAK_MULMOD_PER_S / 1e12, 3), "unit": "Tmulmod/s",
+                "frac": round(achieved / PEAK_MULMOD_PER_S, 4)}
+    roof.update({"traffic": traffic_for(kernel), "kernel": kernel, "kernel_avg_ms": round(tile_avg_ms, 5),
+                 "kernel_Tmulmod_per_s": round(achieved / 1e12, 2), "launches": n_tile,
+                 "reduce_avg_ms": round(ms_red / max(n_red, 1), 5)})
     out = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -381,14 +421,10 @@ def main() -> int:
         "dtype": "u32",
         "data": "synthetic (seeded uniform residues)",
         "config": {"workload": "product_65536: deg 65535 x deg 65535 over p=469762049",
-                   "params": pm.get_params(), "tuned": tuned and {"r": tuned["r"], "s": tuned["kc"]},
+                   "engine": "matrix cores (int8 digits)" if mfma else "VALU tiles",
+                   "params": pm.get_params(), "tuned": tuned and tune_summary(tuned),
                    "parallelism": "single GPU"},
-        "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 3),
-                     "peak": round(PEAK_MULMOD_PER_S / 1e12, 3), "unit": "Tmulmod/s",
-                     "frac": round(achieved / PEAK_MULMOD_PER_S, 4),
-                     "traffic": traffic_for(work),
-                     "kernel": "mul_tile_kernel", "kernel_avg_ms": round(tile_avg_ms, 5),
-                     "launches": n_tile, "reduce_avg_ms": round(ms_red / max(n_red, 1), 5)},
+        "roofline": roof,
     }
     pm.set_params()
     if not args.no_batched:

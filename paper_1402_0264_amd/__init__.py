@@ -33,7 +33,7 @@ class PolyModPError(RuntimeError):
 
 class Params(ctypes.Structure):
     _fields_ = [("mul_s", ctypes.c_int32), ("mul_r", ctypes.c_int32),
-                ("div_s", ctypes.c_int32), ("gcd_s", ctypes.c_int32)]
+                ("div_s", ctypes.c_int32), ("gcd_s", ctypes.c_int32), ("mul_engine", ctypes.c_int32)]
 
 
 class GcdItem(ctypes.Structure):
@@ -392,14 +392,18 @@ def last_gcd_stats() -> dict:
     return {"steps": st.steps, "updates": st.updates, "chunks": st.chunks}
 
 
-def set_params(mul_s: int = 0, mul_r: int = 0, div_s: int = 0, gcd_s: int = 0):
-    _check(lib().pm_set_params(ctypes.byref(Params(mul_s, mul_r, div_s, gcd_s))))
+MUL_AUTO, MUL_VALU, MUL_MFMA = 0, 1, 2
+
+
+def set_params(mul_s: int = 0, mul_r: int = 0, div_s: int = 0, gcd_s: int = 0, mul_engine: int = MUL_AUTO):
+    _check(lib().pm_set_params(ctypes.byref(Params(mul_s, mul_r, div_s, gcd_s, mul_engine))))
 
 
 def get_params() -> dict:
     pp = Params()
     lib().pm_get_params(ctypes.byref(pp))
-    return {"mul_s": pp.mul_s, "mul_r": pp.mul_r, "div_s": pp.div_s, "gcd_s": pp.gcd_s}
+    return {"mul_s": pp.mul_s, "mul_r": pp.mul_r, "div_s": pp.div_s, "gcd_s": pp.gcd_s,
+            "mul_engine": pp.mul_engine}
 
 
 def timing_enable(on: bool = True):

@@ -125,7 +125,7 @@ bool redc_ok(uint32_t p) { return (p & 1) != 0; }
 
 // ------------------------------------------------------------ parameters
 std::mutex g_param_mu;
-pm_params g_params = {0, 0, 0, 0};
+pm_params g_params = {0, 0, 0, 0, 0};
 
 pm_params params_now() {
     std::lock_guard<std::mutex> lk(g_param_mu);
@@ -220,9 +220,30 @@ void order_operands(const uint32_t*& a, int64_t& na, const uint32_t*& b, int64_t
     }
 }
 
+// The matrix-core product for large operands: it needs both operands
+// non-empty; below a few million coefficient products its fixed costs
+// (staging, the addition phase) outweigh the VALU tiles.
+bool use_mfma(int64_t na, int64_t nb) {
+    if (na <= 0 || nb <= 0) return false;
+    const pm_params pp = params_now();
+    if (pp.mul_engine == 1) return false;
+    if (pp.mul_engine == 2) return true;
+    if (pp.mul_s > 0 || pp.mul_r > 0) return false;
+    const int64_t lo = na < nb ? na : nb;
+    return lo >= 256 && (double)na * (double)nb >= 4194304.0;
+}
+
 pm_status mul_enqueue(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, const pm::Field& F,
                       uint32_t* f, int64_t* d_nf, int32_t* d_status, hipStream_t stream) {
     order_operands(a, na, b, nb);
+    if (use_mfma(na, nb)) {
+        const pm::MxGeom g = pm::mx_geometry(na, nb, num_cus());
+        Pool* P = nullptr;
+        pm_status st = pool_get(stream, pm::mulx_scratch_words(g), &P);
+        if (st) return st;
+        HIP_TRY(pm::mulx_launch(a, na, b, nb, F, f, g, P->words, d_nf, d_status, stream), "mul launch");
+        return PM_OK;
+    }
     pm::MulPlan plan = mul_plan(na, nb);
     int64_t words = pm::mul_scratch_words(na, nb, plan);
     Pool* P = nullptr;
@@ -330,6 +351,7 @@ pm_status pm_set_params(const pm_params* params) {
     if (q.mul_s < 0 || q.mul_s > 16384) return fail(PM_EINVAL, "mul_s must be in [0, 16384]");
     if (q.div_s < 0 || q.div_s > 64) return fail(PM_EINVAL, "div_s must be in [0, 64]");
     if (q.gcd_s < 0 || q.gcd_s > 256) return fail(PM_EINVAL, "gcd_s must be in [0, 256]");
+    if (q.mul_engine < 0 || q.mul_engine > 2) return fail(PM_EINVAL, "mul_engine must be 0, 1 or 2");
     std::lock_guard<std::mutex> lk(g_param_mu);
     g_params = q;
     return PM_OK;

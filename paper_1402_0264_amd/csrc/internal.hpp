@@ -81,6 +81,26 @@ hipError_t mul_batch_launch(const MulItem* d_items, const MulTask* d_tasks, int 
                             uint32_t fold_min, uint32_t* d_counters, int num_cus, hipStream_t stream);
 hipError_t mul_batch_check_launch(const MulItem* d_items, int count, int32_t* d_status, hipStream_t stream);
 
+// Product on the matrix cores (mul_mfma.hip): int8 digit products of the
+// Toeplitz form of the schoolbook product, split stream-K over equal shares
+// of (output range, b block offset) iterations. mx_geometry plans one
+// product; the scratch holds the partial sums of every share.
+struct MxGeom {
+    int64_t na, nb;   // a: the plain side, b: the Toeplitz side
+    int64_t nab;      // 64-coefficient blocks of a, rounded so that offset ranges start on groups of 8
+    int64_t nJ;       // block offsets of b, rounded up to a multiple of 8
+    int64_t nkr;      // output ranges of 2048
+    int64_t itot;     // (range, group of 8 offsets) iterations
+    int64_t G;        // work-groups (one share each)
+    int64_t maxseg;   // most ranges one share touches
+};
+MxGeom mx_geometry(int64_t na, int64_t nb, int num_cus);
+int64_t mulx_scratch_words(const MxGeom& g);
+// f = a*b for na, nb >= 1 and p < 2^30; out_len/out_status as mul_launch.
+hipError_t mulx_launch(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, const Field& F, uint32_t* f,
+                       const MxGeom& g, uint32_t* scratch, int64_t* out_len, int32_t* out_status,
+                       hipStream_t stream);
+
 // ----------------------------------------------------------------- division
 // Euclidean division (Sec. 3) runs in two launches around one host read of
 // the degrees: divrem_head_launch validates the inputs, finds deg a and

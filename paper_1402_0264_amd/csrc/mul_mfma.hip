@@ -1,0 +1,500 @@
+// mul_mfma.hip -- the plain (schoolbook) product of Sec. 5 on the CDNA4
+// matrix cores.
+//
+// The product f_k = sum_i a_i b_{k-i} is a dense contraction: cut a and the
+// outputs into blocks of 64 positions; then output block K is
+//
+//     f[64K + u] = sum_J sum_v  b[64J + u - v] * a[64(K-J) + v],
+//
+// i.e. for each block offset J a 64x64 Toeplitz matrix of b times the column
+// K-J of the 64 x (n_a/64) matrix of a-blocks. Every coefficient product of
+// the schoolbook method appears exactly once, and nothing else.
+//
+// Exactness on int8 matrix cores. Each residue x < 2^30 is written in signed
+// base-256 digits, x = sum_e d_e 256^e with d_0..d_2 in [-128, 127] and
+// d_3 in [0, 64]; the digits come from two integer operations,
+// (x + 0x808080) ^ 0x808080 read as four signed bytes. One coefficient
+// product is then the 16 digit products d_j(b) d_i(a), weighted 256^(i+j).
+// v_mfma_i32_16x16x64_i8 forms 64-term sums of digit products exactly in
+// int32: |d d'| <= 2^14, so a sum over at most 1024 block offsets (2^16
+// terms) stays below 2^30. The 16 weighted sums are reduced modulo p once,
+// when a work-group finishes an output range. All of it is exact, so the
+// result is bit-identical to the plain definition.
+//
+// GEMM mapping for one 16x16x64 instruction: rows (u, j) = 4 outputs x 4
+// digits of b (the Toeplitz side), columns (K, i) = 4 output blocks x 4
+// digits of a, contraction over v in [0, 64).
+//
+//  * a work-group (4 waves) owns 64 outputs u x 32 output blocks K (2048
+//    consecutive outputs, one "range" kr); wave w owns u in [16w, 16w+16)
+//    (4 row tiles: u = 16w + 4t + ul) and all 32 blocks (8 column tiles), 32
+//    accumulator tiles;
+//  * b's digits are staged in LDS, reversed, in 4 copies shifted by 0..3
+//    bytes. A lane reads the copy that cancels its ul, and then the four row
+//    tiles of one offset J are 16-byte windows at dword steps inside one
+//    16-byte-aligned 32-byte window: two LDS reads per step for all 4 tiles;
+//  * a's digits are staged in LDS in 4 digit planes. Column tile m holds
+//    blocks K0 + m + 8q (q = 0..3), so from one offset J to the next, tile m
+//    becomes tile m-1 and tile 0 is tile 7 shifted by one q (a DPP row
+//    shift) plus one new 16-byte read: the 8 column tiles form a register
+//    ring that returns to its starting registers every 8 offsets;
+//  * work is split stream-K in groups of 8 offsets: the (range, offset
+//    group) iterations are cut into equal contiguous shares, one per
+//    work-group; a work-group writes its partial sums (canonical residues) each
+//    time it leaves a range, and mulx_reduce_kernel adds the partial sums of
+//    each range (the paper's addition phase). Range bounds are rounded out to
+//    whole groups; the extra offsets meet only zeros of a or b.
+//
+// The paper's parameter s (b-coefficients per thread-block) is the staging
+// chunk here: JC offsets, i.e. 64*JC = 2048 coefficients of b per LDS stage.
+#include "internal.hpp"
+
+namespace pm {
+namespace {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+constexpr int MX_T = 64;            // positions per block
+constexpr int MX_KW = 32;           // output blocks per range
+constexpr int MX_RANGE = MX_T * MX_KW;  // outputs per range (2048)
+constexpr int MX_GRP = 8;           // offsets per iteration (one turn of the ring)
+constexpr int MX_JC = 32;           // block offsets per LDS stage
+constexpr int MX_MAXGRP = 128;      // groups summed in int32 before reduction (1024 offsets)
+constexpr int MX_THREADS = 256;
+
+// LDS layout (bytes).
+constexpr int MX_ANEED = (MX_KW + MX_JC - 1) * MX_T;
+constexpr int MX_APL = MX_ANEED + 16;  // a digit plane; /16 odd (conflict-free reads)
+constexpr int MX_BPL = 2128;        // b plane (copy o, digit j): /16 odd, >= JC*64 + 64
+constexpr int MX_BWORDS = MX_BPL / 4;
+constexpr int MX_RAW = MX_BPL + 16; // packed b digits, reversed
+constexpr int MX_LDS_A = 0;
+constexpr int MX_LDS_B = MX_LDS_A + 4 * MX_APL;
+constexpr int MX_LDS_RAW = MX_LDS_B + 16 * MX_BPL;
+constexpr int MX_LDS_BYTES = MX_LDS_RAW + 4 * MX_RAW;
+
+static_assert(MX_APL % 16 == 0 && (MX_APL / 16) % 2 == 1, "a plane");
+static_assert(MX_BPL >= MX_JC * MX_T + 64 && (MX_BPL / 16) % 2 == 1, "b plane");
+static_assert(MX_JC % MX_GRP == 0, "stage of whole groups");
+static_assert(4 * (MX_BWORDS - 1) + 8 <= MX_RAW, "raw window");
+
+}  // namespace
+
+// Iteration space of one product (MxGeom in internal.hpp): ranges kr of
+// 2048 outputs x block offsets J. Range kr needs the offsets
+// [max(0, 32kr - nab_true + 1), min(nJ_true, 32kr + 32)); rounded out to
+// whole groups of 8 this is [lo(kr), hi(kr)) with the same formulas on
+// MxGeom's rounded nab and nJ. Iterations are counted in groups. Shared by
+// the host planner and the kernels.
+__host__ __device__ inline int64_t mx_lo(const MxGeom& g, int64_t r) {
+    int64_t v = MX_KW * r - g.nab + 1;
+    return v > 0 ? v : 0;
+}
+__host__ __device__ inline int64_t mx_hi(const MxGeom& g, int64_t r) {
+    int64_t v = MX_KW * r + MX_KW;
+    return v < g.nJ ? v : g.nJ;
+}
+// Groups before range kr: sum over r < kr of (hi(r) - lo(r)) / 8, in closed
+// form (hi is linear until it reaches nJ, lo is zero until 32r reaches nab).
+__host__ __device__ inline int64_t mx_prefix(const MxGeom& g, int64_t kr) {
+    const int64_t r1 = g.nJ / MX_KW;
+    const int64_t m = kr < r1 ? kr : r1;
+    const int64_t sh = (int64_t)(MX_KW / 2) * m * (m + 1) + (kr - m) * g.nJ;
+    const int64_t r0 = (g.nab + MX_KW - 1) / MX_KW;
+    int64_t sl = 0;
+    if (kr > r0) {
+        const int64_t c = kr - r0;
+        sl = (int64_t)MX_KW * ((r0 + kr - 1) * c / 2) + (1 - g.nab) * c;
+    }
+    return (sh - sl) / MX_GRP;
+}
+__host__ __device__ inline int64_t mx_groups(const MxGeom& g, int64_t kr) {
+    return (mx_hi(g, kr) - mx_lo(g, kr)) / MX_GRP;
+}
+// The range holding group x (0 <= x < itot).
+__host__ __device__ inline int64_t mx_range_of(const MxGeom& g, int64_t x) {
+    int64_t lo = 0, hi = g.nkr - 1;
+    while (lo < hi) {
+        int64_t mid = (lo + hi + 1) / 2;
+        if (mx_prefix(g, mid) <= x) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+__host__ __device__ inline int64_t mx_share_begin(const MxGeom& g, int64_t w) { return w * g.itot / g.G; }
+// The work-group whose share holds group x.
+__host__ __device__ inline int64_t mx_group_of(const MxGeom& g, int64_t x) {
+    return ((x + 1) * g.G + g.itot - 1) / g.itot - 1;
+}
+
+namespace {
+
+struct MxArgs {
+    const uint32_t* a;
+    const uint32_t* b;
+    MxGeom g;
+    uint32_t* part;       // G * maxseg * 2048 partial residues
+    uint32_t* flags;      // G range-check flags
+    uint32_t* f;
+    int64_t nf;
+    int64_t* out_len;
+    int32_t* out_status;
+    Field F;
+    uint32_t w[7];        // 256^e mod p
+    uint32_t c63;         // 2^63 mod p
+    int a_vec;            // a is 16-byte aligned
+    int b_vec;            // b is 16-byte aligned
+};
+
+__device__ __forceinline__ uint32_t digits(uint32_t x) { return (x + 0x808080u) ^ 0x808080u; }
+
+// 4x4 byte transpose: byte m of out[j] = byte j of in[m].
+__device__ __forceinline__ void transpose4(const uint32_t in[4], uint32_t out[4]) {
+    uint32_t t0 = __builtin_amdgcn_perm(in[1], in[0], 0x05010400u);  // in0.b0 in1.b0 in0.b1 in1.b1
+    uint32_t t1 = __builtin_amdgcn_perm(in[3], in[2], 0x05010400u);  // in2.b0 in3.b0 in2.b1 in3.b1
+    uint32_t t2 = __builtin_amdgcn_perm(in[1], in[0], 0x07030602u);  // in0.b2 in1.b2 in0.b3 in1.b3
+    uint32_t t3 = __builtin_amdgcn_perm(in[3], in[2], 0x07030602u);  // in2.b2 in3.b2 in2.b3 in3.b3
+    out[0] = __builtin_amdgcn_perm(t1, t0, 0x05040100u);
+    out[1] = __builtin_amdgcn_perm(t1, t0, 0x07060302u);
+    out[2] = __builtin_amdgcn_perm(t3, t2, 0x05040100u);
+    out[3] = __builtin_amdgcn_perm(t3, t2, 0x07060302u);
+}
+
+// Four consecutive coefficients p[idx .. idx+3] (idx a multiple of 4),
+// zero outside [0, n); one 16-byte load when the quad is whole and p is
+// 16-byte aligned.
+__device__ __forceinline__ uint4 load_quad(const uint32_t* p, int64_t idx, int64_t n, int vec) {
+    if (vec && idx >= 0 && idx + 3 < n) return *(const uint4*)(p + idx);
+    uint4 v;
+    v.x = (idx >= 0 && idx < n) ? p[idx] : 0u;
+    v.y = (idx + 1 >= 0 && idx + 1 < n) ? p[idx + 1] : 0u;
+    v.z = (idx + 2 >= 0 && idx + 2 < n) ? p[idx + 2] : 0u;
+    v.w = (idx + 3 >= 0 && idx + 3 < n) ? p[idx + 3] : 0u;
+    return v;
+}
+
+constexpr int MX_AQ = MX_ANEED / 4;                          // a quads per stage
+constexpr int MX_BQ = MX_RAW / 4;                            // b quads per stage
+constexpr int MX_AQT = (MX_AQ + MX_THREADS - 1) / MX_THREADS;  // per thread
+constexpr int MX_BQT = (MX_BQ + MX_THREADS - 1) / MX_THREADS;
+static_assert(MX_RAW % 16 == 0, "b window in whole aligned quads");
+
+// Stage the digits of one (range, J-chunk) into LDS. a window: positions
+// a0 .. a0 + (KW+JC-1)*64 of a, a0 = 64*(K0 - Js - JC + 1); b window: the
+// positions 64*J1 - 1 - t, t in [0, MX_RAW), J1 = Js + JC, reversed. All
+// global loads are issued before any is used.
+__device__ __forceinline__ uint32_t mx_stage(const MxArgs& A, uint8_t* lds, int64_t K0, int64_t Js) {
+    const int tid = threadIdx.x;
+    const uint32_t p = A.F.p;
+    uint32_t bad = 0;
+    const int64_t a0 = (K0 - Js - MX_JC + 1) * MX_T;
+    const int64_t b0 = (Js + MX_JC) * MX_T - MX_RAW;   // lowest b position of the window
+    uint4 va[MX_AQT], vb[MX_BQT];
+#pragma unroll
+    for (int k = 0; k < MX_AQT; k++) {
+        const int it = tid + k * MX_THREADS;
+        va[k] = it < MX_AQ ? load_quad(A.a, a0 + 4 * it, A.g.na, A.a_vec) : uint4{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int k = 0; k < MX_BQT; k++) {
+        const int c = tid + k * MX_THREADS;
+        vb[k] = c < MX_BQ ? load_quad(A.b, b0 + 4 * c, A.g.nb, A.b_vec) : uint4{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int k = 0; k < MX_AQT; k++) {
+        const int it = tid + k * MX_THREADS;
+        if (it < MX_AQ) {
+            const uint32_t c[4] = {va[k].x, va[k].y, va[k].z, va[k].w};
+            uint32_t d[4], q[4];
+#pragma unroll
+            for (int m = 0; m < 4; m++) {
+                bad |= c[m] >= p;
+                d[m] = digits(c[m]);
+            }
+            transpose4(d, q);
+#pragma unroll
+            for (int j = 0; j < 4; j++) *(uint32_t*)(lds + MX_LDS_A + j * MX_APL + 4 * it) = q[j];
+        }
+    }
+    // raw[t] = digits of b[64*J1 - 1 - t]: quad c (positions b0 + 4c ..) lands
+    // reversed at raw[MX_RAW - 4 - 4c ..]
+    uint32_t* raw = (uint32_t*)(lds + MX_LDS_RAW);
+#pragma unroll
+    for (int k = 0; k < MX_BQT; k++) {
+        const int c = tid + k * MX_THREADS;
+        if (c < MX_BQ) {
+            bad |= (vb[k].x >= p) | (vb[k].y >= p) | (vb[k].z >= p) | (vb[k].w >= p);
+            *(uint4*)(raw + MX_RAW - 4 - 4 * c) =
+                uint4{digits(vb[k].w), digits(vb[k].z), digits(vb[k].y), digits(vb[k].x)};
+        }
+    }
+    __syncthreads();
+    // copy o (0..3) of digit plane j: byte y = digit j of raw[y + o]
+    for (int y4 = tid; y4 < MX_BWORDS; y4 += MX_THREADS) {
+        const uint4 lo = *(const uint4*)(raw + 4 * y4);
+        const uint4 hi = *(const uint4*)(raw + 4 * y4 + 4);
+        const uint32_t W[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+#pragma unroll
+        for (int o = 0; o < 4; o++) {
+            uint32_t d[4], q[4];
+#pragma unroll
+            for (int m = 0; m < 4; m++) d[m] = W[o + m];
+            transpose4(d, q);
+#pragma unroll
+            for (int j = 0; j < 4; j++) *(uint32_t*)(lds + MX_LDS_B + (4 * o + j) * MX_BPL + 4 * y4) = q[j];
+        }
+    }
+    return bad;
+}
+
+__device__ __forceinline__ v4i ld_b128(const uint8_t* lds, int off) { return *(const v4i*)(lds + off); }
+__device__ __forceinline__ v4i ld_2b64(const uint8_t* lds, int off) {
+    const int2* q = (const int2*)(lds + off);
+    int2 lo = q[0], hi = q[1];
+    return v4i{lo.x, lo.y, hi.x, hi.y};
+}
+
+// x mod p for a signed 64-bit x with |x| < 2^63.
+__device__ __forceinline__ uint32_t smod(int64_t x, const MxArgs& A) {
+    uint32_t r = reduce64((uint64_t)x ^ (UINT64_C(1) << 63), A.F);
+    return r >= A.c63 ? r - A.c63 : r + A.F.p - A.c63;
+}
+
+__global__ __launch_bounds__(MX_THREADS, 2) void mulx_kernel(MxArgs A) {
+    __shared__ __attribute__((aligned(16))) uint8_t lds[MX_LDS_BYTES];
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int g = lane >> 4;            // k-slot group: v in [16g, 16g+16)
+    const int rl = lane & 15;           // row (A side) / column (B side) of the 16x16 tile
+    const int ul = rl >> 2, dj = rl & 3;   // A side: output u = 16*wave + 4t + ul, digit j of b
+    const int q = rl >> 2, di = rl & 3;    // B side: block K = K0 + m + 8q, digit i of a
+    const MxGeom& G = A.g;
+    const int64_t w = blockIdx.x;
+    const int64_t Ia = mx_share_begin(G, w), Ib = mx_share_begin(G, w + 1);
+    uint32_t bad = 0;
+
+    // Toeplitz window of this lane: copy o = 3 - ul of digit plane j; at
+    // offset jj the 32 bytes from bwin + (JC - jj)*64 hold row tile t in
+    // dwords 3-t .. 6-t.
+    const int bwin = MX_LDS_B + (4 * (3 - ul) + dj) * MX_BPL - 16 - 16 * wave + 16 * g;
+    // a columns: plane i, block (m + 8q + JC - 1 - jj), k-slot group g
+    const int acol = MX_LDS_A + di * MX_APL + 16 * g;
+    // weights 256^(i+j) mod p of this lane's digit i, for j = 0..3
+    uint32_t wl[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++) wl[j] = A.w[di + j];
+
+    int64_t I = Ia;
+    int64_t kr = Ia < Ib ? mx_range_of(G, Ia) : 0;
+    int seg = 0;
+    while (I < Ib) {
+        const int64_t S0 = mx_prefix(G, kr);
+        const int64_t S1 = S0 + mx_groups(G, kr);
+        const int64_t Iend = Ib < S1 ? Ib : S1;
+        const int64_t Ja = mx_lo(G, kr) + MX_GRP * (I - S0);
+        const int64_t Jend = mx_lo(G, kr) + MX_GRP * (Iend - S0);
+        const int64_t K0 = kr * MX_KW;
+
+        v4i acc[4][8];
+#pragma unroll
+        for (int t = 0; t < 4; t++)
+#pragma unroll
+            for (int m = 0; m < 8; m++) acc[t][m] = v4i{0, 0, 0, 0};
+
+        for (int64_t Js = Ja; Js < Jend; Js += MX_JC) {
+            const int ngrp = (int)((Jend - Js < MX_JC ? Jend - Js : MX_JC) / MX_GRP);
+            const int last = ngrp * MX_GRP - 1;
+            __syncthreads();  // the previous stage is no longer read
+            bad |= mx_stage(A, lds, K0, Js);
+            __syncthreads();
+
+            v4i B[8];
+#pragma unroll
+            for (int m = 0; m < 8; m++) B[m] = ld_b128(lds, acol + (m + 8 * q + MX_JC - 1) * MX_T);
+            v4i W0 = ld_b128(lds, bwin + MX_JC * MX_T), W1 = ld_b128(lds, bwin + MX_JC * MX_T + 16);
+
+            for (int grp = 0; grp < ngrp; grp++) {
+#pragma unroll
+                for (int ph = 0; ph < MX_GRP; ph++) {
+                    const int jj = grp * MX_GRP + ph;
+                    const int jn = jj < last ? jj + 1 : last;  // next offset (clamped, stays in the stage)
+                    // new column for tile 0 at the next offset (only the q = 0
+                    // lanes keep it; the others take tile 7's q - 1 part)
+                    const v4i fresh = ld_b128(lds, acol + (MX_JC - 1 - jn) * MX_T);
+                    const v4i N0 = ld_b128(lds, bwin + (MX_JC - jn) * MX_T);
+                    const v4i N1 = ld_b128(lds, bwin + (MX_JC - jn) * MX_T + 16);
+                    const v4i At[4] = {v4i{W0[3], W1[0], W1[1], W1[2]}, v4i{W0[2], W0[3], W1[0], W1[1]},
+                                       v4i{W0[1], W0[2], W0[3], W1[0]}, W0};
+#pragma unroll
+                    for (int t = 0; t < 4; t++)
+#pragma unroll
+                        for (int m = 0; m < 8; m++)
+                            acc[t][m] = __builtin_amdgcn_mfma_i32_16x16x64_i8(At[t], B[(m - ph) & 7], acc[t][m],
+                                                                              0, 0, 0);
+                    const int slot = (7 - ph) & 7;
+#pragma unroll
+                    for (int c = 0; c < 4; c++)
+                        B[slot][c] = __builtin_amdgcn_update_dpp(fresh[c], B[slot][c], 0x114 /* row_shr:4 */, 0xf,
+                                                                 0xf, false);
+                    W0 = N0;
+                    W1 = N1;
+                }
+            }
+        }
+
+        // Epilogue: f[64K + u] = sum_{i,j} 256^(i+j) C_ij. Lane (u, K, i)
+        // holds C_ij for j = 0..3; weight, reduce, then add over the four
+        // lanes i of a quad. Lane i keeps the sum of column tile m0 + i and
+        // stores it at position (K - K0)*64 + u of the range.
+        uint32_t* out = A.part + ((w * G.maxseg + seg) * MX_RANGE);
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+#pragma unroll
+            for (int m0 = 0; m0 < 8; m0 += 4) {
+                uint32_t keep = 0;
+#pragma unroll
+                for (int dm = 0; dm < 4; dm++) {
+                    const v4i c = acc[t][m0 + dm];
+                    int64_t v = (int64_t)wl[0] * c[0] + (int64_t)wl[1] * c[1] + (int64_t)wl[2] * c[2] +
+                                (int64_t)wl[3] * c[3];
+                    uint32_t r = smod(v, A);
+                    r += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)r, 0xb1 /* quad_perm 1,0,3,2 */, 0xf, 0xf,
+                                                               false);
+                    r += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)r, 0x4e /* quad_perm 2,3,0,1 */, 0xf, 0xf,
+                                                               false);
+                    if (r >= 2 * A.F.p) r -= 2 * A.F.p;
+                    if (r >= A.F.p) r -= A.F.p;
+                    if (dm == di) keep = r;
+                }
+                out[(m0 + di + 8 * q) * MX_T + 16 * wave + 4 * t + (lane >> 4)] = keep;
+            }
+        }
+        I = Iend;
+        kr++;
+        seg++;
+    }
+    bad = __syncthreads_or(bad);
+    if (tid == 0) A.flags[w] = bad;
+}
+
+// Addition phase: work-group (kr, c) adds, for outputs 256c .. 256c+255 of
+// range kr, the partial sums of the work-groups whose shares touched kr. The
+// last work-group checks the flags and the degrees.
+__global__ __launch_bounds__(256) void mulx_reduce_kernel(MxArgs A) {
+    const MxGeom& G = A.g;
+    const int tid = threadIdx.x;
+    if ((int64_t)blockIdx.x == G.nkr * (MX_RANGE / 256)) {
+        if (!A.out_len && !A.out_status) return;
+        __shared__ int64_t s_deg[2];
+        uint32_t bad = 0;
+        for (int64_t w = tid; w < G.G; w += 256) bad |= A.flags[w];
+        bad = __syncthreads_or(bad);
+        const int wave = tid >> 6;
+        if (wave < 2) {
+            int64_t d = top_nonzero_wave(wave == 0 ? A.a : A.b, wave == 0 ? G.na : G.nb);
+            if ((tid & 63) == 0) s_deg[wave] = d;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            if (A.out_len) *A.out_len = (s_deg[0] >= 0 && s_deg[1] >= 0) ? s_deg[0] + s_deg[1] + 1 : 0;
+            if (A.out_status) *A.out_status = bad ? -3 /* PM_ERANGE */ : 0;
+        }
+        return;
+    }
+    const int64_t kr = blockIdx.x / (MX_RANGE / 256);
+    const int x = (int)(blockIdx.x % (MX_RANGE / 256)) * 256 + tid;
+    const int64_t k = kr * MX_RANGE + x;
+    if (k >= A.nf) return;
+    const int64_t S0 = mx_prefix(G, kr), S1 = S0 + mx_groups(G, kr);
+    const int64_t wf = mx_group_of(G, S0), wl = mx_group_of(G, S1 - 1);
+    const int64_t seg0 = kr - mx_range_of(G, mx_share_begin(G, wf));
+    uint64_t s = A.part[(wf * G.maxseg + seg0) * MX_RANGE + x];
+    for (int64_t w = wf + 1; w <= wl; w++) s += A.part[w * G.maxseg * MX_RANGE + x];
+    A.f[k] = reduce64(s, A.F);
+}
+
+uint64_t host_powmod(uint64_t x, uint64_t e, uint64_t p) {
+    uint64_t r = 1 % p;
+    x %= p;
+    while (e) {
+        if (e & 1) r = (unsigned __int128)r * x % p;
+        x = (unsigned __int128)x * x % p;
+        e >>= 1;
+    }
+    return r;
+}
+
+int mx_blocks_per_cu() {
+    static int n = 0;
+    if (!n) {
+        int v = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, (const void*)mulx_kernel, MX_THREADS, 0) != hipSuccess ||
+            v < 1)
+            v = 1;
+        n = v;
+    }
+    return n;
+}
+
+}  // namespace
+
+MxGeom mx_geometry(int64_t na, int64_t nb, int num_cus) {
+    MxGeom g{};
+    g.na = na;
+    g.nb = nb;
+    const int64_t nab = (na + MX_T - 1) / MX_T;   // blocks of a
+    const int64_t nJ = (nb + 62) / MX_T + 1;      // offsets J with 64J - 63 <= nb - 1
+    g.nkr = (nJ + nab - 1 + MX_KW - 1) / MX_KW;
+    // rounded to whole groups: lo rounded down, hi rounded up
+    const int64_t c = (1 - nab) >= 0 ? (1 - nab) / MX_GRP * MX_GRP : -((nab - 1 + MX_GRP - 1) / MX_GRP * MX_GRP);
+    g.nab = 1 - c;
+    g.nJ = (nJ + MX_GRP - 1) / MX_GRP * MX_GRP;
+    g.itot = mx_prefix(g, g.nkr);
+    int64_t G = (int64_t)mx_blocks_per_cu() * num_cus;
+    const int64_t need = (g.itot + MX_MAXGRP - 1) / MX_MAXGRP;
+    if (G < need) G = need;
+    if (G > g.itot) G = g.itot;
+    if (G > (INT64_C(1) << 20)) G = INT64_C(1) << 20;
+    g.G = G;
+    int64_t ms = 1;
+    for (int64_t w = 0; w < G; w++) {
+        const int64_t a = mx_share_begin(g, w), b = mx_share_begin(g, w + 1);
+        if (a >= b) continue;
+        const int64_t s = mx_range_of(g, b - 1) - mx_range_of(g, a) + 1;
+        if (s > ms) ms = s;
+    }
+    g.maxseg = ms;
+    return g;
+}
+
+int64_t mulx_scratch_words(const MxGeom& g) { return g.G * g.maxseg * MX_RANGE + g.G; }
+
+hipError_t mulx_launch(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, const Field& F, uint32_t* f,
+                       const MxGeom& g, uint32_t* scratch, int64_t* out_len, int32_t* out_status,
+                       hipStream_t stream) {
+    MxArgs A{};
+    A.a = a;
+    A.b = b;
+    A.g = g;
+    A.part = scratch;
+    A.flags = scratch + g.G * g.maxseg * MX_RANGE;
+    A.f = f;
+    A.nf = na + nb - 1;
+    A.out_len = out_len;
+    A.out_status = out_status;
+    A.F = F;
+    for (int e = 0; e < 7; e++) A.w[e] = (uint32_t)host_powmod(256, e, F.p);
+    A.c63 = (uint32_t)host_powmod(2, 63, F.p);
+    A.a_vec = ((uintptr_t)a & 15) == 0;
+    A.b_vec = ((uintptr_t)b & 15) == 0;
+    {
+        TimingScope ts("mulx_kernel", stream);
+        hipLaunchKernelGGL(mulx_kernel, dim3((unsigned)g.G), dim3(MX_THREADS), 0, stream, A);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    TimingScope ts("mulx_reduce_kernel", stream);
+    hipLaunchKernelGGL(mulx_reduce_kernel, dim3((unsigned)(g.nkr * (MX_RANGE / 256) + 1)), dim3(256), 0, stream, A);
+    return hipGetLastError();
+}
+
+}  // namespace pm

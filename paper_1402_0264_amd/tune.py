@@ -1,4 +1,4 @@
-"""Autotuner for the product kernels' tile shape.
+"""Autotuner for the product kernels: engine and tile shape.
 
 For the batched product the tunable shape is (r, kc): r outputs per thread
 (a thread-block owns 256*r outputs) and kc coefficients of b staged per
@@ -110,11 +110,21 @@ def tune_mul_batch(items, candidates=BATCH_CANDIDATES, reps: int = 3, use_cache:
     return rec
 
 
+def params_of(rec: dict) -> dict:
+    """pm.set_params keywords for a tune_mul result."""
+    import paper_1402_0264_amd as pm
+    if rec["engine"] == "mfma":
+        return {"mul_engine": pm.MUL_MFMA}
+    return {"mul_engine": pm.MUL_VALU, "mul_r": rec["r"], "mul_s": rec["kc"]}
+
+
 def tune_mul(a, b, p: int, candidates=SINGLE_CANDIDATES, reps: int = 3, use_cache: bool = True) -> dict:
-    """Pick (mul_r, mul_s) for one product of device tensors a, b."""
+    """Pick the engine for one product of device tensors a, b: the matrix
+    cores, or the VALU tiles with their best (mul_r, mul_s). Returns
+    {"engine": "mfma" | "valu", "r", "kc", "ms", "trials", "cached"}."""
     import torch
     import paper_1402_0264_amd as pm
-    key = "mul:%d:%d:pbits%d:%s" % (a.numel(), b.numel(), int(p).bit_length(), _device_name())
+    key = "mul2:%d:%d:pbits%d:%s" % (a.numel(), b.numel(), int(p).bit_length(), _device_name())
     if use_cache:
         rec = _load().get(key)
         if rec:
@@ -128,14 +138,17 @@ def tune_mul(a, b, p: int, candidates=SINGLE_CANDIDATES, reps: int = 3, use_cach
     saved = pm.get_params()
     trials = []
     try:
+        pm.set_params(div_s=saved["div_s"], gcd_s=saved["gcd_s"], mul_engine=pm.MUL_MFMA)
+        ms = _time(lambda: pm.mul_async(a, b, p, f, d_nf, d_st), reps)
+        trials.append({"engine": "mfma", "r": 0, "kc": 0, "ms": round(ms, 5)})
         for r, kc in candidates:
-            pm.set_params(mul_r=r, mul_s=kc, div_s=saved["div_s"], gcd_s=saved["gcd_s"])
+            pm.set_params(mul_r=r, mul_s=kc, div_s=saved["div_s"], gcd_s=saved["gcd_s"], mul_engine=pm.MUL_VALU)
             ms = _time(lambda: pm.mul_async(a, b, p, f, d_nf, d_st), reps)
-            trials.append({"r": r, "kc": kc, "ms": round(ms, 5)})
+            trials.append({"engine": "valu", "r": r, "kc": kc, "ms": round(ms, 5)})
     finally:
         pm.set_params(**saved)
     best = min(trials, key=lambda t: t["ms"])
-    rec = {"r": best["r"], "kc": best["kc"], "ms": best["ms"], "trials": trials}
+    rec = {"engine": best["engine"], "r": best["r"], "kc": best["kc"], "ms": best["ms"], "trials": trials}
     _store(key, rec)
     rec = dict(rec)
     rec["cached"] = False

@@ -59,10 +59,14 @@ def test_host_checks_reject_bad_arguments(L):
 
 def test_params_roundtrip_and_validation():
     pm.set_params(mul_s=512, mul_r=8, div_s=16, gcd_s=32)
-    assert pm.get_params() == {"mul_s": 512, "mul_r": 8, "div_s": 16, "gcd_s": 32}
+    assert pm.get_params() == {"mul_s": 512, "mul_r": 8, "div_s": 16, "gcd_s": 32, "mul_engine": 0}
     with pytest.raises(pm.PolyModPError):
         pm.set_params(mul_r=3)
     with pytest.raises(pm.PolyModPError):
         pm.set_params(gcd_s=1000)
+    with pytest.raises(pm.PolyModPError):
+        pm.set_params(mul_engine=3)
+    pm.set_params(mul_engine=pm.MUL_MFMA)
+    assert pm.get_params()["mul_engine"] == 2
     pm.set_params()
-    assert pm.get_params() == {"mul_s": 0, "mul_r": 0, "div_s": 0, "gcd_s": 0}
+    assert pm.get_params() == {"mul_s": 0, "mul_r": 0, "div_s": 0, "gcd_s": 0, "mul_engine": 0}

@@ -57,6 +57,85 @@ def test_mul_matches_oracle(p):
         assert same(f, oracle.mul(a, b, p)), (p, na, nb)
 
 
+ENGINE_SIZES = MUL_SIZES + [(64, 64), (65, 63), (2047, 2049), (2049, 2047), (4096, 64), (6000, 6000),
+                             (33000, 257), (20000, 9000)]
+
+
+@pytest.mark.parametrize("engine", [pm.MUL_VALU, pm.MUL_MFMA])
+@pytest.mark.parametrize("p", PRIMES + [3, 65521, 2])
+def test_mul_engines_match_oracle(engine, p):
+    """Both product engines, forced, on ragged sizes (empty tails of every
+    64-block, one or many output ranges of 2048, shares spanning ranges)."""
+    st = gen.Stream(111 + p % 991)
+    pm.set_params(mul_engine=engine)
+    try:
+        for na, nb in ENGINE_SIZES:
+            a, b = rnd(st, na, p), rnd(st, nb, p)
+            f = host(pm.mul(dev(a), dev(b), p))
+            assert same(f, oracle.mul(a, b, p)), (engine, p, na, nb)
+    finally:
+        pm.set_params()
+
+
+@pytest.mark.parametrize("p", PRIMES)
+def test_mul_mfma_extreme_digits_full_size(p):
+    """Every coefficient p - 1 (largest residues, so the largest digit sums
+    the int32 accumulators see) at the 65536 x 65536 size: since
+    (p-1)^2 = 1 mod p, f_k is the number of index pairs, min(k+1, n, 2n-1-k),
+    mod p."""
+    n = 65536
+    a = np.full(n, p - 1, dtype=np.uint32)
+    pm.set_params(mul_engine=pm.MUL_MFMA)
+    try:
+        f = host(pm.mul(dev(a), dev(a), p)).astype(np.int64)
+    finally:
+        pm.set_params()
+    k = np.arange(2 * n - 1, dtype=np.int64)
+    want = np.minimum(np.minimum(k + 1, n), 2 * n - 1 - k) % p
+    assert np.array_equal(f, want)
+
+
+def test_mul_engines_identical_on_product_65536():
+    a, b = gen.product_65536()
+    p = gen.P_A
+    da, db = dev(a), dev(b)
+    out = {}
+    for engine in (pm.MUL_VALU, pm.MUL_MFMA):
+        pm.set_params(mul_engine=engine)
+        try:
+            out[engine] = host(pm.mul(da, db, p))
+        finally:
+            pm.set_params()
+    assert same(out[pm.MUL_VALU], out[pm.MUL_MFMA])
+
+
+def test_mul_mfma_range_error_and_async_status():
+    import torch
+    p = gen.P_A
+    st = gen.Stream(112)
+    a, b = rnd(st, 5000, p), rnd(st, 3000, p)
+    pm.set_params(mul_engine=pm.MUL_MFMA)
+    try:
+        bad = b.copy(); bad[2999] = p + 5
+        with pytest.raises(pm.PolyModPError) as e:
+            pm.mul(dev(a), dev(bad), p)
+        assert e.value.status == pm.PM_ERANGE
+        bad = a.copy(); bad[0] = 0xFFFFFFFF
+        with pytest.raises(pm.PolyModPError) as e:
+            pm.mul(dev(bad), dev(b), p)
+        assert e.value.status == pm.PM_ERANGE
+        a_hz = np.concatenate([a, np.zeros(100, dtype=np.uint32)])
+        f = torch.zeros(a_hz.size + b.size - 1, dtype=torch.int32, device="cuda")
+        d_nf = torch.full((1,), -1, dtype=torch.int64, device="cuda")
+        d_st = torch.full((1,), 7, dtype=torch.int32, device="cuda")
+        pm.mul_async(dev(a_hz), dev(b), p, f, d_nf, d_st)
+        torch.cuda.synchronize()
+        assert int(d_st.item()) == 0 and int(d_nf.item()) == a.size + b.size - 1
+        assert same(host(f)[: a.size + b.size - 1], oracle.mul(a, b, p))
+    finally:
+        pm.set_params()
+
+
 @pytest.mark.parametrize("r,s", [(1, 1), (2, 2), (4, 4), (8, 8), (16, 16), (4, 2048), (16, 512), (32, 64),
                                  (32, 4096), (1, 3), (8, 100)])
 def test_mul_invariant_under_s(r, s):
