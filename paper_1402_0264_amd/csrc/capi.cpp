@@ -274,8 +274,10 @@ hipEvent_t take_event() {
         g_event_pool.pop_back();
         return e;
     }
+    // no system-scope fence: the events only timestamp the stream, and a
+    // fence (an L2 write-back) at every record would slow the timed launches
     hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
     return e;
 }
 

@@ -16,19 +16,22 @@
 // (x + 0x808080) ^ 0x808080 read as four signed bytes. One coefficient
 // product is then the 16 digit products d_j(b) d_i(a), weighted 256^(i+j).
 // v_mfma_i32_16x16x64_i8 forms 64-term sums of digit products exactly in
-// int32: |d d'| <= 2^14, so a sum over at most 1024 block offsets (2^16
-// terms) stays below 2^30. The 16 weighted sums are reduced modulo p once,
-// when a work-group finishes an output range. All of it is exact, so the
+// int32: |d d'| <= 2^14, so a sum over at most 512 block offsets (2^15
+// terms) stays below 2^29. The 16 weighted sums are combined exactly in
+// int64 and reduced modulo p once, when a work-group finishes an output
+// range. All of it is exact, so the
 // result is bit-identical to the plain definition.
 //
 // GEMM mapping for one 16x16x64 instruction: rows (u, j) = 4 outputs x 4
 // digits of b (the Toeplitz side), columns (K, i) = 4 output blocks x 4
 // digits of a, contraction over v in [0, 64).
 //
-//  * a work-group (4 waves) owns 64 outputs u x 32 output blocks K (2048
-//    consecutive outputs, one "range" kr); wave w owns u in [16w, 16w+16)
-//    (4 row tiles: u = 16w + 4t + ul) and all 32 blocks (8 column tiles), 32
-//    accumulator tiles;
+//  * a work-group (8 waves, one per CU) owns 64 outputs u x 64 output
+//    blocks K (4096 consecutive outputs, one "range" kr); wave w owns u in
+//    [16(w mod 4), +16) (4 row tiles: u = 16(w mod 4) + 4t + ul) and the 32
+//    blocks of half w div 4 (8 column tiles), 32 accumulator tiles. The two
+//    waves on a SIMD belong to the same work-group and meet at every stage,
+//    so they stay in step and finish together;
 //  * b's digits are staged in LDS, reversed, in 4 copies shifted by 0..3
 //    bytes. A lane reads the copy that cancels its ul, and then the four row
 //    tiles of one offset J are 16-byte windows at dword steps inside one
@@ -46,8 +49,12 @@
 //    whole groups; the extra offsets meet only zeros of a or b.
 //
 // The paper's parameter s (b-coefficients per thread-block) is the staging
-// chunk here: JC offsets, i.e. 64*JC = 2048 coefficients of b per LDS stage.
+// chunk here: JC offsets, i.e. 64*JC = 4096 coefficients of b per LDS stage.
 #include "internal.hpp"
+
+#include <map>
+#include <mutex>
+#include <tuple>
 
 namespace pm {
 namespace {
@@ -55,17 +62,17 @@ namespace {
 typedef int v4i __attribute__((ext_vector_type(4)));
 
 constexpr int MX_T = 64;            // positions per block
-constexpr int MX_KW = 32;           // output blocks per range
-constexpr int MX_RANGE = MX_T * MX_KW;  // outputs per range (2048)
+constexpr int MX_KW = 64;           // output blocks per range
+constexpr int MX_RANGE = MX_T * MX_KW;  // outputs per range (4096)
 constexpr int MX_GRP = 8;           // offsets per iteration (one turn of the ring)
-constexpr int MX_JC = 32;           // block offsets per LDS stage
-constexpr int MX_MAXGRP = 128;      // groups summed in int32 before reduction (1024 offsets)
-constexpr int MX_THREADS = 256;
+constexpr int MX_JC = 64;           // block offsets per LDS stage
+constexpr int MX_MAXGRP = 64;       // groups one share sums (512 offsets, |digit sum| < 2^29)
+constexpr int MX_THREADS = 512;
 
 // LDS layout (bytes).
 constexpr int MX_ANEED = (MX_KW + MX_JC - 1) * MX_T;
 constexpr int MX_APL = MX_ANEED + 16;  // a digit plane; /16 odd (conflict-free reads)
-constexpr int MX_BPL = 2128;        // b plane (copy o, digit j): /16 odd, >= JC*64 + 64
+constexpr int MX_BPL = 4176;        // b plane (copy o, digit j): /16 odd, >= JC*64 + 64
 constexpr int MX_BWORDS = MX_BPL / 4;
 constexpr int MX_RAW = MX_BPL + 16; // packed b digits, reversed
 constexpr int MX_LDS_A = 0;
@@ -81,8 +88,8 @@ static_assert(4 * (MX_BWORDS - 1) + 8 <= MX_RAW, "raw window");
 }  // namespace
 
 // Iteration space of one product (MxGeom in internal.hpp): ranges kr of
-// 2048 outputs x block offsets J. Range kr needs the offsets
-// [max(0, 32kr - nab_true + 1), min(nJ_true, 32kr + 32)); rounded out to
+// 4096 outputs x block offsets J. Range kr needs the offsets
+// [max(0, 64kr - nab_true + 1), min(nJ_true, 64kr + 64)); rounded out to
 // whole groups of 8 this is [lo(kr), hi(kr)) with the same formulas on
 // MxGeom's rounded nab and nJ. Iterations are counted in groups. Shared by
 // the host planner and the kernels.
@@ -95,7 +102,7 @@ __host__ __device__ inline int64_t mx_hi(const MxGeom& g, int64_t r) {
     return v < g.nJ ? v : g.nJ;
 }
 // Groups before range kr: sum over r < kr of (hi(r) - lo(r)) / 8, in closed
-// form (hi is linear until it reaches nJ, lo is zero until 32r reaches nab).
+// form (hi is linear until it reaches nJ, lo is zero until 64r reaches nab).
 __host__ __device__ inline int64_t mx_prefix(const MxGeom& g, int64_t kr) {
     const int64_t r1 = g.nJ / MX_KW;
     const int64_t m = kr < r1 ? kr : r1;
@@ -253,20 +260,33 @@ __device__ __forceinline__ v4i ld_2b64(const uint8_t* lds, int off) {
     return v4i{lo.x, lo.y, hi.x, hi.y};
 }
 
+// The value of the lane i ^ 1 (resp. i ^ 2) of the same quad.
+__device__ __forceinline__ int64_t quad_xor1(int64_t v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, 0xb1 /* quad_perm 1,0,3,2 */, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), 0xb1, 0xf, 0xf, false);
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+__device__ __forceinline__ int64_t quad_xor2(int64_t v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, 0x4e /* quad_perm 2,3,0,1 */, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), 0x4e, 0xf, 0xf, false);
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
 // x mod p for a signed 64-bit x with |x| < 2^63.
 __device__ __forceinline__ uint32_t smod(int64_t x, const MxArgs& A) {
     uint32_t r = reduce64((uint64_t)x ^ (UINT64_C(1) << 63), A.F);
     return r >= A.c63 ? r - A.c63 : r + A.F.p - A.c63;
 }
 
-__global__ __launch_bounds__(MX_THREADS, 2) void mulx_kernel(MxArgs A) {
+__global__ __launch_bounds__(MX_THREADS, 1) void mulx_kernel(MxArgs A) {
     __shared__ __attribute__((aligned(16))) uint8_t lds[MX_LDS_BYTES];
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
+    const int wu = wave & 3, wk = wave >> 2;  // u slice [16wu, +16), block half [32wk, +32)
     const int g = lane >> 4;            // k-slot group: v in [16g, 16g+16)
     const int rl = lane & 15;           // row (A side) / column (B side) of the 16x16 tile
-    const int ul = rl >> 2, dj = rl & 3;   // A side: output u = 16*wave + 4t + ul, digit j of b
-    const int q = rl >> 2, di = rl & 3;    // B side: block K = K0 + m + 8q, digit i of a
+    const int ul = rl >> 2, dj = rl & 3;   // A side: output u = 16*wu + 4t + ul, digit j of b
+    const int q = rl >> 2, di = rl & 3;    // B side: block K = K0 + 32*wk + m + 8q, digit i of a
     const MxGeom& G = A.g;
     const int64_t w = blockIdx.x;
     const int64_t Ia = mx_share_begin(G, w), Ib = mx_share_begin(G, w + 1);
@@ -275,9 +295,9 @@ __global__ __launch_bounds__(MX_THREADS, 2) void mulx_kernel(MxArgs A) {
     // Toeplitz window of this lane: copy o = 3 - ul of digit plane j; at
     // offset jj the 32 bytes from bwin + (JC - jj)*64 hold row tile t in
     // dwords 3-t .. 6-t.
-    const int bwin = MX_LDS_B + (4 * (3 - ul) + dj) * MX_BPL - 16 - 16 * wave + 16 * g;
-    // a columns: plane i, block (m + 8q + JC - 1 - jj), k-slot group g
-    const int acol = MX_LDS_A + di * MX_APL + 16 * g;
+    const int bwin = MX_LDS_B + (4 * (3 - ul) + dj) * MX_BPL - 16 - 16 * wu + 16 * g;
+    // a columns: plane i, block (32wk + m + 8q + JC - 1 - jj), k-slot group g
+    const int acol = MX_LDS_A + di * MX_APL + 16 * g + 32 * wk * MX_T;
     // weights 256^(i+j) mod p of this lane's digit i, for j = 0..3
     uint32_t wl[4];
 #pragma unroll
@@ -310,7 +330,10 @@ __global__ __launch_bounds__(MX_THREADS, 2) void mulx_kernel(MxArgs A) {
             v4i B[8];
 #pragma unroll
             for (int m = 0; m < 8; m++) B[m] = ld_b128(lds, acol + (m + 8 * q + MX_JC - 1) * MX_T);
-            v4i W0 = ld_b128(lds, bwin + MX_JC * MX_T), W1 = ld_b128(lds, bwin + MX_JC * MX_T + 16);
+            // two Toeplitz windows, used alternately: offset jj reads window
+            // jj mod 2 while the next offset's window loads into the other
+            v4i Wa0 = ld_b128(lds, bwin + MX_JC * MX_T), Wa1 = ld_b128(lds, bwin + MX_JC * MX_T + 16);
+            v4i Wb0 = Wa0, Wb1 = Wa1;
 
             for (int grp = 0; grp < ngrp; grp++) {
 #pragma unroll
@@ -320,10 +343,19 @@ __global__ __launch_bounds__(MX_THREADS, 2) void mulx_kernel(MxArgs A) {
                     // new column for tile 0 at the next offset (only the q = 0
                     // lanes keep it; the others take tile 7's q - 1 part)
                     const v4i fresh = ld_b128(lds, acol + (MX_JC - 1 - jn) * MX_T);
-                    const v4i N0 = ld_b128(lds, bwin + (MX_JC - jn) * MX_T);
-                    const v4i N1 = ld_b128(lds, bwin + (MX_JC - jn) * MX_T + 16);
-                    const v4i At[4] = {v4i{W0[3], W1[0], W1[1], W1[2]}, v4i{W0[2], W0[3], W1[0], W1[1]},
-                                       v4i{W0[1], W0[2], W0[3], W1[0]}, W0};
+                    const v4i C0 = (ph & 1) ? Wb0 : Wa0, C1 = (ph & 1) ? Wb1 : Wa1;
+                    if (ph & 1) {
+                        Wa0 = ld_b128(lds, bwin + (MX_JC - jn) * MX_T);
+                        Wa1 = ld_b128(lds, bwin + (MX_JC - jn) * MX_T + 16);
+                    } else {
+                        Wb0 = ld_b128(lds, bwin + (MX_JC - jn) * MX_T);
+                        Wb1 = ld_b128(lds, bwin + (MX_JC - jn) * MX_T + 16);
+                    }
+                    // the three reads above stay ahead of this offset's MFMAs: they
+                    // are used one step later (window) or after all 32 (fresh)
+                    __builtin_amdgcn_sched_barrier(0);
+                    const v4i At[4] = {v4i{C0[3], C1[0], C1[1], C1[2]}, v4i{C0[2], C0[3], C1[0], C1[1]},
+                                       v4i{C0[1], C0[2], C0[3], C1[0]}, C0};
 #pragma unroll
                     for (int t = 0; t < 4; t++)
 #pragma unroll
@@ -335,37 +367,36 @@ __global__ __launch_bounds__(MX_THREADS, 2) void mulx_kernel(MxArgs A) {
                     for (int c = 0; c < 4; c++)
                         B[slot][c] = __builtin_amdgcn_update_dpp(fresh[c], B[slot][c], 0x114 /* row_shr:4 */, 0xf,
                                                                  0xf, false);
-                    W0 = N0;
-                    W1 = N1;
+                    // keep each offset's tile assembly after the previous
+                    // offset's MFMAs, so its LDS reads have a whole step to land
+                    __builtin_amdgcn_sched_barrier(0);
                 }
             }
         }
 
         // Epilogue: f[64K + u] = sum_{i,j} 256^(i+j) C_ij. Lane (u, K, i)
-        // holds C_ij for j = 0..3; weight, reduce, then add over the four
-        // lanes i of a quad. Lane i keeps the sum of column tile m0 + i and
-        // stores it at position (K - K0)*64 + u of the range.
+        // holds C_ij for j = 0..3 of four column tiles m0 + dm. Each weighted
+        // sum v = sum_j w_(i+j) C_ij is exact in int64 and below 2^61 in
+        // magnitude (|C| < 2^29 for at most 512 offsets, w < 2^30), so the four
+        // lanes i of a quad are added exactly before any reduction; lane i then
+        // reduces the sum of tile m0 + i once and stores it at position
+        // (K - K0)*64 + u of the range.
         uint32_t* out = A.part + ((w * G.maxseg + seg) * MX_RANGE);
 #pragma unroll
         for (int t = 0; t < 4; t++) {
 #pragma unroll
             for (int m0 = 0; m0 < 8; m0 += 4) {
-                uint32_t keep = 0;
+                int64_t keep = 0;
 #pragma unroll
                 for (int dm = 0; dm < 4; dm++) {
                     const v4i c = acc[t][m0 + dm];
                     int64_t v = (int64_t)wl[0] * c[0] + (int64_t)wl[1] * c[1] + (int64_t)wl[2] * c[2] +
                                 (int64_t)wl[3] * c[3];
-                    uint32_t r = smod(v, A);
-                    r += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)r, 0xb1 /* quad_perm 1,0,3,2 */, 0xf, 0xf,
-                                                               false);
-                    r += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)r, 0x4e /* quad_perm 2,3,0,1 */, 0xf, 0xf,
-                                                               false);
-                    if (r >= 2 * A.F.p) r -= 2 * A.F.p;
-                    if (r >= A.F.p) r -= A.F.p;
-                    if (dm == di) keep = r;
+                    v += quad_xor1(v);
+                    v += quad_xor2(v);
+                    if (dm == di) keep = v;
                 }
-                out[(m0 + di + 8 * q) * MX_T + 16 * wave + 4 * t + (lane >> 4)] = keep;
+                out[(32 * wk + m0 + di + 8 * q) * MX_T + 16 * wu + 4 * t + (lane >> 4)] = smod(keep, A);
             }
         }
         I = Iend;
@@ -376,13 +407,20 @@ __global__ __launch_bounds__(MX_THREADS, 2) void mulx_kernel(MxArgs A) {
     if (tid == 0) A.flags[w] = bad;
 }
 
-// Addition phase: work-group (kr, c) adds, for outputs 256c .. 256c+255 of
-// range kr, the partial sums of the work-groups whose shares touched kr. The
-// last work-group checks the flags and the degrees.
+// Addition phase: work-group (kr, c) adds, for outputs 1024c .. 1024c+1023
+// of range kr (four consecutive outputs per thread, 16-byte loads), the
+// partial sums of the work-groups whose shares touched kr. The last
+// work-group checks the flags and the degrees.
+constexpr int MX_RED_BLOCKS = MX_RANGE / 1024;   // reduce work-groups per range
+
+__device__ __forceinline__ void add4(uint64_t s[4], const uint4 v) {
+    s[0] += v.x; s[1] += v.y; s[2] += v.z; s[3] += v.w;
+}
+
 __global__ __launch_bounds__(256) void mulx_reduce_kernel(MxArgs A) {
     const MxGeom& G = A.g;
     const int tid = threadIdx.x;
-    if ((int64_t)blockIdx.x == G.nkr * (MX_RANGE / 256)) {
+    if ((int64_t)blockIdx.x == G.nkr * MX_RED_BLOCKS) {
         if (!A.out_len && !A.out_status) return;
         __shared__ int64_t s_deg[2];
         uint32_t bad = 0;
@@ -400,16 +438,34 @@ __global__ __launch_bounds__(256) void mulx_reduce_kernel(MxArgs A) {
         }
         return;
     }
-    const int64_t kr = blockIdx.x / (MX_RANGE / 256);
-    const int x = (int)(blockIdx.x % (MX_RANGE / 256)) * 256 + tid;
+    const int64_t kr = blockIdx.x / MX_RED_BLOCKS;
+    const int x = (int)(blockIdx.x % MX_RED_BLOCKS) * 1024 + 4 * tid;
     const int64_t k = kr * MX_RANGE + x;
     if (k >= A.nf) return;
     const int64_t S0 = mx_prefix(G, kr), S1 = S0 + mx_groups(G, kr);
     const int64_t wf = mx_group_of(G, S0), wl = mx_group_of(G, S1 - 1);
     const int64_t seg0 = kr - mx_range_of(G, mx_share_begin(G, wf));
-    uint64_t s = A.part[(wf * G.maxseg + seg0) * MX_RANGE + x];
-    for (int64_t w = wf + 1; w <= wl; w++) s += A.part[w * G.maxseg * MX_RANGE + x];
-    A.f[k] = reduce64(s, A.F);
+    const uint32_t* part = A.part + x;
+    const int64_t stride = G.maxseg * MX_RANGE;   // one work-group's rows
+    uint64_t s[4] = {0, 0, 0, 0};
+    add4(s, *(const uint4*)(part + (wf * G.maxseg + seg0) * MX_RANGE));
+    int64_t w = wf + 1;
+    for (; w + 3 <= wl; w += 4) {
+        const uint4 v0 = *(const uint4*)(part + w * stride);
+        const uint4 v1 = *(const uint4*)(part + (w + 1) * stride);
+        const uint4 v2 = *(const uint4*)(part + (w + 2) * stride);
+        const uint4 v3 = *(const uint4*)(part + (w + 3) * stride);
+        add4(s, v0); add4(s, v1); add4(s, v2); add4(s, v3);
+    }
+    for (; w <= wl; w++) add4(s, *(const uint4*)(part + w * stride));
+    const uint32_t r[4] = {reduce64(s[0], A.F), reduce64(s[1], A.F), reduce64(s[2], A.F), reduce64(s[3], A.F)};
+    if (k + 3 < A.nf && ((uintptr_t)(A.f + k) & 15) == 0) {
+        *(uint4*)(A.f + k) = uint4{r[0], r[1], r[2], r[3]};
+    } else {
+#pragma unroll
+        for (int e = 0; e < 4; e++)
+            if (k + e < A.nf) A.f[k + e] = r[e];
+    }
 }
 
 uint64_t host_powmod(uint64_t x, uint64_t e, uint64_t p) {
@@ -437,7 +493,30 @@ int mx_blocks_per_cu() {
 
 }  // namespace
 
+namespace {
+MxGeom mx_plan(int64_t na, int64_t nb, int num_cus);
+}
+
+// Plans are cached per shape: planning walks every share (binary searches),
+// which would otherwise cost more host time per call than a small product.
 MxGeom mx_geometry(int64_t na, int64_t nb, int num_cus) {
+    static std::mutex mu;
+    static std::map<std::tuple<int64_t, int64_t, int>, MxGeom> cache;
+    const auto key = std::make_tuple(na, nb, num_cus);
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) return it->second;
+    }
+    const MxGeom g = mx_plan(na, nb, num_cus);
+    std::lock_guard<std::mutex> lk(mu);
+    if (cache.size() > 4096) cache.clear();
+    cache[key] = g;
+    return g;
+}
+
+namespace {
+MxGeom mx_plan(int64_t na, int64_t nb, int num_cus) {
     MxGeom g{};
     g.na = na;
     g.nb = nb;
@@ -449,9 +528,11 @@ MxGeom mx_geometry(int64_t na, int64_t nb, int num_cus) {
     g.nab = 1 - c;
     g.nJ = (nJ + MX_GRP - 1) / MX_GRP * MX_GRP;
     g.itot = mx_prefix(g, g.nkr);
-    int64_t G = (int64_t)mx_blocks_per_cu() * num_cus;
+    // one share per resident work-group, or whole rounds of them when the
+    // shares would exceed MX_MAXGRP groups (equal shares, no straggler round)
+    const int64_t round_size = (int64_t)mx_blocks_per_cu() * num_cus;
     const int64_t need = (g.itot + MX_MAXGRP - 1) / MX_MAXGRP;
-    if (G < need) G = need;
+    int64_t G = (need + round_size - 1) / round_size * round_size;
     if (G > g.itot) G = g.itot;
     if (G > (INT64_C(1) << 20)) G = INT64_C(1) << 20;
     g.G = G;
@@ -465,6 +546,7 @@ MxGeom mx_geometry(int64_t na, int64_t nb, int num_cus) {
     g.maxseg = ms;
     return g;
 }
+}  // namespace
 
 int64_t mulx_scratch_words(const MxGeom& g) { return g.G * g.maxseg * MX_RANGE + g.G; }
 
@@ -493,7 +575,7 @@ hipError_t mulx_launch(const uint32_t* a, int64_t na, const uint32_t* b, int64_t
         if (e != hipSuccess) return e;
     }
     TimingScope ts("mulx_reduce_kernel", stream);
-    hipLaunchKernelGGL(mulx_reduce_kernel, dim3((unsigned)(g.nkr * (MX_RANGE / 256) + 1)), dim3(256), 0, stream, A);
+    hipLaunchKernelGGL(mulx_reduce_kernel, dim3((unsigned)(g.nkr * MX_RED_BLOCKS + 1)), dim3(256), 0, stream, A);
     return hipGetLastError();
 }
 

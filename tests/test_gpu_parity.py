@@ -77,13 +77,12 @@ def test_mul_engines_match_oracle(engine, p):
         pm.set_params()
 
 
-@pytest.mark.parametrize("p", PRIMES)
-def test_mul_mfma_extreme_digits_full_size(p):
+@pytest.mark.parametrize("p,n", [(gen.P_A, 65536), (gen.P_B, 65536), (gen.P_C, 65536), (gen.P_B, 262144)])
+def test_mul_mfma_extreme_digits_full_size(p, n):
     """Every coefficient p - 1 (largest residues, so the largest digit sums
-    the int32 accumulators see) at the 65536 x 65536 size: since
-    (p-1)^2 = 1 mod p, f_k is the number of index pairs, min(k+1, n, 2n-1-k),
-    mod p."""
-    n = 65536
+    the accumulators see; at 262144 the work-group shares reach their cap of
+    512 block offsets): since (p-1)^2 = 1 mod p, f_k is the number of index
+    pairs, min(k+1, n, 2n-1-k), mod p."""
     a = np.full(n, p - 1, dtype=np.uint32)
     pm.set_params(mul_engine=pm.MUL_MFMA)
     try:
