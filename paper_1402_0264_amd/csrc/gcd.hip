@@ -149,8 +149,7 @@ __global__ __launch_bounds__(GCD_THREADS) void gcd_multi_kernel(GcdArgs G) {
             uint32_t hA[E], hB[E];
             load_heads<E>(Acur, Bcur, dA, dB, hA, hB);
             int n, big;
-            head_run<E>(hA, hB, (int)dA, (int)dB, G.s, F, desc, &s_out, n, big);
-            if (!big) build_m(desc, n, F, M);
+            head_run_m<E>(hA, hB, (int)dA, (int)dB, G.s, F, M, desc, &s_out, n, big);
         }
         __syncthreads();
         ChunkOut res = s_out;
@@ -243,11 +242,14 @@ __device__ void gcd_instance(const GcdJob& J, int s, int64_t cap, uint32_t* smem
     const Field F = J.F;
     uint32_t* A = smem + PADLO;                 // cap words (+PADLO zeros below)
     uint32_t* B = A + cap + PADLO;
-    uint32_t* M = B + cap;                      // 256
-    uint32_t* tmp = M + 256;                    // 64 * E
+    uint32_t* Mbuf = B + cap;                   // 2 x 256: M of this chunk and of the next
+    uint32_t* tmp = Mbuf + 512;                 // 64 * E
     StepDesc* desc = (StepDesc*)(tmp + 64 * E); // GCD_MAXSTEPS
-    __shared__ ChunkOut s_out;
+    __shared__ ChunkOut s_out[2];
     __shared__ int64_t s_deg[2];
+    // apply work: waves 1.. own the positions, wave 0 runs the heads
+    constexpr int NA = NT - 64;
+    constexpr int PPA = (NT * PPT + NA - 1) / NA;
 
     const int64_t n = J.na > J.nb ? J.na : J.nb;
     int bad = n > cap;
@@ -285,35 +287,31 @@ __device__ void gcd_instance(const GcdJob& J, int s, int64_t cap, uint32_t* smem
     }
     __syncthreads();
     int64_t dA = uni(s_deg[0]), dB = uni(s_deg[1]);
-    int unkA = 0, unkB = 0;
     int64_t steps = 0, chunks = 0, updates = 0;
     const int64_t max_chunks = (dA > 0 ? dA : 0) + (dB > 0 ? dB : 0) + 4;
     bool ok = true;
-    for (;;) {
-        if (unkA || unkB) {
-            if (wave == 0) {
-                int64_t x = unkA ? top_nonzero_wave(A, dA + 1) : dA;
-                int64_t y = unkB ? top_nonzero_wave(B, dB + 1) : dB;
-                if (lane == 0) { s_deg[0] = x; s_deg[1] = y; }
-            }
-            __syncthreads();
-            dA = uni(s_deg[0]);
-            dB = uni(s_deg[1]);
-            unkA = unkB = 0;
-            __syncthreads();
-        }
-        if (dA < 0 || dB < 0) break;
-        if (chunks >= max_chunks) { ok = false; break; }
-        chunks++;
+    int mb = 0;
+    // the first chunk's steps and M, from the heads of the inputs
+    if (dA >= 0 && dB >= 0) {
         if (wave == 0) {
             uint32_t hA[E], hB[E];
             load_heads<E>(A, B, dA, dB, hA, hB);
             int nst, big;
-            head_run<E>(hA, hB, (int)dA, (int)dB, s, F, desc, &s_out, nst, big);
-            if (!big) build_m(desc, nst, F, M);
+            head_run_m<E>(hA, hB, (int)dA, (int)dB, s, F, Mbuf, desc, &s_out[0], nst, big);
         }
         __syncthreads();
-        ChunkOut res = s_out;
+    }
+    // Each chunk: waves 1.. compute M * (A, B) at every position into
+    // registers while wave 0 computes the top of the new pair (the next
+    // chunk's heads) from the same chunk-start data and runs the next
+    // chunk's steps into the other M buffer; after a barrier the new pair is
+    // written back. A chunk whose heads ran out (degree unknown) or that is
+    // one big step is followed by the serial path: write, rescan, then heads.
+    for (;;) {
+        if (dA < 0 || dB < 0) break;
+        if (chunks >= max_chunks) { ok = false; break; }
+        chunks++;
+        ChunkOut res = s_out[mb];
         res.dA = uni(res.dA);
         res.dB = uni(res.dB);
         res.upd = uni(res.upd);
@@ -322,22 +320,42 @@ __device__ void gcd_instance(const GcdJob& J, int s, int64_t cap, uint32_t* smem
         res.unkA = uni(res.unkA);
         res.unkB = uni(res.unkB);
         res.big = uni(res.big);
+        const uint32_t* Mc = Mbuf + 256 * mb;
+        uint32_t* Mn = Mbuf + 256 * (mb ^ 1);
+        const bool pipe = !res.big && !res.unkA && !res.unkB && res.dA >= 0 && res.dB >= 0;
         const int top = (int)(dA > dB ? dA : dB);
         if (!res.big) {
-            uint32_t nA[PPT], nB[PPT];
+            uint32_t nA[PPA], nB[PPA];
+            if (wave == 0) {
+                if (pipe) {
+                    uint32_t hA[E], hB[E];
 #pragma unroll
-            for (int j = 0; j < PPT; j++) {
-                const int P = tid + j * NT;
-                nA[j] = nB[j] = 0u;
-                if (P <= top) apply_m_at(A, B, P, res.S, M, F, nA[j], nB[j]);
+                    for (int e = 0; e < E; e++) {
+                        const int i = lane + 64 * e;
+                        const int PA = (int)res.dA - i, PB = (int)res.dB - i;
+                        hA[e] = PA >= 0 ? apply_row_at(A, B, PA, res.S, Mc, Mc + 64, F) : 0u;
+                        hB[e] = PB >= 0 ? apply_row_at(A, B, PB, res.S, Mc + 128, Mc + 192, F) : 0u;
+                    }
+                    int nst, big;
+                    head_run_m<E>(hA, hB, (int)res.dA, (int)res.dB, s, F, Mn, desc, &s_out[mb ^ 1], nst, big);
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < PPA; j++) {
+                    const int P = (tid - 64) + j * NA;
+                    nA[j] = nB[j] = 0u;
+                    if (P <= top) apply_m_at(A, B, P, res.S, Mc, F, nA[j], nB[j]);
+                }
             }
             __syncthreads();
+            if (wave != 0) {
 #pragma unroll
-            for (int j = 0; j < PPT; j++) {
-                const int P = tid + j * NT;
-                if (P <= top) {
-                    A[P] = P <= res.dA ? nA[j] : 0u;
-                    B[P] = P <= res.dB ? nB[j] : 0u;
+                for (int j = 0; j < PPA; j++) {
+                    const int P = (tid - 64) + j * NA;
+                    if (P <= top) {
+                        A[P] = P <= res.dA ? nA[j] : 0u;
+                        B[P] = P <= res.dB ? nB[j] : 0u;
+                    }
                 }
             }
         } else {
@@ -355,10 +373,30 @@ __device__ void gcd_instance(const GcdJob& J, int s, int64_t cap, uint32_t* smem
         __syncthreads();
         dA = res.dA;
         dB = res.dB;
-        unkA = res.unkA;
-        unkB = res.unkB;
         steps += res.nsteps;
         updates += res.upd;
+        if (!pipe) {
+            if (res.unkA || res.unkB) {
+                if (wave == 0) {
+                    int64_t x = res.unkA ? top_nonzero_wave(A, dA + 1) : dA;
+                    int64_t y = res.unkB ? top_nonzero_wave(B, dB + 1) : dB;
+                    if (lane == 0) { s_deg[0] = x; s_deg[1] = y; }
+                }
+                __syncthreads();
+                dA = uni(s_deg[0]);
+                dB = uni(s_deg[1]);
+            }
+            if (dA >= 0 && dB >= 0) {
+                if (wave == 0) {
+                    uint32_t hA[E], hB[E];
+                    load_heads<E>(A, B, dA, dB, hA, hB);
+                    int nst, big;
+                    head_run_m<E>(hA, hB, (int)dA, (int)dB, s, F, Mn, desc, &s_out[mb ^ 1], nst, big);
+                }
+                __syncthreads();
+            }
+        }
+        mb ^= 1;
     }
     const uint32_t* R = dA >= 0 ? A : B;
     const int64_t dR = dA >= 0 ? dA : dB;
@@ -445,7 +483,7 @@ __global__ __launch_bounds__(NT) void gcd_worker_kernel(const GcdJob* jobs, cons
 
 template <int NT, int PPT, int E>
 size_t batch_lds_bytes(int64_t cap) {
-    return (size_t)(2 * (cap + PADLO) + 256 + 64 * E) * sizeof(uint32_t) + GCD_MAXSTEPS * sizeof(StepDesc);
+    return (size_t)(2 * (cap + PADLO) + 512 + 64 * E) * sizeof(uint32_t) + GCD_MAXSTEPS * sizeof(StepDesc);
 }
 
 }  // namespace
@@ -506,13 +544,12 @@ hipError_t gcd_worker_launch(const GcdJob* jobs, const uint32_t* order, uint32_t
     (void)hipGetDevice(&dev);
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0) khz = 100000;
     const uint64_t ticks = (uint64_t)(idle_seconds * 1e3 * khz);
-    size_t lds = s > 96 ? batch_lds_bytes<1024, 17, 4>(cap) : batch_lds_bytes<1024, 17, 2>(cap);
-    if (s > 96)
-        hipLaunchKernelGGL((gcd_worker_kernel<1024, 17, 4>), dim3(blocks), dim3(1024), lds, stream, jobs, order,
-                           order_cap, tail, stop, head, s, cap, ticks);
-    else
-        hipLaunchKernelGGL((gcd_worker_kernel<1024, 17, 2>), dim3(blocks), dim3(1024), lds, stream, jobs, order,
-                           order_cap, tail, stop, head, s, cap, ticks);
+    // 128-entry heads for any s: a chunk has at most 2(S+1) <= 128 steps,
+    // which consume about 64 entries of each head (a shorter run is still
+    // exact), and 1024 threads leave 128 VGPRs per lane
+    size_t lds = batch_lds_bytes<1024, 17, 2>(cap);
+    hipLaunchKernelGGL((gcd_worker_kernel<1024, 17, 2>), dim3(blocks), dim3(1024), lds, stream, jobs, order,
+                       order_cap, tail, stop, head, s, cap, ticks);
     return hipGetLastError();
 }
 

@@ -7,19 +7,17 @@
 // i.e. the paper's step lc(X)/lc(Y) scaled by the unit lc(Y)*2^-32, so the
 // degrees of all remainders are the paper's and no inverse is needed.
 //
-// A chunk (the paper's s steps per launch, Sec. 6.2) has three parts:
-//  1. head_run: one wave runs up to s steps on the heads of A and B (their
+// A chunk (the paper's s steps per launch, Sec. 6.2) has two parts:
+//  1. head_run_m: one wave runs up to s steps on the heads of A and B (their
 //     top coefficients, held in registers, element e of lane l = index
 //     l + 64e below the leading one). A head entry stays exact while every
 //     entry it was computed from was loaded; the run stops before the next
 //     leading coefficient would be unknown, or when the total shift of the
-//     chunk would exceed MAXSHIFT. Each step is recorded (multipliers,
-//     shift, operand).
-//  2. build_m: one wave composes the recorded steps into the 2x2 matrix of
-//     polynomials M = [[alpha, beta], [gamma, delta]] of degree <= the total
-//     shift S, such that (A', B') = M * (A, B) for the chunk-start A, B.
-//     Lane k holds coefficient k of each entry.
-//  3. apply: every coefficient position P of the new polynomials is an
+//     chunk would exceed MAXSHIFT. Each step is also applied to the 2x2
+//     matrix of polynomials M = [[alpha, beta], [gamma, delta]] (degree <=
+//     the total shift S; lane k holds coefficient k of each entry), so that
+//     (A', B') = M * (A, B) for the chunk-start A, B.
+//  2. apply: every coefficient position P of the new polynomials is an
 //     independent sum, A'[P] = sum_k alpha_k A[P-k] + beta_k B[P-k] (and
 //     likewise B'), accumulated exactly in 64 bits with lazy folding and
 //     reduced once (the same arithmetic as the plain product).
@@ -82,37 +80,26 @@ __device__ __forceinline__ void head_shift1(uint32_t (&h)[E]) {
     }
 }
 
-// One reduction of the head X by Y (in registers): X <- REDC(m1 X + m2 Y),
-// entries at or beyond v cleared; returns delta, the index of the first
-// non-zero entry after the leading one (the drop of deg X), or 0 when none
-// is left among the first v.
-template <int E>
-__device__ __forceinline__ int head_reduce(uint32_t (&X)[E], const uint32_t (&Y)[E], uint32_t m1, uint32_t m2,
-                                           int v, const Field& F) {
-    const int lane = threadIdx.x & 63;
-    unsigned long long m[E];
-#pragma unroll
-    for (int e = 0; e < E; e++) {
-        const int i = lane + 64 * e;
-        uint32_t x = redc((uint64_t)m1 * X[e] + (uint64_t)m2 * Y[e], F);
-        x = i < v ? x : 0u;
-        X[e] = x;
-        m[e] = __ballot(x != 0);
-    }
-    m[0] &= ~1ull;  // entry 0 is the cancelled leading coefficient
-#pragma unroll
-    for (int e = 0; e < E; e++)
-        if (m[e]) return 64 * e + (int)__builtin_ctzll(m[e]);
-    return 0;
+// lane i <- lane i-d of x (0 for i < d); d uniform, 0 <= d < 64
+__device__ __forceinline__ uint32_t lanes_up_any(uint32_t x, int d) {
+    if (d == 0) return x;
+    if (d == 1) return lanes_up1(x);
+    return lanes_up(x, d);
 }
 
-// Head run by one whole wave. hA/hB: the heads (entry i = coefficient of
-// x^(deg - i)), exact for i < 64*E. Records the steps into desc[] (lane 0
-// writes LDS), returns the chunk summary through *out (lane 0 writes) and
-// the step count and big flag in n_out / big_out.
+// Head run by one whole wave, composing M on the fly. hA/hB: the heads
+// (entry i = coefficient of x^(deg - i)), exact for i < 64*E. Each step
+// reduces the operand of higher degree in the heads and applies the same
+// step to the rows of M held in registers (lane k = coefficient k of alpha,
+// beta, gamma, delta), so no step list has to be replayed afterwards. The
+// reduced operand is chosen with uniform selects rather than two copies of
+// the code. Writes M to LDS (4 rows of 64 words) unless the chunk is a
+// single big step, which is recorded in desc[0] instead; returns the chunk
+// summary through *out (lane 0 writes) and the step count and big flag in
+// n_out / big_out.
 template <int E>
-__device__ void head_run(uint32_t (&hA)[E], uint32_t (&hB)[E], int dA, int dB, int s, const Field& F,
-                         StepDesc* desc, ChunkOut* out, int& n_out, int& big_out) {
+__device__ void head_run_m(uint32_t (&hA)[E], uint32_t (&hB)[E], int dA, int dB, int s, const Field& F,
+                           uint32_t* M, StepDesc* desc, ChunkOut* out, int& n_out, int& big_out) {
     const int lane = threadIdx.x & 63;
     constexpr int H = 64 * E;
     dA = uni(dA);
@@ -120,6 +107,7 @@ __device__ void head_run(uint32_t (&hA)[E], uint32_t (&hB)[E], int dA, int dB, i
     s = uni(s);
     int vA = H, vB = H, S = 0, n = 0, unkA = 0, unkB = 0, big = 0;
     int64_t upd = 0;
+    uint32_t al = lane == 0 ? 1u : 0u, be = 0u, ga = 0u, de = lane == 0 ? 1u : 0u;
     while (n < s && dA >= 0 && dB >= 0) {
         const bool redA = dA >= dB;
         const int d = redA ? dA - dB : dB - dA;
@@ -129,40 +117,73 @@ __device__ void head_run(uint32_t (&hA)[E], uint32_t (&hB)[E], int dA, int dB, i
         }
         const uint32_t lcA = (uint32_t)__builtin_amdgcn_readfirstlane((int)hA[0]);
         const uint32_t lcB = (uint32_t)__builtin_amdgcn_readfirstlane((int)hB[0]);
+        const uint32_t m1 = redA ? lcB : lcA;
+        const uint32_t m2 = F.p - (redA ? lcA : lcB);
         const int v = vA < vB ? vA : vB;
-        uint32_t m1, m2;
-        int delta;
-        if (redA) {
-            m1 = lcB;
-            m2 = F.p - lcA;
-            delta = head_reduce<E>(hA, hB, m1, m2, v, F);
-        } else {
-            m1 = lcA;
-            m2 = F.p - lcB;
-            delta = head_reduce<E>(hB, hA, m1, m2, v, F);
+        // X <- REDC(m1 X + m2 Y) on the heads; entries at or beyond v cleared
+        uint32_t x[E];
+        unsigned long long msk[E];
+#pragma unroll
+        for (int e = 0; e < E; e++) {
+            const uint32_t X = redA ? hA[e] : hB[e];
+            const uint32_t Y = redA ? hB[e] : hA[e];
+            uint32_t t = redc((uint64_t)m1 * X + (uint64_t)m2 * Y, F);
+            t = lane + 64 * e < v ? t : 0u;
+            x[e] = t;
+            msk[e] = __ballot(t != 0);
         }
-        if (lane == 0) desc[n] = StepDesc{m1, m2, d, redA ? 0 : 1};
+        msk[0] &= ~1ull;  // entry 0 is the cancelled leading coefficient
+        int delta = 0;
+#pragma unroll
+        for (int e = E - 1; e >= 0; e--)
+            if (msk[e]) delta = 64 * e + (int)__builtin_ctzll(msk[e]);
+        if (big) {
+            if (lane == 0) desc[0] = StepDesc{m1, m2, d, redA ? 0 : 1};
+        } else {
+            // the same step on M: (rows of X) <- REDC(m1 (rows of X) + m2 x^d (rows of Y))
+            const uint32_t P = redA ? al : ga, Q = redA ? be : de;
+            const uint32_t R = lanes_up_any(redA ? ga : al, d);
+            const uint32_t T = lanes_up_any(redA ? de : be, d);
+            const uint32_t P2 = redc((uint64_t)m1 * P + (uint64_t)m2 * R, F);
+            const uint32_t Q2 = redc((uint64_t)m1 * Q + (uint64_t)m2 * T, F);
+            al = redA ? P2 : al;
+            be = redA ? Q2 : be;
+            ga = redA ? ga : P2;
+            de = redA ? de : Q2;
+            S += d;
+        }
         n++;
-        if (!big) S += d;
         upd += (redA ? dB : dA) + 1;
+        int nd, nv;
+        const int dX = redA ? dA : dB;
         if (delta > 0) {
-            for (int k = 0; k < delta; k++) {
-                if (redA) head_shift1<E>(hA);
-                else head_shift1<E>(hB);
-            }
-            if (redA) { dA -= delta; vA = v - delta; } else { dB -= delta; vB = v - delta; }
+            for (int k = 0; k < delta; k++) head_shift1<E>(x);
+            nd = dX - delta;
+            nv = v - delta;
         } else {
             // the first v entries vanished: deg X <= old deg - v
-            int nd = (redA ? dA : dB) - v;
+            nd = dX - v;
+            nv = 0;
             if (nd < 0) nd = -1;
             else if (redA) unkA = 1;
             else unkB = 1;
-            if (redA) { dA = nd; vA = 0; } else { dB = nd; vB = 0; }
         }
+#pragma unroll
+        for (int e = 0; e < E; e++) {
+            hA[e] = redA ? x[e] : hA[e];
+            hB[e] = redA ? hB[e] : x[e];
+        }
+        if (redA) { dA = nd; vA = nv; } else { dB = nd; vB = nv; }
         if (unkA | unkB | big) break;
     }
     n_out = n;
     big_out = big;
+    if (!big) {
+        M[lane] = al;
+        M[64 + lane] = be;
+        M[128 + lane] = ga;
+        M[192 + lane] = de;
+    }
     if (lane == 0) {
         out->dA = dA;
         out->dB = dB;
@@ -173,42 +194,6 @@ __device__ void head_run(uint32_t (&hA)[E], uint32_t (&hB)[E], int dA, int dB, i
         out->unkB = unkB;
         out->big = big;
     }
-}
-
-// Compose the recorded steps into M (one wave; lane k = coefficient k).
-// Writes M to LDS as 4 rows of 64 words: alpha, beta, gamma, delta.
-// The descriptors are first spread over the lanes (lane j holds step j of
-// each group of 64) so the sequential loop reads them with readlane.
-__device__ __forceinline__ void build_m(const StepDesc* desc, int n, const Field& F, uint32_t* M) {
-    const int lane = threadIdx.x & 63;
-    n = uni(n);
-    uint32_t al = lane == 0 ? 1u : 0u, be = 0u, ga = 0u, de = lane == 0 ? 1u : 0u;
-    for (int k0 = 0; k0 < n; k0 += 64) {
-        StepDesc mine = k0 + lane < n ? desc[k0 + lane] : StepDesc{0, 0, 0, 0};
-        const uint32_t dw = (uint32_t)mine.d | ((uint32_t)mine.which << 31);
-        const int kn = n - k0 < 64 ? n - k0 : 64;
-        for (int k = 0; k < kn; k++) {
-            const uint32_t m1 = (uint32_t)__builtin_amdgcn_readlane((int)mine.m1, k);
-            const uint32_t m2 = (uint32_t)__builtin_amdgcn_readlane((int)mine.m2, k);
-            const uint32_t w = (uint32_t)__builtin_amdgcn_readlane((int)dw, k);
-            const int d = (int)(w & 0x7fffffffu);
-            if ((w >> 31) == 0) {  // (alpha, beta) <- REDC(m1*(alpha, beta) + m2*x^d*(gamma, delta))
-                uint32_t sg = d == 0 ? ga : (d == 1 ? lanes_up1(ga) : lanes_up(ga, d));
-                uint32_t sd = d == 0 ? de : (d == 1 ? lanes_up1(de) : lanes_up(de, d));
-                al = redc((uint64_t)m1 * al + (uint64_t)m2 * sg, F);
-                be = redc((uint64_t)m1 * be + (uint64_t)m2 * sd, F);
-            } else {
-                uint32_t sa = d == 0 ? al : (d == 1 ? lanes_up1(al) : lanes_up(al, d));
-                uint32_t sb = d == 0 ? be : (d == 1 ? lanes_up1(be) : lanes_up(be, d));
-                ga = redc((uint64_t)m1 * ga + (uint64_t)m2 * sa, F);
-                de = redc((uint64_t)m1 * de + (uint64_t)m2 * sb, F);
-            }
-        }
-    }
-    M[lane] = al;
-    M[64 + lane] = be;
-    M[128 + lane] = ga;
-    M[192 + lane] = de;
 }
 
 // New coefficients at one position: (A'[P], B'[P]) from the chunk-start
@@ -234,6 +219,24 @@ __device__ __forceinline__ void apply_m_at(const uint32_t* la, const uint32_t* l
     }
     outA = reduce64(accA, F);
     outB = reduce64(accB, F);
+}
+
+// One new coefficient: sum_k Ma[k] la[x-k] + Mb[k] lb[x-k], k = 0..S (one
+// row of M applied at local index x; x - k >= 0 guaranteed by the caller).
+__device__ __forceinline__ uint32_t apply_row_at(const uint32_t* la, const uint32_t* lb, int x, int S,
+                                                 const uint32_t* Ma, const uint32_t* Mb, const Field& F) {
+    uint64_t acc = 0;
+    uint32_t cnt = 0;
+    const uint32_t half = F.fold_every / 2;
+    for (int k = 0; k <= S; k++) {
+        acc += (uint64_t)Ma[k] * la[x - k];
+        acc += (uint64_t)Mb[k] * lb[x - k];
+        if (++cnt == half) {
+            acc = fold(acc, F.c32);
+            cnt = 0;
+        }
+    }
+    return reduce64(acc, F);
 }
 
 }  // namespace pm

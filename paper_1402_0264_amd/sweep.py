@@ -12,8 +12,10 @@ sums stay in registers). For each s the script prints one JSON line: the
 measured time (median of reps, HIP events around the whole product), the
 multiplication- and addition-phase kernel times, the bytes of M written
 and read, and the model's Corollary-1 estimate T(s) normalised to s = 1.
-A final line names the measured optimum, the model's (s = 1: its estimate
-grows with s) and the paper's own measurement (s = 4).
+A last row times the matrix-core engine (its s is fixed at 4096) on the
+same inputs, and a final line names the measured optimum of the VALU engine,
+the model's (s = 1: its estimate grows with s), the paper's own
+measurement (s = 4) and the matrix-core time.
 """
 from __future__ import annotations
 
@@ -51,7 +53,7 @@ def main() -> int:
     t1_model = mmm.mul_time(args.n, args.n, 1, mmm.U_THROUGHPUT)
     for s in svals:
         r = min(s, 16)
-        pm.set_params(mul_r=r, mul_s=s)
+        pm.set_params(mul_r=r, mul_s=s, mul_engine=pm.MUL_VALU)
         pm.mul_async(a, b, p, f, d_nf, d_st)
         torch.cuda.synchronize()
         if ref is None:
@@ -83,12 +85,32 @@ def main() -> int:
                "identical_to_s1": same}
         rows.append(rec)
         print(json.dumps(rec), flush=True)
+    # the matrix-core engine (its s is fixed: 4096 b-coefficients per stage)
+    pm.set_params(mul_engine=pm.MUL_MFMA)
+    pm.mul_async(a, b, p, f, d_nf, d_st)
+    torch.cuda.synchronize()
+    same = bool(torch.equal(f, ref)) and int(d_st.item()) == 0
+    times = []
+    for _ in range(args.reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        pm.mul_async(a, b, p, f, d_nf, d_st)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    times.sort()
+    ms = times[len(times) // 2]
+    mx = {"engine": "mfma", "s": 4096, "ms": round(ms, 4), "mulmods_per_s": round(args.n * args.n / (ms * 1e-3), 1),
+          "identical_to_s1": same}
+    print(json.dumps(mx), flush=True)
     pm.set_params()
     best = min(rows, key=lambda x: x["ms"])
     print(json.dumps({"summary": True, "n": args.n, "measured_best_s": best["s"], "measured_best_ms": best["ms"],
+                      "mfma_engine_ms": mx["ms"],
                       "model_best_s": min(rows, key=lambda x: x["model_T_over_T1"])["s"],
                       "paper_measured_best_s": 4, "U": round(mmm.U_THROUGHPUT, 3), "Z": mmm.Z_MI355X,
-                      "all_identical": all(x["identical_to_s1"] for x in rows)}), flush=True)
+                      "all_identical": all(x["identical_to_s1"] for x in rows) and mx["identical_to_s1"]}), flush=True)
     return 0
 
 
