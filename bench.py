@@ -24,13 +24,17 @@ Beside it, in the same line:
                 in one persistent launch replayed from a captured graph,
                 tile shape from the autotuner, beside the same products as
                 4096 separate calls on the same stream;
+  product_2048  the degree-2047 product: single-call host latency, and the
+                steady rate of 100 calls captured in one graph and replayed;
   gcd_32768     Euclidean division and remainder-sequence gcd of the degree
-                32768 / 32767 pair with a planted degree-1000 gcd;
+                32768 / 32767 pair with a planted degree-1000 gcd (time per
+                division step, grid syncs, updates/s against the VALU peak);
   served        a Poisson stream of 2048 gcd requests (degrees log-uniform
                 in [64, 16384], planted gcd, three primes) through the
                 continuous-batching server: saturated GCDs/s, then p50/p99
-                latency at 0.8 of that rate, beside the same trace served
-                one synchronous call per request (FIFO).
+                latency at 0.8 of that rate (and at 0.5, 1.0, 1.2), beside
+                the same trace served one synchronous call per request (FIFO)
+                at 0.8.
 """
 from __future__ import annotations
 
@@ -256,7 +260,7 @@ def run_one_call_trace(reqs, scale: float):
     return lat, span
 
 
-def bench_served(n_req: int, warm: int, load: float, baseline: bool) -> dict:
+def bench_served(n_req: int, warm: int, load: float, baseline: bool, loads=(0.5, 1.0, 1.2)) -> dict:
     import torch
     reqs = served_inputs(n_req + warm)
     warm_reqs, reqs = reqs[:warm], reqs[warm:]
@@ -276,6 +280,13 @@ def bench_served(n_req: int, warm: int, load: float, baseline: bool) -> dict:
            "gcds_per_s": round(len(reqs) / span, 1),
            "p50_ms": round(_pct(lat, 0.50), 3), "p99_ms": round(_pct(lat, 0.99), 3),
            "max_ms": round(max(lat), 3)}
+    sweep = [{"load": load, "gcds_per_s": out["gcds_per_s"], "p50_ms": out["p50_ms"], "p99_ms": out["p99_ms"]}]
+    for ld in loads:
+        sc = 1.0 / (ld * sat * mean_gap)
+        l2, sp2 = run_server_trace(reqs, sc)
+        sweep.append({"load": ld, "gcds_per_s": round(len(reqs) / sp2, 1), "p50_ms": round(_pct(l2, 0.50), 3),
+                      "p99_ms": round(_pct(l2, 0.99), 3)})
+    out["loads"] = sorted(sweep, key=lambda x: x["load"])
     if baseline:
         run_one_call_trace(warm_reqs[:16], 0.0)
         lat1, span1 = run_one_call_trace(reqs, scale)
@@ -286,6 +297,54 @@ def bench_served(n_req: int, warm: int, load: float, baseline: bool) -> dict:
         out["p99_ratio_one_call_over_served"] = round(out["one_call_per_instance"]["p99_ms"] / out["p99_ms"], 2)
     torch.cuda.synchronize()
     return out
+
+
+def bench_product_2048(reps: int) -> dict:
+    """The degree-2047 product: host wall time of one synchronous call
+    (launch-latency bound), and the steady rate of 100 asynchronous calls
+    captured in one graph and replayed."""
+    import torch
+    import paper_1402_0264_amd as pm
+    from paper_1402_0264_amd import gen
+    a_np, b_np = gen.product_2048()
+    p = gen.P_A
+    a, b = pm.to_device(a_np), pm.to_device(b_np)
+    work = float(a_np.size) * float(b_np.size)
+    pm.mul(a, b, p)
+    torch.cuda.synchronize()
+    lat = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        pm.mul(a, b, p)
+        lat.append((time.perf_counter() - t0) * 1e3)
+    stream = torch.cuda.Stream()
+    f = torch.empty(a_np.size + b_np.size - 1, dtype=torch.int32, device="cuda")
+    d_nf = torch.zeros(1, dtype=torch.int64, device="cuda")
+    d_st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    calls = 100
+    with torch.cuda.stream(stream):
+        for _ in range(3):          # scratch and plan exist before the capture
+            pm.mul_async(a, b, p, f, d_nf, d_st)
+    stream.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=stream):
+        for _ in range(calls):
+            pm.mul_async(a, b, p, f, d_nf, d_st)
+    graph.replay()
+    torch.cuda.synchronize()
+    ok = int(d_st.item()) == 0 and int(d_nf.item()) == a_np.size + b_np.size - 1
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    per = e0.elapsed_time(e1) / (10 * calls)
+    return {"workload": "product_2048: deg 2047 x deg 2047 over p=469762049",
+            "single_call_ms_median": round(sorted(lat)[len(lat) // 2], 4), "single_call_ms_min": round(min(lat), 4),
+            "graph_ms_per_product": round(per, 5), "graph_mulmods_per_s": round(work / (per * 1e-3), 1),
+            "graph_calls": calls, "device_checks_ok": ok}
 
 
 def bench_gcd(reps: int) -> dict:
@@ -320,6 +379,9 @@ def bench_gcd(reps: int) -> dict:
             "gcd_ms_median": round(t_gcd * 1e3, 4), "gcd_ms_min": round(min(times) * 1e3, 4),
             "gcds_per_s": round(1.0 / t_gcd, 2), "division_steps": st["steps"], "updates": st["updates"],
             "updates_per_s": round(st["updates"] / t_gcd, 1), "chunks": st["chunks"],
+            "ns_per_division_step": round(t_gcd * 1e9 / max(st["steps"], 1), 1),
+            "grid_syncs": st["chunks"],
+            "updates_frac_of_valu_peak": round(st["updates"] / t_gcd / PEAK_MULMOD_PER_S, 5),
             "gcd_equals_planted": ok}
 
 
@@ -427,6 +489,7 @@ def main() -> int:
         "roofline": roof,
     }
     pm.set_params()
+    out["product_2048"] = bench_product_2048(20)
     if not args.no_batched:
         out["batched_4096"] = bench_batched(10)
     if not args.no_gcd:

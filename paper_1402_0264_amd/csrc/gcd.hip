@@ -87,6 +87,7 @@ __global__ __launch_bounds__(GCD_THREADS) void gcd_multi_kernel(GcdArgs G) {
     StepDesc* desc = (StepDesc*)(tmp + 64 * E); // GCD_MAXSTEPS
     __shared__ ChunkOut s_out;
     __shared__ int64_t s_deg[2];
+    __shared__ StepLog s_log;
     const Field F = G.F;
     unsigned gen = __hip_atomic_load(&G.info->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     uint32_t* const A0 = G.buf;
@@ -94,6 +95,7 @@ __global__ __launch_bounds__(GCD_THREADS) void gcd_multi_kernel(GcdArgs G) {
     uint32_t* const A1 = G.buf + 2 * N;
     uint32_t* const B1 = G.buf + 3 * N;
 
+    if (tid == 0) steplog_reset(&s_log);
     int bad = 0;
     for (int64_t i = lo + tid; i < hi; i += GCD_THREADS) {
         uint32_t x = i < G.na ? G.a[i] : 0u;
@@ -149,7 +151,9 @@ __global__ __launch_bounds__(GCD_THREADS) void gcd_multi_kernel(GcdArgs G) {
             uint32_t hA[E], hB[E];
             load_heads<E>(Acur, Bcur, dA, dB, hA, hB);
             int n, big;
-            head_run_m<E>(hA, hB, (int)dA, (int)dB, G.s, F, M, desc, &s_out, n, big);
+            head_run_log<E>(hA, hB, (int)dA, (int)dB, G.s, F, desc, &s_log, &s_out, n, big);
+        } else if (wave == 1) {
+            m_build_live(desc, &s_log, F, M);
         }
         __syncthreads();
         ChunkOut res = s_out;
@@ -199,6 +203,7 @@ __global__ __launch_bounds__(GCD_THREADS) void gcd_multi_kernel(GcdArgs G) {
                 }
             }
         }
+        if (tid == 0) steplog_reset(&s_log);  // read by the next chunk after the barrier
         grid_sync(G.info, G.groups, gen);
         cur ^= 1;
         dA = res.dA;
@@ -247,13 +252,15 @@ __device__ void gcd_instance(const GcdJob& J, int s, int64_t cap, uint32_t* smem
     StepDesc* desc = (StepDesc*)(tmp + 64 * E); // GCD_MAXSTEPS
     __shared__ ChunkOut s_out[2];
     __shared__ int64_t s_deg[2];
-    // apply work: waves 1.. own the positions, wave 0 runs the heads
-    constexpr int NA = NT - 64;
+    __shared__ StepLog s_log;
+    // wave 0 runs the heads, wave 1 composes M, waves 2.. own the positions
+    constexpr int NA = NT - 128;
     constexpr int PPA = (NT * PPT + NA - 1) / NA;
 
     const int64_t n = J.na > J.nb ? J.na : J.nb;
     int bad = n > cap;
     if (tid < PADLO) { A[tid - PADLO] = 0u; B[tid - PADLO] = 0u; }
+    if (tid == 0) steplog_reset(&s_log);
     if (J.fresh) {
         for (int64_t i = tid; i < cap; i += NT) {
             uint32_t x = i < J.na ? __hip_atomic_load(J.a + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) : 0u;
@@ -297,15 +304,19 @@ __device__ void gcd_instance(const GcdJob& J, int s, int64_t cap, uint32_t* smem
             uint32_t hA[E], hB[E];
             load_heads<E>(A, B, dA, dB, hA, hB);
             int nst, big;
-            head_run_m<E>(hA, hB, (int)dA, (int)dB, s, F, Mbuf, desc, &s_out[0], nst, big);
+            head_run_log<E>(hA, hB, (int)dA, (int)dB, s, F, desc, &s_log, &s_out[0], nst, big);
+        } else if (wave == 1) {
+            m_build_live(desc, &s_log, F, Mbuf);
         }
         __syncthreads();
+        if (tid == 0) steplog_reset(&s_log);
+        __syncthreads();
     }
-    // Each chunk: waves 1.. compute M * (A, B) at every position into
+    // Each chunk: waves 2.. compute M * (A, B) at every position into
     // registers while wave 0 computes the top of the new pair (the next
     // chunk's heads) from the same chunk-start data and runs the next
-    // chunk's steps into the other M buffer; after a barrier the new pair is
-    // written back. A chunk whose heads ran out (degree unknown) or that is
+    // chunk's steps, which wave 1 composes into the other M buffer; after a
+    // barrier the new pair is written back. A chunk whose heads ran out (degree unknown) or that is
     // one big step is followed by the serial path: write, rescan, then heads.
     for (;;) {
         if (dA < 0 || dB < 0) break;
@@ -337,21 +348,24 @@ __device__ void gcd_instance(const GcdJob& J, int s, int64_t cap, uint32_t* smem
                         hB[e] = PB >= 0 ? apply_row_at(A, B, PB, res.S, Mc + 128, Mc + 192, F) : 0u;
                     }
                     int nst, big;
-                    head_run_m<E>(hA, hB, (int)res.dA, (int)res.dB, s, F, Mn, desc, &s_out[mb ^ 1], nst, big);
+                    head_run_log<E>(hA, hB, (int)res.dA, (int)res.dB, s, F, desc, &s_log, &s_out[mb ^ 1], nst, big);
                 }
+            } else if (wave == 1) {
+                if (pipe) m_build_live(desc, &s_log, F, Mn);
             } else {
 #pragma unroll
                 for (int j = 0; j < PPA; j++) {
-                    const int P = (tid - 64) + j * NA;
+                    const int P = (tid - 128) + j * NA;
                     nA[j] = nB[j] = 0u;
                     if (P <= top) apply_m_at(A, B, P, res.S, Mc, F, nA[j], nB[j]);
                 }
             }
             __syncthreads();
-            if (wave != 0) {
+            if (tid == 0) steplog_reset(&s_log);  // the run above is over
+            if (wave >= 2) {
 #pragma unroll
                 for (int j = 0; j < PPA; j++) {
-                    const int P = (tid - 64) + j * NA;
+                    const int P = (tid - 128) + j * NA;
                     if (P <= top) {
                         A[P] = P <= res.dA ? nA[j] : 0u;
                         B[P] = P <= res.dB ? nB[j] : 0u;
@@ -391,8 +405,12 @@ __device__ void gcd_instance(const GcdJob& J, int s, int64_t cap, uint32_t* smem
                     uint32_t hA[E], hB[E];
                     load_heads<E>(A, B, dA, dB, hA, hB);
                     int nst, big;
-                    head_run_m<E>(hA, hB, (int)dA, (int)dB, s, F, Mn, desc, &s_out[mb ^ 1], nst, big);
+                    head_run_log<E>(hA, hB, (int)dA, (int)dB, s, F, desc, &s_log, &s_out[mb ^ 1], nst, big);
+                } else if (wave == 1) {
+                    m_build_live(desc, &s_log, F, Mn);
                 }
+                __syncthreads();
+                if (tid == 0) steplog_reset(&s_log);
                 __syncthreads();
             }
         }

@@ -8,12 +8,13 @@
 // degrees of all remainders are the paper's and no inverse is needed.
 //
 // A chunk (the paper's s steps per launch, Sec. 6.2) has two parts:
-//  1. head_run_m: one wave runs up to s steps on the heads of A and B (their
-//     top coefficients, held in registers, element e of lane l = index
-//     l + 64e below the leading one). A head entry stays exact while every
-//     entry it was computed from was loaded; the run stops before the next
-//     leading coefficient would be unknown, or when the total shift of the
-//     chunk would exceed MAXSHIFT. Each step is also applied to the 2x2
+//  1. head_run_log: one wave runs up to s steps on the heads of A and B
+//     (their top coefficients, held in registers, element e of lane l =
+//     index l + 64e below the leading one). A head entry stays exact while
+//     every entry it was computed from was loaded; the run stops before the
+//     next leading coefficient would be unknown, or when the total shift of
+//     the chunk would exceed MAXSHIFT. Each step is published as soon as it
+//     is known, and a second wave (m_build_live) applies it to the 2x2
 //     matrix of polynomials M = [[alpha, beta], [gamma, delta]] (degree <=
 //     the total shift S; lane k holds coefficient k of each entry), so that
 //     (A', B') = M * (A, B) for the chunk-start A, B.
@@ -87,19 +88,27 @@ __device__ __forceinline__ uint32_t lanes_up_any(uint32_t x, int d) {
     return lanes_up(x, d);
 }
 
-// Head run by one whole wave, composing M on the fly. hA/hB: the heads
-// (entry i = coefficient of x^(deg - i)), exact for i < 64*E. Each step
-// reduces the operand of higher degree in the heads and applies the same
-// step to the rows of M held in registers (lane k = coefficient k of alpha,
-// beta, gamma, delta), so no step list has to be replayed afterwards. The
-// reduced operand is chosen with uniform selects rather than two copies of
-// the code. Writes M to LDS (4 rows of 64 words) unless the chunk is a
-// single big step, which is recorded in desc[0] instead; returns the chunk
-// summary through *out (lane 0 writes) and the step count and big flag in
-// n_out / big_out.
+// Progress of a head run, read by the wave that composes M while the run
+// goes on. Reset (prog = 0, end = -1) before every run, behind a barrier.
+struct StepLog {
+    int prog;  // steps published in desc[]
+    int end;   // total steps once the run has finished, else -1
+};
+
+__device__ __forceinline__ void steplog_reset(StepLog* L) {
+    L->prog = 0;
+    L->end = -1;
+}
+
+// Head run by one whole wave. hA/hB: the heads (entry i = coefficient of
+// x^(deg - i)), exact for i < 64*E. Each step reduces the operand of higher
+// degree (chosen with uniform selects, not two copies of the code) and is
+// published in desc[] for the M builder on another wave (m_build_live).
+// Returns the chunk summary through *out (lane 0 writes) and the step
+// count and big flag in n_out / big_out; a big step is desc[0].
 template <int E>
-__device__ void head_run_m(uint32_t (&hA)[E], uint32_t (&hB)[E], int dA, int dB, int s, const Field& F,
-                           uint32_t* M, StepDesc* desc, ChunkOut* out, int& n_out, int& big_out) {
+__device__ void head_run_log(uint32_t (&hA)[E], uint32_t (&hB)[E], int dA, int dB, int s, const Field& F,
+                             StepDesc* desc, StepLog* L, ChunkOut* out, int& n_out, int& big_out) {
     const int lane = threadIdx.x & 63;
     constexpr int H = 64 * E;
     dA = uni(dA);
@@ -107,7 +116,6 @@ __device__ void head_run_m(uint32_t (&hA)[E], uint32_t (&hB)[E], int dA, int dB,
     s = uni(s);
     int vA = H, vB = H, S = 0, n = 0, unkA = 0, unkB = 0, big = 0;
     int64_t upd = 0;
-    uint32_t al = lane == 0 ? 1u : 0u, be = 0u, ga = 0u, de = lane == 0 ? 1u : 0u;
     while (n < s && dA >= 0 && dB >= 0) {
         const bool redA = dA >= dB;
         const int d = redA ? dA - dB : dB - dA;
@@ -119,6 +127,10 @@ __device__ void head_run_m(uint32_t (&hA)[E], uint32_t (&hB)[E], int dA, int dB,
         const uint32_t lcB = (uint32_t)__builtin_amdgcn_readfirstlane((int)hB[0]);
         const uint32_t m1 = redA ? lcB : lcA;
         const uint32_t m2 = F.p - (redA ? lcA : lcB);
+        if (lane == 0) {
+            desc[n] = StepDesc{m1, m2, d, redA ? 0 : 1};
+            __hip_atomic_store(&L->prog, n + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
         const int v = vA < vB ? vA : vB;
         // X <- REDC(m1 X + m2 Y) on the heads; entries at or beyond v cleared
         uint32_t x[E];
@@ -137,22 +149,8 @@ __device__ void head_run_m(uint32_t (&hA)[E], uint32_t (&hB)[E], int dA, int dB,
 #pragma unroll
         for (int e = E - 1; e >= 0; e--)
             if (msk[e]) delta = 64 * e + (int)__builtin_ctzll(msk[e]);
-        if (big) {
-            if (lane == 0) desc[0] = StepDesc{m1, m2, d, redA ? 0 : 1};
-        } else {
-            // the same step on M: (rows of X) <- REDC(m1 (rows of X) + m2 x^d (rows of Y))
-            const uint32_t P = redA ? al : ga, Q = redA ? be : de;
-            const uint32_t R = lanes_up_any(redA ? ga : al, d);
-            const uint32_t T = lanes_up_any(redA ? de : be, d);
-            const uint32_t P2 = redc((uint64_t)m1 * P + (uint64_t)m2 * R, F);
-            const uint32_t Q2 = redc((uint64_t)m1 * Q + (uint64_t)m2 * T, F);
-            al = redA ? P2 : al;
-            be = redA ? Q2 : be;
-            ga = redA ? ga : P2;
-            de = redA ? de : Q2;
-            S += d;
-        }
         n++;
+        if (!big) S += d;
         upd += (redA ? dB : dA) + 1;
         int nd, nv;
         const int dX = redA ? dA : dB;
@@ -178,12 +176,6 @@ __device__ void head_run_m(uint32_t (&hA)[E], uint32_t (&hB)[E], int dA, int dB,
     }
     n_out = n;
     big_out = big;
-    if (!big) {
-        M[lane] = al;
-        M[64 + lane] = be;
-        M[128 + lane] = ga;
-        M[192 + lane] = de;
-    }
     if (lane == 0) {
         out->dA = dA;
         out->dB = dB;
@@ -193,7 +185,44 @@ __device__ void head_run_m(uint32_t (&hA)[E], uint32_t (&hB)[E], int dA, int dB,
         out->unkA = unkA;
         out->unkB = unkB;
         out->big = big;
+        __hip_atomic_store(&L->end, n, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
+}
+
+// Composes M from the steps of a head run while it goes on (one whole
+// wave, lane k = coefficient k of alpha, beta, gamma, delta): each published
+// step (rows of X) <- REDC(m1 (rows of X) + m2 x^d (rows of Y)) is applied
+// as soon as it appears. Writes M to LDS as 4 rows of 64 words. Waits only
+// on the head run, which never waits on it.
+__device__ void m_build_live(const StepDesc* desc, StepLog* L, const Field& F, uint32_t* M) {
+    const int lane = threadIdx.x & 63;
+    uint32_t al = lane == 0 ? 1u : 0u, be = 0u, ga = 0u, de = lane == 0 ? 1u : 0u;
+    int k = 0;
+    for (;;) {
+        const int end = uni(__hip_atomic_load(&L->end, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP));
+        const int avail = uni(__hip_atomic_load(&L->prog, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP));
+        for (; k < avail; k++) {
+            const StepDesc D = desc[k];
+            const uint32_t m1 = uni(D.m1), m2 = uni(D.m2);
+            const int d = uni(D.d);
+            const bool redA = uni(D.which) == 0;
+            const uint32_t P = redA ? al : ga, Q = redA ? be : de;
+            const uint32_t R = lanes_up_any(redA ? ga : al, d);
+            const uint32_t T = lanes_up_any(redA ? de : be, d);
+            const uint32_t P2 = redc((uint64_t)m1 * P + (uint64_t)m2 * R, F);
+            const uint32_t Q2 = redc((uint64_t)m1 * Q + (uint64_t)m2 * T, F);
+            al = redA ? P2 : al;
+            be = redA ? Q2 : be;
+            ga = redA ? ga : P2;
+            de = redA ? de : Q2;
+        }
+        if (end >= 0 && k >= end) break;
+        if (k >= avail) __builtin_amdgcn_s_sleep(1);
+    }
+    M[lane] = al;
+    M[64 + lane] = be;
+    M[128 + lane] = ga;
+    M[192 + lane] = de;
 }
 
 // New coefficients at one position: (A'[P], B'[P]) from the chunk-start
