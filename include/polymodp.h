@@ -187,7 +187,7 @@ typedef struct {
     int32_t max_inflight;  /* requests admitted at once (0 = 1024)             */
     int32_t streams;       /* unused, 0                                        */
     int64_t arena_words;   /* budget of resident input words (0 = 32 Mi)       */
-    int32_t s;             /* Euclidean steps fused per chunk (0 = 64)         */
+    int32_t s;             /* Euclidean steps fused per chunk (0 = 128)        */
     int32_t reserved;
 } pm_server_opts;
 typedef struct {
@@ -231,13 +231,13 @@ void pm_last_gcd_stats(pm_gcd_stats *out);
  *   mul_s   : b-coefficients per thread-block in the product (0 = default)
  *   mul_r   : outputs per thread in the product (1,2,4,8,16,32; 0 = default)
  *   div_s   : division steps fused per pass in the quotient (1..64; 0 = 64)
- *   gcd_s   : Euclidean steps fused per chunk (1..256; 0 = 64)
+ *   gcd_s   : Euclidean steps fused per chunk (1..256; 0 = 128)
  *   mul_engine : which kernels compute a product (poly_mul_modp and
  *             poly_mul_modp_async): 0 = automatic (the matrix cores for
  *             products with n_a * n_b >= 2^22 and min(n_a, n_b) >= 256
  *             unless mul_s or mul_r is set), 1 = the VALU tile kernels
  *             (Sec. 5's layout, tuned by mul_s and mul_r), 2 = the matrix
- *             cores (int8 digit products; s fixed at 2048). Results are
+ *             cores (int8 digit products; s fixed at 4096). Results are
  *             identical.
  * The settings are per process and apply to later calls.
  */

@@ -601,7 +601,7 @@ pm_status poly_gcd_modp_batch(const pm_gcd_item* items, int32_t count, pm_gcd_re
     HIP_TRY(hipMemcpyAsync(d_order, order.data(), order.size() * sizeof(int32_t), hipMemcpyHostToDevice, s),
             "copy order");
     pm_params pp = params_now();
-    const int gs = pp.gcd_s > 0 ? pp.gcd_s : 64;
+    const int gs = pp.gcd_s > 0 ? pp.gcd_s : 128;
     if (!large.empty())
         HIP_TRY(pm::gcd_batch_launch(d_jobs, d_order, (int)large.size(), 1, gs, s), "gcd batch launch");
     if (!small.empty())

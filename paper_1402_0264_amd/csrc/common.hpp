@@ -122,4 +122,28 @@ struct CallInfo {
     uint32_t bar_gen;
 };
 
+// Grid-wide barrier of a cooperative launch (all nblocks resident): one
+// arrival counter and a generation word in device memory (CallInfo). gen
+// is the caller's copy of the generation, read once at kernel start.
+__device__ __forceinline__ void grid_sync(CallInfo* info, unsigned nblocks, unsigned& gen) {
+    __threadfence();
+    __syncthreads();
+    if (nblocks > 1) {
+        if (threadIdx.x == 0) {
+            unsigned arrived = atomicAdd(&info->bar_count, 1u);
+            if (arrived == nblocks - 1) {
+                atomicExch(&info->bar_count, 0u);
+                __threadfence();
+                atomicAdd(&info->bar_gen, 1u);
+            } else {
+                while (__hip_atomic_load(&info->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen)
+                    __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        gen++;
+        __syncthreads();
+        __threadfence();
+    }
+}
+
 }  // namespace pm

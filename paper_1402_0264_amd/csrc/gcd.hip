@@ -38,27 +38,6 @@ struct GcdArgs {
     int groups, slice, s;
 };
 
-__device__ __forceinline__ void grid_sync(CallInfo* info, unsigned nblocks, unsigned& gen) {
-    __threadfence();
-    __syncthreads();
-    if (nblocks > 1) {
-        if (threadIdx.x == 0) {
-            unsigned arrived = atomicAdd(&info->bar_count, 1u);
-            if (arrived == nblocks - 1) {
-                atomicExch(&info->bar_count, 0u);
-                __threadfence();
-                atomicAdd(&info->bar_gen, 1u);
-            } else {
-                while (__hip_atomic_load(&info->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen)
-                    __builtin_amdgcn_s_sleep(1);
-            }
-        }
-        gen++;
-        __syncthreads();
-        __threadfence();
-    }
-}
-
 template <int E>
 __device__ __forceinline__ void load_heads(const uint32_t* A, const uint32_t* B, int64_t dA, int64_t dB,
                                            uint32_t (&hA)[E], uint32_t (&hB)[E]) {
@@ -508,9 +487,9 @@ size_t batch_lds_bytes(int64_t cap) {
 
 GcdPlan gcd_default_plan(int64_t n, int num_cus, int s) {
     GcdPlan P{};
-    P.s = s > 0 ? s : 64;
+    P.s = s > 0 ? s : 128;
     if (P.s > GCD_MAXSTEPS) P.s = GCD_MAXSTEPS;
-    P.head = P.s <= 96 ? 128 : 256;
+    P.head = 128;  // a chunk has at most 2(S+1) <= 128 steps: about 64 entries of each head
     P.slice = 256;
     int64_t groups = (n + P.slice - 1) / P.slice;
     const int64_t max_groups = 2LL * num_cus;
@@ -538,18 +517,17 @@ hipError_t gcd_launch(const uint32_t* a, int64_t na, const uint32_t* b, int64_t 
     A.flags = scratch + 4 * A.N;
     A.g = g; A.g_cap = g_cap; A.F = F; A.info = info;
     A.groups = plan.groups; A.slice = plan.slice; A.s = plan.s;
-    const int E = plan.head / 64;
+    constexpr int E = 2;  // 128-entry heads (GcdPlan::head)
     size_t lds = (size_t)(2 * (plan.slice + GCD_MAXSHIFT + 1) + 256 + 64 * E) * sizeof(uint32_t) +
                  GCD_MAXSTEPS * sizeof(StepDesc);
     void* args[] = {&A};
-    const void* fn = E == 2 ? (const void*)gcd_multi_kernel<2> : (const void*)gcd_multi_kernel<4>;
     TimingScope ts("gcd_multi_kernel", stream);
     if (plan.groups == 1) {
-        if (E == 2) hipLaunchKernelGGL((gcd_multi_kernel<2>), dim3(1), dim3(GCD_THREADS), lds, stream, A);
-        else hipLaunchKernelGGL((gcd_multi_kernel<4>), dim3(1), dim3(GCD_THREADS), lds, stream, A);
+        hipLaunchKernelGGL((gcd_multi_kernel<E>), dim3(1), dim3(GCD_THREADS), lds, stream, A);
         return hipGetLastError();
     }
-    return hipLaunchCooperativeKernel(fn, dim3(plan.groups), dim3(GCD_THREADS), args, (unsigned)lds, stream);
+    return hipLaunchCooperativeKernel((const void*)gcd_multi_kernel<E>, dim3(plan.groups), dim3(GCD_THREADS), args,
+                                      (unsigned)lds, stream);
 }
 
 int64_t gcd_batch_cap(int kind) { return kind == 0 ? 256 * 16 : 1024 * 17; }
@@ -574,30 +552,17 @@ hipError_t gcd_worker_launch(const GcdJob* jobs, const uint32_t* order, uint32_t
 hipError_t gcd_batch_launch(const GcdJob* d_jobs, const int32_t* d_order, int njobs, int kind, int s,
                             hipStream_t stream) {
     if (njobs <= 0) return hipSuccess;
-    if (s > 96) {
-        if (kind == 0) {
-            size_t lds = batch_lds_bytes<256, 16, 4>(gcd_batch_cap(0));
-            TimingScope ts("gcd_batch_kernel", stream);
-            hipLaunchKernelGGL((gcd_batch_kernel<256, 16, 4>), dim3(njobs), dim3(256), lds, stream, d_jobs, d_order,
-                               njobs, s, gcd_batch_cap(0));
-        } else {
-            size_t lds = batch_lds_bytes<1024, 17, 4>(gcd_batch_cap(1));
-            TimingScope ts("gcd_batch_kernel", stream);
-            hipLaunchKernelGGL((gcd_batch_kernel<1024, 17, 4>), dim3(njobs), dim3(1024), lds, stream, d_jobs,
-                               d_order, njobs, s, gcd_batch_cap(1));
-        }
+    // 128-entry heads for any s (see gcd_worker_launch)
+    if (kind == 0) {
+        size_t lds = batch_lds_bytes<256, 16, 2>(gcd_batch_cap(0));
+        TimingScope ts("gcd_batch_kernel", stream);
+        hipLaunchKernelGGL((gcd_batch_kernel<256, 16, 2>), dim3(njobs), dim3(256), lds, stream, d_jobs, d_order,
+                           njobs, s, gcd_batch_cap(0));
     } else {
-        if (kind == 0) {
-            size_t lds = batch_lds_bytes<256, 16, 2>(gcd_batch_cap(0));
-            TimingScope ts("gcd_batch_kernel", stream);
-            hipLaunchKernelGGL((gcd_batch_kernel<256, 16, 2>), dim3(njobs), dim3(256), lds, stream, d_jobs, d_order,
-                               njobs, s, gcd_batch_cap(0));
-        } else {
-            size_t lds = batch_lds_bytes<1024, 17, 2>(gcd_batch_cap(1));
-            TimingScope ts("gcd_batch_kernel", stream);
-            hipLaunchKernelGGL((gcd_batch_kernel<1024, 17, 2>), dim3(njobs), dim3(1024), lds, stream, d_jobs,
-                               d_order, njobs, s, gcd_batch_cap(1));
-        }
+        size_t lds = batch_lds_bytes<1024, 17, 2>(gcd_batch_cap(1));
+        TimingScope ts("gcd_batch_kernel", stream);
+        hipLaunchKernelGGL((gcd_batch_kernel<1024, 17, 2>), dim3(njobs), dim3(1024), lds, stream, d_jobs, d_order,
+                           njobs, s, gcd_batch_cap(1));
     }
     return hipGetLastError();
 }

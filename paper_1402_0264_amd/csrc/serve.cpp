@@ -178,7 +178,7 @@ pm_status pm_server_create(const pm_server_opts* opts, pm_server** out) {
         delete S;
         return pm::server_fail(PM_EINVAL, "s must be in [0, 256]");
     }
-    if (S->opt.s == 0) S->opt.s = 64;
+    if (S->opt.s == 0) S->opt.s = 128;
     (void)hipGetDevice(&S->device);
     S->t0 = std::chrono::steady_clock::now();
     S->cap = pm::gcd_batch_cap(1);

@@ -1,7 +1,22 @@
-"""Sweep of the program parameter s for the plain product (Sec. 5), beside
-the model's estimate.
+"""Sweeps of the program parameter s beside the model's estimate: the plain
+product (Sec. 5), Euclidean division with a large quotient (Sec. 3) and the
+Euclidean gcd (Sec. 6), where s = 1 is the paper's naive kernel.
 
-    python -m paper_1402_0264_amd.sweep [--n 65536] [--s 1,2,4,...,512] [--reps 5]
+    python -m paper_1402_0264_amd.sweep [--op mul] [--n 65536] [--s 1,2,4,...,512] [--reps 5]
+    python -m paper_1402_0264_amd.sweep --op div [--n 65536] [--s 1,2,...,64]
+    python -m paper_1402_0264_amd.sweep --op gcd [--s 1,2,...,256]
+
+Division: a of n terms and b of n/2 terms (quotient of n/2 + 1 terms, the
+paper's n = 2m case); s is the number of division steps fused per pass over
+the heads. The model's T(s) (Corollary 1 with the printed N, L, C of the
+optimized division) decreases with s, so its prediction is "as large as
+fits"; the paper's printed R = T_1/T_s at s = Z/7 is reported beside it.
+
+Gcd: the degree 32768 / 32767 pair with a planted degree-1000 gcd; s caps
+the division steps fused per chunk (one grid barrier each). The model's
+T(s) is minimised at s* = sqrt(8U(2n+m)/3) (our derivation from the printed
+N, L, C); the paper measured 4.24x from s = 1 to s = 512 at 10000 x 9000
+(Table 2).
 
 s keeps the paper's meaning: the number of coefficients of b that one
 thread-block multiplies (so b is cut into m/s chunks and the partial sums
@@ -29,12 +44,108 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 
+def _median_ms(fn, reps: int) -> float:
+    import time
+    import torch
+    times = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t0) * 1e3)
+    times.sort()
+    return times[len(times) // 2]
+
+
+def sweep_div(args) -> int:
+    import torch
+    import paper_1402_0264_amd as pm
+    from paper_1402_0264_amd import gen, mmm
+    torch.cuda.set_device(0)
+    n, m = args.n, args.n // 2
+    st = gen.Stream(gen.SEED_BASE + 6)
+    a_np, b_np = st.uniform_poly(n - 1, gen.P_A), st.uniform_poly(m - 1, gen.P_A)
+    a, b = pm.to_device(a_np), pm.to_device(b_np)
+    svals = [int(x) for x in (args.s or "1,2,4,8,16,32,64").split(",")]
+    ref = None
+    rows = []
+    t1 = mmm.div_time(n, m, 1, mmm.U_THROUGHPUT)
+    for s in svals:
+        pm.set_params(div_s=s)
+        q, r = pm.divrem(a, b, gen.P_A)
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = (q.clone(), r.clone())
+        same = bool(torch.equal(q, ref[0]) and torch.equal(r, ref[1]))
+        ms = _median_ms(lambda: pm.divrem(a, b, gen.P_A), args.reps)
+        rec = {"op": "divrem", "s": s, "ms": round(ms, 4), "quotient_terms": int(q.numel()),
+               "model_T_over_T1": round(mmm.div_time(n, m, s, mmm.U_THROUGHPUT) / t1, 4),
+               "identical_to_first": same}
+        rows.append(rec)
+        print(json.dumps(rec), flush=True)
+    pm.set_params()
+    best = min(rows, key=lambda x: x["ms"])
+    print(json.dumps({"summary": True, "op": "divrem", "n": n, "m": m, "measured_best_s": best["s"],
+                      "measured_T1_over_Tbest": round(rows[0]["ms"] / best["ms"], 3),
+                      "model_best_s": min(rows, key=lambda x: x["model_T_over_T1"])["s"],
+                      "paper_R_printed_at_Z": round(mmm.div_ratio_printed(mmm.Z_MI355X, mmm.U_THROUGHPUT), 3),
+                      "all_identical": all(x["identical_to_first"] for x in rows)}), flush=True)
+    return 0
+
+
+def sweep_gcd(args) -> int:
+    import numpy as np
+    import torch
+    import paper_1402_0264_amd as pm
+    from paper_1402_0264_amd import gen, mmm
+    torch.cuda.set_device(0)
+    pl = gen.gcd_32768()
+    p = pl.p
+    g = pm.to_device(pl.g)
+    a = pm.mul(g, pm.to_device(pl.u), p)
+    b = pm.mul(g, pm.to_device(pl.v), p)
+    n, m = a.numel() - 1, b.numel() - 1
+    svals = [int(x) for x in (args.s or "1,2,4,8,16,32,64,128,256").split(",")]
+    rows = []
+    t1 = mmm.gcd_time(n, m, 1, mmm.U_THROUGHPUT)
+    for s in svals:
+        pm.set_params(gcd_s=s)
+        out = pm.gcd(a, b, p)
+        torch.cuda.synchronize()
+        ok = bool(np.array_equal(pm.to_numpy(out), pl.g))
+        ms = _median_ms(lambda: pm.gcd(a, b, p), args.reps)
+        stt = pm.last_gcd_stats()
+        rec = {"op": "gcd", "s": s, "ms": round(ms, 3), "chunks": stt["chunks"], "steps": stt["steps"],
+               "ns_per_step": round(ms * 1e6 / max(stt["steps"], 1), 1),
+               "model_T_over_T1": round(mmm.gcd_time(n, m, s, mmm.U_THROUGHPUT) / t1, 4),
+               "gcd_equals_planted": ok}
+        rows.append(rec)
+        print(json.dumps(rec), flush=True)
+    pm.set_params()
+    best = min(rows, key=lambda x: x["ms"])
+    print(json.dumps({"summary": True, "op": "gcd", "n": n, "m": m, "measured_best_s": best["s"],
+                      "measured_T1_over_Tbest": round(rows[0]["ms"] / best["ms"], 3),
+                      "model_s_star": round(mmm.gcd_s_star(n, m, mmm.U_THROUGHPUT), 1),
+                      "model_T1_over_T_at_best": round(1.0 / min(x["model_T_over_T1"] for x in rows), 3),
+                      "paper_table2_s1_over_s512": 4.24,
+                      "all_correct": all(x["gcd_equals_planted"] for x in rows)}), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
+    ap.add_argument("--op", choices=("mul", "div", "gcd"), default="mul")
     ap.add_argument("--n", type=int, default=65536)
-    ap.add_argument("--s", default="1,2,4,8,16,32,64,128,256,512,1024,2048,4096")
+    ap.add_argument("--s", default=None)
     ap.add_argument("--reps", type=int, default=5)
     args = ap.parse_args()
+    if args.op == "div":
+        return sweep_div(args)
+    if args.op == "gcd":
+        return sweep_gcd(args)
+    if args.s is None:
+        args.s = "1,2,4,8,16,32,64,128,256,512,1024,2048,4096"
     import torch
     import paper_1402_0264_amd as pm
     from paper_1402_0264_amd import gen, mmm
