@@ -525,7 +525,7 @@ pm_status poly_divrem_modp(const uint32_t* a, int64_t na, const uint32_t* b, int
     if ((st = pool_get(s, pm::divrem_head_words(na), &P))) return st;
     pm_params pp = params_now();
     HIP_TRY(pm::divrem_head_launch(a, na, b, nb, F, q, q_cap, r_cap, P->words, P->d_info,
-                                   pp.div_s > 0 ? pp.div_s : 64, s),
+                                   pp.div_s > 0 ? pp.div_s : 64, num_cus(), s),
             "divrem head launch");
     if ((st = read_info(P, s))) return st;
     const pm::CallInfo I = *P->h_info;

@@ -102,18 +102,23 @@ hipError_t mulx_launch(const uint32_t* a, int64_t na, const uint32_t* b, int64_t
                        hipStream_t stream);
 
 // ----------------------------------------------------------------- division
-// Euclidean division (Sec. 3) runs in two launches around one host read of
-// the degrees: divrem_head_launch validates the inputs, finds deg a and
-// deg b, and computes the whole quotient from the heads of a and b (the
-// division steps, s at a time); the remainder r = a - q*b restricted to
-// exponents below deg b is then one product launch with a subtracting
-// epilogue (mul_launch with sub_from = a), and trim_launch finds its length.
+// Euclidean division (Sec. 3) runs in two steps around one host read of the
+// degrees: divrem_head_launch validates the inputs, finds deg a and deg b,
+// and computes the whole quotient from the head of a and b (the division
+// steps, s at a time, on up to num_cus cooperating blocks); the remainder
+// r = a - q*b restricted to exponents below deg b is then one product launch
+// with a subtracting epilogue (mul_launch with sub_from = a), and
+// trim_launch finds its length.
 constexpr int DIV_THREADS = 256;
-// Scratch words for the head of a (deg a - deg b + 1 words at most).
-inline int64_t divrem_head_words(int64_t na) { return na > 0 ? na : 1; }
+// Scratch words: the head of a (deg a - deg b + 1 <= na words) and one
+// 64-bit published word per quotient term.
+inline int64_t divrem_head_words(int64_t na) {
+    const int64_t w = na > 0 ? na : 1;
+    return ((w + 1) & ~1LL) + 2 * w;
+}
 hipError_t divrem_head_launch(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb,
                               const Field& F, uint32_t* q, int64_t q_cap, int64_t r_cap,
-                              uint32_t* head, CallInfo* info, int s, hipStream_t stream);
+                              uint32_t* head, CallInfo* info, int s, int num_cus, hipStream_t stream);
 // info->n1 = 1 + (largest k < n with r[k] != 0), or 0.
 hipError_t trim_launch(const uint32_t* r, int64_t n, CallInfo* info, hipStream_t stream);
 // Degrees and range check only (info->deg_a, deg_b, status).

@@ -235,6 +235,49 @@ def test_divrem_invariant_under_s(s):
     assert same(host(q), wq) and same(host(r), wr)
 
 
+# Long quotients run on many cooperating blocks (runs of about 512 head
+# positions each); divisors from degree 1 up, every s kind (1, odd, 64).
+LONG_DIV = [(40000, 3000, 1), (40000, 3000, 3), (40000, 3000, 17), (40000, 3000, 64), (50000, 2, 64),
+            (50000, 40, 7), (20000, 19000, 64), (70000, 600, 64), (9000, 70, 64)]
+
+
+@pytest.mark.parametrize("na,nb,s", LONG_DIV)
+def test_divrem_long_quotient(na, nb, s):
+    p = gen.P_B
+    st = gen.Stream(204 + na % 1000 + nb + s)
+    a, b = rnd(st, na, p), rnd(st, nb, p)
+    wq, wr = oracle.divrem(a, b, p)
+    pm.set_params(div_s=s)
+    try:
+        q, r = pm.divrem(dev(a), dev(b), p)
+    finally:
+        pm.set_params()
+    assert same(host(q), wq) and same(host(r), wr), (na, nb, s)
+
+
+def test_divrem_head_longer_than_planned():
+    # zeros above the top coefficient of b: the head is longer than the
+    # lengths suggest, so blocks own several runs of it
+    p = gen.P_A
+    st = gen.Stream(205)
+    a = rnd(st, 30000, p)
+    b = np.concatenate([rnd(st, 1000, p), np.zeros(20000, dtype=np.uint32)])
+    q, r = pm.divrem(dev(a), dev(b), p)
+    wq, wr = oracle.divrem(a, b, p)
+    assert host(q).size == 29001
+    assert same(host(q), wq) and same(host(r), wr)
+
+
+def test_divrem_full_size_65536_by_32768():
+    # the division workload of the s sweep: 32769 quotient terms
+    p = gen.P_A
+    st = gen.Stream(206)
+    a, b = rnd(st, 65536, p), rnd(st, 32768, p)
+    q, r = pm.divrem(dev(a), dev(b), p)
+    wq, wr = oracle.divrem(a, b, p)
+    assert same(host(q), wq) and same(host(r), wr)
+
+
 def test_divrem_gcd_workload():
     pl = gen.gcd_32768()
     p = pl.p
