@@ -26,6 +26,8 @@ Beside it, in the same line:
                 4096 separate calls on the same stream;
   product_2048  the degree-2047 product: single-call host latency, and the
                 steady rate of 100 calls captured in one graph and replayed;
+  divrem_65536  Euclidean division with a long quotient: degree 65535 by
+                degree 32767 (32769 quotient terms) at the default s;
   gcd_32768     Euclidean division and remainder-sequence gcd of the degree
                 32768 / 32767 pair with a planted degree-1000 gcd (time per
                 division step, grid syncs, updates/s against the VALU peak);
@@ -385,6 +387,33 @@ def bench_gcd(reps: int) -> dict:
             "gcd_equals_planted": ok}
 
 
+def bench_divrem(reps: int) -> dict:
+    """Euclidean division with a long quotient: a of degree 65535 by b of
+    degree 32767 (32769 quotient terms), at the default s; median of reps
+    synchronous calls (both host reads of the call included)."""
+    import torch
+    import paper_1402_0264_amd as pm
+    from paper_1402_0264_amd import gen
+    st = gen.Stream(gen.SEED_BASE + 6)
+    a_np, b_np = st.uniform_poly(65535, gen.P_A), st.uniform_poly(32767, gen.P_A)
+    a, b = pm.to_device(a_np), pm.to_device(b_np)
+    pm.divrem(a, b, gen.P_A)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        q, r = pm.divrem(a, b, gen.P_A)
+        times.append(time.perf_counter() - t0)
+    t = sorted(times)[len(times) // 2]
+    mu, db = int(q.numel()), b_np.size - 1
+    updates = mu * (db + 1)
+    return {"workload": "deg a 65535 / deg b 32767 over p=469762049 (the s sweep's division)",
+            "s": pm.get_params()["div_s"] or 64, "divrem_ms_median": round(t * 1e3, 4),
+            "divrem_ms_min": round(min(times) * 1e3, 4), "quotient_terms": mu, "remainder_terms": int(r.numel()),
+            "updates": updates, "updates_per_s": round(updates / t, 1)}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -394,6 +423,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gcd", action="store_true")
     ap.add_argument("--gcd-reps", type=int, default=5)
+    ap.add_argument("--no-div", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--served-requests", type=int, default=2048)
@@ -492,6 +522,8 @@ def main() -> int:
     out["product_2048"] = bench_product_2048(20)
     if not args.no_batched:
         out["batched_4096"] = bench_batched(10)
+    if not args.no_div:
+        out["divrem_65536"] = bench_divrem(5)
     if not args.no_gcd:
         out["gcd_32768"] = bench_gcd(args.gcd_reps)
     if not args.no_served:
