@@ -117,7 +117,11 @@ pm_status poly_mul_modp_batch(const pm_mul_item *items, int32_t count, int32_t *
  *   r, r_cap : remainder (device); needs deg b words, or deg a + 1 when
  *              deg a < deg b
  *   nq, nr   : host; normalised lengths
- * Returns PM_EDIVZERO when b is the zero polynomial.
+ * The quotient comes from the top deg a - deg b + 1 coefficients of a, s
+ * division steps per chunk (pm_params.div_s), on up to one cooperating
+ * thread-block per CU; the library's scratch holds 3 na words for it.
+ * Returns PM_EDIVZERO when b is the zero polynomial, PM_ERANGE for a
+ * coefficient >= p.
  */
 pm_status poly_divrem_modp(const uint32_t *a, int64_t na, const uint32_t *b, int64_t nb, uint32_t p,
                            uint32_t *q, int64_t q_cap, int64_t *nq, uint32_t *r, int64_t r_cap, int64_t *nr,
@@ -230,7 +234,7 @@ void pm_last_gcd_stats(pm_gcd_stats *out);
  * Tuning (the paper's program parameter s).
  *   mul_s   : b-coefficients per thread-block in the product (0 = default)
  *   mul_r   : outputs per thread in the product (1,2,4,8,16,32; 0 = default)
- *   div_s   : division steps fused per pass in the quotient (1..64; 0 = 64)
+ *   div_s   : division steps fused per chunk of the quotient (1..64; 0 = 64)
  *   gcd_s   : Euclidean steps fused per chunk (1..256; 0 = 128)
  *   mul_engine : which kernels compute a product (poly_mul_modp and
  *             poly_mul_modp_async): 0 = automatic (the matrix cores for
