@@ -217,8 +217,10 @@ def served_inputs(count: int):
 
 
 def run_server_trace(reqs, scale: float):
-    """Submit each request at arrival * scale seconds; returns latencies (ms)
-    and the span from the first arrival to the last completion."""
+    """Submit each request at arrival * scale seconds (the requests that have
+    arrived by each pass of the loop go in one submit_many call); returns
+    latencies (ms) and the span from the first arrival to the last
+    completion."""
     import paper_1402_0264_amd as pm
     srv = pm.Server()
     t0 = time.perf_counter()
@@ -230,10 +232,11 @@ def run_server_trace(reqs, scale: float):
         now = time.perf_counter() - t0
         if time.perf_counter() > deadline:
             raise TimeoutError("served trace did not finish")
-        while i < len(reqs) and reqs[i][3] * scale <= now:
-            a, b, p = reqs[i][0], reqs[i][1], reqs[i][2]
-            srv.submit(a, b, p, tag=i)
+        due = []
+        while i < len(reqs) and reqs[i][3] * scale <= now:  # every request that has arrived, one call
+            due.append((reqs[i][0], reqs[i][1], reqs[i][2], i))
             i += 1
+        srv.submit_many(due)
         for c in srv.poll():
             if c["status"] != 0:
                 raise RuntimeError("served request %d failed: %d" % (c["tag"], c["status"]))

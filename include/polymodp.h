@@ -170,12 +170,12 @@ pm_status poly_gcd_modp_batch(const pm_gcd_item *items, int32_t count, pm_gcd_re
 /*
  * GCD server with continuous batching. Requests of mixed degree (up to
  * PM_GCD_BATCH_MAX terms) and prime are queued by pm_server_submit (inputs
- * are copied; the caller may reuse its arrays at once). pm_server_poll
- * returns the requests that finished since the last poll and admits queued
- * requests in arrival order while a slot (max_inflight) and room in the
- * resident-input budget (arena_words) are free; admitted requests are
- * published to the GPU at once, their inputs staged in pinned memory mapped
- * into the device's address space.
+ * are copied; the caller may reuse its arrays at once). pm_server_submit
+ * and pm_server_poll admit queued requests in arrival order while a slot
+ * (max_inflight) and room in the resident-input budget (arena_words) are
+ * free; admitted requests are published to the GPU at once, their inputs
+ * staged in pinned memory mapped into the device's address space.
+ * pm_server_poll returns the requests that finished since the last poll.
  * A persistent worker kernel (one block per CU) runs the published
  * requests one block each, taking the next one as soon as it finishes, so
  * requests join and leave the GPU individually. Each request's remainder
@@ -213,11 +213,14 @@ typedef struct {
     int64_t steps;
     int64_t updates;
     double t_submit_ms;    /* pm_server_submit                          */
-    double t_start_ms;     /* admitted and launched                     */
+    double t_start_ms;     /* admitted and published to the GPU         */
     double t_done_ms;      /* seen finished by pm_server_poll           */
 } pm_completion;
 pm_status pm_server_create(const pm_server_opts *opts, pm_server **out);
 pm_status pm_server_submit(pm_server *srv, const pm_gcd_request *req, uint64_t *ticket);
+/* count requests in one call (tickets: count entries, or NULL); all are
+ * checked first, so an error queues none of them. */
+pm_status pm_server_submit_batch(pm_server *srv, const pm_gcd_request *reqs, int32_t count, uint64_t *tickets);
 pm_status pm_server_poll(pm_server *srv, pm_completion *out, int32_t max, int32_t *n);
 int64_t pm_server_pending(pm_server *srv);   /* queued + on the device */
 void pm_server_destroy(pm_server *srv);

@@ -114,6 +114,9 @@ def lib() -> ctypes.CDLL:
     L.pm_server_create.restype = ctypes.c_int32
     L.pm_server_submit.argtypes = [ctypes.c_void_p, ctypes.POINTER(GcdRequest), ctypes.POINTER(ctypes.c_uint64)]
     L.pm_server_submit.restype = ctypes.c_int32
+    L.pm_server_submit_batch.argtypes = [ctypes.c_void_p, ctypes.POINTER(GcdRequest), ctypes.c_int32,
+                                         ctypes.POINTER(ctypes.c_uint64)]
+    L.pm_server_submit_batch.restype = ctypes.c_int32
     L.pm_server_poll.argtypes = [ctypes.c_void_p, ctypes.POINTER(Completion), ctypes.c_int32,
                                  ctypes.POINTER(ctypes.c_int32)]
     L.pm_server_poll.restype = ctypes.c_int32
@@ -346,6 +349,27 @@ class Server:
         _check(lib().pm_server_submit(self.handle, ctypes.byref(req), ctypes.byref(t)))
         self._out[t.value] = g
         return t.value
+
+    def submit_many(self, reqs) -> list:
+        """Submits [(a, b, p, tag), ...] in one call; returns the tickets."""
+        import numpy as np
+        n = len(reqs)
+        if n == 0:
+            return []
+        arr = (GcdRequest * n)()
+        keep = []
+        for i, (a, b, p, tag) in enumerate(reqs):
+            a = np.ascontiguousarray(np.asarray(a, dtype=np.uint32))
+            b = np.ascontiguousarray(np.asarray(b, dtype=np.uint32))
+            g = np.zeros(max(a.size, b.size, 1), dtype=np.uint32)
+            keep.append((a, b, g))
+            arr[i] = GcdRequest(a.ctypes.data if a.size else None, a.size, b.ctypes.data if b.size else None,
+                                b.size, p, g.ctypes.data, g.size, tag)
+        tickets = (ctypes.c_uint64 * n)()
+        _check(lib().pm_server_submit_batch(self.handle, arr, n, tickets))
+        for i in range(n):
+            self._out[tickets[i]] = keep[i][2]
+        return list(tickets)
 
     def poll(self) -> list:
         n = ctypes.c_int32(0)

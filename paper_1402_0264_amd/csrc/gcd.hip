@@ -318,6 +318,9 @@ __device__ void gcd_instance(const GcdJob& J, int s, int64_t cap, uint32_t* smem
             uint32_t nA[PPA], nB[PPA];
             if (wave == 0) {
                 if (pipe) {
+                    // the step chain bounds the chunk: its wave goes first on
+                    // a SIMD it shares with apply waves
+                    __builtin_amdgcn_s_setprio(3);
                     uint32_t hA[E], hB[E];
 #pragma unroll
                     for (int e = 0; e < E; e++) {
@@ -328,9 +331,14 @@ __device__ void gcd_instance(const GcdJob& J, int s, int64_t cap, uint32_t* smem
                     }
                     int nst, big;
                     head_run_log<E>(hA, hB, (int)res.dA, (int)res.dB, s, F, desc, &s_log, &s_out[mb ^ 1], nst, big);
+                    __builtin_amdgcn_s_setprio(0);
                 }
             } else if (wave == 1) {
-                if (pipe) m_build_live(desc, &s_log, F, Mn);
+                if (pipe) {
+                    __builtin_amdgcn_s_setprio(2);
+                    m_build_live(desc, &s_log, F, Mn);
+                    __builtin_amdgcn_s_setprio(0);
+                }
             } else {
 #pragma unroll
                 for (int j = 0; j < PPA; j++) {

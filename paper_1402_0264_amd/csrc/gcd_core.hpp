@@ -13,8 +13,8 @@
 //     index l + 64e below the leading one). A head entry stays exact while
 //     every entry it was computed from was loaded; the run stops before the
 //     next leading coefficient would be unknown, or when the total shift of
-//     the chunk would exceed MAXSHIFT. Each step is published as soon as it
-//     is known, and a second wave (m_build_live) applies it to the 2x2
+//     the chunk would exceed MAXSHIFT. Each step is published when its head
+//     update is done, and a second wave (m_build_live) applies it to the 2x2
 //     matrix of polynomials M = [[alpha, beta], [gamma, delta]] (degree <=
 //     the total shift S; lane k holds coefficient k of each entry), so that
 //     (A', B') = M * (A, B) for the chunk-start A, B.
@@ -102,8 +102,9 @@ __device__ __forceinline__ void steplog_reset(StepLog* L) {
 
 // Head run by one whole wave. hA/hB: the heads (entry i = coefficient of
 // x^(deg - i)), exact for i < 64*E. Each step reduces the operand of higher
-// degree (chosen with uniform selects, not two copies of the code) and is
-// published in desc[] for the M builder on another wave (m_build_live).
+// degree (chosen with uniform selects, not two copies of the code; the run's
+// state is kept in scalar registers) and is published in desc[] for the M
+// builder on another wave (m_build_live).
 // Returns the chunk summary through *out (lane 0 writes) and the step
 // count and big flag in n_out / big_out; a big step is desc[0].
 template <int E>
@@ -116,7 +117,16 @@ __device__ void head_run_log(uint32_t (&hA)[E], uint32_t (&hB)[E], int dA, int d
     s = uni(s);
     int vA = H, vB = H, S = 0, n = 0, unkA = 0, unkB = 0, big = 0;
     int64_t upd = 0;
-    while (n < s && dA >= 0 && dB >= 0) {
+    for (;;) {
+        // the run's state is wave-uniform: keep it in scalar registers, so
+        // that the loop and its branches stay scalar (no exec masking)
+        dA = uni(dA);
+        dB = uni(dB);
+        vA = uni(vA);
+        vB = uni(vB);
+        S = uni(S);
+        n = uni(n);
+        if (!(n < s && dA >= 0 && dB >= 0)) break;
         const bool redA = dA >= dB;
         const int d = redA ? dA - dB : dB - dA;
         if (S + d > GCD_MAXSHIFT) {
@@ -127,10 +137,7 @@ __device__ void head_run_log(uint32_t (&hA)[E], uint32_t (&hB)[E], int dA, int d
         const uint32_t lcB = (uint32_t)__builtin_amdgcn_readfirstlane((int)hB[0]);
         const uint32_t m1 = redA ? lcB : lcA;
         const uint32_t m2 = F.p - (redA ? lcA : lcB);
-        if (lane == 0) {
-            desc[n] = StepDesc{m1, m2, d, redA ? 0 : 1};
-            __hip_atomic_store(&L->prog, n + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-        }
+        if (lane == 0) desc[n] = StepDesc{m1, m2, d, redA ? 0 : 1};
         const int v = vA < vB ? vA : vB;
         // X <- REDC(m1 X + m2 Y) on the heads; entries at or beyond v cleared
         uint32_t x[E];
@@ -150,6 +157,9 @@ __device__ void head_run_log(uint32_t (&hA)[E], uint32_t (&hB)[E], int dA, int d
         for (int e = E - 1; e >= 0; e--)
             if (msk[e]) delta = 64 * e + (int)__builtin_ctzll(msk[e]);
         n++;
+        // publish the step once its record has long been written (the release
+        // then finds no LDS store of this step outstanding)
+        if (lane == 0) __hip_atomic_store(&L->prog, n, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (!big) S += d;
         upd += (redA ? dB : dA) + 1;
         int nd, nv;

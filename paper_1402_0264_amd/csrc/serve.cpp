@@ -9,10 +9,10 @@
 // claims the next one. Requests therefore join and leave the GPU one by one:
 // nothing waits for a batch or a launch to finish.
 //
-// The host side (pm_server_poll, called by one thread):
-//  1. harvests finished slots (done flag, acquire) and frees them;
-//  2. admits queued requests in FIFO order while a slot and room in the
-//     resident-input budget are free: the inputs go into the slot's pinned
+// The host side (pm_server_submit and pm_server_poll, called by one thread):
+//  1. poll harvests finished slots (done flag, acquire) and frees them;
+//  2. submit and poll admit queued requests in FIFO order while a slot and
+//     room in the resident-input budget are free: the inputs go into the slot's pinned
 //     staging buffer (mapped into the device's address space), and the
 //     request is published at once by raising the shared tail (release);
 //     the claiming block reads the inputs once, past the caches, straight
@@ -163,6 +163,48 @@ pm_status ensure_worker(pm_server* S) {
     return PM_OK;
 }
 
+// Admits queued requests in FIFO order while a slot and room in the budget
+// are free and publishes them. With `check`, also makes sure the worker runs
+// (a query of its stream); without it, only a worker never launched is
+// started, and the next poll relaunches one that has left.
+pm_status admit(pm_server* S, bool check) {
+    bool published = false;
+    const double t = S->now_ms();
+    while (!S->queue.empty() && !S->free_slots.empty()) {
+        Pending& P = S->queue.front();
+        const int64_t len = P.na + P.nb;
+        int64_t off = 0;
+        if (!S->arena->alloc(len, &off)) break;  // FIFO: wait for room, no overtaking
+        const int si = S->free_slots.back();
+        S->free_slots.pop_back();
+        Slot& sl = S->slots[si];
+        sl.busy = true;
+        sl.ticket = P.ticket;
+        sl.tag = P.tag;
+        sl.arena_off = off;
+        sl.arena_len = len;
+        sl.g_user = P.g_user;
+        sl.g_cap = P.g_cap;
+        sl.t_submit = P.t_submit;
+        sl.t_start = t;
+        std::memset(&S->h_results[si], 0, sizeof(pm::GcdResult));
+        uint32_t* stage = S->h_in + (int64_t)si * 2 * S->cap;
+        if (len) std::memcpy(stage, P.ab.data(), (size_t)len * 4);
+        S->h_jobs[si] = pm::GcdJob{stage, stage + P.na, P.na, P.nb, S->h_g + (int64_t)si * S->cap, S->cap,
+                                   &S->h_results[si], P.F, 1, 0};
+        S->h_order[S->tail & (ORDER_CAP - 1)] = (uint32_t)si;
+        S->tail++;
+        S->inflight++;
+        S->queue.pop_front();
+        published = true;
+    }
+    if (published) __atomic_store_n(&S->h_ctl[0], S->tail, __ATOMIC_RELEASE);
+    // (re)launch the worker whenever published work may be waiting and the
+    // previous worker has left (it leaves after an idle period)
+    if (S->inflight > 0 && (check || !S->worker_launched)) return ensure_worker(S);
+    return PM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -210,8 +252,12 @@ pm_status pm_server_create(const pm_server_opts* opts, pm_server** out) {
 
 void pm_server_destroy(pm_server* S) { destroy(S); }
 
-pm_status pm_server_submit(pm_server* S, const pm_gcd_request* r, uint64_t* ticket) {
-    if (!S || !r) return pm::server_fail(PM_EINVAL, "null argument");
+}  // extern "C"
+
+namespace {
+
+pm_status enqueue(pm_server* S, const pm_gcd_request* r, uint64_t* ticket) {
+    if (!r) return pm::server_fail(PM_EINVAL, "null request");
     if (r->na < 0 || r->nb < 0 || (r->na > 0 && !r->a) || (r->nb > 0 && !r->b) || r->g_cap < 0 ||
         (r->g_cap > 0 && !r->g))
         return pm::server_fail(PM_EINVAL, "bad request buffers");
@@ -238,6 +284,42 @@ pm_status pm_server_submit(pm_server* S, const pm_gcd_request* r, uint64_t* tick
     if (ticket) *ticket = P.ticket;
     S->queue.push_back(std::move(P));
     return PM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pm_status pm_server_submit(pm_server* S, const pm_gcd_request* r, uint64_t* ticket) {
+    if (!S || !r) return pm::server_fail(PM_EINVAL, "null argument");
+    pm_status st = enqueue(S, r, ticket);
+    if (st) return st;
+    return admit(S, false);  // on the GPU at once when a slot is free
+}
+
+pm_status pm_server_submit_batch(pm_server* S, const pm_gcd_request* reqs, int32_t count, uint64_t* tickets) {
+    if (!S || count < 0 || (count > 0 && !reqs)) return pm::server_fail(PM_EINVAL, "null argument");
+    // every request is checked before any is queued: a bad one queues none
+    for (int32_t i = 0; i < count; i++) {
+        const pm_gcd_request* r = &reqs[i];
+        const int64_t n = r->na > r->nb ? r->na : r->nb;
+        if (r->na < 0 || r->nb < 0 || (r->na > 0 && !r->a) || (r->nb > 0 && !r->b) || r->g_cap < 0 ||
+            (r->g_cap > 0 && !r->g) || n > S->cap || Arena::grain(r->na + r->nb) > S->opt.arena_words)
+            return pm::server_fail(PM_EINVAL, "bad request in the batch");
+        pm::Field F;
+        pm_status st = pm::server_field(r->p, &F);
+        if (st) return st;
+        if ((r->p & 1u) == 0) return pm::server_fail(PM_EMODULUS, "p = 2 is not supported by the gcd");
+    }
+    for (int32_t i = 0; i < count; i++) {
+        pm_status st = enqueue(S, &reqs[i], tickets ? &tickets[i] : nullptr);
+        if (st) return st;
+        if ((i & 15) == 15) {  // the first requests start while the rest are copied
+            st = admit(S, false);
+            if (st) return st;
+        }
+    }
+    return admit(S, false);
 }
 
 int64_t pm_server_pending(pm_server* S) { return S ? (int64_t)S->queue.size() + S->inflight : 0; }
@@ -275,45 +357,7 @@ pm_status pm_server_poll(pm_server* S, pm_completion* out, int32_t max, int32_t*
         sl.busy = false;
         S->free_slots.push_back(si);
     }
-    // 2. admit in FIFO order while a slot and room in the budget are free
-    bool published = false;
-    const double t = S->now_ms();
-    while (!S->queue.empty() && !S->free_slots.empty()) {
-        Pending& P = S->queue.front();
-        const int64_t len = P.na + P.nb;
-        int64_t off = 0;
-        if (!S->arena->alloc(len, &off)) break;  // FIFO: wait for room, no overtaking
-        const int si = S->free_slots.back();
-        S->free_slots.pop_back();
-        Slot& sl = S->slots[si];
-        sl.busy = true;
-        sl.ticket = P.ticket;
-        sl.tag = P.tag;
-        sl.arena_off = off;
-        sl.arena_len = len;
-        sl.g_user = P.g_user;
-        sl.g_cap = P.g_cap;
-        sl.t_submit = P.t_submit;
-        sl.t_start = t;
-        std::memset(&S->h_results[si], 0, sizeof(pm::GcdResult));
-        uint32_t* stage = S->h_in + (int64_t)si * 2 * S->cap;
-        if (len) std::memcpy(stage, P.ab.data(), (size_t)len * 4);
-        S->h_jobs[si] = pm::GcdJob{stage, stage + P.na, P.na, P.nb, S->h_g + (int64_t)si * S->cap, S->cap,
-                                   &S->h_results[si], P.F, 1, 0};
-        S->h_order[S->tail & (ORDER_CAP - 1)] = (uint32_t)si;
-        S->tail++;
-        S->inflight++;
-        S->queue.pop_front();
-        published = true;
-    }
-    if (published) __atomic_store_n(&S->h_ctl[0], S->tail, __ATOMIC_RELEASE);
-    // 3. (re)launch the worker whenever published work may be waiting and
-    // the previous worker has left (it leaves after an idle period)
-    if (S->inflight > 0) {
-        pm_status st = ensure_worker(S);
-        if (st) return st;
-    }
-    return PM_OK;
+    return admit(S, true);
 }
 
 }  // extern "C"

@@ -551,6 +551,27 @@ def test_server_results_same_alone_and_in_the_mix():
         solo.close()
 
 
+def test_server_batch_submission():
+    # one call submits many requests: the first ones start while the rest are
+    # copied, more than the slots hold wait in the queue, and the results
+    # equal the oracle's; a batch with one bad request queues none of them
+    reqs = _served_requests(40, 504, lo=8, hi=4000)
+    srv = pm.Server(max_inflight=16)
+    tickets = srv.submit_many([(a, b, p, i) for i, (a, b, p) in enumerate(reqs)])
+    assert len(set(tickets)) == len(reqs)
+    out = srv.drain()
+    assert sorted(c["tag"] for c in out) == list(range(len(reqs)))
+    for c in out:
+        a, b, p = reqs[c["tag"]]
+        assert c["status"] == 0 and same(c["g"], oracle.gcd(a, b, p)), c["tag"]
+    ok = reqs[0]
+    with pytest.raises(pm.PolyModPError) as e:
+        srv.submit_many([(ok[0], ok[1], ok[2], 0), (ok[0], ok[1], 91, 1)])
+    assert e.value.status == pm.PM_EMODULUS
+    assert srv.pending() == 0
+    srv.close()
+
+
 def test_server_admission_waits_for_memory_and_slots():
     reqs = _served_requests(20, 503, lo=500, hi=3000)
     srv = pm.Server(max_inflight=3, arena_words=8192)  # at most a few resident at once
