@@ -65,6 +65,18 @@ class GcdRequest(ctypes.Structure):
                 ("tag", ctypes.c_uint64)]
 
 
+# pm_gcd_request as a numpy record (same field offsets as GcdRequest)
+
+def _req_dtype():
+    import numpy as np
+    return np.dtype({"names": ["a", "na", "b", "nb", "p", "g", "g_cap", "tag"],
+                     "formats": ["<u8", "<i8", "<u8", "<i8", "<u4", "<u8", "<i8", "<u8"],
+                     "offsets": [GcdRequest.a.offset, GcdRequest.na.offset, GcdRequest.b.offset,
+                                 GcdRequest.nb.offset, GcdRequest.p.offset, GcdRequest.g.offset,
+                                 GcdRequest.g_cap.offset, GcdRequest.tag.offset],
+                     "itemsize": ctypes.sizeof(GcdRequest)})
+
+
 class Completion(ctypes.Structure):
     _fields_ = [("ticket", ctypes.c_uint64), ("tag", ctypes.c_uint64), ("status", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("ng", ctypes.c_int64), ("steps", ctypes.c_int64),
@@ -351,25 +363,42 @@ class Server:
         return t.value
 
     def submit_many(self, reqs) -> list:
-        """Submits [(a, b, p, tag), ...] in one call; returns the tickets."""
+        """Submits [(a, b, p, tag), ...] in one call; returns the tickets. The
+        request records are built as one numpy array with the layout of
+        pm_gcd_request, and the outputs are views of one buffer."""
         import numpy as np
         n = len(reqs)
         if n == 0:
             return []
-        arr = (GcdRequest * n)()
-        keep = []
-        for i, (a, b, p, tag) in enumerate(reqs):
-            a = np.ascontiguousarray(np.asarray(a, dtype=np.uint32))
-            b = np.ascontiguousarray(np.asarray(b, dtype=np.uint32))
-            g = np.zeros(max(a.size, b.size, 1), dtype=np.uint32)
-            keep.append((a, b, g))
-            arr[i] = GcdRequest(a.ctypes.data if a.size else None, a.size, b.ctypes.data if b.size else None,
-                                b.size, p, g.ctypes.data, g.size, tag)
-        tickets = (ctypes.c_uint64 * n)()
-        _check(lib().pm_server_submit_batch(self.handle, arr, n, tickets))
+        ins = []
+        for a, b, p, tag in reqs:
+            if not (isinstance(a, np.ndarray) and a.dtype == np.uint32 and a.flags.c_contiguous):
+                a = np.ascontiguousarray(np.asarray(a, dtype=np.uint32))
+            if not (isinstance(b, np.ndarray) and b.dtype == np.uint32 and b.flags.c_contiguous):
+                b = np.ascontiguousarray(np.asarray(b, dtype=np.uint32))
+            ins.append((a, b))
+        na = np.fromiter((x[0].size for x in ins), dtype=np.int64, count=n)
+        nb = np.fromiter((x[1].size for x in ins), dtype=np.int64, count=n)
+        cap = np.maximum(np.maximum(na, nb), 1)
+        offs = np.zeros(n, dtype=np.int64)
+        np.cumsum(cap[:-1], out=offs[1:])
+        gbuf = np.zeros(int(offs[-1] + cap[-1]), dtype=np.uint32)
+        rec = np.zeros(n, dtype=_req_dtype())
+        rec["a"] = np.fromiter((x[0].ctypes.data if x[0].size else 0 for x in ins), dtype=np.uint64, count=n)
+        rec["na"] = na
+        rec["b"] = np.fromiter((x[1].ctypes.data if x[1].size else 0 for x in ins), dtype=np.uint64, count=n)
+        rec["nb"] = nb
+        rec["p"] = np.fromiter((r[2] for r in reqs), dtype=np.uint32, count=n)
+        rec["g"] = gbuf.ctypes.data + 4 * offs.astype(np.uint64)
+        rec["g_cap"] = cap
+        rec["tag"] = np.fromiter((r[3] for r in reqs), dtype=np.uint64, count=n)
+        tickets = np.zeros(n, dtype=np.uint64)
+        _check(lib().pm_server_submit_batch(self.handle, ctypes.cast(rec.ctypes.data, ctypes.POINTER(GcdRequest)),
+                                            n, ctypes.cast(tickets.ctypes.data, ctypes.POINTER(ctypes.c_uint64))))
         for i in range(n):
-            self._out[tickets[i]] = keep[i][2]
-        return list(tickets)
+            o = int(offs[i])
+            self._out[int(tickets[i])] = gbuf[o:o + int(cap[i])]
+        return [int(t) for t in tickets]
 
     def poll(self) -> list:
         n = ctypes.c_int32(0)

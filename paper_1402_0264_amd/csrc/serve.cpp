@@ -163,12 +163,39 @@ pm_status ensure_worker(pm_server* S) {
     return PM_OK;
 }
 
+// Puts one request into slot si at arena offset off: inputs into the slot's
+// pinned staging, the job record, and the next entry of the order ring
+// (published by the caller with one store of the tail).
+void place(pm_server* S, int si, int64_t off, uint64_t ticket, uint64_t tag, const uint32_t* a, int64_t na,
+           const uint32_t* b, int64_t nb, uint32_t* g_user, int64_t g_cap, const pm::Field& F, double t_submit,
+           double t_start) {
+    Slot& sl = S->slots[si];
+    sl.busy = true;
+    sl.ticket = ticket;
+    sl.tag = tag;
+    sl.arena_off = off;
+    sl.arena_len = na + nb;
+    sl.g_user = g_user;
+    sl.g_cap = g_cap;
+    sl.t_submit = t_submit;
+    sl.t_start = t_start;
+    std::memset(&S->h_results[si], 0, sizeof(pm::GcdResult));
+    uint32_t* stage = S->h_in + (int64_t)si * 2 * S->cap;
+    if (na) std::memcpy(stage, a, (size_t)na * 4);
+    if (nb) std::memcpy(stage + na, b, (size_t)nb * 4);
+    S->h_jobs[si] = pm::GcdJob{stage, stage + na, na, nb, S->h_g + (int64_t)si * S->cap, S->cap,
+                               &S->h_results[si], F, 1, 0};
+    S->h_order[S->tail & (ORDER_CAP - 1)] = (uint32_t)si;
+    S->tail++;
+    S->inflight++;
+}
+
 // Admits queued requests in FIFO order while a slot and room in the budget
 // are free and publishes them. With `check`, also makes sure the worker runs
 // (a query of its stream); without it, only a worker never launched is
 // started, and the next poll relaunches one that has left.
 pm_status admit(pm_server* S, bool check) {
-    bool published = false;
+    bool published = __atomic_load_n(&S->h_ctl[0], __ATOMIC_RELAXED) != S->tail;  // direct placements
     const double t = S->now_ms();
     while (!S->queue.empty() && !S->free_slots.empty()) {
         Pending& P = S->queue.front();
@@ -177,24 +204,8 @@ pm_status admit(pm_server* S, bool check) {
         if (!S->arena->alloc(len, &off)) break;  // FIFO: wait for room, no overtaking
         const int si = S->free_slots.back();
         S->free_slots.pop_back();
-        Slot& sl = S->slots[si];
-        sl.busy = true;
-        sl.ticket = P.ticket;
-        sl.tag = P.tag;
-        sl.arena_off = off;
-        sl.arena_len = len;
-        sl.g_user = P.g_user;
-        sl.g_cap = P.g_cap;
-        sl.t_submit = P.t_submit;
-        sl.t_start = t;
-        std::memset(&S->h_results[si], 0, sizeof(pm::GcdResult));
-        uint32_t* stage = S->h_in + (int64_t)si * 2 * S->cap;
-        if (len) std::memcpy(stage, P.ab.data(), (size_t)len * 4);
-        S->h_jobs[si] = pm::GcdJob{stage, stage + P.na, P.na, P.nb, S->h_g + (int64_t)si * S->cap, S->cap,
-                                   &S->h_results[si], P.F, 1, 0};
-        S->h_order[S->tail & (ORDER_CAP - 1)] = (uint32_t)si;
-        S->tail++;
-        S->inflight++;
+        place(S, si, off, P.ticket, P.tag, P.ab.data(), P.na, P.ab.data() + P.na, P.nb, P.g_user, P.g_cap, P.F,
+              P.t_submit, t);
         S->queue.pop_front();
         published = true;
     }
@@ -269,6 +280,18 @@ pm_status enqueue(pm_server* S, const pm_gcd_request* r, uint64_t* ticket) {
     pm_status st = pm::server_field(r->p, &F);
     if (st) return st;
     if ((r->p & 1u) == 0) return pm::server_fail(PM_EMODULUS, "p = 2 is not supported by the gcd");
+    int64_t off = 0;
+    if (S->queue.empty() && !S->free_slots.empty() && S->arena->alloc(r->na + r->nb, &off)) {
+        // nothing waits ahead of it: straight from the caller's arrays into a
+        // slot (published by the caller's next admission pass)
+        const int si = S->free_slots.back();
+        S->free_slots.pop_back();
+        const uint64_t t = S->next_ticket++;
+        const double now = S->now_ms();
+        place(S, si, off, t, r->tag, r->a, r->na, r->b, r->nb, r->g, r->g_cap, F, now, now);
+        if (ticket) *ticket = t;
+        return PM_OK;
+    }
     Pending P;
     P.ticket = S->next_ticket++;
     P.tag = r->tag;
