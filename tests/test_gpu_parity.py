@@ -255,6 +255,20 @@ def test_divrem_long_quotient(na, nb, s):
     assert same(host(q), wq) and same(host(r), wr), (na, nb, s)
 
 
+@pytest.mark.parametrize("p", [2, 3, gen.P_C])
+def test_divrem_long_quotient_small_and_other_primes(p):
+    st = gen.Stream(207 + p % 1000)
+    for na, nb, s in [(30000, 700, 64), (12000, 5, 9), (9000, 8900, 1)]:
+        a, b = rnd(st, na, p), rnd(st, nb, p)
+        wq, wr = oracle.divrem(a, b, p)
+        pm.set_params(div_s=s)
+        try:
+            q, r = pm.divrem(dev(a), dev(b), p)
+        finally:
+            pm.set_params()
+        assert same(host(q), wq) and same(host(r), wr), (p, na, nb, s)
+
+
 def test_divrem_head_longer_than_planned():
     # zeros above the top coefficient of b: the head is longer than the
     # lengths suggest, so blocks own several runs of it
