@@ -546,14 +546,21 @@ pm_status poly_divrem_modp(const uint32_t* a, int64_t na, const uint32_t* b, int
         *nr = 0;
         return PM_OK;
     }
-    // r_k = a_k - (q*b)_k for k < deg b
+    // r_k = a_k - (q*b)_k for k < deg b: only b_0 .. b_{deg b - 1} and
+    // q_0 .. q_{deg b - 1} reach those exponents
     const uint32_t *x = b, *y = q;
-    int64_t nx = db + 1, ny = mu;
+    int64_t nx = db, ny = mu < db ? mu : db;
     order_operands(x, nx, y, ny);
-    pm::MulPlan plan = mul_plan(nx, ny);
-    int64_t words = pm::mul_scratch_words(nx, ny, plan);
-    if ((st = pool_get(s, words, &P))) return st;
-    HIP_TRY(pm::mul_launch(x, nx, y, ny, F, r, plan, P->words, nullptr, nullptr, a, db, s), "remainder launch");
+    if (use_mfma(nx, ny)) {
+        const pm::MxGeom g = pm::mx_geometry(nx, ny, num_cus(), db);
+        if ((st = pool_get(s, pm::mulx_scratch_words(g), &P))) return st;
+        HIP_TRY(pm::mulx_launch(x, nx, y, ny, F, r, g, P->words, nullptr, nullptr, s, a, db), "remainder launch");
+    } else {
+        pm::MulPlan plan = mul_plan(nx, ny);
+        int64_t words = pm::mul_scratch_words(nx, ny, plan);
+        if ((st = pool_get(s, words, &P))) return st;
+        HIP_TRY(pm::mul_launch(x, nx, y, ny, F, r, plan, P->words, nullptr, nullptr, a, db, s), "remainder launch");
+    }
     HIP_TRY(pm::trim_launch(r, db, P->d_info, s), "trim launch");
     if ((st = read_info(P, s))) return st;
     *nr = P->h_info->n1;

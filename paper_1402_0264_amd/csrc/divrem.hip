@@ -28,42 +28,46 @@
 // The part of a below deg b only ever receives updates, never feeds a
 // decision, so it is done afterwards in one fully parallel launch:
 // r_k = a_k - sum_t q_t b_{k-t} for k < deg b, a product with a subtracting
-// epilogue (mul.hip).
+// epilogue (mul_mfma.hip or mul.hip).
 #include "internal.hpp"
 
 namespace pm {
 namespace {
 
-// Degrees (largest non-zero index) of a and b by two waves, range check by
-// all threads. Results in the block's shared variables.
-__device__ void block_degrees(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb,
-                              uint32_t p, int64_t* s_deg, int* s_bad) {
-    if (threadIdx.x == 0) *s_bad = 0;
-    __syncthreads();
-    int bad = 0;
-    for (int64_t i = threadIdx.x; i < na; i += blockDim.x) bad |= a[i] >= p;
-    for (int64_t i = threadIdx.x; i < nb; i += blockDim.x) bad |= b[i] >= p;
-    if (bad) atomicOr(s_bad, 1);
+// Degrees (largest non-zero index) of a and b, by two waves scanning from
+// the top; resets the call's results. The range check runs in
+// zero_check_kernel, next in the stream, on many blocks.
+__global__ __launch_bounds__(256) void degrees_kernel(const uint32_t* a, int64_t na, const uint32_t* b,
+                                                      int64_t nb, CallInfo* info) {
     const int wave = threadIdx.x >> 6;
     if (wave < 2) {
-        int64_t d = top_nonzero_wave(wave == 0 ? a : b, wave == 0 ? na : nb);
-        if ((threadIdx.x & 63) == 0) s_deg[wave] = d;
+        const int64_t d = top_nonzero_wave(wave == 0 ? a : b, wave == 0 ? na : nb);
+        if ((threadIdx.x & 63) == 0) {
+            if (wave == 0) info->deg_a = d;
+            else info->deg_b = d;
+        }
     }
-    __syncthreads();
-}
-
-__global__ __launch_bounds__(256) void degrees_kernel(const uint32_t* a, int64_t na, const uint32_t* b,
-                                                      int64_t nb, Field F, CallInfo* info) {
-    __shared__ int64_t s_deg[2];
-    __shared__ int s_bad;
-    block_degrees(a, na, b, nb, F.p, s_deg, &s_bad);
     if (threadIdx.x == 0) {
-        info->deg_a = s_deg[0];
-        info->deg_b = s_deg[1];
-        info->status = s_bad ? -3 /* PM_ERANGE */ : 0;
+        info->status = 0;
+        info->flags = 0;
         info->n0 = info->n1 = 0;
         info->steps = info->chunks = info->updates = 0;
     }
+}
+
+// Clears the published-term words and checks every coefficient of a and b
+// against p (info->flags = 1 when one is not a residue).
+__global__ __launch_bounds__(256) void zero_check_kernel(uint64_t* qlog, int64_t nq, const uint32_t* a, int64_t na,
+                                                         const uint32_t* b, int64_t nb, uint32_t p, CallInfo* info) {
+    int bad = 0;
+    const int64_t n = nq > na ? (nq > nb ? nq : nb) : (na > nb ? na : nb);
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        if (i < nq) qlog[i] = 0;
+        if (i < na) bad |= a[i] >= p;
+        if (i < nb) bad |= b[i] >= p;
+    }
+    bad = __syncthreads_or(bad);
+    if (bad && threadIdx.x == 0) atomicOr(&info->flags, 1);
 }
 
 constexpr int DIVF_QB = 4096;                   // quotient terms one batch holds in LDS
@@ -312,7 +316,7 @@ __global__ __launch_bounds__(DIV_THREADS) void divrem_flow_kernel(DivFlow D) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     CallInfo* info = D.info;
     const int64_t da = info->deg_a, db = info->deg_b;  // from degrees_kernel
-    int status = info->status;
+    int status = info->flags ? -3 /* PM_ERANGE */ : info->status;
     if (status == 0 && db < 0) status = -4;                  // PM_EDIVZERO
     const int64_t mu = (status == 0 && da >= db) ? da - db + 1 : 0;
     const int64_t nr_max = (da < db) ? da + 1 : db;          // room the remainder may need
@@ -452,17 +456,6 @@ __global__ __launch_bounds__(256) void trim_kernel(const uint32_t* r, int64_t n,
 
 }  // namespace
 
-hipError_t degrees_launch(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, const Field& F,
-                          CallInfo* info, hipStream_t stream) {
-    TimingScope ts("degrees_kernel", stream);
-    hipLaunchKernelGGL(degrees_kernel, dim3(1), dim3(256), 0, stream, a, na, b, nb, F, info);
-    return hipGetLastError();
-}
-
-__global__ __launch_bounds__(256) void zero_u64_kernel(uint64_t* p, int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = 0;
-}
-
 hipError_t divrem_head_launch(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, const Field& F,
                               uint32_t* q, int64_t q_cap, int64_t r_cap, uint32_t* head, CallInfo* info,
                               int s, int num_cus, hipStream_t stream) {
@@ -490,15 +483,18 @@ hipError_t divrem_head_launch(const uint32_t* a, int64_t na, const uint32_t* b, 
     if (blocks < 1) blocks = 1;
     {
         TimingScope ts("degrees_kernel", stream);
-        hipLaunchKernelGGL(degrees_kernel, dim3(1), dim3(256), 0, stream, a, na, b, nb, F, info);
+        hipLaunchKernelGGL(degrees_kernel, dim3(1), dim3(256), 0, stream, a, na, b, nb, info);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     {
-        int zb = (int)((words + 255) / 256);
-        if (zb > 1024) zb = 1024;
-        TimingScope ts("zero_u64_kernel", stream);
-        hipLaunchKernelGGL(zero_u64_kernel, dim3(zb), dim3(256), 0, stream, D.qlog, words);
+        const int64_t n = words > nb ? words : nb;
+        int zb = (int)((n + 1023) / 1024);
+        if (zb > 2048) zb = 2048;
+        if (zb < 1) zb = 1;
+        TimingScope ts("zero_check_kernel", stream);
+        hipLaunchKernelGGL(zero_check_kernel, dim3(zb), dim3(256), 0, stream, D.qlog, words, a, na, b, nb, F.p,
+                           info);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     TimingScope ts("divrem_flow_kernel", stream);

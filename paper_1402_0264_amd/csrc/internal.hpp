@@ -94,12 +94,15 @@ struct MxGeom {
     int64_t G;        // work-groups (one share each)
     int64_t maxseg;   // most ranges one share touches
 };
-MxGeom mx_geometry(int64_t na, int64_t nb, int num_cus);
+// nout > 0: only the ranges holding outputs below nout are planned.
+MxGeom mx_geometry(int64_t na, int64_t nb, int num_cus, int64_t nout = -1);
 int64_t mulx_scratch_words(const MxGeom& g);
 // f = a*b for na, nb >= 1 and p < 2^30; out_len/out_status as mul_launch.
+// With sub_from, f[k] = sub_from[k] - (a*b)[k]; with nout > 0 only f[k] for
+// k < nout is written (g planned with the same nout).
 hipError_t mulx_launch(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, const Field& F, uint32_t* f,
                        const MxGeom& g, uint32_t* scratch, int64_t* out_len, int32_t* out_status,
-                       hipStream_t stream);
+                       hipStream_t stream, const uint32_t* sub_from = nullptr, int64_t nout = -1);
 
 // ----------------------------------------------------------------- division
 // Euclidean division (Sec. 3) runs in two steps around one host read of the
@@ -107,8 +110,8 @@ hipError_t mulx_launch(const uint32_t* a, int64_t na, const uint32_t* b, int64_t
 // and computes the whole quotient from the head of a and b (the division
 // steps, s at a time, on up to num_cus cooperating blocks); the remainder
 // r = a - q*b restricted to exponents below deg b is then one product launch
-// with a subtracting epilogue (mul_launch with sub_from = a), and
-// trim_launch finds its length.
+// with a subtracting epilogue (mulx_launch or mul_launch with sub_from = a),
+// and trim_launch finds its length.
 constexpr int DIV_THREADS = 256;
 // Scratch words: the head of a (deg a - deg b + 1 <= na words) and one
 // 64-bit published word per quotient term.
@@ -121,9 +124,6 @@ hipError_t divrem_head_launch(const uint32_t* a, int64_t na, const uint32_t* b, 
                               uint32_t* head, CallInfo* info, int s, int num_cus, hipStream_t stream);
 // info->n1 = 1 + (largest k < n with r[k] != 0), or 0.
 hipError_t trim_launch(const uint32_t* r, int64_t n, CallInfo* info, hipStream_t stream);
-// Degrees and range check only (info->deg_a, deg_b, status).
-hipError_t degrees_launch(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb,
-                          const Field& F, CallInfo* info, hipStream_t stream);
 
 // ---------------------------------------------------------------------- gcd
 struct GcdPlan {

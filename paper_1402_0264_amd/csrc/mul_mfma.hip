@@ -143,6 +143,7 @@ struct MxArgs {
     uint32_t* flags;      // G range-check flags
     uint32_t* f;
     int64_t nf;
+    const uint32_t* sub;  // when set, f[k] = sub[k] - (a b)[k] for k < nf
     int64_t* out_len;
     int32_t* out_status;
     Field F;
@@ -458,7 +459,12 @@ __global__ __launch_bounds__(256) void mulx_reduce_kernel(MxArgs A) {
         add4(s, v0); add4(s, v1); add4(s, v2); add4(s, v3);
     }
     for (; w <= wl; w++) add4(s, *(const uint4*)(part + w * stride));
-    const uint32_t r[4] = {reduce64(s[0], A.F), reduce64(s[1], A.F), reduce64(s[2], A.F), reduce64(s[3], A.F)};
+    uint32_t r[4] = {reduce64(s[0], A.F), reduce64(s[1], A.F), reduce64(s[2], A.F), reduce64(s[3], A.F)};
+    if (A.sub) {
+#pragma unroll
+        for (int e = 0; e < 4; e++)
+            if (k + e < A.nf) r[e] = submod(A.sub[k + e], r[e], A.F.p);
+    }
     if (k + 3 < A.nf && ((uintptr_t)(A.f + k) & 15) == 0) {
         *(uint4*)(A.f + k) = uint4{r[0], r[1], r[2], r[3]};
     } else {
@@ -494,21 +500,21 @@ int mx_blocks_per_cu() {
 }  // namespace
 
 namespace {
-MxGeom mx_plan(int64_t na, int64_t nb, int num_cus);
+MxGeom mx_plan(int64_t na, int64_t nb, int num_cus, int64_t nout);
 }
 
 // Plans are cached per shape: planning walks every share (binary searches),
 // which would otherwise cost more host time per call than a small product.
-MxGeom mx_geometry(int64_t na, int64_t nb, int num_cus) {
+MxGeom mx_geometry(int64_t na, int64_t nb, int num_cus, int64_t nout) {
     static std::mutex mu;
-    static std::map<std::tuple<int64_t, int64_t, int>, MxGeom> cache;
-    const auto key = std::make_tuple(na, nb, num_cus);
+    static std::map<std::tuple<int64_t, int64_t, int, int64_t>, MxGeom> cache;
+    const auto key = std::make_tuple(na, nb, num_cus, nout);
     {
         std::lock_guard<std::mutex> lk(mu);
         auto it = cache.find(key);
         if (it != cache.end()) return it->second;
     }
-    const MxGeom g = mx_plan(na, nb, num_cus);
+    const MxGeom g = mx_plan(na, nb, num_cus, nout);
     std::lock_guard<std::mutex> lk(mu);
     if (cache.size() > 4096) cache.clear();
     cache[key] = g;
@@ -516,13 +522,15 @@ MxGeom mx_geometry(int64_t na, int64_t nb, int num_cus) {
 }
 
 namespace {
-MxGeom mx_plan(int64_t na, int64_t nb, int num_cus) {
+MxGeom mx_plan(int64_t na, int64_t nb, int num_cus, int64_t nout) {
     MxGeom g{};
     g.na = na;
     g.nb = nb;
     const int64_t nab = (na + MX_T - 1) / MX_T;   // blocks of a
     const int64_t nJ = (nb + 62) / MX_T + 1;      // offsets J with 64J - 63 <= nb - 1
     g.nkr = (nJ + nab - 1 + MX_KW - 1) / MX_KW;
+    if (nout > 0 && (nout + MX_RANGE - 1) / MX_RANGE < g.nkr)
+        g.nkr = (nout + MX_RANGE - 1) / MX_RANGE;  // only the ranges below nout
     // rounded to whole groups: lo rounded down, hi rounded up
     const int64_t c = (1 - nab) >= 0 ? (1 - nab) / MX_GRP * MX_GRP : -((nab - 1 + MX_GRP - 1) / MX_GRP * MX_GRP);
     g.nab = 1 - c;
@@ -552,7 +560,7 @@ int64_t mulx_scratch_words(const MxGeom& g) { return g.G * g.maxseg * MX_RANGE +
 
 hipError_t mulx_launch(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, const Field& F, uint32_t* f,
                        const MxGeom& g, uint32_t* scratch, int64_t* out_len, int32_t* out_status,
-                       hipStream_t stream) {
+                       hipStream_t stream, const uint32_t* sub_from, int64_t nout) {
     MxArgs A{};
     A.a = a;
     A.b = b;
@@ -560,7 +568,8 @@ hipError_t mulx_launch(const uint32_t* a, int64_t na, const uint32_t* b, int64_t
     A.part = scratch;
     A.flags = scratch + g.G * g.maxseg * MX_RANGE;
     A.f = f;
-    A.nf = na + nb - 1;
+    A.nf = nout > 0 && nout < na + nb - 1 ? nout : na + nb - 1;
+    A.sub = sub_from;
     A.out_len = out_len;
     A.out_status = out_status;
     A.F = F;
