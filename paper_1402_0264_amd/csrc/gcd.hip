@@ -498,7 +498,9 @@ GcdPlan gcd_default_plan(int64_t n, int num_cus, int s) {
     P.s = s > 0 ? s : 128;
     if (P.s > GCD_MAXSTEPS) P.s = GCD_MAXSTEPS;
     P.head = 128;  // a chunk has at most 2(S+1) <= 128 steps: about 64 entries of each head
-    P.slice = 256;
+    // 512 positions per block: fewer blocks make the per-chunk grid barrier
+    // cheaper, while the apply (two positions per thread) stays short
+    P.slice = 512;
     int64_t groups = (n + P.slice - 1) / P.slice;
     const int64_t max_groups = 2LL * num_cus;
     while (groups > max_groups) {
