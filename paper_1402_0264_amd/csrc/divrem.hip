@@ -71,7 +71,7 @@ __global__ __launch_bounds__(256) void zero_check_kernel(uint64_t* qlog, int64_t
 }
 
 constexpr int DIVF_QB = 4096;                   // quotient terms one batch holds in LDS
-constexpr int DIVF_RUN = 512;                   // head positions per run, rounded up to whole tiles
+constexpr int DIVF_RUN = 384;                   // head positions per run, rounded up to whole tiles
 constexpr int DIVF_RMAX = DIVF_RUN + 64;        // most positions of a run
 constexpr int DIVF_BW = DIVF_QB + DIVF_RMAX + 8;  // distance window of one batch
 constexpr int DIVF_GRP = 8;                     // products summed between folds (p < 2^30)
@@ -473,7 +473,7 @@ hipError_t divrem_head_launch(const uint32_t* a, int64_t na, const uint32_t* b, 
     D.qlog = (uint64_t*)(head + ((words + 1) & ~1LL));
     D.info = info;
     D.S = s;
-    D.K = (512 + s - 1) / s;  // runs of about 512 head positions
+    D.K = (DIVF_RUN + s - 1) / s;  // runs of about DIVF_RUN head positions
     // blocks: one per run of the head when b has a non-zero top coefficient
     // (the device finds the true degrees; a longer head only gives a block
     // more runs)
