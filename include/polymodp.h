@@ -138,6 +138,22 @@ pm_status poly_gcd_modp(const uint32_t *a, int64_t na, const uint32_t *b, int64_
                         uint32_t *g, int64_t g_cap, int64_t *ng, void *stream);
 
 /*
+ * The naive algorithms of the paper, for the s = 1 end of the sweeps over s:
+ * one division step per kernel launch, each launch a global synchronisation
+ * (Sec. 3, naive division, Alg. 1/2; Sec. 6, naive gcd, Alg. 8/9, with the
+ * exact inverse of the divisor's leading coefficient at every step).
+ * Arguments, results and errors as poly_divrem_modp and poly_gcd_modp; the
+ * gcd also accepts p = 2. The library's scratch holds a working copy of the
+ * inputs. They cost deg a - deg b + 1 launches (division) and about
+ * 2 (deg a + deg b) launches (gcd), and are not meant for production use.
+ */
+pm_status poly_divrem_modp_naive(const uint32_t *a, int64_t na, const uint32_t *b, int64_t nb, uint32_t p,
+                                 uint32_t *q, int64_t q_cap, int64_t *nq, uint32_t *r, int64_t r_cap, int64_t *nr,
+                                 void *stream);
+pm_status poly_gcd_modp_naive(const uint32_t *a, int64_t na, const uint32_t *b, int64_t nb, uint32_t p,
+                              uint32_t *g, int64_t g_cap, int64_t *ng, void *stream);
+
+/*
  * Many independent gcds in one launch (one thread-block per instance, both
  * polynomials resident in LDS for the whole remainder sequence). Items may
  * mix degrees and primes; each needs max(na, nb) <= PM_GCD_BATCH_MAX.

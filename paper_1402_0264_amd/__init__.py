@@ -111,6 +111,10 @@ def lib() -> ctypes.CDLL:
     L.poly_divrem_modp.restype = ctypes.c_int32
     L.poly_gcd_modp.argtypes = [_vp, _i64, _vp, _i64, ctypes.c_uint32, _vp, _i64, _i64p, _vp]
     L.poly_gcd_modp.restype = ctypes.c_int32
+    L.poly_divrem_modp_naive.argtypes = L.poly_divrem_modp.argtypes
+    L.poly_divrem_modp_naive.restype = ctypes.c_int32
+    L.poly_gcd_modp_naive.argtypes = L.poly_gcd_modp.argtypes
+    L.poly_gcd_modp_naive.restype = ctypes.c_int32
     L.poly_gcd_modp_batch.argtypes = [ctypes.POINTER(GcdItem), ctypes.c_int32, ctypes.POINTER(GcdResult), _vp]
     L.poly_gcd_modp_batch.restype = ctypes.c_int32
     L.pm_mul_batch_create.argtypes = [ctypes.POINTER(MulItem), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -235,8 +239,9 @@ def mul_async(a, b, p: int, f, d_nf, d_status, stream=None):
                                      f.numel(), d_nf.data_ptr(), d_status.data_ptr(), _stream_handle(stream)))
 
 
-def divrem(a, b, p: int, stream=None):
-    """(q, r) with a = q*b + r, deg r < deg b."""
+def divrem(a, b, p: int, stream=None, naive: bool = False):
+    """(q, r) with a = q*b + r, deg r < deg b. ``naive``: one division step
+    per launch (poly_divrem_modp_naive)."""
     torch = _torch()
     a, b = _as_u32_tensor(a), _as_u32_tensor(b)
     na, nb = a.numel(), b.numel()
@@ -247,21 +252,23 @@ def divrem(a, b, p: int, stream=None):
     q = torch.empty(max(qcap, 1), dtype=torch.int32, device=dev)
     r = torch.empty(rcap, dtype=torch.int32, device=dev)
     nq, nr = ctypes.c_int64(0), ctypes.c_int64(0)
-    _check(lib().poly_divrem_modp(_dev_ptr(a), na, _dev_ptr(b), nb, p, q.data_ptr(), qcap, ctypes.byref(nq),
-                                  r.data_ptr(), rcap, ctypes.byref(nr), _stream_handle(stream)))
+    fn = lib().poly_divrem_modp_naive if naive else lib().poly_divrem_modp
+    _check(fn(_dev_ptr(a), na, _dev_ptr(b), nb, p, q.data_ptr(), qcap, ctypes.byref(nq), r.data_ptr(), rcap,
+              ctypes.byref(nr), _stream_handle(stream)))
     return q[:nq.value], r[:nr.value]
 
 
-def gcd(a, b, p: int, stream=None):
-    """Monic gcd(a, b) mod p."""
+def gcd(a, b, p: int, stream=None, naive: bool = False):
+    """Monic gcd(a, b) mod p. ``naive``: one division step per launch
+    (poly_gcd_modp_naive)."""
     torch = _torch()
     a, b = _as_u32_tensor(a), _as_u32_tensor(b)
     na, nb = a.numel(), b.numel()
     cap = max(na, nb, 1)
     g = torch.empty(cap, dtype=torch.int32, device=a.device if na else b.device)
     ng = ctypes.c_int64(0)
-    _check(lib().poly_gcd_modp(_dev_ptr(a), na, _dev_ptr(b), nb, p, g.data_ptr(), cap, ctypes.byref(ng),
-                               _stream_handle(stream)))
+    fn = lib().poly_gcd_modp_naive if naive else lib().poly_gcd_modp
+    _check(fn(_dev_ptr(a), na, _dev_ptr(b), nb, p, g.data_ptr(), cap, ctypes.byref(ng), _stream_handle(stream)))
     return g[:ng.value]
 
 

@@ -567,6 +567,96 @@ pm_status poly_divrem_modp(const uint32_t* a, int64_t na, const uint32_t* b, int
     return PM_OK;
 }
 
+pm_status poly_divrem_modp_naive(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, uint32_t p,
+                                 uint32_t* q, int64_t q_cap, int64_t* nq, uint32_t* r, int64_t r_cap, int64_t* nr,
+                                 void* stream) {
+    if (!nq || !nr) return fail(PM_EINVAL, "null nq or nr");
+    if (bad_len(a, na) || bad_len(b, nb)) return fail(PM_EINVAL, "null input or negative length");
+    if (q_cap < 0 || r_cap < 0 || (q_cap > 0 && !q) || (r_cap > 0 && !r))
+        return fail(PM_EINVAL, "bad output buffer");
+    if (nb == 0) return fail(PM_EDIVZERO, "division by the zero polynomial");
+    if (na - nb + 1 > q_cap) return fail(PM_EINVAL, "q_cap %lld < na - nb + 1", (long long)q_cap);
+    pm::Field F;
+    pm_status st = field_for(p, &F);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    Pool* P = nullptr;
+    if ((st = pool_get(s, na > 0 ? na : 1, &P))) return st;
+    HIP_TRY(pm::naive_prep_launch(a, na, b, nb, F, P->d_info, s), "naive prep launch");
+    if ((st = read_info(P, s))) return st;
+    const int64_t da = P->h_info->deg_a, db = P->h_info->deg_b;
+    if (P->h_info->flags) return fail(PM_ERANGE, "%s", status_text(PM_ERANGE));
+    if (db < 0) return fail(PM_EDIVZERO, "division by the zero polynomial");
+    if (da < db) {  // q = 0, r = a
+        if (da + 1 > r_cap) return fail(PM_EINVAL, "r_cap %lld < deg a + 1", (long long)r_cap);
+        if (da >= 0)
+            HIP_TRY(hipMemcpyAsync(r, a, (size_t)(da + 1) * 4, hipMemcpyDeviceToDevice, s), "copy r");
+        HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+        *nq = 0;
+        *nr = da + 1;
+        return PM_OK;
+    }
+    const int64_t mu = da - db + 1;
+    if (mu > q_cap || db > r_cap) return fail(PM_EINVAL, "output capacity below the true degrees");
+    uint32_t lc = 0;
+    HIP_TRY(hipMemcpy(&lc, b + db, 4, hipMemcpyDeviceToHost), "read lc(b)");
+    const uint32_t inv = (uint32_t)powmod_host(lc, p - 2, p);
+    uint32_t* w = P->words;
+    HIP_TRY(hipMemcpyAsync(w, a, (size_t)(da + 1) * 4, hipMemcpyDeviceToDevice, s), "copy a");
+    HIP_TRY(pm::naive_divrem_launch(w, b, da, db, inv, q, F, s), "naive division launch");
+    *nq = mu;
+    if (db == 0) {
+        HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+        *nr = 0;
+        return PM_OK;
+    }
+    HIP_TRY(hipMemcpyAsync(r, w, (size_t)db * 4, hipMemcpyDeviceToDevice, s), "copy r");
+    HIP_TRY(pm::trim_launch(r, db, P->d_info, s), "trim launch");
+    if ((st = read_info(P, s))) return st;
+    *nr = P->h_info->n1;
+    return PM_OK;
+}
+
+pm_status poly_gcd_modp_naive(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, uint32_t p, uint32_t* g,
+                              int64_t g_cap, int64_t* ng, void* stream) {
+    if (!ng) return fail(PM_EINVAL, "null ng");
+    if (bad_len(a, na) || bad_len(b, nb)) return fail(PM_EINVAL, "null input or negative length");
+    if (g_cap < 0 || (g_cap > 0 && !g)) return fail(PM_EINVAL, "bad output buffer");
+    pm::Field F;
+    pm_status st = field_for(p, &F);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    g_gcd_stats = pm_gcd_stats{0, 0, 0};
+    const int64_t n = (na > nb ? na : nb) > 0 ? (na > nb ? na : nb) : 1;
+    Pool* P = nullptr;
+    if ((st = pool_get(s, 2 * n, &P))) return st;
+    uint32_t* A = P->words;
+    uint32_t* B = P->words + n;
+    HIP_TRY(pm::naive_prep_launch(a, na, b, nb, F, P->d_info, s), "naive prep launch");
+    HIP_TRY(hipMemsetAsync(P->words, 0, (size_t)(2 * n) * 4, s), "clear");
+    if (na) HIP_TRY(hipMemcpyAsync(A, a, (size_t)na * 4, hipMemcpyDeviceToDevice, s), "copy a");
+    if (nb) HIP_TRY(hipMemcpyAsync(B, b, (size_t)nb * 4, hipMemcpyDeviceToDevice, s), "copy b");
+    if ((st = read_info(P, s))) return st;
+    if (P->h_info->flags) return fail(PM_ERANGE, "%s", status_text(PM_ERANGE));
+    // every step lowers deg a + deg b by at least one; the host checks for
+    // the end every 512 steps (later launches of a finished run do nothing)
+    int64_t left = (P->h_info->deg_a > 0 ? P->h_info->deg_a : 0) + (P->h_info->deg_b > 0 ? P->h_info->deg_b : 0) + 2;
+    while (P->h_info->deg_a >= 0 && P->h_info->deg_b >= 0 && left > 0) {
+        const int64_t k = left < 512 ? left : 512;
+        HIP_TRY(pm::naive_gcd_steps_launch(A, B, n, k, F, P->d_info, s), "naive gcd launch");
+        left -= k;
+        if ((st = read_info(P, s))) return st;
+    }
+    if (P->h_info->deg_a >= 0 && P->h_info->deg_b >= 0) return fail(PM_EDEVICE, "naive gcd did not finish");
+    const int64_t dR = P->h_info->deg_a >= 0 ? P->h_info->deg_a : P->h_info->deg_b;
+    g_gcd_stats = pm_gcd_stats{P->h_info->steps, P->h_info->updates, P->h_info->steps};
+    if (dR + 1 > g_cap) return fail(PM_EINVAL, "g_cap %lld < deg gcd + 1", (long long)g_cap);
+    if (dR >= 0) HIP_TRY(pm::naive_monic_launch(A, B, g, g_cap, n, F, P->d_info, s), "monic launch");
+    HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+    *ng = dR + 1;
+    return PM_OK;
+}
+
 static_assert(sizeof(pm_gcd_result) == sizeof(pm::GcdResult), "result layouts differ");
 
 pm_status poly_gcd_modp_batch(const pm_gcd_item* items, int32_t count, pm_gcd_result* results, void* stream) {

@@ -42,13 +42,23 @@ struct StepDesc {
 
 struct ChunkOut {
     int64_t dA, dB;   // degrees after the chunk (upper bounds when unk*)
-    int64_t upd;      // coefficient updates: sum of (deg Y + 1)
-    int32_t nsteps;
+    int64_t upd;      // coefficient updates: sum of (deg Y + 1) over all steps counted
+    int32_t nsteps;   // steps run (records in desc[])
     int32_t S;        // total shift = max degree of the entries of M
     int32_t unkA, unkB;
     int32_t big;      // 1: a single step whose shift exceeds GCD_MAXSHIFT
-    int32_t pad;
+    int32_t zsteps;   // steps with a zero multiplier, counted not run (see zero_steps)
+    int64_t zX, zY;   // a step whose new degree is unknown (unk*): deg X and deg Y before it, else -1
 };
+
+// The long division visits every position from deg X down to deg Y
+// (Alg. 1/2): after a step that leaves X with degree nd, the positions
+// between are steps with a zero multiplier, each updating deg Y + 1
+// coefficients with nothing. They are counted, not run.
+__host__ __device__ __forceinline__ int64_t zero_steps(int64_t dX, int64_t dY, int64_t nd) {
+    const int64_t fl = nd > dY - 1 ? nd : dY - 1;
+    return dX - 1 - fl > 0 ? dX - 1 - fl : 0;
+}
 
 // lane i <- lane i+1 of x (lane 63 <- `in63`)
 __device__ __forceinline__ uint32_t lanes_down1(uint32_t x, uint32_t in63) {
@@ -115,8 +125,8 @@ __device__ void head_run_log(uint32_t (&hA)[E], uint32_t (&hB)[E], int dA, int d
     dA = uni(dA);
     dB = uni(dB);
     s = uni(s);
-    int vA = H, vB = H, S = 0, n = 0, unkA = 0, unkB = 0, big = 0;
-    int64_t upd = 0;
+    int vA = H, vB = H, S = 0, n = 0, unkA = 0, unkB = 0, big = 0, zs = 0;
+    int64_t upd = 0, zX = -1, zY = -1;
     for (;;) {
         // the run's state is wave-uniform: keep it in scalar registers, so
         // that the loop and its branches stay scalar (no exec masking)
@@ -164,6 +174,7 @@ __device__ void head_run_log(uint32_t (&hA)[E], uint32_t (&hB)[E], int dA, int d
         upd += (redA ? dB : dA) + 1;
         int nd, nv;
         const int dX = redA ? dA : dB;
+        const int dY = redA ? dB : dA;
         if (delta > 0) {
             for (int k = 0; k < delta; k++) head_shift1<E>(x);
             nd = dX - delta;
@@ -175,6 +186,14 @@ __device__ void head_run_log(uint32_t (&hA)[E], uint32_t (&hB)[E], int dA, int d
             if (nd < 0) nd = -1;
             else if (redA) unkA = 1;
             else unkB = 1;
+        }
+        if (unkA | unkB) {
+            zX = dX;  // the zero steps wait for the true degree
+            zY = dY;
+        } else {
+            const int z = (int)zero_steps(dX, dY, nd);
+            zs += z;
+            upd += (int64_t)z * (dY + 1);
         }
 #pragma unroll
         for (int e = 0; e < E; e++) {
@@ -195,6 +214,9 @@ __device__ void head_run_log(uint32_t (&hA)[E], uint32_t (&hB)[E], int dA, int d
         out->unkA = unkA;
         out->unkB = unkB;
         out->big = big;
+        out->zsteps = zs;
+        out->zX = zX;
+        out->zY = zY;
         __hip_atomic_store(&L->end, n, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
 }

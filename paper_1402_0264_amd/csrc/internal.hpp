@@ -125,6 +125,23 @@ hipError_t divrem_head_launch(const uint32_t* a, int64_t na, const uint32_t* b, 
 // info->n1 = 1 + (largest k < n with r[k] != 0), or 0.
 hipError_t trim_launch(const uint32_t* r, int64_t n, CallInfo* info, hipStream_t stream);
 
+// ------------------------------------------------- naive division and gcd
+// One division step per launch (Sec. 3 Alg. 1/2, Sec. 6 Alg. 8/9).
+// Degrees, range check (info->flags) and reset of the call's results.
+hipError_t naive_prep_launch(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, const Field& F,
+                             CallInfo* info, hipStream_t stream);
+// The steps at head positions da .. db of the working copy w of a, one
+// launch each; q[i - db] for every step i.
+hipError_t naive_divrem_launch(uint32_t* w, const uint32_t* b, int64_t da, int64_t db, uint32_t inv, uint32_t* q,
+                               const Field& F, hipStream_t stream);
+// count gcd steps (two launches each) on the working copies A, B of n
+// words, degrees in info (no-ops once one operand is zero).
+hipError_t naive_gcd_steps_launch(uint32_t* A, uint32_t* B, int64_t n, int64_t count, const Field& F,
+                                  CallInfo* info, hipStream_t stream);
+// g = the non-zero one of A, B made monic (nothing when g_cap is too small).
+hipError_t naive_monic_launch(const uint32_t* A, const uint32_t* B, uint32_t* g, int64_t g_cap, int64_t n,
+                              const Field& F, CallInfo* info, hipStream_t stream);
+
 // ---------------------------------------------------------------------- gcd
 struct GcdPlan {
     int groups;      // cooperating thread-blocks (1 = single block)

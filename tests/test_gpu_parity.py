@@ -322,6 +322,36 @@ def test_divrem_edge_cases():
     assert e.value.status == pm.PM_ERANGE
 
 
+# The naive division (one step per launch), the s = 1 end of the sweep.
+@pytest.mark.parametrize("p", [gen.P_A, gen.P_B, 3, 2])
+def test_divrem_naive_matches_oracle(p):
+    st = gen.Stream(208 + p % 997)
+    for na, nb in [(1, 1), (10, 1), (10, 3), (100, 99), (500, 17), (300, 300), (3, 10), (2049, 2048), (3000, 1100),
+                   (1000, 999), (700, 2)]:
+        a, b = rnd(st, na, p), rnd(st, nb, p)
+        q, r = pm.divrem(dev(a), dev(b), p, naive=True)
+        wq, wr = oracle.divrem(a, b, p)
+        assert same(host(q), wq) and same(host(r), wr), (p, na, nb)
+
+
+def test_divrem_naive_edge_cases():
+    p = gen.P_B
+    st = gen.Stream(209)
+    a, b = rnd(st, 50, p), rnd(st, 9, p)
+    with pytest.raises(pm.PolyModPError) as e:
+        pm.divrem(dev(a), dev(np.zeros(4, dtype=np.uint32)), p, naive=True)
+    assert e.value.status == pm.PM_EDIVZERO
+    for x, y in [(np.zeros(0, dtype=np.uint32), b), (a, a), (a, np.array([7], dtype=np.uint32)),
+                 (np.concatenate([a, np.zeros(5, dtype=np.uint32)]), np.concatenate([b, np.zeros(50, dtype=np.uint32)]))]:
+        q, r = pm.divrem(dev(x), dev(y), p, naive=True)
+        wq, wr = oracle.divrem(x, y, p)
+        assert same(host(q), wq) and same(host(r), wr)
+    bad = b.copy(); bad[0] = p + 5
+    with pytest.raises(pm.PolyModPError) as e:
+        pm.divrem(dev(a), dev(bad), p, naive=True)
+    assert e.value.status == pm.PM_ERANGE
+
+
 # --------------------------------------------------------------------- gcd
 GCD_CASES = [(5, 3, 0), (40, 40, 3), (100, 60, 20), (60, 100, 59), (200, 199, 50), (300, 300, 0),
              (1000, 999, 10), (2500, 2400, 700), (5000, 4999, 1234), (3000, 10, 2), (700, 1, 0)]
@@ -362,6 +392,41 @@ def test_gcd_workload_32768():
     assert same(g, want) and same(g, pl.g)
     got = pm.last_gcd_stats()
     assert got["steps"] == stats.steps and got["updates"] == stats.updates
+
+
+# The naive gcd (one division step per launch, exact inverses): the monic
+# gcd and the exact step and update counts of the oracle.
+@pytest.mark.parametrize("p", [gen.P_A, gen.P_C, 3, 2])
+def test_gcd_naive_matches_oracle(p):
+    st = gen.Stream(304 + p % 997)
+    for da, db, dg in [(5, 3, 0), (40, 40, 3), (100, 60, 20), (60, 100, 59), (200, 199, 50), (300, 300, 0),
+                       (1000, 999, 10), (2500, 2400, 700)]:
+        pl = gen.planted_gcd(da, db, dg, p, st)
+        a, b = oracle.mul(pl.g, pl.u, p), oracle.mul(pl.g, pl.v, p)
+        g = host(pm.gcd(dev(a), dev(b), p, naive=True))
+        want, degs, stats = oracle.gcd(a, b, p, with_info=True)
+        assert same(g, want), (p, da, db, dg)
+        got = pm.last_gcd_stats()
+        assert got["steps"] == stats.steps and got["updates"] == stats.updates, (p, da, db, dg)
+    z = np.zeros(0, dtype=np.uint32)
+    x = rnd(st, 30, p)
+    for u, v in [(z, z), (x, z), (z, x), (x, x), (x, np.array([1], dtype=np.uint32))]:
+        assert same(host(pm.gcd(dev(u), dev(v), p, naive=True)), oracle.gcd(u, v, p))
+
+
+@pytest.mark.parametrize("p", [3, 5, gen.P_A])
+def test_gcd_counts_match_oracle(p):
+    # steps and updates as the oracle counts them, also when leading
+    # coefficients vanish (small primes): one block and the cooperative grid
+    st = gen.Stream(305 + p % 997)
+    for da, db, dg in [(40, 40, 3), (200, 199, 50), (1000, 999, 10), (6000, 5999, 100)]:
+        pl = gen.planted_gcd(da, db, dg, p, st)
+        a, b = oracle.mul(pl.g, pl.u, p), oracle.mul(pl.g, pl.v, p)
+        g = host(pm.gcd(dev(a), dev(b), p))
+        want, degs, stats = oracle.gcd(a, b, p, with_info=True)
+        assert same(g, want), (p, da, db, dg)
+        got = pm.last_gcd_stats()
+        assert got["steps"] == stats.steps and got["updates"] == stats.updates, (p, da, db, dg, got, stats.steps)
 
 
 def test_gcd_edge_cases():
