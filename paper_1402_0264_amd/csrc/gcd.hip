@@ -102,7 +102,6 @@ __global__ __launch_bounds__(GCD_THREADS) void gcd_multi_kernel(GcdArgs G) {
     }
     int64_t dA = uni(s_deg[0]), dB = uni(s_deg[1]);
     int unkA = 0, unkB = 0;
-    int64_t zX = -1, zY = -1;  // the step before an unknown degree (zero steps to count)
     int cur = 0;
     int64_t steps = 0, chunks = 0, updates = 0;
     const int64_t max_chunks = (dA > 0 ? dA : 0) + (dB > 0 ? dB : 0) + 4;
@@ -119,8 +118,11 @@ __global__ __launch_bounds__(GCD_THREADS) void gcd_multi_kernel(GcdArgs G) {
                 if (lane == 0) { s_deg[0] = x; s_deg[1] = y; }
             }
             __syncthreads();
+            // the zero steps after the step whose new degree was unknown
+            // (s_out still holds the last chunk's summary)
             const int64_t nd = uni(unkA ? s_deg[0] : s_deg[1]);
-            const int64_t z = zero_steps(zX, zY, nd);
+            const int64_t zY = uni(s_out.zY);
+            const int64_t z = zero_steps(uni(s_out.zX), zY, nd);
             steps += z;
             updates += z * (zY + 1);
             dA = uni(s_deg[0]);
@@ -194,8 +196,6 @@ __global__ __launch_bounds__(GCD_THREADS) void gcd_multi_kernel(GcdArgs G) {
         dB = res.dB;
         unkA = res.unkA;
         unkB = res.unkB;
-        zX = uni(res.zX);
-        zY = uni(res.zY);
         steps += res.nsteps + res.zsteps;
         updates += res.upd;
     }
@@ -394,9 +394,10 @@ __device__ void gcd_instance(const GcdJob& J, int s, int64_t cap, uint32_t* smem
                 dA = uni(s_deg[0]);
                 dB = uni(s_deg[1]);
                 // the zero steps after the step whose new degree was unknown
-                const int64_t z = zero_steps(uni(res.zX), uni(res.zY), res.unkA ? dA : dB);
+                const int64_t zY = uni(s_out[mb].zY);
+                const int64_t z = zero_steps(uni(s_out[mb].zX), zY, res.unkA ? dA : dB);
                 steps += z;
-                updates += z * (uni(res.zY) + 1);
+                updates += z * (zY + 1);
             }
             if (dA >= 0 && dB >= 0) {
                 if (wave == 0) {

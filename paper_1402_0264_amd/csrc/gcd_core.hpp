@@ -103,11 +103,24 @@ __device__ __forceinline__ uint32_t lanes_up_any(uint32_t x, int d) {
 struct StepLog {
     int prog;  // steps published in desc[]
     int end;   // total steps once the run has finished, else -1
+    int zs;    // zero-multiplier steps counted so far (written by the run's lane 0)
+    int pad;
+    int64_t zupd;  // their updates
 };
 
 __device__ __forceinline__ void steplog_reset(StepLog* L) {
     L->prog = 0;
     L->end = -1;
+    L->zs = 0;
+    L->zupd = 0;
+}
+
+// Adds the zero-multiplier steps of one step (X from degree dX to nd,
+// divisor of degree dY) to the run's counts. One lane.
+__device__ __forceinline__ void count_zero_steps(StepLog* L, int dX, int dY, int nd) {
+    const int z = (int)zero_steps(dX, dY, nd);
+    L->zs += z;
+    L->zupd += (int64_t)z * (dY + 1);
 }
 
 // Head run by one whole wave. hA/hB: the heads (entry i = coefficient of
@@ -125,8 +138,8 @@ __device__ void head_run_log(uint32_t (&hA)[E], uint32_t (&hB)[E], int dA, int d
     dA = uni(dA);
     dB = uni(dB);
     s = uni(s);
-    int vA = H, vB = H, S = 0, n = 0, unkA = 0, unkB = 0, big = 0, zs = 0;
-    int64_t upd = 0, zX = -1, zY = -1;
+    int vA = H, vB = H, S = 0, n = 0, unkA = 0, unkB = 0, big = 0;
+    int64_t upd = 0;
     for (;;) {
         // the run's state is wave-uniform: keep it in scalar registers, so
         // that the loop and its branches stay scalar (no exec masking)
@@ -175,25 +188,33 @@ __device__ void head_run_log(uint32_t (&hA)[E], uint32_t (&hB)[E], int dA, int d
         int nd, nv;
         const int dX = redA ? dA : dB;
         const int dY = redA ? dB : dA;
-        if (delta > 0) {
+        if (__builtin_expect(delta == 1, 1)) {
+            head_shift1<E>(x);
+            nd = dX - 1;
+            nv = v - 1;
+        } else if (delta > 1) {
+            // positions below deg X vanished too: shift them out, and count
+            // the zero-multiplier steps among them (in LDS, so the common
+            // path keeps no extra scalar state)
             for (int k = 0; k < delta; k++) head_shift1<E>(x);
             nd = dX - delta;
             nv = v - delta;
+            if (lane == 0) count_zero_steps(L, dX, dY, nd);
         } else {
             // the first v entries vanished: deg X <= old deg - v
             nd = dX - v;
             nv = 0;
-            if (nd < 0) nd = -1;
-            else if (redA) unkA = 1;
-            else unkB = 1;
-        }
-        if (unkA | unkB) {
-            zX = dX;  // the zero steps wait for the true degree
-            zY = dY;
-        } else {
-            const int z = (int)zero_steps(dX, dY, nd);
-            zs += z;
-            upd += (int64_t)z * (dY + 1);
+            if (nd < 0) {
+                nd = -1;
+                if (lane == 0) count_zero_steps(L, dX, dY, nd);
+            } else {
+                if (redA) unkA = 1;
+                else unkB = 1;
+                if (lane == 0) {  // the zero steps wait for the true degree
+                    out->zX = dX;
+                    out->zY = dY;
+                }
+            }
         }
 #pragma unroll
         for (int e = 0; e < E; e++) {
@@ -208,15 +229,17 @@ __device__ void head_run_log(uint32_t (&hA)[E], uint32_t (&hB)[E], int dA, int d
     if (lane == 0) {
         out->dA = dA;
         out->dB = dB;
-        out->upd = upd;
+        out->upd = upd + L->zupd;
         out->nsteps = n;
         out->S = S;
         out->unkA = unkA;
         out->unkB = unkB;
         out->big = big;
-        out->zsteps = zs;
-        out->zX = zX;
-        out->zY = zY;
+        out->zsteps = L->zs;
+        if (!(unkA | unkB)) {
+            out->zX = -1;
+            out->zY = -1;
+        }
         __hip_atomic_store(&L->end, n, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
 }
