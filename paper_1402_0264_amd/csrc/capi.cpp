@@ -509,8 +509,15 @@ pm_status poly_mul_modp(const uint32_t* a, int64_t na, const uint32_t* b, int64_
     return PM_OK;
 }
 
-pm_status poly_divrem_modp(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, uint32_t p, uint32_t* q,
-                           int64_t q_cap, int64_t* nq, uint32_t* r, int64_t r_cap, int64_t* nr, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// The division of poly_divrem_modp; also reports deg a and deg b (degs[0],
+// degs[1]) when degs is given.
+pm_status divrem_impl(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, uint32_t p, uint32_t* q,
+                      int64_t q_cap, int64_t* nq, uint32_t* r, int64_t r_cap, int64_t* nr, void* stream,
+                      int64_t* degs) {
     if (!nq || !nr) return fail(PM_EINVAL, "null nq or nr");
     if (bad_len(a, na) || bad_len(b, nb)) return fail(PM_EINVAL, "null input or negative length");
     if (q_cap < 0 || r_cap < 0 || (q_cap > 0 && !q) || (r_cap > 0 && !r))
@@ -531,6 +538,10 @@ pm_status poly_divrem_modp(const uint32_t* a, int64_t na, const uint32_t* b, int
     const pm::CallInfo I = *P->h_info;
     if (I.status) return fail(I.status, "%s", status_text(I.status));
     const int64_t da = I.deg_a, db = I.deg_b;
+    if (degs) {
+        degs[0] = da;
+        degs[1] = db;
+    }
     if (da < db) {  // q = 0, r = a
         if (da >= 0)
             HIP_TRY(hipMemcpyAsync(r, a, (size_t)(da + 1) * 4, hipMemcpyDeviceToDevice, s), "copy r");
@@ -565,6 +576,15 @@ pm_status poly_divrem_modp(const uint32_t* a, int64_t na, const uint32_t* b, int
     if ((st = read_info(P, s))) return st;
     *nr = P->h_info->n1;
     return PM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pm_status poly_divrem_modp(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, uint32_t p, uint32_t* q,
+                           int64_t q_cap, int64_t* nq, uint32_t* r, int64_t r_cap, int64_t* nr, void* stream) {
+    return divrem_impl(a, na, b, nb, p, q, q_cap, nq, r, r_cap, nr, stream, nullptr);
 }
 
 pm_status poly_divrem_modp_naive(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, uint32_t p,
@@ -710,6 +730,131 @@ pm_status poly_gcd_modp_batch(const pm_gcd_item* items, int32_t count, pm_gcd_re
     return PM_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// A degree gap of at least this many positions starts the gcd with one
+// Euclidean division: the chunked steps would take each step of a long
+// quotient alone (its shift is beyond what a chunk's matrix holds).
+constexpr int64_t GCD_LEAD_GAP = 128;
+
+// Scratch of the gcd's leading division (quotient, remainder, folded
+// operand), apart from the pool that the division and the gcd use.
+struct Aux {
+    uint32_t* w = nullptr;
+    int64_t cap = 0;
+};
+std::map<std::pair<int, hipStream_t>, Aux> g_aux;  // guarded by g_pool_mu
+
+pm_status aux_get(hipStream_t stream, int64_t words, uint32_t** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    Aux& X = g_aux[{dev, stream}];
+    if (words > X.cap) {
+        if (X.w) {
+            HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
+            HIP_TRY(hipFree(X.w), "hipFree");
+            X.w = nullptr;
+            X.cap = 0;
+        }
+        const int64_t want = words + words / 4 + 1024;
+        if (hipMalloc((void**)&X.w, (size_t)want * sizeof(uint32_t)) != hipSuccess) {
+            X.w = nullptr;
+            return fail(PM_ENOMEM, "cannot allocate %lld scratch words", (long long)want);
+        }
+        X.cap = want;
+    }
+    *out = X.w;
+    return PM_OK;
+}
+
+// The gcd of validated operands: one block in LDS when the larger fits,
+// else the cooperative kernel. Sets the call's counts.
+pm_status gcd_run(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, uint32_t p, const pm::Field& F,
+                  uint32_t* g, int64_t g_cap, int64_t* ng, hipStream_t s) {
+    const int64_t n = na > nb ? na : nb;
+    pm_params pp = params_now();
+    if (n <= pm::gcd_batch_cap(0)) {
+        // one block holds the whole instance in LDS
+        pm_gcd_item it{a, na, b, nb, p, g, g_cap};
+        pm_gcd_result res{};
+        pm_status st1 = poly_gcd_modp_batch(&it, 1, &res, s);
+        if (st1) return st1;
+        g_gcd_stats = pm_gcd_stats{res.steps, res.updates, res.chunks};
+        if (res.status) return fail(res.status, "%s", status_text(res.status));
+        *ng = res.ng;
+        return PM_OK;
+    }
+    pm::GcdPlan plan = pm::gcd_default_plan(n > 0 ? n : 1, num_cus(), pp.gcd_s);
+    Pool* P = nullptr;
+    pm_status st;
+    if ((st = pool_get(s, pm::gcd_scratch_words(n, plan), &P))) return st;
+    HIP_TRY(pm::gcd_launch(a, na, b, nb, F, g, g_cap, P->words, P->d_info, plan, s), "gcd launch");
+    if ((st = read_info(P, s))) return st;
+    const pm::CallInfo I = *P->h_info;
+    g_gcd_stats = pm_gcd_stats{I.steps, I.updates, I.chunks};
+    if (I.status) return fail(I.status, "%s", status_text(I.status));
+    *ng = I.n0;
+    return PM_OK;
+}
+
+// The first division of the remainder sequence (Sec. 6) as one Euclidean
+// division (Sec. 3), then the chunked gcd on what remains. The operand of
+// higher degree, X, loses steps at every position from deg X down to deg Y,
+// except that on a tie the paper reduces a: when X = b, the steps stop
+// above deg a, so b becomes r + q_0 a rather than r. The steps and updates
+// the division stands for are counted as the steps would be: one per
+// position, deg Y + 1 updates each.
+pm_status gcd_lead_division(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, uint32_t p,
+                            const pm::Field& F, uint32_t* g, int64_t g_cap, int64_t* ng, hipStream_t s) {
+    Pool* P = nullptr;
+    pm_status st;
+    if ((st = pool_get(s, 0, &P))) return st;
+    HIP_TRY(pm::naive_prep_launch(a, na, b, nb, F, P->d_info, s), "degree scan");
+    if ((st = read_info(P, s))) return st;
+    if (P->h_info->flags) return fail(PM_ERANGE, "%s", status_text(PM_ERANGE));
+    const int64_t dA = P->h_info->deg_a, dB = P->h_info->deg_b;
+    const int64_t gap = dA > dB ? dA - dB : dB - dA;
+    if (dA < 0 || dB < 0 || gap < GCD_LEAD_GAP) return gcd_run(a, na, b, nb, p, F, g, g_cap, ng, s);
+    const bool redA = dA > dB;
+    const uint32_t* X = redA ? a : b;
+    const uint32_t* Y = redA ? b : a;
+    const int64_t dX = redA ? dA : dB, dY = redA ? dB : dA;
+    const int64_t mu = dX - dY + 1;
+    uint32_t* w = nullptr;
+    const int64_t qw = (mu + 63) & ~63LL, rw = (dY + 1 + 63) & ~63LL;
+    if ((st = aux_get(s, qw + 2 * rw, &w))) return st;
+    uint32_t* q = w;
+    uint32_t* r = w + qw;
+    uint32_t* fold = r + rw;
+    int64_t nq = 0, nr = 0;
+    if ((st = divrem_impl(X, dX + 1, Y, dY + 1, p, q, mu, &nq, r, dY + 1, &nr, s, nullptr))) return st;
+    int64_t count = mu;
+    if (redA) {
+        st = gcd_run(r, nr, b, dB + 1, p, F, g, g_cap, ng, s);
+    } else {
+        uint32_t q0 = 0;
+        HIP_TRY(hipMemcpyAsync(&q0, q, sizeof(q0), hipMemcpyDeviceToHost, s), "copy q_0");
+        HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+        if (q0 == 0) {
+            st = gcd_run(a, dA + 1, r, nr, p, F, g, g_cap, ng, s);
+        } else {
+            count = mu - 1;  // position deg a is a's step (the tie)
+            HIP_TRY(pm::fold_q0_launch(r, nr, q, a, dA + 1, fold, F, s), "fold launch");
+            st = gcd_run(a, dA + 1, fold, dA + 1, p, F, g, g_cap, ng, s);
+        }
+    }
+    g_gcd_stats.steps += count;
+    g_gcd_stats.updates += count * (dY + 1);
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
 pm_status poly_gcd_modp(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, uint32_t p, uint32_t* g,
                         int64_t g_cap, int64_t* ng, void* stream) {
     if (!ng) return fail(PM_EINVAL, "null ng");
@@ -721,29 +866,9 @@ pm_status poly_gcd_modp(const uint32_t* a, int64_t na, const uint32_t* b, int64_
     if (!redc_ok(p)) return fail(PM_EMODULUS, "p = 2 is not supported by the gcd");
     hipStream_t s = (hipStream_t)stream;
     g_gcd_stats = pm_gcd_stats{0, 0, 0};
-    int64_t n = na > nb ? na : nb;
-    pm_params pp = params_now();
-    if (n <= pm::gcd_batch_cap(0)) {
-        // one block holds the whole instance in LDS
-        pm_gcd_item it{a, na, b, nb, p, g, g_cap};
-        pm_gcd_result res{};
-        pm_status st1 = poly_gcd_modp_batch(&it, 1, &res, stream);
-        if (st1) return st1;
-        g_gcd_stats = pm_gcd_stats{res.steps, res.updates, res.chunks};
-        if (res.status) return fail(res.status, "%s", status_text(res.status));
-        *ng = res.ng;
-        return PM_OK;
-    }
-    pm::GcdPlan plan = pm::gcd_default_plan(n > 0 ? n : 1, num_cus(), pp.gcd_s);
-    Pool* P = nullptr;
-    if ((st = pool_get(s, pm::gcd_scratch_words(n, plan), &P))) return st;
-    HIP_TRY(pm::gcd_launch(a, na, b, nb, F, g, g_cap, P->words, P->d_info, plan, s), "gcd launch");
-    if ((st = read_info(P, s))) return st;
-    const pm::CallInfo I = *P->h_info;
-    g_gcd_stats = pm_gcd_stats{I.steps, I.updates, I.chunks};
-    if (I.status) return fail(I.status, "%s", status_text(I.status));
-    *ng = I.n0;
-    return PM_OK;
+    const int64_t gap = na > nb ? na - nb : nb - na;
+    if (na > 0 && nb > 0 && gap >= GCD_LEAD_GAP) return gcd_lead_division(a, na, b, nb, p, F, g, g_cap, ng, s);
+    return gcd_run(a, na, b, nb, p, F, g, g_cap, ng, s);
 }
 
 }  // extern "C"

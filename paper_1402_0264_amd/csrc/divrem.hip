@@ -447,6 +447,18 @@ __global__ __launch_bounds__(DIV_THREADS) void divrem_flow_kernel(DivFlow D) {
     }
 }
 
+// out = r + q_0 y over n terms (r has nr <= n terms): what remains of the
+// dividend when the division steps stop one position early, above the
+// divisor's degree instead of at it (the gcd's tie rule, Sec. 6).
+__global__ __launch_bounds__(256) void fold_q0_kernel(const uint32_t* r, int64_t nr, const uint32_t* q,
+                                                      const uint32_t* y, int64_t n, uint32_t* out, Field F) {
+    const uint32_t q0 = q[0];
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const uint32_t ri = i < nr ? r[i] : 0u;
+        out[i] = addmod(ri, mulmod(q0, y[i], F), F.p);
+    }
+}
+
 __global__ __launch_bounds__(256) void trim_kernel(const uint32_t* r, int64_t n, CallInfo* info) {
     if (threadIdx.x < 64) {
         int64_t d = top_nonzero_wave(r, n);
@@ -505,6 +517,15 @@ hipError_t divrem_head_launch(const uint32_t* a, int64_t na, const uint32_t* b, 
     void* args[] = {&D};
     return hipLaunchCooperativeKernel((const void*)divrem_flow_kernel, dim3(blocks), dim3(DIV_THREADS), args, 0,
                                       stream);
+}
+
+hipError_t fold_q0_launch(const uint32_t* r, int64_t nr, const uint32_t* q, const uint32_t* y, int64_t n,
+                          uint32_t* out, const Field& F, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    int64_t grid = (n + 255) / 256;
+    if (grid > 1024) grid = 1024;
+    hipLaunchKernelGGL(fold_q0_kernel, dim3((unsigned)grid), dim3(256), 0, stream, r, nr, q, y, n, out, F);
+    return hipGetLastError();
 }
 
 hipError_t trim_launch(const uint32_t* r, int64_t n, CallInfo* info, hipStream_t stream) {

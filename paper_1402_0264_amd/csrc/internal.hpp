@@ -124,6 +124,9 @@ hipError_t divrem_head_launch(const uint32_t* a, int64_t na, const uint32_t* b, 
                               uint32_t* head, CallInfo* info, int s, int num_cus, hipStream_t stream);
 // info->n1 = 1 + (largest k < n with r[k] != 0), or 0.
 hipError_t trim_launch(const uint32_t* r, int64_t n, CallInfo* info, hipStream_t stream);
+// out[i] = r[i] + q[0] y[i] for i < n (r read as zero past nr)
+hipError_t fold_q0_launch(const uint32_t* r, int64_t nr, const uint32_t* q, const uint32_t* y, int64_t n,
+                          uint32_t* out, const Field& F, hipStream_t stream);
 
 // ------------------------------------------------- naive division and gcd
 // One division step per launch (Sec. 3 Alg. 1/2, Sec. 6 Alg. 8/9).

@@ -44,6 +44,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 
+# threads per block of the naive kernels (the paper's l)
+ELL = 256
+
+
 def _median_ms(fn, reps: int) -> float:
     import time
     import torch
@@ -71,6 +75,7 @@ def sweep_div(args) -> int:
     ref = None
     rows = []
     t1 = mmm.div_time(n, m, 1, mmm.U_THROUGHPUT)
+    tn = mmm.div_time_naive(n, m, mmm.U_THROUGHPUT, ELL)
     for s in svals:
         pm.set_params(div_s=s)
         q, r = pm.divrem(a, b, gen.P_A)
@@ -79,18 +84,29 @@ def sweep_div(args) -> int:
             ref = (q.clone(), r.clone())
         same = bool(torch.equal(q, ref[0]) and torch.equal(r, ref[1]))
         ms = _median_ms(lambda: pm.divrem(a, b, gen.P_A), args.reps)
-        rec = {"op": "divrem", "s": s, "ms": round(ms, 4), "quotient_terms": int(q.numel()),
+        rec = {"op": "divrem", "kernel": "fused", "s": s, "ms": round(ms, 4), "quotient_terms": int(q.numel()),
                "model_T_over_T1": round(mmm.div_time(n, m, s, mmm.U_THROUGHPUT) / t1, 4),
+               "model_T_over_Tnaive": round(mmm.div_time(n, m, s, mmm.U_THROUGHPUT) / tn, 4),
                "identical_to_first": same}
         rows.append(rec)
         print(json.dumps(rec), flush=True)
     pm.set_params()
+    # the naive algorithm (one division step per launch), the s0 end
+    q, r = pm.divrem(a, b, gen.P_A, naive=True)
+    torch.cuda.synchronize()
+    same = bool(torch.equal(q, ref[0]) and torch.equal(r, ref[1]))
+    ms_n = _median_ms(lambda: pm.divrem(a, b, gen.P_A, naive=True), max(1, args.reps // 2))
+    print(json.dumps({"op": "divrem", "kernel": "naive", "s": 1, "ms": round(ms_n, 4), "launches": n - m + 1,
+                      "us_per_step": round(ms_n * 1e3 / (n - m + 1), 3), "model_T_over_Tnaive": 1.0,
+                      "identical_to_first": same}), flush=True)
     best = min(rows, key=lambda x: x["ms"])
     print(json.dumps({"summary": True, "op": "divrem", "n": n, "m": m, "measured_best_s": best["s"],
                       "measured_T1_over_Tbest": round(rows[0]["ms"] / best["ms"], 3),
+                      "measured_Tnaive_over_Tbest": round(ms_n / best["ms"], 3),
                       "model_best_s": min(rows, key=lambda x: x["model_T_over_T1"])["s"],
+                      "model_Tnaive_over_T_at_measured_best": round(1.0 / best["model_T_over_Tnaive"], 3),
                       "paper_R_printed_at_Z": round(mmm.div_ratio_printed(mmm.Z_MI355X, mmm.U_THROUGHPUT), 3),
-                      "all_identical": all(x["identical_to_first"] for x in rows)}), flush=True)
+                      "all_identical": all(x["identical_to_first"] for x in rows) and same}), flush=True)
     return 0
 
 
@@ -109,6 +125,7 @@ def sweep_gcd(args) -> int:
     svals = [int(x) for x in (args.s or "1,2,4,8,16,32,64,128,256").split(",")]
     rows = []
     t1 = mmm.gcd_time(n, m, 1, mmm.U_THROUGHPUT)
+    tn = mmm.gcd_time_naive(n, m, mmm.U_THROUGHPUT, ELL)
     for s in svals:
         pm.set_params(gcd_s=s)
         out = pm.gcd(a, b, p)
@@ -116,26 +133,93 @@ def sweep_gcd(args) -> int:
         ok = bool(np.array_equal(pm.to_numpy(out), pl.g))
         ms = _median_ms(lambda: pm.gcd(a, b, p), args.reps)
         stt = pm.last_gcd_stats()
-        rec = {"op": "gcd", "s": s, "ms": round(ms, 3), "chunks": stt["chunks"], "steps": stt["steps"],
-               "ns_per_step": round(ms * 1e6 / max(stt["steps"], 1), 1),
+        rec = {"op": "gcd", "kernel": "fused", "s": s, "ms": round(ms, 3), "chunks": stt["chunks"],
+               "steps": stt["steps"], "ns_per_step": round(ms * 1e6 / max(stt["steps"], 1), 1),
                "model_T_over_T1": round(mmm.gcd_time(n, m, s, mmm.U_THROUGHPUT) / t1, 4),
+               "model_T_over_Tnaive": round(mmm.gcd_time(n, m, s, mmm.U_THROUGHPUT) / tn, 4),
                "gcd_equals_planted": ok}
         rows.append(rec)
         print(json.dumps(rec), flush=True)
     pm.set_params()
+    # the naive algorithm (one division step per launch), the s0 end
+    out = pm.gcd(a, b, p, naive=True)
+    torch.cuda.synchronize()
+    ok_n = bool(np.array_equal(pm.to_numpy(out), pl.g))
+    ms_n = _median_ms(lambda: pm.gcd(a, b, p, naive=True), max(1, args.reps // 2))
+    stt = pm.last_gcd_stats()
+    print(json.dumps({"op": "gcd", "kernel": "naive", "s": 1, "ms": round(ms_n, 3), "steps": stt["steps"],
+                      "ns_per_step": round(ms_n * 1e6 / max(stt["steps"], 1), 1), "model_T_over_Tnaive": 1.0,
+                      "gcd_equals_planted": ok_n}), flush=True)
     best = min(rows, key=lambda x: x["ms"])
     print(json.dumps({"summary": True, "op": "gcd", "n": n, "m": m, "measured_best_s": best["s"],
                       "measured_T1_over_Tbest": round(rows[0]["ms"] / best["ms"], 3),
+                      "measured_Tnaive_over_Tbest": round(ms_n / best["ms"], 3),
                       "model_s_star": round(mmm.gcd_s_star(n, m, mmm.U_THROUGHPUT), 1),
                       "model_T1_over_T_at_best": round(1.0 / min(x["model_T_over_T1"] for x in rows), 3),
+                      "model_Tnaive_over_T_at_measured_best": round(1.0 / best["model_T_over_Tnaive"], 3),
+                      "paper_R_printed": round(mmm.gcd_ratio_printed(n, mmm.Z_MI355X, mmm.U_THROUGHPUT), 3),
                       "paper_table2_s1_over_s512": 4.24,
-                      "all_correct": all(x["gcd_equals_planted"] for x in rows)}), flush=True)
+                      "all_correct": all(x["gcd_equals_planted"] for x in rows) and ok_n}), flush=True)
+    return 0
+
+
+# The (n, m) pairs of Table 2 (term counts; deg a = n - 1, deg b = m - 1) and
+# the times the paper printed there, in seconds, for s = 1 and s = 512 on its
+# own GPU: context for the shape of the ratio, not a target.
+TABLE2 = ((2000, 1500, 0.058, 0.024), (3000, 2500, 0.108, 0.039), (4000, 3500, 0.158, 0.053),
+          (5000, 4500, 0.203, 0.069), (6000, 5000, 0.235, 0.056), (7000, 6000, 0.282, 0.066),
+          (8000, 7000, 0.324, 0.076), (9000, 8000, 0.367, 0.087), (10000, 9000, 0.411, 0.097))
+
+
+def table2(args) -> int:
+    """The shape of Table 2 on this GPU: for each (n, m) pair, a uniform
+    random a of n terms and b of m terms over p_A (coprime with high
+    probability, so the remainder sequence runs to the end), timed with the
+    naive gcd (one step per launch) and the fused gcd at its default s."""
+    import torch
+    import paper_1402_0264_amd as pm
+    from paper_1402_0264_amd import gen, mmm
+    torch.cuda.set_device(0)
+    p = gen.P_A
+    pm.set_params()
+    gs = pm.get_params()["gcd_s"] or 128
+    ratios = []
+    for k, (n, m, t1_paper, t512_paper) in enumerate(TABLE2):
+        st = gen.Stream(gen.SEED_BASE + 40 + k)
+        a = pm.to_device(st.uniform_poly(n - 1, p))
+        b = pm.to_device(st.uniform_poly(m - 1, p))
+        g_f = pm.gcd(a, b, p)
+        torch.cuda.synchronize()
+        ms_f = _median_ms(lambda: pm.gcd(a, b, p), args.reps)
+        steps_f = pm.last_gcd_stats()["steps"]
+        g_n = pm.gcd(a, b, p, naive=True)
+        torch.cuda.synchronize()
+        ms_n = _median_ms(lambda: pm.gcd(a, b, p, naive=True), args.reps)
+        steps_n = pm.last_gcd_stats()["steps"]
+        same = bool(torch.equal(g_f, g_n)) and steps_f == steps_n
+        model = mmm.gcd_time_naive(n - 1, m - 1, mmm.U_THROUGHPUT, ELL) / mmm.gcd_time(n - 1, m - 1, gs,
+                                                                                         mmm.U_THROUGHPUT)
+        rec = {"op": "table2", "n": n, "m": m, "naive_ms": round(ms_n, 3), "fused_ms": round(ms_f, 3),
+               "fused_s": gs, "steps": steps_f, "gcd_degree": int(g_f.numel()) - 1,
+               "measured_Tnaive_over_Tfused": round(ms_n / ms_f, 2),
+               "model_Tnaive_over_Ts": round(model, 2),
+               "paper_s1_s": t1_paper, "paper_s512_s": t512_paper,
+               "paper_s1_over_s512": round(t1_paper / t512_paper, 2),
+               "naive_equals_fused": same}
+        ratios.append(rec["measured_Tnaive_over_Tfused"])
+        print(json.dumps(rec), flush=True)
+    print(json.dumps({"summary": True, "op": "table2", "measured_ratio_min": min(ratios),
+                      "measured_ratio_max": max(ratios),
+                      "paper_ratio_min": round(min(r[2] / r[3] for r in TABLE2), 2),
+                      "paper_ratio_max": round(max(r[2] / r[3] for r in TABLE2), 2),
+                      "model_R_limit": round((3 + 5 * mmm.U_THROUGHPUT) * mmm.Z_MI355X
+                                             / (3 * (mmm.Z_MI355X + 16 * mmm.U_THROUGHPUT)), 2)}), flush=True)
     return 0
 
 
 def main() -> int:
     ap = argparse.ArgumentParser()
-    ap.add_argument("--op", choices=("mul", "div", "gcd"), default="mul")
+    ap.add_argument("--op", choices=("mul", "div", "gcd", "table2"), default="mul")
     ap.add_argument("--n", type=int, default=65536)
     ap.add_argument("--s", default=None)
     ap.add_argument("--reps", type=int, default=5)
@@ -144,6 +228,8 @@ def main() -> int:
         return sweep_div(args)
     if args.op == "gcd":
         return sweep_gcd(args)
+    if args.op == "table2":
+        return table2(args)
     if args.s is None:
         args.s = "1,2,4,8,16,32,64,128,256,512,1024,2048,4096"
     import torch

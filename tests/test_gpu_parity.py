@@ -429,6 +429,41 @@ def test_gcd_counts_match_oracle(p):
         assert got["steps"] == stats.steps and got["updates"] == stats.updates, (p, da, db, dg, got, stats.steps)
 
 
+@pytest.mark.parametrize("p", [3, gen.P_A])
+def test_gcd_leading_division(p):
+    # a degree gap of 128 or more starts with one Euclidean division; the
+    # gcd and the step and update counts stay the oracle's in both
+    # orientations (b of higher degree stops one position early, Sec. 6's
+    # tie rule), on one block and on the cooperative grid
+    st = gen.Stream(306 + p % 997)
+    cases = []
+    for da, db, dg in [(1000, 300, 10), (300, 1000, 10), (500, 372, 5), (372, 500, 5), (500, 373, 5),
+                       (6000, 2000, 50), (2000, 6000, 50), (3000, 40, 0)]:
+        pl = gen.planted_gcd(da, db, dg, p, st)
+        cases.append((oracle.mul(pl.g, pl.u, p), oracle.mul(pl.g, pl.v, p), (da, db, dg)))
+    # b = a x q' + r: the division's constant quotient term is zero
+    a = st.uniform_poly(400, p)
+    b = oracle.mul(a, np.concatenate([np.zeros(1, np.uint32), st.uniform_poly(300, p)]), p)
+    r = st.uniform_poly(250, p)
+    b[:r.size] = (b[:r.size].astype(np.uint64) + r) % p
+    cases.append((a, b.astype(np.uint32), "q0 = 0"))
+    # constant divisors, b_0 = 0 and b_0 != 0
+    c = np.array([2], dtype=np.uint32)
+    x = st.uniform_poly(300, p)
+    x0 = x.copy(); x0[0] = 0
+    cases += [(x, c, "const b"), (c, x, "const a"), (c, x0, "const a, b_0 = 0")]
+    # leading zeros: the term counts differ by more than the true degrees
+    pl = gen.planted_gcd(200, 199, 7, p, st)
+    pad = np.concatenate([oracle.mul(pl.g, pl.u, p), np.zeros(200, dtype=np.uint32)])
+    cases.append((pad, oracle.mul(pl.g, pl.v, p), "padded"))
+    for u, v, tag in cases:
+        g = host(pm.gcd(dev(u), dev(v), p))
+        want, degs, stats = oracle.gcd(u, v, p, with_info=True)
+        assert same(g, want), (p, tag)
+        got = pm.last_gcd_stats()
+        assert got["steps"] == stats.steps and got["updates"] == stats.updates, (p, tag, got, stats.steps)
+
+
 def test_gcd_edge_cases():
     p = gen.P_A
     st = gen.Stream(303)
