@@ -133,6 +133,12 @@ pm_status poly_divrem_modp(const uint32_t *a, int64_t na, const uint32_t *b, int
  *   g, g_cap : output (device); needs deg gcd + 1 words, at most
  *              max(deg a, deg b) + 1 (checked on the device)
  *   ng       : host; length of g
+ * Up to s division steps per chunk (pm_params.gcd_s) on one cooperating
+ * thread-block per 512 positions. When the degrees differ by 128 or more,
+ * the first division of the sequence runs as one poly_divrem_modp-style
+ * division (the chunks would take each step of a long quotient alone);
+ * pm_last_gcd_stats counts its steps position by position all the same.
+ * Returns PM_ERANGE for a coefficient >= p, PM_EMODULUS for p = 2.
  */
 pm_status poly_gcd_modp(const uint32_t *a, int64_t na, const uint32_t *b, int64_t nb, uint32_t p,
                         uint32_t *g, int64_t g_cap, int64_t *ng, void *stream);

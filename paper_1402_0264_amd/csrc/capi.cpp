@@ -770,23 +770,15 @@ pm_status aux_get(hipStream_t stream, int64_t words, uint32_t** out) {
     return PM_OK;
 }
 
-// The gcd of validated operands: one block in LDS when the larger fits,
-// else the cooperative kernel. Sets the call's counts.
-pm_status gcd_run(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, uint32_t p, const pm::Field& F,
-                  uint32_t* g, int64_t g_cap, int64_t* ng, hipStream_t s) {
+// The gcd of validated operands on the cooperative kernel, at every size:
+// one call's latency is its step chain, and slices of 512 positions per
+// block keep the apply short (one block below 513 terms). The one-block
+// instance of the batch, which holds the pair in LDS, is for throughput
+// over many instances. Sets the call's counts.
+pm_status gcd_run(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, const pm::Field& F, uint32_t* g,
+                  int64_t g_cap, int64_t* ng, hipStream_t s) {
     const int64_t n = na > nb ? na : nb;
     pm_params pp = params_now();
-    if (n <= pm::gcd_batch_cap(0)) {
-        // one block holds the whole instance in LDS
-        pm_gcd_item it{a, na, b, nb, p, g, g_cap};
-        pm_gcd_result res{};
-        pm_status st1 = poly_gcd_modp_batch(&it, 1, &res, s);
-        if (st1) return st1;
-        g_gcd_stats = pm_gcd_stats{res.steps, res.updates, res.chunks};
-        if (res.status) return fail(res.status, "%s", status_text(res.status));
-        *ng = res.ng;
-        return PM_OK;
-    }
     pm::GcdPlan plan = pm::gcd_default_plan(n > 0 ? n : 1, num_cus(), pp.gcd_s);
     Pool* P = nullptr;
     pm_status st;
@@ -817,7 +809,7 @@ pm_status gcd_lead_division(const uint32_t* a, int64_t na, const uint32_t* b, in
     if (P->h_info->flags) return fail(PM_ERANGE, "%s", status_text(PM_ERANGE));
     const int64_t dA = P->h_info->deg_a, dB = P->h_info->deg_b;
     const int64_t gap = dA > dB ? dA - dB : dB - dA;
-    if (dA < 0 || dB < 0 || gap < GCD_LEAD_GAP) return gcd_run(a, na, b, nb, p, F, g, g_cap, ng, s);
+    if (dA < 0 || dB < 0 || gap < GCD_LEAD_GAP) return gcd_run(a, na, b, nb, F, g, g_cap, ng, s);
     const bool redA = dA > dB;
     const uint32_t* X = redA ? a : b;
     const uint32_t* Y = redA ? b : a;
@@ -833,17 +825,17 @@ pm_status gcd_lead_division(const uint32_t* a, int64_t na, const uint32_t* b, in
     if ((st = divrem_impl(X, dX + 1, Y, dY + 1, p, q, mu, &nq, r, dY + 1, &nr, s, nullptr))) return st;
     int64_t count = mu;
     if (redA) {
-        st = gcd_run(r, nr, b, dB + 1, p, F, g, g_cap, ng, s);
+        st = gcd_run(r, nr, b, dB + 1, F, g, g_cap, ng, s);
     } else {
         uint32_t q0 = 0;
         HIP_TRY(hipMemcpyAsync(&q0, q, sizeof(q0), hipMemcpyDeviceToHost, s), "copy q_0");
         HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
         if (q0 == 0) {
-            st = gcd_run(a, dA + 1, r, nr, p, F, g, g_cap, ng, s);
+            st = gcd_run(a, dA + 1, r, nr, F, g, g_cap, ng, s);
         } else {
             count = mu - 1;  // position deg a is a's step (the tie)
             HIP_TRY(pm::fold_q0_launch(r, nr, q, a, dA + 1, fold, F, s), "fold launch");
-            st = gcd_run(a, dA + 1, fold, dA + 1, p, F, g, g_cap, ng, s);
+            st = gcd_run(a, dA + 1, fold, dA + 1, F, g, g_cap, ng, s);
         }
     }
     g_gcd_stats.steps += count;
@@ -868,7 +860,7 @@ pm_status poly_gcd_modp(const uint32_t* a, int64_t na, const uint32_t* b, int64_
     g_gcd_stats = pm_gcd_stats{0, 0, 0};
     const int64_t gap = na > nb ? na - nb : nb - na;
     if (na > 0 && nb > 0 && gap >= GCD_LEAD_GAP) return gcd_lead_division(a, na, b, nb, p, F, g, g_cap, ng, s);
-    return gcd_run(a, na, b, nb, p, F, g, g_cap, ng, s);
+    return gcd_run(a, na, b, nb, F, g, g_cap, ng, s);
 }
 
 }  // extern "C"
