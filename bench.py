@@ -30,7 +30,8 @@ Beside it, in the same line:
                 degree 32767 (32769 quotient terms) at the default s;
   gcd_32768     Euclidean division and remainder-sequence gcd of the degree
                 32768 / 32767 pair with a planted degree-1000 gcd (time per
-                division step, grid syncs, updates/s against the VALU peak);
+                division step, grid syncs, updates/s against the VALU peak),
+                and the extended gcd (Bezout cofactors) of the same pair;
   served        a Poisson stream of 2048 gcd requests (degrees log-uniform
                 in [64, 16384], planted gcd, three primes) through the
                 continuous-batching server: saturated GCDs/s, then p50/p99
@@ -379,6 +380,16 @@ def bench_gcd(reps: int) -> dict:
     st = pm.last_gcd_stats()
     t_gcd = sorted(times)[len(times) // 2]
     ok = bool(np.array_equal(pm.to_numpy(out), pl.g))
+    # the extended gcd (Bezout cofactors) on the same pair
+    gx, sx, tx = pm.xgcd(a, b, p)
+    xtimes = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gx, sx, tx = pm.xgcd(a, b, p)
+        xtimes.append(time.perf_counter() - t0)
+    t_xgcd = sorted(xtimes)[len(xtimes) // 2]
+    ok_x = bool(np.array_equal(pm.to_numpy(gx), pl.g))
     return {"workload": "deg a 32768, deg b 32767, planted monic gcd of degree 1000, p=469762049",
             "divrem_ms": round(t_div * 1e3, 4), "quotient_terms": int(q.numel()),
             "gcd_ms_median": round(t_gcd * 1e3, 4), "gcd_ms_min": round(min(times) * 1e3, 4),
@@ -387,7 +398,9 @@ def bench_gcd(reps: int) -> dict:
             "ns_per_division_step": round(t_gcd * 1e9 / max(st["steps"], 1), 1),
             "grid_syncs": st["chunks"],
             "updates_frac_of_valu_peak": round(st["updates"] / t_gcd / PEAK_MULMOD_PER_S, 5),
-            "gcd_equals_planted": ok}
+            "gcd_equals_planted": ok,
+            "xgcd_ms_median": round(t_xgcd * 1e3, 4), "xgcd_cofactor_terms": [int(sx.numel()), int(tx.numel())],
+            "xgcd_gcd_equals_planted": ok_x}
 
 
 def bench_divrem(reps: int) -> dict:

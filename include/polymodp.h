@@ -144,6 +144,25 @@ pm_status poly_gcd_modp(const uint32_t *a, int64_t na, const uint32_t *b, int64_
                         uint32_t *g, int64_t g_cap, int64_t *ng, void *stream);
 
 /*
+ * Extended Euclidean algorithm (the Bezout certificate of Sec. 6's gcd):
+ * monic g = gcd(a, b) and cofactors s, t with s a + t b = g. Of all such
+ * pairs it returns the unique one with deg s < deg b - deg g (s = 0 when
+ * deg g = deg b); for b = 0, s = 1/lc(a) and t = 0; gcd(0, 0) gives three
+ * empty outputs.
+ *   g, s, t  : outputs (device), with capacities g_cap, s_cap, t_cap; each
+ *              needs at most max(deg a, deg b) + 1 words (checked)
+ *   ng, ns, nt : host; normalised lengths
+ * The remainder sequence is poly_gcd_modp's, with the cofactor of a taken
+ * through every chunk's matrix; the cofactor is then reduced modulo b/g
+ * when needed, and t = (g - s a)/b is one exact division (PM_EDEVICE if it
+ * is not exact: an internal invariant). Host reads: a few per call.
+ * Returns PM_ERANGE for a coefficient >= p, PM_EMODULUS for p = 2.
+ */
+pm_status poly_xgcd_modp(const uint32_t *a, int64_t na, const uint32_t *b, int64_t nb, uint32_t p,
+                         uint32_t *g, int64_t g_cap, int64_t *ng, uint32_t *s, int64_t s_cap, int64_t *ns,
+                         uint32_t *t, int64_t t_cap, int64_t *nt, void *stream);
+
+/*
  * The naive algorithms of the paper, for the s = 1 end of the sweeps over s:
  * one division step per kernel launch, each launch a global synchronisation
  * (Sec. 3, naive division, Alg. 1/2; Sec. 6, naive gcd, Alg. 8/9, with the

@@ -115,6 +115,10 @@ def lib() -> ctypes.CDLL:
     L.poly_divrem_modp_naive.restype = ctypes.c_int32
     L.poly_gcd_modp_naive.argtypes = L.poly_gcd_modp.argtypes
     L.poly_gcd_modp_naive.restype = ctypes.c_int32
+    L.poly_xgcd_modp.argtypes = [_vp, ctypes.c_int64, _vp, ctypes.c_int64, ctypes.c_uint32,
+                                 _vp, ctypes.c_int64, _i64p, _vp, ctypes.c_int64, _i64p,
+                                 _vp, ctypes.c_int64, _i64p, _vp]
+    L.poly_xgcd_modp.restype = ctypes.c_int32
     L.poly_gcd_modp_batch.argtypes = [ctypes.POINTER(GcdItem), ctypes.c_int32, ctypes.POINTER(GcdResult), _vp]
     L.poly_gcd_modp_batch.restype = ctypes.c_int32
     L.pm_mul_batch_create.argtypes = [ctypes.POINTER(MulItem), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -270,6 +274,25 @@ def gcd(a, b, p: int, stream=None, naive: bool = False):
     fn = lib().poly_gcd_modp_naive if naive else lib().poly_gcd_modp
     _check(fn(_dev_ptr(a), na, _dev_ptr(b), nb, p, g.data_ptr(), cap, ctypes.byref(ng), _stream_handle(stream)))
     return g[:ng.value]
+
+
+def xgcd(a, b, p: int, stream=None):
+    """(g, s, t) with s a + t b = g, g = monic gcd(a, b) mod p, and the
+    unique cofactors with deg s < deg b - deg g (s = 0 when deg g = deg b;
+    s = 1/lc(a), t = 0 when b = 0)."""
+    torch = _torch()
+    a, b = _as_u32_tensor(a), _as_u32_tensor(b)
+    na, nb = a.numel(), b.numel()
+    cap = max(na, nb, 1)
+    dev = a.device if na else b.device
+    g = torch.empty(cap, dtype=torch.int32, device=dev)
+    s = torch.empty(cap, dtype=torch.int32, device=dev)
+    t = torch.empty(cap, dtype=torch.int32, device=dev)
+    ng, ns, nt = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(lib().poly_xgcd_modp(_dev_ptr(a), na, _dev_ptr(b), nb, p, g.data_ptr(), cap, ctypes.byref(ng),
+                                s.data_ptr(), cap, ctypes.byref(ns), t.data_ptr(), cap, ctypes.byref(nt),
+                                _stream_handle(stream)))
+    return g[:ng.value], s[:ns.value], t[:nt.value]
 
 
 class MulBatch:

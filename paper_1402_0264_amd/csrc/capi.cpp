@@ -864,3 +864,173 @@ pm_status poly_gcd_modp(const uint32_t* a, int64_t na, const uint32_t* b, int64_
 }
 
 }  // extern "C"
+
+namespace {
+
+// Consecutive 64-word-aligned pieces of one scratch buffer.
+struct Carve {
+    uint32_t* base;
+    int64_t used;
+    uint32_t* take(int64_t words) {
+        uint32_t* p = base + used;
+        used += (words + 63) & ~63LL;
+        return p;
+    }
+};
+
+pm_status trimmed_length(const uint32_t* x, int64_t n, hipStream_t s, int64_t* out) {
+    *out = 0;
+    if (n <= 0) return PM_OK;
+    Pool* P = nullptr;
+    pm_status st;
+    if ((st = pool_get(s, 0, &P))) return st;
+    HIP_TRY(pm::trim_launch(x, n, P->d_info, s), "trim launch");
+    if ((st = read_info(P, s))) return st;
+    *out = P->h_info->n1;
+    return PM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pm_status poly_xgcd_modp(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, uint32_t p, uint32_t* g,
+                         int64_t g_cap, int64_t* ng, uint32_t* s_out, int64_t s_cap, int64_t* ns, uint32_t* t_out,
+                         int64_t t_cap, int64_t* nt, void* stream) {
+    if (!ng || !ns || !nt) return fail(PM_EINVAL, "null ng, ns or nt");
+    if (bad_len(a, na) || bad_len(b, nb)) return fail(PM_EINVAL, "null input or negative length");
+    if (g_cap < 0 || (g_cap > 0 && !g) || s_cap < 0 || (s_cap > 0 && !s_out) || t_cap < 0 || (t_cap > 0 && !t_out))
+        return fail(PM_EINVAL, "bad output buffer");
+    pm::Field F;
+    pm_status st = field_for(p, &F);
+    if (st) return st;
+    if (!redc_ok(p)) return fail(PM_EMODULUS, "p = 2 is not supported by the gcd");
+    hipStream_t hs = (hipStream_t)stream;
+    g_gcd_stats = pm_gcd_stats{0, 0, 0};
+    *ng = *ns = *nt = 0;
+    Pool* P = nullptr;
+    if ((st = pool_get(hs, 0, &P))) return st;
+    HIP_TRY(pm::naive_prep_launch(a, na, b, nb, F, P->d_info, hs), "degree scan");
+    if ((st = read_info(P, hs))) return st;
+    if (P->h_info->flags) return fail(PM_ERANGE, "%s", status_text(PM_ERANGE));
+    const int64_t dA = P->h_info->deg_a, dB = P->h_info->deg_b;
+    if (dA < 0 && dB < 0) return PM_OK;  // gcd(0, 0) = 0 = 0 a + 0 b
+    const int64_t n = (dA > dB ? dA : dB) + 1;
+    pm_params pp = params_now();
+    const pm::GcdPlan plan = pm::gcd_default_plan(n, num_cus(), pp.gcd_s);
+    const int64_t N = pm::gcd_positions(plan);
+    uint32_t* wbase = nullptr;
+    if ((st = aux_get(hs, N + 20 * (n + 64) + 64, &wbase))) return st;
+    Carve W{wbase, 0};
+    uint32_t* one = W.take(1);
+    HIP_TRY(hipMemsetD32Async((hipDeviceptr_t)one, 1u, 1, hs), "set 1");
+
+    // the pair the gcd kernel starts from, and the cofactor of a in each
+    const uint32_t *A1 = a, *B1 = b;
+    int64_t nA1 = dA + 1, nB1 = dB + 1;
+    const uint32_t* sb0 = nullptr;
+    int64_t nsb = 0, count = 0, cY = 0;
+    const int64_t gap = dA > dB ? dA - dB : dB - dA;
+    if (dA >= 0 && dB >= 0 && gap >= GCD_LEAD_GAP) {
+        // the leading division, as in poly_gcd_modp
+        const bool redA = dA > dB;
+        const uint32_t* X = redA ? a : b;
+        const uint32_t* Y = redA ? b : a;
+        const int64_t dX = redA ? dA : dB, dY = redA ? dB : dA;
+        const int64_t mu = dX - dY + 1;
+        uint32_t* q = W.take(mu);
+        uint32_t* r = W.take(dY + 1);
+        int64_t nq = 0, nr = 0;
+        if ((st = divrem_impl(X, dX + 1, Y, dY + 1, p, q, mu, &nq, r, dY + 1, &nr, hs, nullptr))) return st;
+        count = mu;
+        cY = dY + 1;
+        if (redA) {
+            A1 = r;  // a - q b: cofactor 1
+            nA1 = nr;
+        } else {
+            uint32_t q0 = 0;
+            HIP_TRY(hipMemcpyAsync(&q0, q, sizeof(q0), hipMemcpyDeviceToHost, hs), "copy q_0");
+            HIP_TRY(hipStreamSynchronize(hs), "hipStreamSynchronize");
+            uint32_t* sneg = W.take(mu);
+            HIP_TRY(pm::negate_launch(q, mu, sneg, p, q0 != 0, hs), "negate launch");
+            sb0 = sneg;  // b - q a, or b - (q - q_0) a: cofactor -q or -(q - q_0)
+            nsb = mu;
+            if (q0 == 0) {
+                B1 = r;
+                nB1 = nr;
+            } else {
+                count = mu - 1;
+                uint32_t* fold = W.take(dA + 1);
+                HIP_TRY(pm::fold_q0_launch(r, nr, q, a, dA + 1, fold, F, hs), "fold launch");
+                B1 = fold;
+                nB1 = dA + 1;
+            }
+        }
+    }
+
+    // the remainder sequence with the cofactor of a carried along
+    uint32_t* s_res = W.take(N);
+    if ((st = pool_get(hs, pm::gcd_scratch_words(n, plan, true), &P))) return st;
+    const pm::GcdCofactors xg{one, 1, sb0, nsb, dB > 0 ? dB : 0, s_res};
+    HIP_TRY(pm::gcd_launch(A1, nA1, B1, nB1, F, g, g_cap, P->words, P->d_info, plan, hs, &xg), "gcd launch");
+    if ((st = read_info(P, hs))) return st;
+    const pm::CallInfo I = *P->h_info;
+    g_gcd_stats = pm_gcd_stats{I.steps + count, I.updates + count * cY, I.chunks};
+    if (I.status) return fail(I.status, "%s", status_text(I.status));
+    const int64_t n_g = I.n0, dg = n_g - 1;
+
+    // the unique cofactors: deg s < deg b - deg g (s = 0 when g ~ b), and
+    // t = (g - s a) / b exactly; t = 0 when b = 0
+    int64_t ls = 0;
+    if ((st = trimmed_length(s_res, dB > 0 ? dB + 1 : 1, hs, &ls))) return st;
+    const uint32_t* sf = s_res;
+    int64_t nsf = ls;
+    const uint32_t* tf = nullptr;
+    int64_t ntf = 0;
+    if (dB >= 0) {
+        if (dg == dB) {
+            nsf = 0;
+        } else if (ls - 1 >= dB - dg) {
+            uint32_t* h = W.take(dB + 1);
+            uint32_t* hr = W.take(dB + 1);
+            int64_t nh = 0, nhr = 0;
+            if ((st = divrem_impl(b, dB + 1, g, n_g, p, h, dB + 1, &nh, hr, dB + 1, &nhr, hs, nullptr))) return st;
+            if (nhr != 0) return fail(PM_EDEVICE, "extended gcd: g does not divide b");
+            uint32_t* sq = W.take(ls);
+            uint32_t* sc = W.take(dB + 1);
+            int64_t nsq = 0, nsc = 0;
+            if ((st = divrem_impl(s_res, ls, h, nh, p, sq, ls, &nsq, sc, dB + 1, &nsc, hs, nullptr))) return st;
+            sf = sc;
+            nsf = nsc;
+        }
+        const uint32_t* w = g;
+        int64_t nw = n_g;
+        if (nsf > 0) {
+            if (dA < 0) return fail(PM_EDEVICE, "extended gcd: non-zero cofactor of a = 0");
+            const int64_t nprod = nsf + dA;
+            uint32_t* prod = W.take(nprod);
+            if ((st = mul_enqueue(sf, nsf, a, dA + 1, F, prod, nullptr, nullptr, hs))) return st;
+            nw = nprod > n_g ? nprod : n_g;
+            uint32_t* wd = W.take(nw);
+            HIP_TRY(pm::sub_launch(g, n_g, prod, nprod, nw, wd, p, hs), "sub launch");
+            w = wd;
+        }
+        uint32_t* tq = W.take(nw);
+        uint32_t* tr = W.take(dB + 1);
+        int64_t ntr = 0;
+        if ((st = divrem_impl(w, nw, b, dB + 1, p, tq, nw, &ntf, tr, dB + 1, &ntr, hs, nullptr))) return st;
+        if (ntr != 0) return fail(PM_EDEVICE, "extended gcd: g - s a is not a multiple of b");
+        tf = tq;
+    }
+    if (nsf > s_cap) return fail(PM_EINVAL, "s_cap %lld < %lld", (long long)s_cap, (long long)nsf);
+    if (ntf > t_cap) return fail(PM_EINVAL, "t_cap %lld < %lld", (long long)t_cap, (long long)ntf);
+    if (nsf > 0) HIP_TRY(hipMemcpyAsync(s_out, sf, (size_t)nsf * 4, hipMemcpyDeviceToDevice, hs), "copy s");
+    if (ntf > 0) HIP_TRY(hipMemcpyAsync(t_out, tf, (size_t)ntf * 4, hipMemcpyDeviceToDevice, hs), "copy t");
+    HIP_TRY(hipStreamSynchronize(hs), "hipStreamSynchronize");
+    *ng = n_g;
+    *ns = nsf;
+    *nt = ntf;
+    return PM_OK;
+}
+
+}  // extern "C"

@@ -459,6 +459,21 @@ __global__ __launch_bounds__(256) void fold_q0_kernel(const uint32_t* r, int64_t
     }
 }
 
+// out[i] = -x[i] for i < n; out[0] = 0 when drop0 (the cofactor of a in
+// b - (q - q_0) a after the gcd's leading division)
+__global__ __launch_bounds__(256) void negate_kernel(const uint32_t* x, int64_t n, uint32_t* out, uint32_t p,
+                                                     int drop0) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        out[i] = (drop0 && i == 0) ? 0u : submod(0u, x[i], p);
+}
+
+// out[i] = x[i] - y[i] for i < n, x read as zero past nx and y past ny
+__global__ __launch_bounds__(256) void sub_kernel(const uint32_t* x, int64_t nx, const uint32_t* y, int64_t ny,
+                                                  int64_t n, uint32_t* out, uint32_t p) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        out[i] = submod(i < nx ? x[i] : 0u, i < ny ? y[i] : 0u, p);
+}
+
 __global__ __launch_bounds__(256) void trim_kernel(const uint32_t* r, int64_t n, CallInfo* info) {
     if (threadIdx.x < 64) {
         int64_t d = top_nonzero_wave(r, n);
@@ -525,6 +540,28 @@ hipError_t fold_q0_launch(const uint32_t* r, int64_t nr, const uint32_t* q, cons
     int64_t grid = (n + 255) / 256;
     if (grid > 1024) grid = 1024;
     hipLaunchKernelGGL(fold_q0_kernel, dim3((unsigned)grid), dim3(256), 0, stream, r, nr, q, y, n, out, F);
+    return hipGetLastError();
+}
+
+namespace {
+unsigned elementwise_grid(int64_t n) {
+    int64_t grid = (n + 255) / 256;
+    return (unsigned)(grid < 1 ? 1 : grid > 1024 ? 1024 : grid);
+}
+}  // namespace
+
+hipError_t negate_launch(const uint32_t* x, int64_t n, uint32_t* out, uint32_t p, bool drop0,
+                         hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(negate_kernel, dim3(elementwise_grid(n)), dim3(256), 0, stream, x, n, out, p,
+                       drop0 ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t sub_launch(const uint32_t* x, int64_t nx, const uint32_t* y, int64_t ny, int64_t n, uint32_t* out,
+                      uint32_t p, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(sub_kernel, dim3(elementwise_grid(n)), dim3(256), 0, stream, x, nx, y, ny, n, out, p);
     return hipGetLastError();
 }
 

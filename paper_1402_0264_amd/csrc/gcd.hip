@@ -36,6 +36,15 @@ struct GcdArgs {
     Field F;
     CallInfo* info;
     int groups, slice, s;
+    // extended variant: the cofactor of the caller's a in both operands,
+    // carried through every chunk by the same M (A = S_A a + T_A b, and
+    // likewise for B); its degree never exceeds deg b (s_deg_cap)
+    uint32_t* sbuf;  // SA0 | SB0 | SA1 | SB1, N words each
+    const uint32_t* sa0;
+    const uint32_t* sb0;
+    int64_t nsa, nsb;
+    int64_t s_deg_cap;
+    uint32_t* s_res;  // N words: the cofactor of the last non-zero remainder, scaled as g is
 };
 
 template <int E>
@@ -50,7 +59,7 @@ __device__ __forceinline__ void load_heads(const uint32_t* A, const uint32_t* B,
     }
 }
 
-template <int E>
+template <int E, bool XG>
 __global__ __launch_bounds__(GCD_THREADS) void gcd_multi_kernel(GcdArgs G) {
     extern __shared__ uint32_t smem[];
     const int tid = threadIdx.x;
@@ -83,6 +92,14 @@ __global__ __launch_bounds__(GCD_THREADS) void gcd_multi_kernel(GcdArgs G) {
         A0[i] = x;
         B0[i] = y;
     }
+    if constexpr (XG) {
+        for (int64_t i = lo + tid; i < hi; i += GCD_THREADS) {
+            G.sbuf[i] = i < G.nsa ? G.sa0[i] : 0u;
+            G.sbuf[N + i] = i < G.nsb ? G.sb0[i] : 0u;
+            G.sbuf[2 * N + i] = 0u;  // a block's slice of the other half is read
+            G.sbuf[3 * N + i] = 0u;  // before its first write once the degree grows
+        }
+    }
     bad = __syncthreads_or(bad);
     if (tid == 0) G.flags[blockIdx.x] = (uint32_t)bad;
     if (wave < 2) {
@@ -106,6 +123,8 @@ __global__ __launch_bounds__(GCD_THREADS) void gcd_multi_kernel(GcdArgs G) {
     int64_t steps = 0, chunks = 0, updates = 0;
     const int64_t max_chunks = (dA > 0 ? dA : 0) + (dB > 0 ? dB : 0) + 4;
     bool ok = true;
+    // bound on the cofactors' degree; grows by each chunk's shift
+    int64_t cdeg = XG ? uni((G.nsa > G.nsb ? G.nsa : G.nsb) - 1) : 0;
     for (;;) {
         const uint32_t* Acur = cur ? A1 : A0;
         const uint32_t* Bcur = cur ? B1 : B0;
@@ -189,6 +208,51 @@ __global__ __launch_bounds__(GCD_THREADS) void gcd_multi_kernel(GcdArgs G) {
                 }
             }
         }
+        if constexpr (XG) {
+            // the cofactors take the same M; a block computes its whole
+            // slice once the bound reaches it (values past the true degree
+            // come out zero)
+            const int64_t grow = res.big ? (int64_t)desc[0].d : (int64_t)res.S;
+            int64_t cdn = cdeg + grow;
+            if (cdn > G.s_deg_cap) cdn = G.s_deg_cap;
+            cdeg = uni(cdn);
+            const uint32_t* SAc = G.sbuf + (cur ? 2 * N : 0);
+            const uint32_t* SBc = SAc + N;
+            uint32_t* SAn = G.sbuf + (cur ? 0 : 2 * N);
+            uint32_t* SBn = SAn + N;
+            if (lo <= cdeg) {
+                if (!res.big) {
+                    const int S = res.S;
+                    const int64_t base = lo - S;
+                    const int len = slice + S;
+                    __syncthreads();  // the state's windows have been read
+                    for (int x = tid; x < len; x += GCD_THREADS) {
+                        int64_t P = base + x;
+                        la[x] = P >= 0 ? SAc[P] : 0u;
+                        lb[x] = P >= 0 ? SBc[P] : 0u;
+                    }
+                    __syncthreads();
+                    for (int x = tid; x < slice; x += GCD_THREADS) {
+                        uint32_t sa_, sb_;
+                        apply_m_at(la, lb, x + S, S, M, F, sa_, sb_);
+                        SAn[lo + x] = sa_;
+                        SBn[lo + x] = sb_;
+                    }
+                } else {
+                    const StepDesc D = desc[0];
+                    const uint32_t* Xc = D.which ? SBc : SAc;
+                    const uint32_t* Yc = D.which ? SAc : SBc;
+                    uint32_t* Xn = D.which ? SBn : SAn;
+                    uint32_t* Yn = D.which ? SAn : SBn;
+                    for (int x = tid; x < slice; x += GCD_THREADS) {
+                        const int64_t P = lo + x;
+                        uint32_t y = P - D.d >= 0 ? Yc[P - D.d] : 0u;
+                        Xn[P] = redc((uint64_t)D.m1 * Xc[P] + (uint64_t)D.m2 * y, F);
+                        Yn[P] = Yc[P];
+                    }
+                }
+            }
+        }
         if (tid == 0) steplog_reset(&s_log);  // read by the next chunk after the barrier
         grid_sync(G.info, G.groups, gen);
         cur ^= 1;
@@ -210,6 +274,12 @@ __global__ __launch_bounds__(GCD_THREADS) void gcd_multi_kernel(GcdArgs G) {
     if (status == 0 && dR >= 0) {
         const uint32_t inv = invmod(Rp[dR], F);
         for (int64_t P = lo + tid; P < hi && P <= dR; P += GCD_THREADS) G.g[P] = mulmod(Rp[P], inv, F);
+    }
+    if constexpr (XG) {
+        // the cofactor of a in the last non-zero remainder, scaled as g is
+        const uint32_t* SR = G.sbuf + (cur ? 2 * N : 0) + (dA >= 0 ? 0 : N);
+        const uint32_t inv = (status == 0 && dR >= 0) ? invmod(Rp[dR], F) : 0u;
+        for (int64_t P = lo + tid; P < hi; P += GCD_THREADS) G.s_res[P] = mulmod(SR[P], inv, F);
     }
     if (blockIdx.x == 0 && tid == 0) {
         G.info->status = status;
@@ -524,32 +594,44 @@ GcdPlan gcd_default_plan(int64_t n, int num_cus, int s) {
     return P;
 }
 
-int64_t gcd_scratch_words(int64_t n, const GcdPlan& plan) {
-    int64_t N = (int64_t)plan.groups * plan.slice;
+int64_t gcd_positions(const GcdPlan& plan) { return (int64_t)plan.groups * plan.slice; }
+
+int64_t gcd_scratch_words(int64_t n, const GcdPlan& plan, bool cofactors) {
+    int64_t N = gcd_positions(plan);
     if (N < n) N = n;
-    return 4 * N + plan.groups + 64;
+    const int64_t base = ((4 * N + plan.groups + 64) + 63) & ~63LL;
+    return cofactors ? base + 4 * N : base;
 }
 
 hipError_t gcd_launch(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, const Field& F, uint32_t* g,
-                      int64_t g_cap, uint32_t* scratch, CallInfo* info, const GcdPlan& plan, hipStream_t stream) {
+                      int64_t g_cap, uint32_t* scratch, CallInfo* info, const GcdPlan& plan, hipStream_t stream,
+                      const GcdCofactors* xg) {
     GcdArgs A{};
     A.a = a; A.b = b; A.na = na; A.nb = nb;
-    A.N = (int64_t)plan.groups * plan.slice;
+    A.N = gcd_positions(plan);
     A.buf = scratch;
     A.flags = scratch + 4 * A.N;
     A.g = g; A.g_cap = g_cap; A.F = F; A.info = info;
     A.groups = plan.groups; A.slice = plan.slice; A.s = plan.s;
+    if (xg) {
+        A.sbuf = scratch + (((4 * A.N + plan.groups + 64) + 63) & ~63LL);
+        A.sa0 = xg->sa0; A.nsa = xg->nsa;
+        A.sb0 = xg->sb0; A.nsb = xg->nsb;
+        A.s_deg_cap = xg->deg_cap;
+        A.s_res = xg->s_res;
+    }
     constexpr int E = 2;  // 128-entry heads (GcdPlan::head)
     size_t lds = (size_t)(2 * (plan.slice + GCD_MAXSHIFT + 1) + 256 + 64 * E) * sizeof(uint32_t) +
                  GCD_MAXSTEPS * sizeof(StepDesc);
     void* args[] = {&A};
-    TimingScope ts("gcd_multi_kernel", stream);
+    TimingScope ts(xg ? "gcd_multi_kernel_xg" : "gcd_multi_kernel", stream);
+    const void* fn = xg ? (const void*)gcd_multi_kernel<E, true> : (const void*)gcd_multi_kernel<E, false>;
     if (plan.groups == 1) {
-        hipLaunchKernelGGL((gcd_multi_kernel<E>), dim3(1), dim3(GCD_THREADS), lds, stream, A);
+        if (xg) hipLaunchKernelGGL((gcd_multi_kernel<E, true>), dim3(1), dim3(GCD_THREADS), lds, stream, A);
+        else hipLaunchKernelGGL((gcd_multi_kernel<E, false>), dim3(1), dim3(GCD_THREADS), lds, stream, A);
         return hipGetLastError();
     }
-    return hipLaunchCooperativeKernel((const void*)gcd_multi_kernel<E>, dim3(plan.groups), dim3(GCD_THREADS), args,
-                                      (unsigned)lds, stream);
+    return hipLaunchCooperativeKernel(fn, dim3(plan.groups), dim3(GCD_THREADS), args, (unsigned)lds, stream);
 }
 
 int64_t gcd_batch_cap(int kind) { return kind == 0 ? 256 * 16 : 1024 * 17; }

@@ -124,6 +124,12 @@ hipError_t divrem_head_launch(const uint32_t* a, int64_t na, const uint32_t* b, 
                               uint32_t* head, CallInfo* info, int s, int num_cus, hipStream_t stream);
 // info->n1 = 1 + (largest k < n with r[k] != 0), or 0.
 hipError_t trim_launch(const uint32_t* r, int64_t n, CallInfo* info, hipStream_t stream);
+// out[i] = -x[i] for i < n (out[0] = 0 when drop0)
+hipError_t negate_launch(const uint32_t* x, int64_t n, uint32_t* out, uint32_t p, bool drop0,
+                         hipStream_t stream);
+// out[i] = x[i] - y[i] for i < n (x read as zero past nx, y past ny)
+hipError_t sub_launch(const uint32_t* x, int64_t nx, const uint32_t* y, int64_t ny, int64_t n, uint32_t* out,
+                      uint32_t p, hipStream_t stream);
 // out[i] = r[i] + q[0] y[i] for i < n (r read as zero past nr)
 hipError_t fold_q0_launch(const uint32_t* r, int64_t nr, const uint32_t* q, const uint32_t* y, int64_t n,
                           uint32_t* out, const Field& F, hipStream_t stream);
@@ -197,9 +203,25 @@ hipError_t gcd_worker_launch(const GcdJob* jobs, const uint32_t* order, uint32_t
                              hipStream_t stream);
 constexpr int GCD_THREADS = 256;
 GcdPlan gcd_default_plan(int64_t n, int num_cus, int s);
-int64_t gcd_scratch_words(int64_t n, const GcdPlan& plan);
+// The extended gcd's cofactor tracking: the cofactor of the caller's a in
+// the kernel's two operands starts as sa0 / sb0 (device, nsa / nsb words)
+// and takes every chunk's M; s_res (gcd_positions(plan) words) receives
+// the cofactor of the last non-zero remainder, scaled as g is. deg_cap
+// (deg of the caller's b) bounds every cofactor's degree.
+struct GcdCofactors {
+    const uint32_t* sa0;
+    int64_t nsa;
+    const uint32_t* sb0;
+    int64_t nsb;
+    int64_t deg_cap;
+    uint32_t* s_res;
+};
+// coefficient positions of the plan's grid (>= n)
+int64_t gcd_positions(const GcdPlan& plan);
+int64_t gcd_scratch_words(int64_t n, const GcdPlan& plan, bool cofactors = false);
 hipError_t gcd_launch(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb,
                       const Field& F, uint32_t* g, int64_t g_cap, uint32_t* scratch,
-                      CallInfo* info, const GcdPlan& plan, hipStream_t stream);
+                      CallInfo* info, const GcdPlan& plan, hipStream_t stream,
+                      const GcdCofactors* xg = nullptr);
 
 }  // namespace pm

@@ -464,6 +464,69 @@ def test_gcd_leading_division(p):
         assert got["steps"] == stats.steps and got["updates"] == stats.updates, (p, tag, got, stats.steps)
 
 
+@pytest.mark.parametrize("p", [3, 5, gen.P_A])
+def test_xgcd_matches_oracle(p):
+    # (g, s, t) bit-exact against the oracle's extended Euclid: planted pairs
+    # in both orientations, leading degree gaps (both orientations, q_0 = 0),
+    # one block and the cooperative grid, and the degenerate inputs
+    st = gen.Stream(307 + p % 997)
+    cases = []
+    for da, db, dg in [(5, 3, 0), (3, 5, 0), (40, 40, 3), (200, 199, 50), (199, 200, 50), (1000, 999, 10),
+                       (1000, 300, 10), (300, 1000, 10), (3000, 40, 0), (6000, 5999, 100), (2000, 6000, 50)]:
+        pl = gen.planted_gcd(da, db, dg, p, st)
+        cases.append((oracle.mul(pl.g, pl.u, p), oracle.mul(pl.g, pl.v, p), (da, db, dg)))
+    a = st.uniform_poly(400, p)
+    b = oracle.mul(a, np.concatenate([np.zeros(1, np.uint32), st.uniform_poly(300, p)]), p)
+    r = st.uniform_poly(250, p)
+    b[:r.size] = (b[:r.size].astype(np.uint64) + r) % p
+    cases.append((a, b.astype(np.uint32), "q0 = 0"))
+    x = st.uniform_poly(60, p)
+    xy = oracle.mul(x, st.uniform_poly(20, p), p)
+    xbig = oracle.mul(x, st.uniform_poly(300, p), p)
+    c = np.array([2], dtype=np.uint32)
+    z = np.zeros(0, dtype=np.uint32)
+    pad = np.concatenate([x, np.zeros(7, dtype=np.uint32)])
+    cases += [(x, x, "a = b"), (x, xy, "a | b"), (xy, x, "b | a"), (xbig, x, "b | a, gap"), (x, xbig, "a | b, gap"),
+              (x, z, "b = 0"), (z, x, "a = 0"), (z, z, "both 0"), (c, x, "const a"), (x, c, "const b"),
+              (pad, xy, "padded")]
+    for u, v, tag in cases:
+        g, s_, t_ = (host(y) for y in pm.xgcd(dev(u), dev(v), p))
+        wg, ws, wt = oracle.xgcd(u, v, p)
+        assert same(g, wg) and same(s_, ws) and same(t_, wt), (p, tag)
+        if g.size:
+            want, degs, stats = oracle.gcd(u, v, p, with_info=True)
+            got = pm.last_gcd_stats()
+            assert got["steps"] == stats.steps and got["updates"] == stats.updates, (p, tag)
+
+
+def test_xgcd_workload_32768_certificate():
+    # the degree 32768 / 32767 pair with a planted degree-1000 gcd: g is the
+    # planted one and s a + t b = g, checked by the product path against the
+    # oracle's product at sampled coefficients and in full on the device
+    pl = gen.gcd_32768()
+    p = pl.p
+    gd = pm.to_device(pl.g)
+    a = pm.mul(gd, pm.to_device(pl.u), p)
+    b = pm.mul(gd, pm.to_device(pl.v), p)
+    g, s_, t_ = pm.xgcd(a, b, p)
+    assert same(host(g), pl.g)
+    assert s_.numel() - 1 < (b.numel() - 1) - (g.numel() - 1)
+    sa = pm.mul(s_, a, p)
+    tb = pm.mul(t_, b, p)
+    n = max(sa.numel(), tb.numel())
+    lhs = np.zeros(n, dtype=np.uint64)
+    lhs[:sa.numel()] += host(sa)
+    lhs[:tb.numel()] += host(tb)
+    lhs %= p
+    want = np.zeros(n, dtype=np.uint64)
+    want[:pl.g.size] = pl.g
+    assert np.array_equal(lhs, want)
+    hs, ha = host(s_), host(a)
+    rng = np.random.default_rng(5)
+    for k in rng.integers(0, sa.numel(), 8):
+        assert oracle.mul_coeff(hs, ha, p, int(k)) == int(host(sa)[k])
+
+
 def test_gcd_edge_cases():
     p = gen.P_A
     st = gen.Stream(303)

@@ -195,6 +195,72 @@ def test_divrem_gcd_workload_first_division(orc):
 
 
 # --------------------------------------------------------------------- gcd
+def _deg(x):
+    x = ck.trim(list(int(v) for v in x))
+    return len(x) - 1
+
+
+def _divides(d, x, p):
+    return ck.sympy_poly(x, p).rem(ck.sympy_poly(d, p)).is_zero
+
+
+@pytest.mark.parametrize("p", PRIMES + TINY)
+def test_xgcd_cofactors_are_the_minimal_pair(orc, p):
+    # s a + t b = g (independent multiply), g monic and dividing both, and
+    # deg s < deg b - deg g (s = 0 when deg g = deg b): the pair that these
+    # conditions make unique; b = 0 gives s = 1/lc(a), t = 0
+    st = gen.Stream(35 + p % 1000)
+    cases = []
+    for da, db, dg in [(5, 3, 0), (3, 5, 0), (40, 40, 3), (100, 60, 20), (60, 100, 59), (200, 199, 50), (30, 2, 1)]:
+        pl = gen.planted_gcd(da, db, dg, p, st)
+        cases.append((orc.mul(pl.g, pl.u, p), orc.mul(pl.g, pl.v, p)))
+    x = rnd(st, 9, p)
+    xy = orc.mul(x, rnd(st, 4, p), p)
+    c = np.array([3 % p or 1], dtype=np.uint32)
+    z = np.zeros(0, dtype=np.uint32)
+    cases += [(x, x), (x, xy), (xy, x), (x, z), (z, x), (c, x), (x, c)]
+    for a, b in cases:
+        g, s, t = orc.xgcd(a, b, p)
+        assert g.size and g[-1] == 1
+        sa, tb = ck.kronecker_mul(s, a, p), ck.kronecker_mul(t, b, p)
+        L = max(len(sa), len(tb))
+        comb = [((sa[i] if i < len(sa) else 0) + (tb[i] if i < len(tb) else 0)) % p for i in range(L)]
+        assert ck.trim(comb) == ck.trim(g)
+        assert _divides(g, a, p) and _divides(g, b, p)
+        da, db, dg = _deg(a), _deg(b), _deg(g)
+        if db < 0:
+            assert list(s) == [pow(int(a[da]), p - 2, p)] and t.size == 0
+        elif db == dg:
+            assert s.size == 0
+        else:
+            assert _deg(s) < db - dg
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_xgcd_brute_force_uniqueness(orc, p):
+    # over a tiny field, every s of degree < deg b - deg g is tried: exactly
+    # one makes g - s a a multiple of b, and it is the oracle's
+    st = gen.Stream(36 + p)
+    checked = 0
+    for _ in range(12):
+        a, b = rnd(st, 1 + st.uniform_int(1, 4), p), rnd(st, 1 + st.uniform_int(1, 4), p)
+        g, s, t = orc.xgcd(a, b, p)
+        k = _deg(b) - _deg(g)
+        if k <= 0:
+            continue
+        checked += 1
+        hits = []
+        for coeffs in itertools.product(range(p), repeat=k):
+            cand = ck.trim(list(coeffs))
+            prod = ck.kronecker_mul(np.array(cand, dtype=np.uint32), a, p) if cand else []
+            w = [((int(g[i]) if i < g.size else 0) - (prod[i] if i < len(prod) else 0)) % p
+                 for i in range(max(g.size, len(prod)))]
+            if not ck.trim(w) or _divides(b, np.array(ck.trim(w), dtype=np.uint32), p):
+                hits.append(cand)
+        assert hits == [ck.trim(list(int(v) for v in s))]
+    assert checked >= 6
+
+
 @pytest.mark.parametrize("p", PRIMES + TINY)
 def test_gcd_bezout_certificate(orc, p):
     st = gen.Stream(31 + p % 1000)
