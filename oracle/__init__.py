@@ -63,6 +63,8 @@ def lib():
         L.orc_gcd.argtypes = [_u32p, ctypes.c_int64, _u32p, ctypes.c_int64, ctypes.c_uint32,
                               _u32p, _i64p, ctypes.c_int64, _i64p, ctypes.POINTER(Stats)]
         L.orc_gcd.restype = ctypes.c_int64
+        L.orc_radix_sort.argtypes = [_u32p, _u32p, ctypes.c_int64, ctypes.c_int, ctypes.c_int, _u32p, _u32p]
+        L.orc_radix_sort.restype = ctypes.c_int
         L.orc_xgcd.argtypes = [_u32p, ctypes.c_int64, _u32p, ctypes.c_int64, ctypes.c_uint32,
                                _u32p, _i64p, _u32p, _i64p, _u32p, _i64p]
         L.orc_xgcd.restype = ctypes.c_int
@@ -139,6 +141,22 @@ def xgcd(a, b, p: int):
     lib().orc_xgcd(_ptr(a), a.size, _ptr(b), b.size, p, _ptr(g), ctypes.byref(ng),
                    _ptr(s), ctypes.byref(ns), _ptr(t), ctypes.byref(nt))
     return g[:ng.value].copy(), s[:ns.value].copy(), t[:nt.value].copy()
+
+
+def radix_sort(keys, vals=None, c: int = 32, s: int = 8):
+    """Stable LSD radix sort of uint32 keys on their low c bits with s-bit
+    digits (Sec. 4); returns (keys, vals) sorted (vals None when not given)."""
+    k = _arr(keys)
+    n = k.size
+    ko = np.zeros(max(n, 1), dtype=np.uint32)
+    v = _arr(vals) if vals is not None else None
+    vo = np.zeros(max(n, 1), dtype=np.uint32) if v is not None else None
+    null = ctypes.cast(None, _u32p)
+    rc = lib().orc_radix_sort(_ptr(k) if n else null, _ptr(v) if v is not None and n else null, n, c, s,
+                              _ptr(ko), _ptr(vo) if vo is not None else null)
+    if rc != 0:
+        raise ValueError("bad c or s")
+    return ko[:n].copy(), (vo[:n].copy() if vo is not None else None)
 
 
 def euclid_step(a: np.ndarray, da: int, b: np.ndarray, db: int, p: int):

@@ -16,6 +16,9 @@
  *
  * Arithmetic: every product is formed in 64 or 128 bits and reduced with the
  * C remainder operator, so there is no modular trick here to get wrong.
+ *
+ * The radix-sort case study (Sec. 4) has its plain stable LSD radix sort at
+ * the end of the file.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -325,4 +328,57 @@ int orc_euclid_step(uint32_t *a, int64_t *da, uint32_t *b, int64_t *db, uint32_t
     while (*dx >= 0 && x[*dx] == 0)
         (*dx)--;
     return 1;
+}
+
+/*
+ * Radix sort (Sec. 4): the stable least-significant-digit sort of n keys
+ * of c bits (1 <= c <= 32; only the low c bits of a key are its sort key)
+ * with digits of s bits (1 <= s <= 16), in ceil(c/s) passes from the low
+ * digit up. Each pass is one counting sort on its digit: the histogram of
+ * the digit values, its exclusive prefix sum (where each value's run
+ * starts), and a scatter in input order, which keeps equal digits in their
+ * previous order. vals (may be NULL, then vals_out is ignored) moves with
+ * its key. Returns 0, or -1 for bad c or s.
+ */
+int orc_radix_sort(const uint32_t *keys, const uint32_t *vals, int64_t n, int c, int s,
+                   uint32_t *keys_out, uint32_t *vals_out)
+{
+    if (c < 1 || c > 32 || s < 1 || s > 16)
+        return -1;
+    uint32_t *k0 = malloc((size_t)(n > 0 ? n : 1) * 4), *k1 = malloc((size_t)(n > 0 ? n : 1) * 4);
+    uint32_t *v0 = malloc((size_t)(n > 0 ? n : 1) * 4), *v1 = malloc((size_t)(n > 0 ? n : 1) * 4);
+    int64_t *count = malloc(((size_t)1 << s) * sizeof(int64_t));
+    for (int64_t i = 0; i < n; i++) {
+        k0[i] = keys[i];
+        v0[i] = vals ? vals[i] : 0;
+    }
+    for (int shift = 0; shift < c; shift += s) {
+        int bits = c - shift < s ? c - shift : s;
+        uint32_t mask = (uint32_t)((1ull << bits) - 1);
+        int64_t r = (int64_t)1 << bits;
+        for (int64_t d = 0; d < r; d++)
+            count[d] = 0;
+        for (int64_t i = 0; i < n; i++)
+            count[(k0[i] >> shift) & mask]++;
+        int64_t run = 0;  /* exclusive prefix sum: start of each digit's run */
+        for (int64_t d = 0; d < r; d++) {
+            int64_t c_d = count[d];
+            count[d] = run;
+            run += c_d;
+        }
+        for (int64_t i = 0; i < n; i++) {
+            int64_t at = count[(k0[i] >> shift) & mask]++;
+            k1[at] = k0[i];
+            v1[at] = v0[i];
+        }
+        uint32_t *t = k0; k0 = k1; k1 = t;
+        t = v0; v0 = v1; v1 = t;
+    }
+    for (int64_t i = 0; i < n; i++) {
+        keys_out[i] = k0[i];
+        if (vals && vals_out)
+            vals_out[i] = v0[i];
+    }
+    free(k0); free(k1); free(v0); free(v1); free(count);
+    return 0;
 }

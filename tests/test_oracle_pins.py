@@ -394,3 +394,38 @@ def test_inverse_and_primality(orc):
         assert orc.inv(0, p) == 0
     for n in [0, 1, 4, 469762051, 2**30 - 1]:
         assert not orc.is_prime(n)
+
+
+# -------------------------------------------------------------- radix sort
+def _stable_order(keys, c):
+    # the plain definition: indices ordered by (low c bits of the key, index),
+    # by Python's own sort (a merge sort, not a radix sort)
+    mask = (1 << c) - 1
+    return sorted(range(len(keys)), key=lambda i: (int(keys[i]) & mask, i))
+
+
+@pytest.mark.parametrize("c,s", [(32, 1), (32, 3), (32, 8), (32, 11), (32, 16), (20, 4), (7, 8), (1, 1)])
+def test_radix_sort_is_the_stable_order(orc, c, s):
+    st = gen.Stream(41 + 7 * c + s)
+    for n, spread in [(0, 1), (1, 1), (5, 3), (1000, 1 << 32), (4097, 16), (3000, 1 << 12)]:
+        keys = (st.raw(n) % np.uint64(spread)).astype(np.uint32) if n else np.zeros(0, np.uint32)
+        vals = np.arange(n, dtype=np.uint32)
+        ko, vo = orc.radix_sort(keys, vals, c, s)
+        order = _stable_order(keys, c)
+        assert list(vo) == order
+        assert np.array_equal(ko, keys[order] if n else keys)
+
+
+def test_radix_sort_brute_force_tiny(orc):
+    # every sequence of 4 keys from {0..3}: the output is sorted on the low
+    # c bits, a permutation of the input, and equal keys keep their order
+    for c, s in [(2, 1), (2, 2), (1, 1)]:
+        for keys in itertools.product(range(4), repeat=4):
+            k = np.array(keys, dtype=np.uint32)
+            ko, vo = orc.radix_sort(k, np.arange(4, dtype=np.uint32), c, s)
+            low = [int(x) & ((1 << c) - 1) for x in ko]
+            assert low == sorted(low)
+            assert sorted(vo.tolist()) == [0, 1, 2, 3] and np.array_equal(ko, k[vo])
+            for i in range(3):
+                if low[i] == low[i + 1]:
+                    assert vo[i] < vo[i + 1]
