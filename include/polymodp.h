@@ -317,6 +317,23 @@ void pm_release(void);
 /* Thread-local description of the last non-OK status. */
 const char *pm_last_error(void);
 
+/*
+ * Radix sort (Sec. 4, the paper's third case study): the stable sort of n
+ * uint32 keys on their low key_bits bits (1..32), least significant digit
+ * first with digits of s bits (1..8; 0 = 8), in ceil(key_bits/s) passes.
+ * Each pass is a digit histogram per tile of 4096 keys, an exclusive prefix
+ * sum over the histograms (digit-major), and a stable scatter through LDS.
+ *   keys, vals       : input (device), n words each; vals may be NULL
+ *   keys_out, vals_out : output (device), n words each; vals_out is needed
+ *                    when vals is given; no output may overlap an input or
+ *                    the other output
+ * n <= 2^32 - 1. Asynchronous on the stream: no host read; the library's
+ * scratch holds (1 or 2) n + 2^s n / 4096 words. Returns PM_EINVAL for bad
+ * arguments.
+ */
+pm_status pm_radix_sort_u32(const uint32_t *keys, const uint32_t *vals, int64_t n, int32_t key_bits, int32_t s,
+                            uint32_t *keys_out, uint32_t *vals_out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -119,6 +119,8 @@ def lib() -> ctypes.CDLL:
                                  _vp, ctypes.c_int64, _i64p, _vp, ctypes.c_int64, _i64p,
                                  _vp, ctypes.c_int64, _i64p, _vp]
     L.poly_xgcd_modp.restype = ctypes.c_int32
+    L.pm_radix_sort_u32.argtypes = [_vp, _vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp]
+    L.pm_radix_sort_u32.restype = ctypes.c_int32
     L.poly_gcd_modp_batch.argtypes = [ctypes.POINTER(GcdItem), ctypes.c_int32, ctypes.POINTER(GcdResult), _vp]
     L.poly_gcd_modp_batch.restype = ctypes.c_int32
     L.pm_mul_batch_create.argtypes = [ctypes.POINTER(MulItem), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -293,6 +295,25 @@ def xgcd(a, b, p: int, stream=None):
                                 s.data_ptr(), cap, ctypes.byref(ns), t.data_ptr(), cap, ctypes.byref(nt),
                                 _stream_handle(stream)))
     return g[:ng.value], s[:ns.value], t[:nt.value]
+
+
+def radix_sort(keys, values=None, s: int = 0, key_bits: int = 32, stream=None, out=None):
+    """Stable LSD radix sort of uint32 keys (int32 tensors holding the bit
+    patterns) on their low key_bits bits with s-bit digits (pm_radix_sort_u32);
+    returns (keys, values) sorted, values None when not given. ``out``:
+    optional (keys_out, values_out) tensors to write into."""
+    torch = _torch()
+    k = _as_u32_tensor(keys)
+    n = k.numel()
+    v = _as_u32_tensor(values) if values is not None else None
+    if out is not None:
+        ko, vo = out
+    else:
+        ko = torch.empty(n, dtype=torch.int32, device=k.device)
+        vo = torch.empty(n, dtype=torch.int32, device=k.device) if v is not None else None
+    _check(lib().pm_radix_sort_u32(_dev_ptr(k), _dev_ptr(v) if v is not None else None, n, key_bits, s,
+                                   _dev_ptr(ko), _dev_ptr(vo) if vo is not None else None, _stream_handle(stream)))
+    return ko, vo
 
 
 class MulBatch:

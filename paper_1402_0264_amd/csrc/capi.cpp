@@ -1033,4 +1033,26 @@ pm_status poly_xgcd_modp(const uint32_t* a, int64_t na, const uint32_t* b, int64
     return PM_OK;
 }
 
+pm_status pm_radix_sort_u32(const uint32_t* keys, const uint32_t* vals, int64_t n, int32_t key_bits, int32_t s,
+                            uint32_t* keys_out, uint32_t* vals_out, void* stream) {
+    if (n < 0 || n > (int64_t)0xFFFFFFFFLL) return fail(PM_EINVAL, "n must be in [0, 2^32 - 1]");
+    if (key_bits < 1 || key_bits > 32) return fail(PM_EINVAL, "key_bits must be in [1, 32]");
+    if (s < 0 || s > 8) return fail(PM_EINVAL, "s must be in [0, 8]");
+    if (n == 0) return PM_OK;
+    if (!keys || !keys_out) return fail(PM_EINVAL, "null keys");
+    if (vals && !vals_out) return fail(PM_EINVAL, "vals given without vals_out");
+    auto overlap = [n](const uint32_t* x, const uint32_t* y) { return x && y && x < y + n && y < x + n; };
+    if (overlap(keys, keys_out) || overlap(vals, vals_out) || overlap(keys, vals_out) || overlap(vals, keys_out) ||
+        overlap(keys_out, vals_out))
+        return fail(PM_EINVAL, "outputs overlap the inputs or each other");
+    const int sd = s > 0 ? s : 8;
+    hipStream_t hs = (hipStream_t)stream;
+    Pool* P = nullptr;
+    pm_status st = pool_get(hs, pm::radix_scratch_words(n, sd, vals != nullptr), &P);
+    if (st) return st;
+    HIP_TRY(pm::radix_sort_launch(keys, vals, n, key_bits, sd, keys_out, vals ? vals_out : nullptr, P->words, hs),
+            "radix sort launch");
+    return PM_OK;
+}
+
 }  // extern "C"

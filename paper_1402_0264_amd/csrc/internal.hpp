@@ -216,6 +216,13 @@ struct GcdCofactors {
     int64_t deg_cap;
     uint32_t* s_res;
 };
+// ---- radix sort (radix.hip): stable LSD sort of uint32 keys on their low
+// key_bits bits, s-bit digits (1..8), vals (may be null) moving along;
+// scratch: radix_scratch_words(n, s, vals != null) words
+int64_t radix_scratch_words(int64_t n, int s, bool with_vals);
+hipError_t radix_sort_launch(const uint32_t* keys, const uint32_t* vals, int64_t n, int key_bits, int s,
+                             uint32_t* keys_out, uint32_t* vals_out, uint32_t* scratch, hipStream_t stream);
+
 // coefficient positions of the plan's grid (>= n)
 int64_t gcd_positions(const GcdPlan& plan);
 int64_t gcd_scratch_words(int64_t n, const GcdPlan& plan, bool cofactors = false);

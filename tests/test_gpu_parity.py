@@ -767,3 +767,67 @@ def test_server_admission_waits_for_memory_and_slots():
         srv.submit(big[:5], big[:3], 91)
     assert e.value.status == pm.PM_EMODULUS
     srv.close()
+
+
+# ------------------------------------------------------------- radix sort
+def _sort_inputs(st, n, kind):
+    if kind == "uniform":
+        return st.raw(n).astype(np.uint32) if n else np.zeros(0, np.uint32)
+    if kind == "few":
+        return (st.raw(n) % np.uint64(4)).astype(np.uint32)
+    if kind == "sorted":
+        return np.sort(st.raw(n).astype(np.uint32))
+    if kind == "reversed":
+        return np.sort(st.raw(n).astype(np.uint32))[::-1].copy()
+    return np.full(n, 0xDEADBEEF, dtype=np.uint32)
+
+
+@pytest.mark.parametrize("s", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_radix_sort_matches_oracle(s):
+    # keys and values bit-exact against the oracle's stable LSD sort: empty,
+    # one key, ragged tails around the 4096-key tile, several tiles, every
+    # digit width, key_bits below 32 (only the low bits order the keys)
+    st = gen.Stream(400 + s)
+    for n, kind, bits in [(0, "uniform", 32), (1, "uniform", 32), (100, "few", 32), (4095, "uniform", 32),
+                          (4096, "sorted", 32), (4097, "reversed", 32), (50000, "uniform", 20),
+                          (70001, "few", 7), (12288, "equal", 32), (200003, "uniform", 32)]:
+        keys = _sort_inputs(st, n, kind)
+        vals = st.raw(n).astype(np.uint32) if n else np.zeros(0, np.uint32)
+        ko, vo = pm.radix_sort(dev(keys), dev(vals), s=s, key_bits=bits)
+        wk, wv = oracle.radix_sort(keys, vals, bits, s)
+        assert same(host(ko), wk) and same(host(vo), wv), (s, n, kind, bits)
+        ko2, vo2 = pm.radix_sort(dev(keys), None, s=s, key_bits=bits)
+        assert vo2 is None and same(host(ko2), wk), (s, n, kind, "keys only")
+
+
+def test_radix_sort_workload_64m_properties():
+    # the 2^26-key workload of the sweep, at the default s: sorted, a
+    # permutation (values = input positions), stable (equal keys keep order)
+    import torch
+    n = 1 << 26
+    st = gen.Stream(gen.SEED_BASE + 9)
+    keys = st.raw(n).astype(np.uint32)
+    k = dev(keys)
+    idx = torch.arange(n, dtype=torch.int32, device="cuda")
+    ko, vo = pm.radix_sort(k, idx)
+    hk, hv = host(ko), host(vo)
+    assert np.all(hk[1:] >= hk[:-1])
+    assert np.array_equal(np.sort(hv), np.arange(n, dtype=np.uint32))
+    assert np.array_equal(keys[hv], hk)
+    eq = hk[1:] == hk[:-1]
+    assert np.all(hv[1:][eq] > hv[:-1][eq])
+
+
+def test_radix_sort_rejects_bad_arguments():
+    import torch
+    k = dev(np.arange(10, dtype=np.uint32))
+    out = torch.empty(10, dtype=torch.int32, device="cuda")
+    for kw in [dict(s=9), dict(key_bits=0), dict(key_bits=33)]:
+        with pytest.raises(pm.PolyModPError) as e:
+            pm.radix_sort(k, **kw)
+        assert e.value.status == pm.PM_EINVAL
+    with pytest.raises(pm.PolyModPError) as e:
+        pm.radix_sort(k, out=(k, None))
+    assert e.value.status == pm.PM_EINVAL
+    ko, _ = pm.radix_sort(k, out=(out, None))
+    assert same(host(ko), np.arange(10, dtype=np.uint32))
