@@ -320,7 +320,7 @@ const char *pm_last_error(void);
 /*
  * Radix sort (Sec. 4, the paper's third case study): the stable sort of n
  * uint32 keys on their low key_bits bits (1..32), least significant digit
- * first with digits of s bits (1..8; 0 = 8), in ceil(key_bits/s) passes.
+ * first with digits of s bits (1..10; 0 = 8), in ceil(key_bits/s) passes.
  * Each pass is a digit histogram per tile of 4096 keys, an exclusive prefix
  * sum over the histograms (digit-major), and a stable scatter through LDS.
  *   keys, vals       : input (device), n words each; vals may be NULL

@@ -1037,7 +1037,7 @@ pm_status pm_radix_sort_u32(const uint32_t* keys, const uint32_t* vals, int64_t 
                             uint32_t* keys_out, uint32_t* vals_out, void* stream) {
     if (n < 0 || n > (int64_t)0xFFFFFFFFLL) return fail(PM_EINVAL, "n must be in [0, 2^32 - 1]");
     if (key_bits < 1 || key_bits > 32) return fail(PM_EINVAL, "key_bits must be in [1, 32]");
-    if (s < 0 || s > 8) return fail(PM_EINVAL, "s must be in [0, 8]");
+    if (s < 0 || s > 10) return fail(PM_EINVAL, "s must be in [0, 10]");
     if (n == 0) return PM_OK;
     if (!keys || !keys_out) return fail(PM_EINVAL, "null keys");
     if (vals && !vals_out) return fail(PM_EINVAL, "vals given without vals_out");

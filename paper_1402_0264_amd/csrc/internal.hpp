@@ -217,7 +217,7 @@ struct GcdCofactors {
     uint32_t* s_res;
 };
 // ---- radix sort (radix.hip): stable LSD sort of uint32 keys on their low
-// key_bits bits, s-bit digits (1..8), vals (may be null) moving along;
+// key_bits bits, s-bit digits (1..10), vals (may be null) moving along;
 // scratch: radix_scratch_words(n, s, vals != null) words
 int64_t radix_scratch_words(int64_t n, int s, bool with_vals);
 hipError_t radix_sort_launch(const uint32_t* keys, const uint32_t* vals, int64_t n, int key_bits, int s,

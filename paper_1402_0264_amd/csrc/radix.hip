@@ -67,26 +67,59 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s
     return before + x - v;
 }
 
+// The histogram needs no order: with few digit values each wave counts
+// them with one ballot per value; with many, each lane adds to its wave's
+// own copy of the bins in LDS, reading four keys per 16-byte load.
 template <int S>
 __global__ __launch_bounds__(RS_NT) void radix_hist_kernel(const uint32_t* keys, int64_t n, int shift, uint32_t mask,
                                                            uint32_t* hist, int64_t tiles) {
     constexpr int R = 1 << S;
-    __shared__ uint32_t cnt[R];
+    __shared__ uint32_t cnt[RS_WAVES][R];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int d = tid; d < R; d += RS_NT) cnt[d] = 0;
+    for (int i = tid; i < RS_WAVES * R; i += RS_NT) (&cnt[0][0])[i] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * RS_TILE;
-    const unsigned long long lt = (1ull << lane) - 1ull;
+    if constexpr (S <= 3) {
+        uint32_t mine[R];
+#pragma unroll
+        for (int v = 0; v < R; v++) mine[v] = 0;
 #pragma unroll 4
-    for (int j = 0; j < RS_IPT; j++) {
-        const int64_t pos = base + tile_pos(wave, j, lane);
-        const bool valid = pos < n;
-        const uint32_t d = valid ? (keys[pos] >> shift) & mask : 0u;
-        const unsigned long long m = match_digit<S>(d, valid);
-        if (valid && (m & lt) == 0) atomicAdd(&cnt[d], (uint32_t)__popcll(m));
+        for (int j = 0; j < RS_IPT; j++) {
+            const int64_t pos = base + tile_pos(wave, j, lane);
+            const bool valid = pos < n;
+            const uint32_t d = valid ? (keys[pos] >> shift) & mask : 0u;
+#pragma unroll
+            for (int v = 0; v < R; v++) mine[v] += (uint32_t)__popcll(__ballot(valid && d == (uint32_t)v));
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int v = 0; v < R; v++) cnt[wave][v] = mine[v];
+        }
+    } else {
+        const bool vec = (((uintptr_t)keys) & 15u) == 0;
+#pragma unroll 2
+        for (int j = 0; j < RS_IPT / 4; j++) {
+            const int64_t pos = base + 4 * ((int64_t)j * RS_NT + tid);
+            uint32_t x[4];
+            if (vec && pos + 3 < n) {
+                const uint4 q = *(const uint4*)(keys + pos);
+                x[0] = q.x; x[1] = q.y; x[2] = q.z; x[3] = q.w;
+#pragma unroll
+                for (int e = 0; e < 4; e++) atomicAdd(&cnt[wave][(x[e] >> shift) & mask], 1u);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; e++)
+                    if (pos + e < n) atomicAdd(&cnt[wave][(keys[pos + e] >> shift) & mask], 1u);
+            }
+        }
     }
     __syncthreads();
-    for (int d = tid; d < R; d += RS_NT) hist[(int64_t)d * tiles + blockIdx.x] = cnt[d];
+    for (int d = tid; d < R; d += RS_NT) {
+        uint32_t c = 0;
+#pragma unroll
+        for (int w = 0; w < RS_WAVES; w++) c += cnt[w][d];
+        hist[(int64_t)d * tiles + blockIdx.x] = c;
+    }
 }
 
 template <int S>
@@ -130,21 +163,36 @@ __global__ __launch_bounds__(RS_NT) void radix_scatter_kernel(const uint32_t* ki
         rank[j] = r;
     }
     __syncthreads();
-    // waves before this one, and digits before this one, in the tile
-    uint32_t tot = 0;
-    if (tid < R) {
+    // waves before this one, and digits before this one, in the tile (each
+    // thread takes DPT consecutive digit values)
+    constexpr int DPT = R > RS_NT ? R / RS_NT : 1;
+    uint32_t tots[DPT];
+    uint32_t mine = 0;
 #pragma unroll
-        for (int w = 0; w < RS_WAVES; w++) {
-            const uint32_t c = s_wcnt[w][tid];
-            s_wcnt[w][tid] = tot;
-            tot += c;
+    for (int e = 0; e < DPT; e++) {
+        const int d = tid * DPT + e;
+        uint32_t tot = 0;
+        if (d < R) {
+#pragma unroll
+            for (int w = 0; w < RS_WAVES; w++) {
+                const uint32_t c = s_wcnt[w][d];
+                s_wcnt[w][d] = tot;
+                tot += c;
+            }
         }
+        tots[e] = tot;
+        mine += tot;
     }
     uint32_t all;
-    const uint32_t db = block_exclusive_scan(tid < R ? tot : 0u, s_tmp, &all);
-    if (tid < R) {
-        s_dbase[tid] = db;
-        s_gofs[tid] = offs[(int64_t)tid * tiles + blockIdx.x];
+    uint32_t run = block_exclusive_scan(mine, s_tmp, &all);
+#pragma unroll
+    for (int e = 0; e < DPT; e++) {
+        const int d = tid * DPT + e;
+        if (d < R) {
+            s_dbase[d] = run;
+            s_gofs[d] = offs[(int64_t)d * tiles + blockIdx.x];
+        }
+        run += tots[e];
     }
     __syncthreads();
     // the tile sorted by digit in LDS
@@ -290,6 +338,8 @@ hipError_t radix_sort_launch(const uint32_t* keys, const uint32_t* vals, int64_t
             case 6: e = radix_pass<6>(kin, vin, ko, vo, n, shift, bits, hist, sums, stream); break;
             case 7: e = radix_pass<7>(kin, vin, ko, vo, n, shift, bits, hist, sums, stream); break;
             case 8: e = radix_pass<8>(kin, vin, ko, vo, n, shift, bits, hist, sums, stream); break;
+            case 9: e = radix_pass<9>(kin, vin, ko, vo, n, shift, bits, hist, sums, stream); break;
+            case 10: e = radix_pass<10>(kin, vin, ko, vo, n, shift, bits, hist, sums, stream); break;
             default: return hipErrorInvalidValue;
         }
         if (e != hipSuccess) return e;

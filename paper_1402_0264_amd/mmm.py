@@ -97,6 +97,30 @@ def gcd_s_star(n: float, m: float, U: float) -> float:
     return math.sqrt(8 * U * (2 * n + m) / 3)
 
 
+# ----------------------------------------------------------- radix sort
+def sort_terms(n: float, c: float, s: float, U: float, ell: float = 256):
+    """(N_s, L_s, C_s, K_s) of the radix sort (Sec. 4): N_s = (c/s)(1/(2l) +
+    2^s/(8 l^2)) n, L_s = 5c/s, C_s = s(41 + 8 log2 l) + 12 + 9U; K_s = the
+    blocks of one pass's widest kernel, one per tile of 4l keys."""
+    N = (c / s) * (1 / (2 * ell) + 2 ** s / (8 * ell * ell)) * n
+    L = 5 * c / s
+    C = s * (41 + 8 * math.log2(ell)) + 12 + 9 * U
+    K = n / (4 * ell)
+    return N, L, C, K
+
+
+def sort_time(n: float, c: float, s: float, U: float, ell: float = 256) -> float:
+    """Corollary 1 estimate (N_s/K_s + L_s) C_s; s = 1 is the naive sort."""
+    N, L, C, K = sort_terms(n, c, s, U, ell)
+    return (N / K + L) * C
+
+
+def sort_ratio_printed(s: float, U: float, ell: float = 256) -> float:
+    """The paper's printed R = T_1/T_s of the radix sort (Sec. 4)."""
+    lg = math.log2(ell)
+    return (14 * ell + 2) * (53 + 8 * lg + 9 * U) * s / ((14 * ell + 2 ** s) * (41 * s + 8 * s * lg + 12 + 9 * U))
+
+
 def argmin(fn, candidates):
     best = min(candidates, key=fn)
     return best, fn(best)

@@ -5,6 +5,8 @@ Euclidean gcd (Sec. 6), where s = 1 is the paper's naive kernel.
     python -m paper_1402_0264_amd.sweep [--op mul] [--n 65536] [--s 1,2,4,...,512] [--reps 5]
     python -m paper_1402_0264_amd.sweep --op div [--n 65536] [--s 1,2,...,64]
     python -m paper_1402_0264_amd.sweep --op gcd [--s 1,2,...,256]
+    python -m paper_1402_0264_amd.sweep --op table2
+    python -m paper_1402_0264_amd.sweep --op sort [--s 1,2,...,10]
 
 Division: a of n terms and b of n/2 terms (quotient of n/2 + 1 terms, the
 paper's n = 2m case); s is the number of division steps fused per pass over
@@ -217,9 +219,62 @@ def table2(args) -> int:
     return 0
 
 
+def sweep_sort(args) -> int:
+    """The radix sort of Sec. 4 over its digit width s: 2^26 uniform 32-bit
+    keys (keys only), s = 1..10, beside the model's T_s/T_1 and the printed
+    R = T_1/T_s at l = 256 threads per block."""
+    import torch
+    import paper_1402_0264_amd as pm
+    from paper_1402_0264_amd import gen, mmm
+    torch.cuda.set_device(0)
+    n = args.n if args.n != 65536 else 1 << 26
+    st = gen.Stream(gen.SEED_BASE + 9)
+    keys = pm.to_device(st.raw(n).astype("uint32"))
+    ko = torch.empty(n, dtype=torch.int32, device="cuda")
+    svals = [int(x) for x in (args.s or "1,2,3,4,5,6,7,8,9,10").split(",")]
+    ref = None
+    rows = []
+    t1 = mmm.sort_time(n, 32, 1, mmm.U_THROUGHPUT)
+    for sv in svals:
+        pm.radix_sort(keys, s=sv, out=(ko, None))
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = ko.clone()
+        same = bool(torch.equal(ko, ref))
+        times = []
+        for _ in range(args.reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            pm.radix_sort(keys, s=sv, out=(ko, None))
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        times.sort()
+        ms = times[len(times) // 2]
+        passes = (32 + sv - 1) // sv
+        moved = passes * 12.0 * n   # per pass: keys read twice (histogram, scatter), written once
+        rec = {"op": "sort", "s": sv, "passes": passes, "ms": round(ms, 4), "keys_per_s": round(n / (ms * 1e-3), 1),
+               "GB_per_s_at_12B_per_key_per_pass": round(moved / (ms * 1e-3) / 1e9, 1),
+               "model_T_over_T1": round(mmm.sort_time(n, 32, sv, mmm.U_THROUGHPUT) / t1, 4),
+               "paper_R_printed": round(mmm.sort_ratio_printed(sv, mmm.U_THROUGHPUT), 3),
+               "identical_to_first": same}
+        rows.append(rec)
+        print(json.dumps(rec), flush=True)
+    best = min(rows, key=lambda x: x["ms"])
+    model_best = max(range(1, 17), key=lambda sv: mmm.sort_ratio_printed(sv, mmm.U_THROUGHPUT))
+    print(json.dumps({"summary": True, "op": "sort", "n": n, "key_bits": 32, "measured_best_s": best["s"],
+                      "measured_T1_over_Tbest": round(rows[0]["ms"] / best["ms"], 3) if rows[0]["s"] == 1 else None,
+                      "model_best_s_1_to_16": model_best,
+                      "model_R_at_measured_best": round(mmm.sort_ratio_printed(best["s"], mmm.U_THROUGHPUT), 3),
+                      "threads_per_block": 256, "log2_l": 8,
+                      "all_identical": all(x["identical_to_first"] for x in rows)}), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
-    ap.add_argument("--op", choices=("mul", "div", "gcd", "table2"), default="mul")
+    ap.add_argument("--op", choices=("mul", "div", "gcd", "table2", "sort"), default="mul")
     ap.add_argument("--n", type=int, default=65536)
     ap.add_argument("--s", default=None)
     ap.add_argument("--reps", type=int, default=5)
@@ -230,6 +285,8 @@ def main() -> int:
         return sweep_gcd(args)
     if args.op == "table2":
         return table2(args)
+    if args.op == "sort":
+        return sweep_sort(args)
     if args.s is None:
         args.s = "1,2,4,8,16,32,64,128,256,512,1024,2048,4096"
     import torch

@@ -782,7 +782,7 @@ def _sort_inputs(st, n, kind):
     return np.full(n, 0xDEADBEEF, dtype=np.uint32)
 
 
-@pytest.mark.parametrize("s", [1, 2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("s", [1, 2, 3, 4, 5, 6, 7, 8, 9, 10])
 def test_radix_sort_matches_oracle(s):
     # keys and values bit-exact against the oracle's stable LSD sort: empty,
     # one key, ragged tails around the 4096-key tile, several tiles, every
@@ -822,7 +822,7 @@ def test_radix_sort_rejects_bad_arguments():
     import torch
     k = dev(np.arange(10, dtype=np.uint32))
     out = torch.empty(10, dtype=torch.int32, device="cuda")
-    for kw in [dict(s=9), dict(key_bits=0), dict(key_bits=33)]:
+    for kw in [dict(s=11), dict(key_bits=0), dict(key_bits=33)]:
         with pytest.raises(pm.PolyModPError) as e:
             pm.radix_sort(k, **kw)
         assert e.value.status == pm.PM_EINVAL

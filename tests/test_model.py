@@ -11,10 +11,11 @@ from paper_1402_0264_amd import mmm
 
 GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_model.json")))
 n, m, U, Z, s, ell = sp.symbols("n m U Z s l", positive=True)
+c_ = sp.symbols("c", positive=True)
 
 
 def _expr(key):
-    return sp.sympify(GOLD[key]["expr"], locals={"n": n, "U": U, "Z": Z, "s": s, "log": sp.log})
+    return sp.sympify(GOLD[key]["expr"], locals={"n": n, "U": U, "Z": Z, "s": s, "l": ell, "log": sp.log})
 
 
 def test_division_ratio_matches_printed():
@@ -69,3 +70,36 @@ def test_model_directions_on_mi355x_constants():
     for s_ in [1, 2, 8, 64]:
         assert mmm.mul_time(65536, 65536, s_, 20) < mmm.mul_time(65536, 65536, 2 * s_, 20)
     assert math.isclose(mmm.U_THROUGHPUT, 64 / (8e12 / 4 / 256 / 2.4e9))
+
+
+def test_sort_ratio_matches_printed():
+    # T_1/T_s from the printed N_s, L_s, C_s (Corollary 1, one block per tile
+    # of 4l keys) is the printed R, for every n, c, l, U and s
+    lg = sp.log(ell, 2)
+
+    def T(sv):
+        N = (c_ / sv) * (1 / (2 * ell) + 2 ** sv / (8 * ell ** 2)) * n
+        L = 5 * c_ / sv
+        C = sv * (41 + 8 * lg) + 12 + 9 * U
+        return (N / (n / (4 * ell)) + L) * C
+    assert sp.simplify(T(1) / T(s) - _expr("sort_R")) == 0
+    for nv, cv, sv, lv, uv in [(1 << 26, 32, 8, 256, 19.7), (1000, 20, 3, 64, 2.0)]:
+        got = mmm.sort_time(nv, cv, 1, uv, lv) / mmm.sort_time(nv, cv, sv, uv, lv)
+        assert abs(got - mmm.sort_ratio_printed(sv, uv, lv)) < 1e-9 * got
+        want = float(_expr("sort_R").subs({ell: lv, s: sv, U: uv}))
+        assert abs(got - want) < 1e-9 * got
+
+
+def test_sort_overhead_ratio_and_threshold():
+    # O_s as printed; O_1/O_s tends to the printed ratio as n grows, and the
+    # leading-term quotient at s = log2 l exceeds 1 exactly below the
+    # printed threshold l < 2^(15.75 U)
+    def O(sv):
+        return c_ * U * (sp.Rational(9, 2) / (sv * ell) * n + 17 * 2 ** sv / (16 * sv * ell ** 2) * n - 1 / sv)
+    lim = sp.limit(O(1) / O(s), n, sp.oo)
+    assert sp.simplify(lim - _expr("sort_overhead_ratio")) == 0
+    q = sp.lambdify((ell, U), _expr("sort_leading_quotient"))
+    t = GOLD["sort_threshold_log2_l_over_U"]["value"]
+    for uv in [0.5, 1, 4]:
+        edge = 2 ** (t * uv)
+        assert q(edge * 0.9, uv) > 1 > q(edge * 1.1, uv)
