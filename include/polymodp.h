@@ -260,7 +260,9 @@ typedef struct {
 pm_status pm_server_create(const pm_server_opts *opts, pm_server **out);
 pm_status pm_server_submit(pm_server *srv, const pm_gcd_request *req, uint64_t *ticket);
 /* count requests in one call (tickets: count entries, or NULL); all are
- * checked first, so an error queues none of them. */
+ * checked first, so an error queues none of them. The requests of one call
+ * are queued longest first (by na * nb; equal ones in the given order), so
+ * their tickets need not increase in the given order. */
 pm_status pm_server_submit_batch(pm_server *srv, const pm_gcd_request *reqs, int32_t count, uint64_t *tickets);
 pm_status pm_server_poll(pm_server *srv, pm_completion *out, int32_t max, int32_t *n);
 int64_t pm_server_pending(pm_server *srv);   /* queued + on the device */

@@ -11,8 +11,9 @@
 //
 // The host side (pm_server_submit and pm_server_poll, called by one thread):
 //  1. poll harvests finished slots (done flag, acquire) and frees them;
-//  2. submit and poll admit queued requests in FIFO order while a slot and
-//     room in the resident-input budget are free: the inputs go into the slot's pinned
+//  2. submit and poll admit queued requests in FIFO order (the requests of
+//     one batch call longest first) while a slot and room in the
+//     resident-input budget are free: the inputs go into the slot's pinned
 //     staging buffer (mapped into the device's address space), and the
 //     request is published at once by raising the shared tail (release);
 //     the claiming block reads the inputs once, past the caches, straight
@@ -22,6 +23,7 @@
 // All device and pinned memory is allocated by pm_server_create.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cstring>
 #include <deque>
@@ -334,10 +336,20 @@ pm_status pm_server_submit_batch(pm_server* S, const pm_gcd_request* reqs, int32
         if (st) return st;
         if ((r->p & 1u) == 0) return pm::server_fail(PM_EMODULUS, "p = 2 is not supported by the gcd");
     }
-    for (int32_t i = 0; i < count; i++) {
+    // The requests of one call arrive together, so they may start in any
+    // order: longest first (work ~ na * nb), which keeps the largest
+    // remainder sequences, each bound by its own step chain on one CU, from
+    // starting last and setting the span.
+    std::vector<int32_t> order((size_t)count);
+    for (int32_t i = 0; i < count; i++) order[(size_t)i] = i;
+    std::stable_sort(order.begin(), order.end(), [reqs](int32_t x, int32_t y) {
+        return (double)reqs[x].na * (double)reqs[x].nb > (double)reqs[y].na * (double)reqs[y].nb;
+    });
+    for (int32_t k = 0; k < count; k++) {
+        const int32_t i = order[(size_t)k];
         pm_status st = enqueue(S, &reqs[i], tickets ? &tickets[i] : nullptr);
         if (st) return st;
-        if ((i & 15) == 15) {  // the first requests start while the rest are copied
+        if ((k & 15) == 15) {  // the first requests start while the rest are copied
             st = admit(S, false);
             if (st) return st;
         }
