@@ -93,6 +93,8 @@ def sweep_div(args) -> int:
         rows.append(rec)
         print(json.dumps(rec), flush=True)
     pm.set_params()
+    if args.no_naive:
+        return 0
     # the naive algorithm (one division step per launch), the s0 end
     q, r = pm.divrem(a, b, gen.P_A, naive=True)
     torch.cuda.synchronize()
@@ -143,6 +145,8 @@ def sweep_gcd(args) -> int:
         rows.append(rec)
         print(json.dumps(rec), flush=True)
     pm.set_params()
+    if args.no_naive:
+        return 0
     # the naive algorithm (one division step per launch), the s0 end
     out = pm.gcd(a, b, p, naive=True)
     torch.cuda.synchronize()
@@ -278,6 +282,7 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=65536)
     ap.add_argument("--s", default=None)
     ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--no-naive", action="store_true", help="division and gcd: skip the naive kernels")
     args = ap.parse_args()
     if args.op == "div":
         return sweep_div(args)
