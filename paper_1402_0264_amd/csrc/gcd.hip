@@ -290,6 +290,303 @@ __global__ __launch_bounds__(GCD_THREADS) void gcd_multi_kernel(GcdArgs G) {
     }
 }
 
+// ------------------------------------------------------- pipelined grid
+// The arrive half of a grid barrier, called by each of the block's nwaves
+// arriving waves once they are done with the chunk-start operands (and
+// their writes of the new ones are issued): the last of them to arrive (an
+// LDS counter) arrives for the block.
+__device__ __forceinline__ void arrive_by_waves(CallInfo* info, unsigned nblocks, uint32_t* s_arrive, int nwaves) {
+    __threadfence();  // this wave's writes, at agent scope
+    if ((threadIdx.x & 63) == 0) {
+        const uint32_t before = atomicAdd(s_arrive, 1u);
+        if (before == (uint32_t)nwaves - 1) {
+            *s_arrive = 0u;  // every apply wave has counted; reused after the block barrier
+            if (nblocks > 1) {
+                __threadfence();
+                const unsigned arrived = atomicAdd(&info->bar_count, 1u);
+                if (arrived == nblocks - 1) {
+                    atomicExch(&info->bar_count, 0u);
+                    __threadfence();
+                    atomicAdd(&info->bar_gen, 1u);
+                }
+            }
+        }
+    }
+}
+
+// The wait half: thread 0 waits until every block has arrived for
+// generation gen. Called by all threads of the block.
+__device__ __forceinline__ void wait_grid(CallInfo* info, unsigned nblocks, unsigned& gen) {
+    if (nblocks > 1) {
+        if (threadIdx.x == 0)
+            while (__hip_atomic_load(&info->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen)
+                __builtin_amdgcn_s_sleep(1);
+        gen++;
+    }
+    __syncthreads();
+    __threadfence();
+}
+
+// The top 64 E entries of both operands after a chunk, from the chunk-start
+// operands A, B (device memory) and the chunk's M: the next chunk's heads.
+// The whole block: it stages four windows of 64 E + 64 words (A and B
+// below each new degree), then wave w computes head vector w (A's entries
+// 0-63 and 64-127, then B's) into hbuf. Ends with the block's barrier.
+template <int E>
+__device__ void heads_after_chunk(const uint32_t* A, const uint32_t* B, int64_t ndA, int64_t ndB, int S,
+                                  const uint32_t* Mc, const Field& F, uint32_t* hw, uint32_t* hbuf) {
+    static_assert(2 * E == GCD_THREADS / 64, "one head vector per wave");
+    constexpr int WH = 64 * E + 64;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t baseA = ndA - WH + 1, baseB = ndB - WH + 1;
+    for (int x = tid; x < 4 * WH; x += GCD_THREADS) {
+        const int win = x / WH, off = x - win * WH;
+        const int64_t P = (win < 2 ? baseA : baseB) + off;
+        const uint32_t* src = (win & 1) ? B : A;
+        hw[x] = P >= 0 ? src[P] : 0u;
+    }
+    __syncthreads();
+    const int row = wave / E, e = wave - row * E;  // row 0: A, 1: B
+    const int i = lane + 64 * e;
+    const int64_t nd = row ? ndB : ndA;
+    const uint32_t* w = hw + 2 * WH * row;
+    hbuf[wave * 64 + lane] =
+        nd - i >= 0 ? apply_row_at(w, w + WH, WH - 1 - i, S, Mc + 128 * row, Mc + 128 * row + 64, F) : 0u;
+    __syncthreads();
+}
+
+// The cooperative gcd with the chunks overlapped: while the apply waves
+// (2 and 3) of every block apply chunk c to their halves of the block's
+// slice, wave 0 computes chunk c+1's heads from the chunk-start operands
+// and chunk c's M and runs chunk c+1's steps, which wave 1 composes into
+// the other M. The grid barrier is split: the apply waves arrive as soon
+// as their writes are out, wave 0 as soon as it has read the chunk-start
+// operands it needs (another block may overwrite that half of the double
+// buffer once the barrier completes), and the block waits only after the
+// head run.
+// A chunk that ends in an unknown degree or a single big step is followed
+// by the serial path (barrier, rescan, heads from device memory).
+template <int E>
+__global__ __launch_bounds__(GCD_THREADS) void gcd_pipe_kernel(GcdArgs G) {
+    static_assert(GCD_THREADS == 256, "waves 0 and 1 run the steps and M, waves 2 and 3 apply");
+    constexpr int NAPPLY = 2;
+    constexpr int NARRIVE = NAPPLY + 1;  // the apply waves and wave 0
+    constexpr int WH = 64 * E + 64;
+    extern __shared__ uint32_t smem[];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int slice = G.slice;
+    const int half = slice / NAPPLY;
+    const int64_t N = G.N;
+    const int64_t lo = (int64_t)blockIdx.x * slice;
+    const int64_t hi = lo + slice;
+    uint32_t* stage = smem;                                  // NAPPLY x 2 x (half + 64)
+    uint32_t* hw = stage + NAPPLY * 2 * (half + 64);         // 4 x WH
+    uint32_t* hbuf = hw + 4 * WH;                            // 2 x 64 E: the next heads
+    uint32_t* Mbuf = hbuf + 128 * E;                         // 2 x 256
+    StepDesc* desc = (StepDesc*)(Mbuf + 512);                // GCD_MAXSTEPS
+    __shared__ ChunkOut s_out[2];
+    __shared__ int64_t s_deg[2];
+    __shared__ StepLog s_log;
+    __shared__ uint32_t s_arrive;
+    const Field F = G.F;
+    unsigned gen = __hip_atomic_load(&G.info->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t* const A0 = G.buf;
+    uint32_t* const B0 = G.buf + N;
+    uint32_t* const A1 = G.buf + 2 * N;
+    uint32_t* const B1 = G.buf + 3 * N;
+
+    if (tid == 0) {
+        steplog_reset(&s_log);
+        s_arrive = 0u;
+    }
+    int bad = 0;
+    for (int64_t i = lo + tid; i < hi; i += GCD_THREADS) {
+        uint32_t x = i < G.na ? G.a[i] : 0u;
+        uint32_t y = i < G.nb ? G.b[i] : 0u;
+        bad |= (x >= F.p) | (y >= F.p);
+        A0[i] = x;
+        B0[i] = y;
+    }
+    bad = __syncthreads_or(bad);
+    if (tid == 0) G.flags[blockIdx.x] = (uint32_t)bad;
+    if (wave < 2) {
+        int64_t d = top_nonzero_wave(wave == 0 ? G.a : G.b, wave == 0 ? G.na : G.nb);
+        if (lane == 0) s_deg[wave] = d;
+    }
+    grid_sync(G.info, G.groups, gen);
+    int anybad = 0;
+    for (int i = tid; i < G.groups; i += GCD_THREADS) anybad |= (int)G.flags[i];
+    anybad = __syncthreads_or(anybad);
+    if (anybad) {
+        if (blockIdx.x == 0 && tid == 0) {
+            G.info->status = -3;  // PM_ERANGE
+            G.info->n0 = 0;
+        }
+        return;
+    }
+    int64_t dA = uni(s_deg[0]), dB = uni(s_deg[1]);
+    int cur = 0, mb = 0;
+    int64_t steps = 0, chunks = 0, updates = 0;
+    const int64_t max_chunks = (dA > 0 ? dA : 0) + (dB > 0 ? dB : 0) + 4;
+    bool ok = true;
+    // chunk 0's steps and M, from the input operands
+    if (dA >= 0 && dB >= 0) {
+        if (wave == 0) {
+            uint32_t hA[E], hB[E];
+            load_heads<E>(A0, B0, dA, dB, hA, hB);
+            int nst, big;
+            head_run_log<E>(hA, hB, (int)dA, (int)dB, G.s, F, desc, &s_log, &s_out[0], nst, big);
+        } else if (wave == 1) {
+            m_build_live(desc, &s_log, F, Mbuf);
+        }
+        __syncthreads();
+        if (tid == 0) steplog_reset(&s_log);
+        __syncthreads();
+    }
+    for (;;) {
+        // state_c (cur) is complete; chunk c's steps are in s_out[mb], M[mb]
+        if (dA < 0 || dB < 0) break;
+        if (chunks >= max_chunks) { ok = false; break; }
+        chunks++;
+        const uint32_t* Acur = cur ? A1 : A0;
+        const uint32_t* Bcur = cur ? B1 : B0;
+        uint32_t* Anext = cur ? A0 : A1;
+        uint32_t* Bnext = cur ? B0 : B1;
+        ChunkOut res = s_out[mb];
+        res.dA = uni(res.dA);
+        res.dB = uni(res.dB);
+        res.upd = uni(res.upd);
+        res.nsteps = uni(res.nsteps);
+        res.S = uni(res.S);
+        res.unkA = uni(res.unkA);
+        res.unkB = uni(res.unkB);
+        res.big = uni(res.big);
+        const uint32_t* Mc = Mbuf + 256 * mb;
+        uint32_t* Mn = Mbuf + 256 * (mb ^ 1);
+        const bool pipe = !res.big && !res.unkA && !res.unkB && res.dA >= 0 && res.dB >= 0;
+        const int64_t top = dA > dB ? dA : dB;
+        if (pipe) heads_after_chunk<E>(Acur, Bcur, res.dA, res.dB, res.S, Mc, F, hw, hbuf);
+        if (wave == 0) {
+            // done with state c (the windows were read before the block's barrier)
+            arrive_by_waves(G.info, G.groups, &s_arrive, NARRIVE);
+            if (pipe) {
+                uint32_t hA[E], hB[E];
+#pragma unroll
+                for (int e = 0; e < E; e++) {
+                    hA[e] = hbuf[64 * e + lane];
+                    hB[e] = hbuf[64 * (E + e) + lane];
+                }
+                int nst, big;
+                head_run_log<E>(hA, hB, (int)res.dA, (int)res.dB, G.s, F, desc, &s_log, &s_out[mb ^ 1], nst, big);
+            }
+        } else if (wave == 1) {
+            if (pipe) m_build_live(desc, &s_log, F, Mn);
+        } else {
+            const int w = wave - 2;
+            const int64_t wlo = lo + (int64_t)w * half;
+            uint32_t* la = stage + w * 2 * (half + 64);
+            uint32_t* lb = la + half + 64;
+            if (wlo <= top) {
+                if (!res.big) {
+                    const int S = res.S;
+                    const int64_t base = wlo - S;
+                    const int len = half + S;
+                    for (int x = lane; x < len; x += 64) {
+                        const int64_t P = base + x;
+                        la[x] = P >= 0 ? Acur[P] : 0u;
+                        lb[x] = P >= 0 ? Bcur[P] : 0u;
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                    for (int x = lane; x < half; x += 64) {
+                        const int64_t P = wlo + x;
+                        uint32_t na_, nb_;
+                        apply_m_at(la, lb, x + S, S, Mc, F, na_, nb_);
+                        Anext[P] = P <= res.dA ? na_ : 0u;
+                        Bnext[P] = P <= res.dB ? nb_ : 0u;
+                    }
+                } else {
+                    const StepDesc D = desc[0];
+                    const uint32_t* Xc = D.which ? Bcur : Acur;
+                    const uint32_t* Yc = D.which ? Acur : Bcur;
+                    uint32_t* Xn = D.which ? Bnext : Anext;
+                    uint32_t* Yn = D.which ? Anext : Bnext;
+                    const int64_t bX = D.which ? res.dB : res.dA;
+                    const int64_t bY = D.which ? res.dA : res.dB;
+                    for (int x = lane; x < half; x += 64) {
+                        const int64_t P = wlo + x;
+                        uint32_t y = P - D.d >= 0 ? Yc[P - D.d] : 0u;
+                        uint32_t nx = redc((uint64_t)D.m1 * Xc[P] + (uint64_t)D.m2 * y, F);
+                        Xn[P] = P <= bX ? nx : 0u;
+                        Yn[P] = P <= bY ? Yc[P] : 0u;
+                    }
+                }
+            }
+            arrive_by_waves(G.info, G.groups, &s_arrive, NARRIVE);
+        }
+        __syncthreads();
+        if (tid == 0) steplog_reset(&s_log);
+        wait_grid(G.info, G.groups, gen);
+        cur ^= 1;
+        dA = res.dA;
+        dB = res.dB;
+        steps += res.nsteps + res.zsteps;
+        updates += res.upd;
+        if (!pipe) {
+            const uint32_t* An = cur ? A1 : A0;
+            const uint32_t* Bn = cur ? B1 : B0;
+            if (res.unkA || res.unkB) {
+                if (wave == 0) {
+                    int64_t x = res.unkA ? top_nonzero_wave(An, dA + 1) : dA;
+                    int64_t y = res.unkB ? top_nonzero_wave(Bn, dB + 1) : dB;
+                    if (lane == 0) { s_deg[0] = x; s_deg[1] = y; }
+                }
+                __syncthreads();
+                dA = uni(s_deg[0]);
+                dB = uni(s_deg[1]);
+                // the zero steps after the step whose new degree was unknown
+                const int64_t zY = uni(s_out[mb].zY);
+                const int64_t z = zero_steps(uni(s_out[mb].zX), zY, res.unkA ? dA : dB);
+                steps += z;
+                updates += z * (zY + 1);
+            }
+            if (dA >= 0 && dB >= 0) {
+                if (wave == 0) {
+                    uint32_t hA[E], hB[E];
+                    load_heads<E>(An, Bn, dA, dB, hA, hB);
+                    int nst, big;
+                    head_run_log<E>(hA, hB, (int)dA, (int)dB, G.s, F, desc, &s_log, &s_out[mb ^ 1], nst, big);
+                } else if (wave == 1) {
+                    m_build_live(desc, &s_log, F, Mn);
+                }
+                __syncthreads();
+                if (tid == 0) steplog_reset(&s_log);
+            }
+            __syncthreads();
+        }
+        mb ^= 1;
+    }
+
+    // The last non-zero remainder, made monic.
+    const uint32_t* Acur = cur ? A1 : A0;
+    const uint32_t* Bcur = cur ? B1 : B0;
+    const uint32_t* Rp = dA >= 0 ? Acur : Bcur;
+    const int64_t dR = dA >= 0 ? dA : dB;
+    int status = ok ? 0 : -6;  // PM_EDEVICE on a broken invariant
+    if (status == 0 && dR + 1 > G.g_cap) status = -1;  // PM_EINVAL: g too small
+    if (status == 0 && dR >= 0) {
+        const uint32_t inv = invmod(Rp[dR], F);
+        for (int64_t P = lo + tid; P < hi && P <= dR; P += GCD_THREADS) G.g[P] = mulmod(Rp[P], inv, F);
+    }
+    if (blockIdx.x == 0 && tid == 0) {
+        G.info->status = status;
+        G.info->n0 = status == 0 ? dR + 1 : 0;
+        G.info->steps = steps;
+        G.info->chunks = chunks;
+        G.info->updates = updates;
+    }
+}
+
 // ------------------------------------------------------------------ batched
 // One block per instance; A and B live in LDS at offset PADLO so that
 // positions below 0 read as zero.
@@ -624,14 +921,26 @@ hipError_t gcd_launch(const uint32_t* a, int64_t na, const uint32_t* b, int64_t 
     size_t lds = (size_t)(2 * (plan.slice + GCD_MAXSHIFT + 1) + 256 + 64 * E) * sizeof(uint32_t) +
                  GCD_MAXSTEPS * sizeof(StepDesc);
     void* args[] = {&A};
-    TimingScope ts(xg ? "gcd_multi_kernel_xg" : "gcd_multi_kernel", stream);
-    const void* fn = xg ? (const void*)gcd_multi_kernel<E, true> : (const void*)gcd_multi_kernel<E, false>;
+    if (!xg) {
+        // the pipelined kernel for the plain gcd
+        const int half = plan.slice / 2;
+        const size_t lds_p = (size_t)(2 * 2 * (half + 64) + 4 * (64 * E + 64) + 128 * E + 512) * sizeof(uint32_t) +
+                             GCD_MAXSTEPS * sizeof(StepDesc);
+        TimingScope ts("gcd_pipe_kernel", stream);
+        if (plan.groups == 1) {
+            hipLaunchKernelGGL((gcd_pipe_kernel<E>), dim3(1), dim3(GCD_THREADS), lds_p, stream, A);
+            return hipGetLastError();
+        }
+        return hipLaunchCooperativeKernel((const void*)gcd_pipe_kernel<E>, dim3(plan.groups), dim3(GCD_THREADS),
+                                          args, (unsigned)lds_p, stream);
+    }
+    TimingScope ts("gcd_multi_kernel_xg", stream);
     if (plan.groups == 1) {
-        if (xg) hipLaunchKernelGGL((gcd_multi_kernel<E, true>), dim3(1), dim3(GCD_THREADS), lds, stream, A);
-        else hipLaunchKernelGGL((gcd_multi_kernel<E, false>), dim3(1), dim3(GCD_THREADS), lds, stream, A);
+        hipLaunchKernelGGL((gcd_multi_kernel<E, true>), dim3(1), dim3(GCD_THREADS), lds, stream, A);
         return hipGetLastError();
     }
-    return hipLaunchCooperativeKernel(fn, dim3(plan.groups), dim3(GCD_THREADS), args, (unsigned)lds, stream);
+    return hipLaunchCooperativeKernel((const void*)gcd_multi_kernel<E, true>, dim3(plan.groups), dim3(GCD_THREADS),
+                                      args, (unsigned)lds, stream);
 }
 
 int64_t gcd_batch_cap(int kind) { return kind == 0 ? 256 * 16 : 1024 * 17; }
