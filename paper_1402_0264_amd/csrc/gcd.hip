@@ -4,14 +4,14 @@
 // Two kernels share the fused chunk of gcd_core.hpp (heads -> recorded
 // steps -> matrix M -> one independent sum per coefficient):
 //
-//  * gcd_multi_kernel, for one large instance: a cooperative persistent
+//  * gcd_pipe_kernel, for one large instance: a cooperative persistent
 //    grid; every block owns a slice of coefficient positions of both
 //    polynomials. Each chunk, every block recomputes the same steps and the
-//    same M from the heads (read from HBM/L2), stages its slice plus the
-//    S positions below it, writes the new slice to the other half of a
-//    double buffer, and meets the others at one grid barrier. No other
-//    communication: the heads are the only cross-block state, as the paper's
-//    s-heads are.
+//    same M from the heads, applies the previous chunk's M to its slice
+//    meanwhile, and meets the others at one split grid barrier. No other
+//    communication: the heads are the only cross-block state, as the
+//    paper's s-heads are. Its extended variant also carries the cofactor of
+//    a through every M.
 //  * gcd_batch_kernel, for many instances: one block per instance, both
 //    polynomials resident in LDS for the whole remainder sequence; each
 //    chunk computes the new coefficients into registers, then overwrites the
@@ -56,237 +56,6 @@ __device__ __forceinline__ void load_heads(const uint32_t* A, const uint32_t* B,
         const int64_t i = lane + 64 * e;
         hA[e] = dA - i >= 0 ? A[dA - i] : 0u;
         hB[e] = dB - i >= 0 ? B[dB - i] : 0u;
-    }
-}
-
-template <int E, bool XG>
-__global__ __launch_bounds__(GCD_THREADS) void gcd_multi_kernel(GcdArgs G) {
-    extern __shared__ uint32_t smem[];
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
-    const int slice = G.slice;
-    const int64_t N = G.N;
-    const int64_t lo = (int64_t)blockIdx.x * slice;
-    const int64_t hi = lo + slice;
-    uint32_t* la = smem;                        // slice + GCD_MAXSHIFT + 1
-    uint32_t* lb = la + slice + GCD_MAXSHIFT + 1;
-    uint32_t* M = lb + slice + GCD_MAXSHIFT + 1;  // 256
-    uint32_t* tmp = M + 256;                    // 64 * E
-    StepDesc* desc = (StepDesc*)(tmp + 64 * E); // GCD_MAXSTEPS
-    __shared__ ChunkOut s_out;
-    __shared__ int64_t s_deg[2];
-    __shared__ StepLog s_log;
-    const Field F = G.F;
-    unsigned gen = __hip_atomic_load(&G.info->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    uint32_t* const A0 = G.buf;
-    uint32_t* const B0 = G.buf + N;
-    uint32_t* const A1 = G.buf + 2 * N;
-    uint32_t* const B1 = G.buf + 3 * N;
-
-    if (tid == 0) steplog_reset(&s_log);
-    int bad = 0;
-    for (int64_t i = lo + tid; i < hi; i += GCD_THREADS) {
-        uint32_t x = i < G.na ? G.a[i] : 0u;
-        uint32_t y = i < G.nb ? G.b[i] : 0u;
-        bad |= (x >= F.p) | (y >= F.p);
-        A0[i] = x;
-        B0[i] = y;
-    }
-    if constexpr (XG) {
-        for (int64_t i = lo + tid; i < hi; i += GCD_THREADS) {
-            G.sbuf[i] = i < G.nsa ? G.sa0[i] : 0u;
-            G.sbuf[N + i] = i < G.nsb ? G.sb0[i] : 0u;
-            G.sbuf[2 * N + i] = 0u;  // a block's slice of the other half is read
-            G.sbuf[3 * N + i] = 0u;  // before its first write once the degree grows
-        }
-    }
-    bad = __syncthreads_or(bad);
-    if (tid == 0) G.flags[blockIdx.x] = (uint32_t)bad;
-    if (wave < 2) {
-        int64_t d = top_nonzero_wave(wave == 0 ? G.a : G.b, wave == 0 ? G.na : G.nb);
-        if (lane == 0) s_deg[wave] = d;
-    }
-    grid_sync(G.info, G.groups, gen);
-    int anybad = 0;
-    for (int i = tid; i < G.groups; i += GCD_THREADS) anybad |= (int)G.flags[i];
-    anybad = __syncthreads_or(anybad);
-    if (anybad) {
-        if (blockIdx.x == 0 && tid == 0) {
-            G.info->status = -3;  // PM_ERANGE
-            G.info->n0 = 0;
-        }
-        return;
-    }
-    int64_t dA = uni(s_deg[0]), dB = uni(s_deg[1]);
-    int unkA = 0, unkB = 0;
-    int cur = 0;
-    int64_t steps = 0, chunks = 0, updates = 0;
-    const int64_t max_chunks = (dA > 0 ? dA : 0) + (dB > 0 ? dB : 0) + 4;
-    bool ok = true;
-    // bound on the cofactors' degree; grows by each chunk's shift
-    int64_t cdeg = XG ? uni((G.nsa > G.nsb ? G.nsa : G.nsb) - 1) : 0;
-    for (;;) {
-        const uint32_t* Acur = cur ? A1 : A0;
-        const uint32_t* Bcur = cur ? B1 : B0;
-        uint32_t* Anext = cur ? A0 : A1;
-        uint32_t* Bnext = cur ? B0 : B1;
-        if (unkA || unkB) {
-            if (wave == 0) {
-                int64_t x = unkA ? top_nonzero_wave(Acur, dA + 1) : dA;
-                int64_t y = unkB ? top_nonzero_wave(Bcur, dB + 1) : dB;
-                if (lane == 0) { s_deg[0] = x; s_deg[1] = y; }
-            }
-            __syncthreads();
-            // the zero steps after the step whose new degree was unknown
-            // (s_out still holds the last chunk's summary)
-            const int64_t nd = uni(unkA ? s_deg[0] : s_deg[1]);
-            const int64_t zY = uni(s_out.zY);
-            const int64_t z = zero_steps(uni(s_out.zX), zY, nd);
-            steps += z;
-            updates += z * (zY + 1);
-            dA = uni(s_deg[0]);
-            dB = uni(s_deg[1]);
-            unkA = unkB = 0;
-            __syncthreads();
-        }
-        if (dA < 0 || dB < 0) break;
-        if (chunks >= max_chunks) { ok = false; break; }
-        chunks++;
-        if (wave == 0) {
-            uint32_t hA[E], hB[E];
-            load_heads<E>(Acur, Bcur, dA, dB, hA, hB);
-            int n, big;
-            head_run_log<E>(hA, hB, (int)dA, (int)dB, G.s, F, desc, &s_log, &s_out, n, big);
-        } else if (wave == 1) {
-            m_build_live(desc, &s_log, F, M);
-        }
-        __syncthreads();
-        ChunkOut res = s_out;
-        res.dA = uni(res.dA);
-        res.dB = uni(res.dB);
-        res.upd = uni(res.upd);
-        res.nsteps = uni(res.nsteps);
-        res.S = uni(res.S);
-        res.unkA = uni(res.unkA);
-        res.unkB = uni(res.unkB);
-        res.big = uni(res.big);
-        const int64_t top = dA > dB ? dA : dB;
-        if (lo <= top) {
-            if (!res.big) {
-                const int S = res.S;
-                const int64_t base = lo - S;
-                const int len = slice + S;
-                for (int x = tid; x < len; x += GCD_THREADS) {
-                    int64_t P = base + x;
-                    la[x] = P >= 0 ? Acur[P] : 0u;
-                    lb[x] = P >= 0 ? Bcur[P] : 0u;
-                }
-                __syncthreads();
-                for (int x = tid; x < slice; x += GCD_THREADS) {
-                    const int64_t P = lo + x;
-                    uint32_t na_, nb_;
-                    apply_m_at(la, lb, x + S, S, M, F, na_, nb_);
-                    Anext[P] = P <= res.dA ? na_ : 0u;
-                    Bnext[P] = P <= res.dB ? nb_ : 0u;
-                }
-            } else {
-                // one step whose shift is beyond the matrix: read the other
-                // operand straight from the chunk-start buffer
-                const StepDesc D = desc[0];
-                const uint32_t* Xc = D.which ? Bcur : Acur;
-                const uint32_t* Yc = D.which ? Acur : Bcur;
-                uint32_t* Xn = D.which ? Bnext : Anext;
-                uint32_t* Yn = D.which ? Anext : Bnext;
-                const int64_t bX = D.which ? res.dB : res.dA;
-                const int64_t bY = D.which ? res.dA : res.dB;
-                for (int x = tid; x < slice; x += GCD_THREADS) {
-                    const int64_t P = lo + x;
-                    uint32_t y = P - D.d >= 0 ? Yc[P - D.d] : 0u;
-                    uint32_t nx = redc((uint64_t)D.m1 * Xc[P] + (uint64_t)D.m2 * y, F);
-                    Xn[P] = P <= bX ? nx : 0u;
-                    Yn[P] = P <= bY ? Yc[P] : 0u;
-                }
-            }
-        }
-        if constexpr (XG) {
-            // the cofactors take the same M; a block computes its whole
-            // slice once the bound reaches it (values past the true degree
-            // come out zero)
-            const int64_t grow = res.big ? (int64_t)desc[0].d : (int64_t)res.S;
-            int64_t cdn = cdeg + grow;
-            if (cdn > G.s_deg_cap) cdn = G.s_deg_cap;
-            cdeg = uni(cdn);
-            const uint32_t* SAc = G.sbuf + (cur ? 2 * N : 0);
-            const uint32_t* SBc = SAc + N;
-            uint32_t* SAn = G.sbuf + (cur ? 0 : 2 * N);
-            uint32_t* SBn = SAn + N;
-            if (lo <= cdeg) {
-                if (!res.big) {
-                    const int S = res.S;
-                    const int64_t base = lo - S;
-                    const int len = slice + S;
-                    __syncthreads();  // the state's windows have been read
-                    for (int x = tid; x < len; x += GCD_THREADS) {
-                        int64_t P = base + x;
-                        la[x] = P >= 0 ? SAc[P] : 0u;
-                        lb[x] = P >= 0 ? SBc[P] : 0u;
-                    }
-                    __syncthreads();
-                    for (int x = tid; x < slice; x += GCD_THREADS) {
-                        uint32_t sa_, sb_;
-                        apply_m_at(la, lb, x + S, S, M, F, sa_, sb_);
-                        SAn[lo + x] = sa_;
-                        SBn[lo + x] = sb_;
-                    }
-                } else {
-                    const StepDesc D = desc[0];
-                    const uint32_t* Xc = D.which ? SBc : SAc;
-                    const uint32_t* Yc = D.which ? SAc : SBc;
-                    uint32_t* Xn = D.which ? SBn : SAn;
-                    uint32_t* Yn = D.which ? SAn : SBn;
-                    for (int x = tid; x < slice; x += GCD_THREADS) {
-                        const int64_t P = lo + x;
-                        uint32_t y = P - D.d >= 0 ? Yc[P - D.d] : 0u;
-                        Xn[P] = redc((uint64_t)D.m1 * Xc[P] + (uint64_t)D.m2 * y, F);
-                        Yn[P] = Yc[P];
-                    }
-                }
-            }
-        }
-        if (tid == 0) steplog_reset(&s_log);  // read by the next chunk after the barrier
-        grid_sync(G.info, G.groups, gen);
-        cur ^= 1;
-        dA = res.dA;
-        dB = res.dB;
-        unkA = res.unkA;
-        unkB = res.unkB;
-        steps += res.nsteps + res.zsteps;
-        updates += res.upd;
-    }
-
-    // The last non-zero remainder, made monic.
-    const uint32_t* Acur = cur ? A1 : A0;
-    const uint32_t* Bcur = cur ? B1 : B0;
-    const uint32_t* Rp = dA >= 0 ? Acur : Bcur;
-    const int64_t dR = dA >= 0 ? dA : dB;
-    int status = ok ? 0 : -6;  // PM_EDEVICE on a broken invariant
-    if (status == 0 && dR + 1 > G.g_cap) status = -1;  // PM_EINVAL: g too small
-    if (status == 0 && dR >= 0) {
-        const uint32_t inv = invmod(Rp[dR], F);
-        for (int64_t P = lo + tid; P < hi && P <= dR; P += GCD_THREADS) G.g[P] = mulmod(Rp[P], inv, F);
-    }
-    if constexpr (XG) {
-        // the cofactor of a in the last non-zero remainder, scaled as g is
-        const uint32_t* SR = G.sbuf + (cur ? 2 * N : 0) + (dA >= 0 ? 0 : N);
-        const uint32_t inv = (status == 0 && dR >= 0) ? invmod(Rp[dR], F) : 0u;
-        for (int64_t P = lo + tid; P < hi; P += GCD_THREADS) G.s_res[P] = mulmod(SR[P], inv, F);
-    }
-    if (blockIdx.x == 0 && tid == 0) {
-        G.info->status = status;
-        G.info->n0 = status == 0 ? dR + 1 : 0;
-        G.info->steps = steps;
-        G.info->chunks = chunks;
-        G.info->updates = updates;
     }
 }
 
@@ -366,7 +135,7 @@ __device__ void heads_after_chunk(const uint32_t* A, const uint32_t* B, int64_t 
 // head run.
 // A chunk that ends in an unknown degree or a single big step is followed
 // by the serial path (barrier, rescan, heads from device memory).
-template <int E>
+template <int E, bool XG>
 __global__ __launch_bounds__(GCD_THREADS) void gcd_pipe_kernel(GcdArgs G) {
     static_assert(GCD_THREADS == 256, "waves 0 and 1 run the steps and M, waves 2 and 3 apply");
     constexpr int NAPPLY = 2;
@@ -408,6 +177,14 @@ __global__ __launch_bounds__(GCD_THREADS) void gcd_pipe_kernel(GcdArgs G) {
         A0[i] = x;
         B0[i] = y;
     }
+    if constexpr (XG) {
+        for (int64_t i = lo + tid; i < hi; i += GCD_THREADS) {
+            G.sbuf[i] = i < G.nsa ? G.sa0[i] : 0u;
+            G.sbuf[N + i] = i < G.nsb ? G.sb0[i] : 0u;
+            G.sbuf[2 * N + i] = 0u;  // a block's slice of the other half is read
+            G.sbuf[3 * N + i] = 0u;  // before its first write once the degree grows
+        }
+    }
     bad = __syncthreads_or(bad);
     if (tid == 0) G.flags[blockIdx.x] = (uint32_t)bad;
     if (wave < 2) {
@@ -426,6 +203,8 @@ __global__ __launch_bounds__(GCD_THREADS) void gcd_pipe_kernel(GcdArgs G) {
         return;
     }
     int64_t dA = uni(s_deg[0]), dB = uni(s_deg[1]);
+    // bound on the cofactors' degree; grows by each chunk's shift
+    int64_t cdeg = XG ? uni((G.nsa > G.nsb ? G.nsa : G.nsb) - 1) : 0;
     int cur = 0, mb = 0;
     int64_t steps = 0, chunks = 0, updates = 0;
     const int64_t max_chunks = (dA > 0 ? dA : 0) + (dB > 0 ? dB : 0) + 4;
@@ -466,6 +245,12 @@ __global__ __launch_bounds__(GCD_THREADS) void gcd_pipe_kernel(GcdArgs G) {
         uint32_t* Mn = Mbuf + 256 * (mb ^ 1);
         const bool pipe = !res.big && !res.unkA && !res.unkB && res.dA >= 0 && res.dB >= 0;
         const int64_t top = dA > dB ? dA : dB;
+        int64_t cdn = 0;
+        if constexpr (XG) {
+            cdn = cdeg + (res.big ? (int64_t)desc[0].d : (int64_t)res.S);
+            if (cdn > G.s_deg_cap) cdn = G.s_deg_cap;
+            cdn = uni(cdn);
+        }
         if (pipe) heads_after_chunk<E>(Acur, Bcur, res.dA, res.dB, res.S, Mc, F, hw, hbuf);
         if (wave == 0) {
             // done with state c (the windows were read before the block's barrier)
@@ -522,6 +307,47 @@ __global__ __launch_bounds__(GCD_THREADS) void gcd_pipe_kernel(GcdArgs G) {
                     }
                 }
             }
+            if constexpr (XG) {
+                // the cofactors take the same M; a wave computes its whole
+                // half once the bound reaches it (values past the true
+                // degree come out zero)
+                const uint32_t* SAc = G.sbuf + (cur ? 2 * N : 0);
+                const uint32_t* SBc = SAc + N;
+                uint32_t* SAn = G.sbuf + (cur ? 0 : 2 * N);
+                uint32_t* SBn = SAn + N;
+                if (wlo <= cdn) {
+                    if (!res.big) {
+                        const int S = res.S;
+                        const int64_t base = wlo - S;
+                        const int len = half + S;
+                        __builtin_amdgcn_wave_barrier();
+                        for (int x = lane; x < len; x += 64) {
+                            const int64_t P = base + x;
+                            la[x] = P >= 0 ? SAc[P] : 0u;
+                            lb[x] = P >= 0 ? SBc[P] : 0u;
+                        }
+                        __builtin_amdgcn_wave_barrier();
+                        for (int x = lane; x < half; x += 64) {
+                            uint32_t sa_, sb_;
+                            apply_m_at(la, lb, x + S, S, Mc, F, sa_, sb_);
+                            SAn[wlo + x] = sa_;
+                            SBn[wlo + x] = sb_;
+                        }
+                    } else {
+                        const StepDesc D = desc[0];
+                        const uint32_t* Xc = D.which ? SBc : SAc;
+                        const uint32_t* Yc = D.which ? SAc : SBc;
+                        uint32_t* Xn = D.which ? SBn : SAn;
+                        uint32_t* Yn = D.which ? SAn : SBn;
+                        for (int x = lane; x < half; x += 64) {
+                            const int64_t P = wlo + x;
+                            uint32_t y = P - D.d >= 0 ? Yc[P - D.d] : 0u;
+                            Xn[P] = redc((uint64_t)D.m1 * Xc[P] + (uint64_t)D.m2 * y, F);
+                            Yn[P] = Yc[P];
+                        }
+                    }
+                }
+            }
             arrive_by_waves(G.info, G.groups, &s_arrive, NARRIVE);
         }
         __syncthreads();
@@ -530,6 +356,7 @@ __global__ __launch_bounds__(GCD_THREADS) void gcd_pipe_kernel(GcdArgs G) {
         cur ^= 1;
         dA = res.dA;
         dB = res.dB;
+        cdeg = cdn;
         steps += res.nsteps + res.zsteps;
         updates += res.upd;
         if (!pipe) {
@@ -577,6 +404,12 @@ __global__ __launch_bounds__(GCD_THREADS) void gcd_pipe_kernel(GcdArgs G) {
     if (status == 0 && dR >= 0) {
         const uint32_t inv = invmod(Rp[dR], F);
         for (int64_t P = lo + tid; P < hi && P <= dR; P += GCD_THREADS) G.g[P] = mulmod(Rp[P], inv, F);
+    }
+    if constexpr (XG) {
+        // the cofactor of a in the last non-zero remainder, scaled as g is
+        const uint32_t* SR = G.sbuf + (cur ? 2 * N : 0) + (dA >= 0 ? 0 : N);
+        const uint32_t inv = (status == 0 && dR >= 0) ? invmod(Rp[dR], F) : 0u;
+        for (int64_t P = lo + tid; P < hi; P += GCD_THREADS) G.s_res[P] = mulmod(SR[P], inv, F);
     }
     if (blockIdx.x == 0 && tid == 0) {
         G.info->status = status;
@@ -918,29 +751,18 @@ hipError_t gcd_launch(const uint32_t* a, int64_t na, const uint32_t* b, int64_t 
         A.s_res = xg->s_res;
     }
     constexpr int E = 2;  // 128-entry heads (GcdPlan::head)
-    size_t lds = (size_t)(2 * (plan.slice + GCD_MAXSHIFT + 1) + 256 + 64 * E) * sizeof(uint32_t) +
-                 GCD_MAXSTEPS * sizeof(StepDesc);
     void* args[] = {&A};
-    if (!xg) {
-        // the pipelined kernel for the plain gcd
-        const int half = plan.slice / 2;
-        const size_t lds_p = (size_t)(2 * 2 * (half + 64) + 4 * (64 * E + 64) + 128 * E + 512) * sizeof(uint32_t) +
-                             GCD_MAXSTEPS * sizeof(StepDesc);
-        TimingScope ts("gcd_pipe_kernel", stream);
-        if (plan.groups == 1) {
-            hipLaunchKernelGGL((gcd_pipe_kernel<E>), dim3(1), dim3(GCD_THREADS), lds_p, stream, A);
-            return hipGetLastError();
-        }
-        return hipLaunchCooperativeKernel((const void*)gcd_pipe_kernel<E>, dim3(plan.groups), dim3(GCD_THREADS),
-                                          args, (unsigned)lds_p, stream);
-    }
-    TimingScope ts("gcd_multi_kernel_xg", stream);
+    const int half = plan.slice / 2;
+    const size_t lds = (size_t)(2 * 2 * (half + 64) + 4 * (64 * E + 64) + 128 * E + 512) * sizeof(uint32_t) +
+                       GCD_MAXSTEPS * sizeof(StepDesc);
+    TimingScope ts(xg ? "gcd_pipe_kernel_xg" : "gcd_pipe_kernel", stream);
+    const void* fn = xg ? (const void*)gcd_pipe_kernel<E, true> : (const void*)gcd_pipe_kernel<E, false>;
     if (plan.groups == 1) {
-        hipLaunchKernelGGL((gcd_multi_kernel<E, true>), dim3(1), dim3(GCD_THREADS), lds, stream, A);
+        if (xg) hipLaunchKernelGGL((gcd_pipe_kernel<E, true>), dim3(1), dim3(GCD_THREADS), lds, stream, A);
+        else hipLaunchKernelGGL((gcd_pipe_kernel<E, false>), dim3(1), dim3(GCD_THREADS), lds, stream, A);
         return hipGetLastError();
     }
-    return hipLaunchCooperativeKernel((const void*)gcd_multi_kernel<E, true>, dim3(plan.groups), dim3(GCD_THREADS),
-                                      args, (unsigned)lds, stream);
+    return hipLaunchCooperativeKernel(fn, dim3(plan.groups), dim3(GCD_THREADS), args, (unsigned)lds, stream);
 }
 
 int64_t gcd_batch_cap(int kind) { return kind == 0 ? 256 * 16 : 1024 * 17; }
