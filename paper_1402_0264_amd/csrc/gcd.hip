@@ -428,14 +428,15 @@ constexpr int PADLO = 64;
 // One whole instance on the calling block (all NT threads).
 template <int NT, int PPT, int E>
 __device__ void gcd_instance(const GcdJob& J, int s, int64_t cap, uint32_t* smem) {
+    static_assert(NT / 64 >= 2 * E, "a wave per head vector");
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const Field F = J.F;
     uint32_t* A = smem + PADLO;                 // cap words (+PADLO zeros below)
     uint32_t* B = A + cap + PADLO;
     uint32_t* Mbuf = B + cap;                   // 2 x 256: M of this chunk and of the next
-    uint32_t* tmp = Mbuf + 512;                 // 64 * E
-    StepDesc* desc = (StepDesc*)(tmp + 64 * E); // GCD_MAXSTEPS
+    uint32_t* hbuf = Mbuf + 512;                // 2 x 64 E: the next chunk's heads
+    StepDesc* desc = (StepDesc*)(hbuf + 128 * E); // GCD_MAXSTEPS
     __shared__ ChunkOut s_out[2];
     __shared__ int64_t s_deg[2];
     __shared__ StepLog s_log;
@@ -523,6 +524,17 @@ __device__ void gcd_instance(const GcdJob& J, int s, int64_t cap, uint32_t* smem
         const int top = (int)(dA > dB ? dA : dB);
         if (!res.big) {
             uint32_t nA[PPA], nB[PPA];
+            if (pipe) {
+                // the next chunk's heads from the chunk-start pair and M, one
+                // 64-entry vector per wave (A's, then B's), off the chain
+                if (wave < 2 * E) {
+                    const int row = wave / E, e = wave - row * E;
+                    const int P = (int)(row ? res.dB : res.dA) - (lane + 64 * e);
+                    hbuf[wave * 64 + lane] =
+                        P >= 0 ? apply_row_at(A, B, P, res.S, Mc + 128 * row, Mc + 128 * row + 64, F) : 0u;
+                }
+                __syncthreads();
+            }
             if (wave == 0) {
                 if (pipe) {
                     // the step chain bounds the chunk: its wave goes first on
@@ -531,10 +543,8 @@ __device__ void gcd_instance(const GcdJob& J, int s, int64_t cap, uint32_t* smem
                     uint32_t hA[E], hB[E];
 #pragma unroll
                     for (int e = 0; e < E; e++) {
-                        const int i = lane + 64 * e;
-                        const int PA = (int)res.dA - i, PB = (int)res.dB - i;
-                        hA[e] = PA >= 0 ? apply_row_at(A, B, PA, res.S, Mc, Mc + 64, F) : 0u;
-                        hB[e] = PB >= 0 ? apply_row_at(A, B, PB, res.S, Mc + 128, Mc + 192, F) : 0u;
+                        hA[e] = hbuf[64 * e + lane];
+                        hB[e] = hbuf[64 * (E + e) + lane];
                     }
                     int nst, big;
                     head_run_log<E>(hA, hB, (int)res.dA, (int)res.dB, s, F, desc, &s_log, &s_out[mb ^ 1], nst, big);
@@ -700,7 +710,7 @@ __global__ __launch_bounds__(NT) void gcd_worker_kernel(const GcdJob* jobs, cons
 
 template <int NT, int PPT, int E>
 size_t batch_lds_bytes(int64_t cap) {
-    return (size_t)(2 * (cap + PADLO) + 512 + 64 * E) * sizeof(uint32_t) + GCD_MAXSTEPS * sizeof(StepDesc);
+    return (size_t)(2 * (cap + PADLO) + 512 + 128 * E) * sizeof(uint32_t) + GCD_MAXSTEPS * sizeof(StepDesc);
 }
 
 }  // namespace
