@@ -32,6 +32,9 @@ Beside it, in the same line:
                 32768 / 32767 pair with a planted degree-1000 gcd (time per
                 division step, grid syncs, updates/s against the VALU peak),
                 and the extended gcd (Bezout cofactors) of the same pair;
+  batched_gcd   the same 2048 gcd requests as one prepared batch (s from the
+                autotuner) replayed from a captured graph, beside one call per
+                request on a sample;
   served        a Poisson stream of 2048 gcd requests (degrees log-uniform
                 in [64, 16384], planted gcd, three primes) through the
                 continuous-batching server: saturated GCDs/s, then p50/p99
@@ -215,6 +218,57 @@ def served_inputs(count: int):
         b.close()
     reqs = [(out[2 * i], out[2 * i + 1], r.p, r.arrival, r.D, r.k) for i, r in enumerate(trace)]
     return reqs
+
+
+def bench_batched_gcd(reqs, one_call_sample: int = 256, reps: int = 3) -> dict:
+    """The served trace's requests as one prepared batch (pm_gcd_batch_*):
+    s picked by the autotuner, the run captured in a CUDA graph and
+    replayed; beside it, the first requests of the same list as one
+    synchronous poly_gcd_modp call each."""
+    import torch
+    import paper_1402_0264_amd as pm
+    from paper_1402_0264_amd import tune
+    items = [(pm.to_device(a), pm.to_device(b), p) for a, b, p, *_ in reqs]
+    t = tune.tune_gcd_batch(items)
+    batch = pm.GcdBatch(items, t["s"])
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        batch.run(stream=side)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        batch.run()
+    graph.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    res = batch.results()
+    ok = all(r["status"] == 0 for _, r in res)
+    # the same requests one call each (the single-instance cooperative path),
+    # on a sample; the sampled gcds must equal the batch's
+    k = min(one_call_sample, len(items))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    singles = [pm.gcd(a, b, p) for a, b, p in items[:k]]
+    torch.cuda.synchronize()
+    t_one = (time.perf_counter() - t0) / k
+    same = all(torch.equal(g1, res[i][0]) for i, g1 in enumerate(singles))
+    batch.close()
+    updates = sum(r["updates"] for _, r in res)
+    return {"workload": "the served trace's %d requests (D log-uniform in [64, 16384], three primes) "
+                        "in one prepared batch replayed from a CUDA graph" % len(items),
+            "s": t["s"], "tune_trials": t["trials"], "model_s_star": t["model_s_star"], "ms": round(ms, 3),
+            "gcds_per_s": round(len(items) / (ms * 1e-3), 1), "updates_per_s": round(updates / (ms * 1e-3), 1),
+            "one_call_per_instance_gcds_per_s": round(1.0 / t_one, 1), "one_call_sample": k,
+            "speedup_vs_one_call_per_instance": round((len(items) / (ms * 1e-3)) * t_one, 1),
+            "all_ok": ok, "sample_equals_one_call": same}
 
 
 def run_server_trace(reqs, scale: float):
@@ -544,6 +598,8 @@ def main() -> int:
         out["gcd_32768"] = bench_gcd(args.gcd_reps)
     if not args.no_served:
         out["served"] = bench_served(args.served_requests, 128, 0.8, not args.no_served_baseline)
+    if not args.no_batched:
+        out["batched_gcd"] = bench_batched_gcd(served_inputs(args.served_requests))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(a_np, b_np, p, args.cpu_seconds)
     print(json.dumps(out), flush=True)

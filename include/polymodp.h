@@ -207,6 +207,23 @@ typedef struct {
     int32_t done;     /* 1 once the item finished                         */
 } pm_gcd_result;
 pm_status poly_gcd_modp_batch(const pm_gcd_item *items, int32_t count, pm_gcd_result *results, void *stream);
+/*
+ * The same batch prepared once and run many times (for hipGraph capture):
+ * pm_gcd_batch_create checks every item on the host, orders the items
+ * longest first within each of the two block shapes, and uploads the job
+ * table (allocates device memory, synchronous; not graph-capturable).
+ * s: division steps per chunk, 0..256 (0 = 128).
+ * pm_gcd_batch_run enqueues one launch per block shape (at most two): no
+ * allocation, no host work, no memset, so it may be captured in a hipGraph
+ * and replayed; every run rewrites each item's g and result in full.
+ * pm_gcd_batch_results copies the results of the last run to the host
+ * (synchronous). A batch object must not run on two streams at once.
+ */
+typedef struct pm_gcd_batch pm_gcd_batch;
+pm_status pm_gcd_batch_create(const pm_gcd_item *items, int32_t count, int32_t s, pm_gcd_batch **out);
+pm_status pm_gcd_batch_run(pm_gcd_batch *batch, void *stream);
+pm_status pm_gcd_batch_results(pm_gcd_batch *batch, pm_gcd_result *results, void *stream);
+void pm_gcd_batch_destroy(pm_gcd_batch *batch);
 
 /*
  * GCD server with continuous batching. Requests of mixed degree (up to

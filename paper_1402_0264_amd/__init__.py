@@ -122,6 +122,15 @@ def lib() -> ctypes.CDLL:
     L.pm_radix_sort_u32.argtypes = [_vp, _vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp]
     L.pm_radix_sort_u32.restype = ctypes.c_int32
     L.poly_gcd_modp_batch.argtypes = [ctypes.POINTER(GcdItem), ctypes.c_int32, ctypes.POINTER(GcdResult), _vp]
+    L.pm_gcd_batch_create.argtypes = [ctypes.POINTER(GcdItem), ctypes.c_int32, ctypes.c_int32,
+                                      ctypes.POINTER(ctypes.c_void_p)]
+    L.pm_gcd_batch_create.restype = ctypes.c_int32
+    L.pm_gcd_batch_run.argtypes = [ctypes.c_void_p, _vp]
+    L.pm_gcd_batch_run.restype = ctypes.c_int32
+    L.pm_gcd_batch_results.argtypes = [ctypes.c_void_p, ctypes.POINTER(GcdResult), _vp]
+    L.pm_gcd_batch_results.restype = ctypes.c_int32
+    L.pm_gcd_batch_destroy.argtypes = [ctypes.c_void_p]
+    L.pm_gcd_batch_destroy.restype = None
     L.poly_gcd_modp_batch.restype = ctypes.c_int32
     L.pm_mul_batch_create.argtypes = [ctypes.POINTER(MulItem), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                       ctypes.POINTER(ctypes.c_void_p)]
@@ -344,6 +353,52 @@ class MulBatch:
     def close(self):
         if self.handle:
             lib().pm_mul_batch_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class GcdBatch:
+    """Prepared batch of gcds (pm_gcd_batch_*). ``items`` is a list of
+    (a, b, p) with a, b device tensors; outputs are allocated here. ``run``
+    enqueues at most two launches and may be captured in a CUDA graph;
+    ``results`` returns [(g, result dict)] of the last run."""
+
+    def __init__(self, items, s: int = 0):
+        torch = _torch()
+        self.keep, self.gs = [], []
+        self.count = len(items)
+        arr = (GcdItem * max(self.count, 1))()
+        for i, (a, b, p) in enumerate(items):
+            a, b = _as_u32_tensor(a), _as_u32_tensor(b)
+            cap = max(a.numel(), b.numel(), 1)
+            g = torch.empty(cap, dtype=torch.int32, device=a.device if a.numel() else b.device)
+            self.keep += [a, b]
+            self.gs.append(g)
+            arr[i] = GcdItem(_dev_ptr(a), a.numel(), _dev_ptr(b), b.numel(), p, g.data_ptr(), cap)
+        self.handle = ctypes.c_void_p()
+        _check(lib().pm_gcd_batch_create(arr, self.count, s, ctypes.byref(self.handle)))
+
+    def run(self, stream=None):
+        _check(lib().pm_gcd_batch_run(self.handle, _stream_handle(stream)))
+
+    def results(self, stream=None):
+        res = (GcdResult * max(self.count, 1))()
+        _check(lib().pm_gcd_batch_results(self.handle, res, _stream_handle(stream)))
+        out = []
+        for i in range(self.count):
+            r = res[i]
+            out.append((self.gs[i][:r.ng], {"status": r.status, "ng": r.ng, "steps": r.steps,
+                                            "updates": r.updates, "chunks": r.chunks}))
+        return out
+
+    def close(self):
+        if self.handle:
+            lib().pm_gcd_batch_destroy(self.handle)
             self.handle = ctypes.c_void_p()
 
     def __del__(self):

@@ -18,6 +18,16 @@
 
 #include <algorithm>
 
+struct pm_gcd_batch {
+    int device = 0;
+    int32_t count = 0;
+    int32_t n_large = 0, n_small = 0;
+    int s = 128;
+    pm::GcdJob* d_jobs = nullptr;
+    int32_t* d_order = nullptr;
+    pm::GcdResult* d_res = nullptr;
+};
+
 struct pm_mul_batch {
     int device = 0;
     int count = 0;
@@ -679,12 +689,19 @@ pm_status poly_gcd_modp_naive(const uint32_t* a, int64_t na, const uint32_t* b, 
 
 static_assert(sizeof(pm_gcd_result) == sizeof(pm::GcdResult), "result layouts differ");
 
-pm_status poly_gcd_modp_batch(const pm_gcd_item* items, int32_t count, pm_gcd_result* results, void* stream) {
-    if (count < 0 || (count > 0 && (!items || !results))) return fail(PM_EINVAL, "bad item or result array");
-    if (count == 0) return PM_OK;
-    hipStream_t s = (hipStream_t)stream;
-    std::vector<pm::GcdJob> jobs((size_t)count);
-    std::vector<int32_t> small, large;
+}  // extern "C"
+
+namespace {
+
+// Checks every item of a gcd batch on the host and builds its jobs (out
+// pointers left null) and the launch order: the items of the 1024-thread
+// shape, then those of the 256-thread shape, each longest first (by
+// na * nb; blocks start in index order, so the longest start first).
+pm_status gcd_batch_jobs(const pm_gcd_item* items, int32_t count, std::vector<pm::GcdJob>& jobs,
+                         std::vector<int32_t>& large, std::vector<int32_t>& small) {
+    jobs.assign((size_t)count, pm::GcdJob{});
+    large.clear();
+    small.clear();
     for (int32_t i = 0; i < count; i++) {
         const pm_gcd_item& it = items[i];
         if (bad_len(it.a, it.na) || bad_len(it.b, it.nb) || it.g_cap < 0 || (it.g_cap > 0 && !it.g))
@@ -698,6 +715,28 @@ pm_status poly_gcd_modp_batch(const pm_gcd_item* items, int32_t count, pm_gcd_re
         if (!redc_ok(it.p)) return fail(PM_EMODULUS, "item %d: p = 2 is not supported by the gcd", i);
         jobs[i] = pm::GcdJob{it.a, it.b, it.na, it.nb, it.g, it.g_cap, nullptr, F, 0, 0};
         (n <= pm::gcd_batch_cap(0) ? small : large).push_back(i);
+    }
+    auto longest_first = [items](int32_t x, int32_t y) {
+        return (double)items[x].na * (double)items[x].nb > (double)items[y].na * (double)items[y].nb;
+    };
+    std::stable_sort(large.begin(), large.end(), longest_first);
+    std::stable_sort(small.begin(), small.end(), longest_first);
+    return PM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pm_status poly_gcd_modp_batch(const pm_gcd_item* items, int32_t count, pm_gcd_result* results, void* stream) {
+    if (count < 0 || (count > 0 && (!items || !results))) return fail(PM_EINVAL, "bad item or result array");
+    if (count == 0) return PM_OK;
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<pm::GcdJob> jobs;
+    std::vector<int32_t> small, large;
+    {
+        pm_status st0 = gcd_batch_jobs(items, count, jobs, large, small);
+        if (st0) return st0;
     }
     // scratch: jobs | order | results
     const int64_t job_words = ((int64_t)count * (int64_t)sizeof(pm::GcdJob) + 3) / 4;
@@ -728,6 +767,77 @@ pm_status poly_gcd_modp_batch(const pm_gcd_item* items, int32_t count, pm_gcd_re
             "copy results");
     HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
     return PM_OK;
+}
+
+pm_status pm_gcd_batch_create(const pm_gcd_item* items, int32_t count, int32_t s, pm_gcd_batch** out) {
+    if (!out || count < 0 || (count > 0 && !items)) return fail(PM_EINVAL, "bad arguments");
+    if (s < 0 || s > 256) return fail(PM_EINVAL, "s must be in [0, 256]");
+    *out = nullptr;
+    std::vector<pm::GcdJob> jobs;
+    std::vector<int32_t> small, large;
+    pm_status st = gcd_batch_jobs(items, count, jobs, large, small);
+    if (st) return st;
+    pm_gcd_batch* B = new pm_gcd_batch();
+    HIP_TRY(hipGetDevice(&B->device), "hipGetDevice");
+    B->count = count;
+    B->n_large = (int32_t)large.size();
+    B->n_small = (int32_t)small.size();
+    B->s = s > 0 ? s : 128;
+    const size_t n = (size_t)(count > 0 ? count : 1);
+    if (hipMalloc((void**)&B->d_jobs, n * sizeof(pm::GcdJob)) != hipSuccess ||
+        hipMalloc((void**)&B->d_order, n * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc((void**)&B->d_res, n * sizeof(pm::GcdResult)) != hipSuccess) {
+        pm_gcd_batch_destroy(B);
+        return fail(PM_ENOMEM, "cannot allocate the batch");
+    }
+    for (int32_t i = 0; i < count; i++) jobs[(size_t)i].out = B->d_res + i;
+    std::vector<int32_t> order;
+    order.insert(order.end(), large.begin(), large.end());
+    order.insert(order.end(), small.begin(), small.end());
+    if ((count > 0 && (hipMemcpy(B->d_jobs, jobs.data(), (size_t)count * sizeof(pm::GcdJob),
+                                 hipMemcpyHostToDevice) != hipSuccess ||
+                       hipMemcpy(B->d_order, order.data(), (size_t)count * sizeof(int32_t),
+                                 hipMemcpyHostToDevice) != hipSuccess)) ||
+        hipMemset(B->d_res, 0, n * sizeof(pm::GcdResult)) != hipSuccess) {
+        pm_gcd_batch_destroy(B);
+        return fail(PM_EDEVICE, "cannot upload the batch");
+    }
+    *out = B;
+    return PM_OK;
+}
+
+pm_status pm_gcd_batch_run(pm_gcd_batch* B, void* stream) {
+    if (!B) return fail(PM_EINVAL, "null batch");
+    hipStream_t hs = (hipStream_t)stream;
+    if (B->n_large > 0)
+        HIP_TRY(pm::gcd_batch_launch(B->d_jobs, B->d_order, B->n_large, 1, B->s, hs), "gcd batch launch");
+    if (B->n_small > 0)
+        HIP_TRY(pm::gcd_batch_launch(B->d_jobs, B->d_order + B->n_large, B->n_small, 0, B->s, hs),
+                "gcd batch launch");
+    return PM_OK;
+}
+
+pm_status pm_gcd_batch_results(pm_gcd_batch* B, pm_gcd_result* results, void* stream) {
+    if (!B || (B->count > 0 && !results)) return fail(PM_EINVAL, "null argument");
+    if (B->count == 0) return PM_OK;
+    hipStream_t hs = (hipStream_t)stream;
+    HIP_TRY(hipMemcpyAsync(results, B->d_res, (size_t)B->count * sizeof(pm::GcdResult), hipMemcpyDeviceToHost, hs),
+            "copy results");
+    HIP_TRY(hipStreamSynchronize(hs), "hipStreamSynchronize");
+    return PM_OK;
+}
+
+void pm_gcd_batch_destroy(pm_gcd_batch* B) {
+    if (!B) return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(B->device);
+    (void)hipDeviceSynchronize();
+    if (B->d_jobs) (void)hipFree(B->d_jobs);
+    if (B->d_order) (void)hipFree(B->d_order);
+    if (B->d_res) (void)hipFree(B->d_res);
+    (void)hipSetDevice(cur);
+    delete B;
 }
 
 }  // extern "C"

@@ -470,6 +470,7 @@ __device__ void gcd_instance(const GcdJob& J, int s, int64_t cap, uint32_t* smem
         if (tid == 0) {
             J.out->status = n > cap ? -1 : -3;
             J.out->ng = 0;
+            J.out->steps = J.out->updates = J.out->chunks = 0;
             __threadfence_system();
             __hip_atomic_store(&J.out->done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
         }

@@ -110,6 +110,42 @@ def tune_mul_batch(items, candidates=BATCH_CANDIDATES, reps: int = 3, use_cache:
     return rec
 
 
+GCD_S_CANDIDATES = (16, 32, 64, 128, 256)
+
+
+def tune_gcd_batch(items, candidates=GCD_S_CANDIDATES, reps: int = 2, use_cache: bool = True) -> dict:
+    """Pick s (division steps per chunk) for a batch of gcds (list of (a, b,
+    p) device tensors), beside the model's s* for the batch's largest
+    instance (the minimiser of the printed T_s over real s; its optimised
+    gcd needs 6s <= Z words of local memory). Returns {"s", "ms", "trials",
+    "model_s_star", "model_s_feasible_max", "cached"}."""
+    import paper_1402_0264_amd as pm
+    from paper_1402_0264_amd import mmm
+    sig = batch_signature(items).replace("mul_batch", "gcd_batch")
+    key = sig + ":" + _device_name()
+    if use_cache:
+        rec = _load().get(key)
+        if rec:
+            rec = dict(rec)
+            rec["cached"] = True
+            return rec
+    trials = []
+    for sv in candidates:
+        b = pm.GcdBatch(items, sv)
+        ms = _time(b.run, reps)
+        b.close()
+        trials.append({"s": sv, "ms": round(ms, 4)})
+    best = min(trials, key=lambda t: t["ms"])
+    n = max(max(a.numel(), b.numel()) for a, b, _ in items) - 1
+    rec = {"s": best["s"], "ms": best["ms"], "trials": trials,
+           "model_s_star": round(mmm.gcd_s_star(n, n - 1, mmm.U_THROUGHPUT), 1),
+           "model_s_feasible_max": mmm.Z_MI355X // 6}
+    _store(key, rec)
+    rec = dict(rec)
+    rec["cached"] = False
+    return rec
+
+
 def params_of(rec: dict) -> dict:
     """pm.set_params keywords for a tune_mul result."""
     import paper_1402_0264_amd as pm

@@ -699,6 +699,50 @@ def _served_requests(count, seed, lo=8, hi=6000):
     return reqs
 
 
+def test_gcd_batch_graph_replay():
+    # the prepared gcd batch: two block shapes, three primes, one bad item,
+    # run eagerly and then replayed from a captured graph with eager work
+    # in between; every replay gives the oracle's gcds and counts again
+    import torch
+    reqs = _served_requests(40, 506, lo=8, hi=6000)
+    bad_a = reqs[5][0].copy()
+    bad_a[0] = reqs[5][2]
+    reqs[5] = (bad_a, reqs[5][1], reqs[5][2])
+    want = [oracle.gcd(a, b, p, with_info=True) if i != 5 else None for i, (a, b, p) in enumerate(reqs)]
+    batch = pm.GcdBatch([(dev(a), dev(b), p) for a, b, p in reqs], s=64)
+
+    def check(tag):
+        for i, (g, r) in enumerate(batch.results()):
+            if i == 5:
+                assert r["status"] == pm.PM_ERANGE, tag
+                continue
+            wg, degs, stats = want[i]
+            assert r["status"] == 0 and same(host(g), wg), (tag, i)
+            assert r["steps"] == stats.steps and r["updates"] == stats.updates, (tag, i)
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        batch.run(stream=side)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    check("eager")
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        batch.run()
+    x = torch.arange(1 << 16, device="cuda", dtype=torch.int64)
+    for rep in range(3):
+        for g in batch.gs:
+            g.fill_(-1)
+        y = (x * rep).sum()              # the program's own work between replays
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert int(y) == rep * ((1 << 16) * ((1 << 16) - 1) // 2)
+        check("replay %d" % rep)
+    batch.close()
+
+
 def test_server_results_same_alone_and_in_the_mix():
     reqs = _served_requests(48, 501) + _served_requests(3, 502, lo=5000, hi=16000)
     want = [oracle.gcd(a, b, p) for a, b, p in reqs]
