@@ -527,6 +527,27 @@ def test_xgcd_workload_32768_certificate():
         assert oracle.mul_coeff(hs, ha, p, int(k)) == int(host(sa)[k])
 
 
+@pytest.mark.parametrize("p", [3, gen.P_A])
+def test_gcd_grid_big_steps_and_rescans(p):
+    # the cooperative kernel at several blocks: degree gaps of 64-127 (no
+    # leading division, so the first steps are single big steps through
+    # the grid), and at p = 3 frequent vanishing leading coefficients
+    # (chunks that end with an unknown degree and a rescan); the gcd, the
+    # counts and the extended gcd's cofactors are the oracle's
+    st = gen.Stream(308 + p % 997)
+    for da, db, dg in [(6000, 5900, 40), (5900, 6000, 40), (3000, 2936, 7), (9000, 8999, 500)]:
+        pl = gen.planted_gcd(da, db, dg, p, st)
+        a, b = oracle.mul(pl.g, pl.u, p), oracle.mul(pl.g, pl.v, p)
+        g = host(pm.gcd(dev(a), dev(b), p))
+        want, degs, stats = oracle.gcd(a, b, p, with_info=True)
+        assert same(g, want), (p, da, db)
+        got = pm.last_gcd_stats()
+        assert got["steps"] == stats.steps and got["updates"] == stats.updates, (p, da, db)
+        gx, sx, tx = (host(y) for y in pm.xgcd(dev(a), dev(b), p))
+        wg, ws, wt = oracle.xgcd(a, b, p)
+        assert same(gx, wg) and same(sx, ws) and same(tx, wt), (p, da, db, "xgcd")
+
+
 def test_gcd_edge_cases():
     p = gen.P_A
     st = gen.Stream(303)
