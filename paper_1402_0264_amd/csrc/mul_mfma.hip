@@ -583,7 +583,8 @@ hipError_t mulx_launch(const uint32_t* a, int64_t na, const uint32_t* b, int64_t
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    TimingScope ts("mulx_reduce_kernel", stream);
+    // no timing events around the addition phase: events between the two
+    // kernels put a gap of several microseconds into every product
     hipLaunchKernelGGL(mulx_reduce_kernel, dim3((unsigned)(g.nkr * MX_RED_BLOCKS + 1)), dim3(256), 0, stream, A);
     return hipGetLastError();
 }
