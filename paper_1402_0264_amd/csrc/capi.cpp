@@ -239,8 +239,11 @@ bool use_mfma(int64_t na, int64_t nb) {
     if (pp.mul_engine == 1) return false;
     if (pp.mul_engine == 2) return true;
     if (pp.mul_s > 0 || pp.mul_r > 0) return false;
+    // measured on graph-replayed products: below about 6400 x 6400 the VALU
+    // tiles finish first (the matrix-core engine has a fixed cost of about
+    // 15 us: staging, stream-K shares, the addition phase)
     const int64_t lo = na < nb ? na : nb;
-    return lo >= 256 && (double)na * (double)nb >= 4194304.0;
+    return lo >= 256 && (double)na * (double)nb >= 40.0e6;
 }
 
 pm_status mul_enqueue(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, const pm::Field& F,

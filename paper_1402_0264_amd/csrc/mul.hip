@@ -382,6 +382,16 @@ int64_t mul_scratch_words(int64_t na, int64_t nb, const MulPlan& plan) {
 MulPlan mul_default_plan(int64_t na, int64_t nb, int num_cus) {
     MulPlan best{1, 64};
     if (na <= 0 || nb <= 0) return best;
+    // products the matrix cores do not take (below about 40M coefficient
+    // products): 4 outputs per thread and short b-chunks, as measured on
+    // graph-replayed square products of 256 to 6144 terms
+    const int64_t lo = na < nb ? na : nb;
+    if ((double)na * (double)nb < 40.0e6) {
+        if (lo <= 256) return MulPlan{2, 64};
+        if (lo <= 512) return MulPlan{4, 64};
+        if (lo <= 3072) return MulPlan{4, 128};
+        return MulPlan{4, 256};
+    }
     const int64_t target = 4LL * num_cus;
     static const int Rs[] = {16, 8, 4, 2, 1};
     static const int64_t KCs[] = {2048, 1024, 512, 256, 128, 64, 32};
