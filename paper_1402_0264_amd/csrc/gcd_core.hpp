@@ -125,110 +125,129 @@ __device__ __forceinline__ void count_zero_steps(StepLog* L, int dX, int dY, int
 
 // Head run by one whole wave. hA/hB: the heads (entry i = coefficient of
 // x^(deg - i)), exact for i < 64*E. Each step reduces the operand of higher
-// degree (chosen with uniform selects, not two copies of the code; the run's
-// state is kept in scalar registers) and is published in desc[] for the M
-// builder on another wave (m_build_live).
+// degree (A on a tie). The run keeps the heads and their scalar state by
+// role, X the operand reduced next and Y the other, so a step reads no
+// select; the roles swap when the degrees cross. Each step is published in
+// desc[] for the M builder on another wave (m_build_live).
 // Returns the chunk summary through *out (lane 0 writes) and the step
 // count and big flag in n_out / big_out; a big step is desc[0].
 template <int E>
-__device__ void head_run_log(uint32_t (&hA)[E], uint32_t (&hB)[E], int dA, int dB, int s, const Field& F,
-                             StepDesc* desc, StepLog* L, ChunkOut* out, int& n_out, int& big_out) {
+__device__ void head_run_log(const uint32_t (&hA)[E], const uint32_t (&hB)[E], int dA, int dB, int s,
+                             const Field& F, StepDesc* desc, StepLog* L, ChunkOut* out, int& n_out,
+                             int& big_out) {
     const int lane = threadIdx.x & 63;
     constexpr int H = 64 * E;
-    dA = uni(dA);
-    dB = uni(dB);
     s = uni(s);
-    int vA = H, vB = H, S = 0, n = 0, unkA = 0, unkB = 0, big = 0;
+    bool xa = uni(dA) >= uni(dB);
+    uint32_t hX[E], hY[E];
+#pragma unroll
+    for (int e = 0; e < E; e++) {
+        hX[e] = xa ? hA[e] : hB[e];
+        hY[e] = xa ? hB[e] : hA[e];
+    }
+    // the run's state is wave-uniform and stays in scalar registers, so the
+    // loop and its branches stay scalar (no exec masking)
+    int dX = uni(xa ? dA : dB), dY = uni(xa ? dB : dA);
+    int vX = H, vY = H, S = 0, n = 0, unkA = 0, unkB = 0, big = 0;
+    uint32_t lcX = (uint32_t)__builtin_amdgcn_readfirstlane((int)hX[0]);
+    uint32_t lcY = (uint32_t)__builtin_amdgcn_readfirstlane((int)hY[0]);
     int64_t upd = 0;
     for (;;) {
-        // the run's state is wave-uniform: keep it in scalar registers, so
-        // that the loop and its branches stay scalar (no exec masking)
-        dA = uni(dA);
-        dB = uni(dB);
-        vA = uni(vA);
-        vB = uni(vB);
-        S = uni(S);
-        n = uni(n);
-        if (!(n < s && dA >= 0 && dB >= 0)) break;
-        const bool redA = dA >= dB;
-        const int d = redA ? dA - dB : dB - dA;
+        if (!(n < s && dY >= 0)) break;  // dX >= dY
+        const int d = dX - dY;
         if (S + d > GCD_MAXSHIFT) {
             if (n > 0) break;
             big = 1;  // one step alone, applied directly
         }
-        const uint32_t lcA = (uint32_t)__builtin_amdgcn_readfirstlane((int)hA[0]);
-        const uint32_t lcB = (uint32_t)__builtin_amdgcn_readfirstlane((int)hB[0]);
-        const uint32_t m1 = redA ? lcB : lcA;
-        const uint32_t m2 = F.p - (redA ? lcA : lcB);
-        if (lane == 0) desc[n] = StepDesc{m1, m2, d, redA ? 0 : 1};
-        const int v = vA < vB ? vA : vB;
+        const uint32_t m1 = lcY;
+        const uint32_t m2 = F.p - lcX;
+        if (lane == 0) desc[n] = StepDesc{m1, m2, d, xa ? 0 : 1};
+        const int v = vX < vY ? vX : vY;
         // X <- REDC(m1 X + m2 Y) on the heads; entries at or beyond v cleared
         uint32_t x[E];
-        unsigned long long msk[E];
 #pragma unroll
         for (int e = 0; e < E; e++) {
-            const uint32_t X = redA ? hA[e] : hB[e];
-            const uint32_t Y = redA ? hB[e] : hA[e];
-            uint32_t t = redc((uint64_t)m1 * X + (uint64_t)m2 * Y, F);
-            t = lane + 64 * e < v ? t : 0u;
-            x[e] = t;
-            msk[e] = __ballot(t != 0);
+            const uint32_t t = redc((uint64_t)m1 * hX[e] + (uint64_t)m2 * hY[e], F);
+            x[e] = lane + 64 * e < v ? t : 0u;
         }
-        msk[0] &= ~1ull;  // entry 0 is the cancelled leading coefficient
-        int delta = 0;
-#pragma unroll
-        for (int e = E - 1; e >= 0; e--)
-            if (msk[e]) delta = 64 * e + (int)__builtin_ctzll(msk[e]);
+        // entry 0 cancelled; entry 1 leads unless it vanished too
+        const uint32_t next_lc = (uint32_t)__builtin_amdgcn_readlane((int)x[0], 1);
         n++;
         // publish the step once its record has long been written (the release
         // then finds no LDS store of this step outstanding)
         if (lane == 0) __hip_atomic_store(&L->prog, n, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (!big) S += d;
-        upd += (redA ? dB : dA) + 1;
+        upd += dY + 1;
         int nd, nv;
-        const int dX = redA ? dA : dB;
-        const int dY = redA ? dB : dA;
-        if (__builtin_expect(delta == 1, 1)) {
+        uint32_t nlc;
+        if (__builtin_expect(next_lc != 0u, 1)) {
             head_shift1<E>(x);
             nd = dX - 1;
             nv = v - 1;
-        } else if (delta > 1) {
-            // positions below deg X vanished too: shift them out, and count
-            // the zero-multiplier steps among them (in LDS, so the common
-            // path keeps no extra scalar state)
-            for (int k = 0; k < delta; k++) head_shift1<E>(x);
-            nd = dX - delta;
-            nv = v - delta;
-            if (lane == 0) count_zero_steps(L, dX, dY, nd);
+            nlc = next_lc;
         } else {
-            // the first v entries vanished: deg X <= old deg - v
-            nd = dX - v;
-            nv = 0;
-            if (nd < 0) {
-                nd = -1;
+            int delta = 0;
+#pragma unroll
+            for (int e = E - 1; e >= 0; e--) {
+                unsigned long long msk = __ballot(x[e] != 0u);
+                if (e == 0) msk &= ~1ull;
+                if (msk) delta = 64 * e + (int)__builtin_ctzll(msk);
+            }
+            if (delta > 1) {
+                // positions below deg X vanished too: shift them out, and
+                // count the zero-multiplier steps among them (in LDS, so the
+                // common path keeps no extra scalar state)
+                for (int k = 0; k < delta; k++) head_shift1<E>(x);
+                nd = dX - delta;
+                nv = v - delta;
+                nlc = (uint32_t)__builtin_amdgcn_readfirstlane((int)x[0]);
                 if (lane == 0) count_zero_steps(L, dX, dY, nd);
             } else {
-                if (redA) unkA = 1;
-                else unkB = 1;
-                if (lane == 0) {  // the zero steps wait for the true degree
-                    out->zX = dX;
-                    out->zY = dY;
+                // the first v entries vanished: deg X <= old deg - v
+                nd = dX - v;
+                nv = 0;
+                nlc = 0u;
+                if (nd < 0) {
+                    nd = -1;
+                    if (lane == 0) count_zero_steps(L, dX, dY, nd);
+                } else {
+                    if (xa) unkA = 1;
+                    else unkB = 1;
+                    if (lane == 0) {  // the zero steps wait for the true degree
+                        out->zX = dX;
+                        out->zY = dY;
+                    }
                 }
             }
         }
+        // the next step reduces the operand of higher degree, A on a tie
+        if (nd > dY || (nd == dY && xa)) {
 #pragma unroll
-        for (int e = 0; e < E; e++) {
-            hA[e] = redA ? x[e] : hA[e];
-            hB[e] = redA ? hB[e] : x[e];
+            for (int e = 0; e < E; e++) hX[e] = x[e];
+            dX = nd;
+            vX = nv;
+            lcX = nlc;
+        } else {
+#pragma unroll
+            for (int e = 0; e < E; e++) {
+                hX[e] = hY[e];
+                hY[e] = x[e];
+            }
+            dX = dY;
+            dY = nd;
+            vX = vY;
+            vY = nv;
+            lcX = lcY;
+            lcY = nlc;
+            xa = !xa;
         }
-        if (redA) { dA = nd; vA = nv; } else { dB = nd; vB = nv; }
         if (unkA | unkB | big) break;
     }
     n_out = n;
     big_out = big;
     if (lane == 0) {
-        out->dA = dA;
-        out->dB = dB;
+        out->dA = xa ? dX : dY;
+        out->dB = xa ? dY : dX;
         out->upd = upd + L->zupd;
         out->nsteps = n;
         out->S = S;
