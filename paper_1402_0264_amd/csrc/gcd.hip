@@ -108,11 +108,23 @@ __device__ void heads_after_chunk(const uint32_t* A, const uint32_t* B, int64_t 
     constexpr int WH = 64 * E + 64;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t baseA = ndA - WH + 1, baseB = ndB - WH + 1;
-    for (int x = tid; x < 4 * WH; x += GCD_THREADS) {
+    // every load of a thread is issued before the first is waited for: the
+    // windows were just written by other blocks, so each is a full trip to
+    // memory, and this is on the path of every chunk
+    constexpr int PER = (4 * WH + GCD_THREADS - 1) / GCD_THREADS;
+    uint32_t v[PER];
+#pragma unroll
+    for (int j = 0; j < PER; j++) {
+        const int x = tid + j * GCD_THREADS;
         const int win = x / WH, off = x - win * WH;
         const int64_t P = (win < 2 ? baseA : baseB) + off;
         const uint32_t* src = (win & 1) ? B : A;
-        hw[x] = P >= 0 ? src[P] : 0u;
+        v[j] = (x < 4 * WH && P >= 0) ? src[P] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < PER; j++) {
+        const int x = tid + j * GCD_THREADS;
+        if (x < 4 * WH) hw[x] = v[j];
     }
     __syncthreads();
     const int row = wave / E, e = wave - row * E;  // row 0: A, 1: B

@@ -161,7 +161,14 @@ __device__ void head_run_log(const uint32_t (&hA)[E], const uint32_t (&hB)[E], i
         }
         const uint32_t m1 = lcY;
         const uint32_t m2 = F.p - lcX;
-        if (lane == 0) desc[n] = StepDesc{m1, m2, d, xa ? 0 : 1};
+        // publish the steps before this one, then record this one: the
+        // release waits for this wave's LDS stores, and the last of them was
+        // issued a whole step ago (publishing a step right after its record
+        // would wait out the LDS write latency on every step)
+        if (lane == 0) {
+            __hip_atomic_store(&L->prog, n, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            desc[n] = StepDesc{m1, m2, d, xa ? 0 : 1};
+        }
         const int v = vX < vY ? vX : vY;
         // X <- REDC(m1 X + m2 Y) on the heads; entries at or beyond v cleared
         uint32_t x[E];
@@ -173,9 +180,6 @@ __device__ void head_run_log(const uint32_t (&hA)[E], const uint32_t (&hB)[E], i
         // entry 0 cancelled; entry 1 leads unless it vanished too
         const uint32_t next_lc = (uint32_t)__builtin_amdgcn_readlane((int)x[0], 1);
         n++;
-        // publish the step once its record has long been written (the release
-        // then finds no LDS store of this step outstanding)
-        if (lane == 0) __hip_atomic_store(&L->prog, n, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (!big) S += d;
         upd += dY + 1;
         int nd, nv;
@@ -273,8 +277,11 @@ __device__ void m_build_live(const StepDesc* desc, StepLog* L, const Field& F, u
     uint32_t al = lane == 0 ? 1u : 0u, be = 0u, ga = 0u, de = lane == 0 ? 1u : 0u;
     int k = 0;
     for (;;) {
+        // end, once set, publishes every step (the run's last step is
+        // published by end alone); before that, prog is the count
         const int end = uni(__hip_atomic_load(&L->end, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP));
-        const int avail = uni(__hip_atomic_load(&L->prog, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP));
+        const int avail =
+            end >= 0 ? end : uni(__hip_atomic_load(&L->prog, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP));
         for (; k < avail; k++) {
             const StepDesc D = desc[k];
             const uint32_t m1 = uni(D.m1), m2 = uni(D.m2);
