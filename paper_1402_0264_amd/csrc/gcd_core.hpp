@@ -91,13 +91,6 @@ __device__ __forceinline__ void head_shift1(uint32_t (&h)[E]) {
     }
 }
 
-// lane i <- lane i-d of x (0 for i < d); d uniform, 0 <= d < 64
-__device__ __forceinline__ uint32_t lanes_up_any(uint32_t x, int d) {
-    if (d == 0) return x;
-    if (d == 1) return lanes_up1(x);
-    return lanes_up(x, d);
-}
-
 // Progress of a head run, read by the wave that composes M while the run
 // goes on. Reset (prog = 0, end = -1) before every run, behind a barrier.
 struct StepLog {
@@ -152,13 +145,13 @@ __device__ void head_run_log(const uint32_t (&hA)[E], const uint32_t (&hB)[E], i
     uint32_t lcX = (uint32_t)__builtin_amdgcn_readfirstlane((int)hX[0]);
     uint32_t lcY = (uint32_t)__builtin_amdgcn_readfirstlane((int)hY[0]);
     int64_t upd = 0;
-    for (;;) {
-        if (!(n < s && dY >= 0)) break;  // dX >= dY
-        const int d = dX - dY;
-        if (S + d > GCD_MAXSHIFT) {
-            if (n > 0) break;
-            big = 1;  // one step alone, applied directly
-        }
+    // a first step whose shift alone exceeds MAXSHIFT is taken alone and
+    // applied directly (big); later steps stop the run before such a shift
+    if (s > 0 && dY >= 0 && dX - dY > GCD_MAXSHIFT) big = 1;
+    // one exit test per step, at its end (a single scalar sign test: every
+    // term is >= 0 exactly when the run goes on)
+    if (s > 0 && dY >= 0) do {
+        const int d = dX - dY;  // dX >= dY
         const uint32_t m1 = lcY;
         const uint32_t m2 = F.p - lcX;
         // publish the steps before this one, then record this one: the
@@ -245,8 +238,7 @@ __device__ void head_run_log(const uint32_t (&hA)[E], const uint32_t (&hB)[E], i
             lcY = nlc;
             xa = !xa;
         }
-        if (unkA | unkB | big) break;
-    }
+    } while (((s - 1 - n) | dY | (GCD_MAXSHIFT - S - (dX - dY)) | -(unkA | unkB | big)) >= 0);
     n_out = n;
     big_out = big;
     if (lane == 0) {
@@ -267,6 +259,20 @@ __device__ void head_run_log(const uint32_t (&hA)[E], const uint32_t (&hB)[E], i
     }
 }
 
+// One step on M's rows: (P, Q) <- m1 (P, Q) + m2 x^d (R, T).
+__device__ __forceinline__ void m_row_step(uint32_t& P, uint32_t& Q, uint32_t R, uint32_t T, uint32_t m1,
+                                           uint32_t m2, int d, const Field& F) {
+    if (d == 1) {
+        R = lanes_up1(R);
+        T = lanes_up1(T);
+    } else if (d != 0) {
+        R = lanes_up(R, d);
+        T = lanes_up(T, d);
+    }
+    P = redc((uint64_t)m1 * P + (uint64_t)m2 * R, F);
+    Q = redc((uint64_t)m1 * Q + (uint64_t)m2 * T, F);
+}
+
 // Composes M from the steps of a head run while it goes on (one whole
 // wave, lane k = coefficient k of alpha, beta, gamma, delta): each published
 // step (rows of X) <- REDC(m1 (rows of X) + m2 x^d (rows of Y)) is applied
@@ -282,20 +288,18 @@ __device__ void m_build_live(const StepDesc* desc, StepLog* L, const Field& F, u
         const int end = uni(__hip_atomic_load(&L->end, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP));
         const int avail =
             end >= 0 ? end : uni(__hip_atomic_load(&L->prog, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP));
-        for (; k < avail; k++) {
-            const StepDesc D = desc[k];
-            const uint32_t m1 = uni(D.m1), m2 = uni(D.m2);
-            const int d = uni(D.d);
-            const bool redA = uni(D.which) == 0;
-            const uint32_t P = redA ? al : ga, Q = redA ? be : de;
-            const uint32_t R = lanes_up_any(redA ? ga : al, d);
-            const uint32_t T = lanes_up_any(redA ? de : be, d);
-            const uint32_t P2 = redc((uint64_t)m1 * P + (uint64_t)m2 * R, F);
-            const uint32_t Q2 = redc((uint64_t)m1 * Q + (uint64_t)m2 * T, F);
-            al = redA ? P2 : al;
-            be = redA ? Q2 : be;
-            ga = redA ? ga : P2;
-            de = redA ? de : Q2;
+        if (k < avail) {
+            StepDesc D = desc[k];
+            for (;;) {
+                // the next published record is read while this one is applied
+                const StepDesc Dn = desc[k + 1 < avail ? k + 1 : k];
+                const uint32_t m1 = uni(D.m1), m2 = uni(D.m2);
+                const int d = uni(D.d);
+                if (uni(D.which) == 0) m_row_step(al, be, ga, de, m1, m2, d, F);
+                else m_row_step(ga, de, al, be, m1, m2, d, F);
+                if (++k >= avail) break;
+                D = Dn;
+            }
         }
         if (end >= 0 && k >= end) break;
         if (k >= avail) __builtin_amdgcn_s_sleep(1);
