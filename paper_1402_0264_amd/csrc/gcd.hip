@@ -287,20 +287,18 @@ __global__ __launch_bounds__(GCD_THREADS) void gcd_pipe_kernel(GcdArgs G) {
             if (wlo <= top) {
                 if (!res.big) {
                     const int S = res.S;
-                    const int64_t base = wlo - S;
-                    const int len = half + S;
-                    for (int x = lane; x < len; x += 64) {
-                        const int64_t P = base + x;
-                        la[x] = P >= 0 ? Acur[P] : 0u;
-                        lb[x] = P >= 0 ? Bcur[P] : 0u;
-                    }
+                    stage_pair(la, lb, Acur, Bcur, wlo - S, half + S);
                     __builtin_amdgcn_wave_barrier();
-                    for (int x = lane; x < half; x += 64) {
-                        const int64_t P = wlo + x;
-                        uint32_t na_, nb_;
-                        apply_m_at(la, lb, x + S, S, Mc, F, na_, nb_);
-                        Anext[P] = P <= res.dA ? na_ : 0u;
-                        Bnext[P] = P <= res.dB ? nb_ : 0u;
+                    // half is a multiple of 256: four positions per lane at a time
+                    for (int x0 = 0; x0 < half; x0 += 256) {
+                        uint32_t na_[4], nb_[4];
+                        apply_m_at4(la, lb, x0 + lane + S, S, Mc, F, na_, nb_);
+#pragma unroll
+                        for (int j = 0; j < 4; j++) {
+                            const int64_t P = wlo + x0 + lane + 64 * j;
+                            Anext[P] = P <= res.dA ? na_[j] : 0u;
+                            Bnext[P] = P <= res.dB ? nb_[j] : 0u;
+                        }
                     }
                 } else {
                     const StepDesc D = desc[0];
@@ -330,20 +328,17 @@ __global__ __launch_bounds__(GCD_THREADS) void gcd_pipe_kernel(GcdArgs G) {
                 if (wlo <= cdn) {
                     if (!res.big) {
                         const int S = res.S;
-                        const int64_t base = wlo - S;
-                        const int len = half + S;
                         __builtin_amdgcn_wave_barrier();
-                        for (int x = lane; x < len; x += 64) {
-                            const int64_t P = base + x;
-                            la[x] = P >= 0 ? SAc[P] : 0u;
-                            lb[x] = P >= 0 ? SBc[P] : 0u;
-                        }
+                        stage_pair(la, lb, SAc, SBc, wlo - S, half + S);
                         __builtin_amdgcn_wave_barrier();
-                        for (int x = lane; x < half; x += 64) {
-                            uint32_t sa_, sb_;
-                            apply_m_at(la, lb, x + S, S, Mc, F, sa_, sb_);
-                            SAn[wlo + x] = sa_;
-                            SBn[wlo + x] = sb_;
+                        for (int x0 = 0; x0 < half; x0 += 256) {
+                            uint32_t sa_[4], sb_[4];
+                            apply_m_at4(la, lb, x0 + lane + S, S, Mc, F, sa_, sb_);
+#pragma unroll
+                            for (int j = 0; j < 4; j++) {
+                                SAn[wlo + x0 + lane + 64 * j] = sa_[j];
+                                SBn[wlo + x0 + lane + 64 * j] = sb_[j];
+                            }
                         }
                     } else {
                         const StepDesc D = desc[0];
@@ -759,6 +754,8 @@ int64_t gcd_scratch_words(int64_t n, const GcdPlan& plan, bool cofactors) {
 hipError_t gcd_launch(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, const Field& F, uint32_t* g,
                       int64_t g_cap, uint32_t* scratch, CallInfo* info, const GcdPlan& plan, hipStream_t stream,
                       const GcdCofactors* xg) {
+    // each apply wave takes half a slice, four positions per lane at a time
+    if (plan.slice <= 0 || plan.slice % 512 != 0) return hipErrorInvalidValue;
     GcdArgs A{};
     A.a = a; A.b = b; A.na = na; A.nb = nb;
     A.N = gcd_positions(plan);

@@ -335,6 +335,71 @@ __device__ __forceinline__ void apply_m_at(const uint32_t* la, const uint32_t* l
     outB = reduce64(accB, F);
 }
 
+// apply_m_at for the four positions x, x + 64, x + 128 and x + 192 of one
+// lane: each coefficient of M read from LDS serves all four, and the four
+// sums give the loop independent work between its LDS reads.
+__device__ __forceinline__ void apply_m_at4(const uint32_t* la, const uint32_t* lb, int x, int S,
+                                            const uint32_t* M, const Field& F, uint32_t (&outA)[4],
+                                            uint32_t (&outB)[4]) {
+    uint64_t accA[4], accB[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++) accA[j] = accB[j] = 0;
+    uint32_t cnt = 0;
+    const uint32_t half = F.fold_every / 2;
+    S = uni(S);
+    for (int k = 0; k <= S; k++) {
+        const uint32_t ma = M[k], mb = M[64 + k], mc = M[128 + k], md = M[192 + k];
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const uint32_t a = la[x + 64 * j - k], b = lb[x + 64 * j - k];
+            accA[j] += (uint64_t)ma * a;
+            accA[j] += (uint64_t)mb * b;
+            accB[j] += (uint64_t)mc * a;
+            accB[j] += (uint64_t)md * b;
+        }
+        if (++cnt == half) {
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                accA[j] = fold(accA[j], F.c32);
+                accB[j] = fold(accB[j], F.c32);
+            }
+            cnt = 0;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        outA[j] = reduce64(accA[j], F);
+        outB[j] = reduce64(accB[j], F);
+    }
+}
+
+// One wave copies src[base + x] (0 below position 0) into l[x] for x < len,
+// for two arrays at once; all of a lane's loads of a 256-word block are
+// issued before the first is waited for.
+__device__ __forceinline__ void stage_pair(uint32_t* la, uint32_t* lb, const uint32_t* A, const uint32_t* B,
+                                           int64_t base, int len) {
+    const int lane = threadIdx.x & 63;
+    for (int x0 = 0; x0 < len; x0 += 256) {
+        uint32_t va[4], vb[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const int x = x0 + lane + 64 * j;
+            const int64_t P = base + x;
+            const bool in = x < len && P >= 0;
+            va[j] = in ? A[P] : 0u;
+            vb[j] = in ? B[P] : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const int x = x0 + lane + 64 * j;
+            if (x < len) {
+                la[x] = va[j];
+                lb[x] = vb[j];
+            }
+        }
+    }
+}
+
 // One new coefficient: sum_k Ma[k] la[x-k] + Mb[k] lb[x-k], k = 0..S (one
 // row of M applied at local index x; x - k >= 0 guaranteed by the caller).
 __device__ __forceinline__ uint32_t apply_row_at(const uint32_t* la, const uint32_t* lb, int x, int S,
