@@ -292,7 +292,7 @@ __global__ __launch_bounds__(GCD_THREADS) void gcd_pipe_kernel(GcdArgs G) {
                     // half is a multiple of 256: four positions per lane at a time
                     for (int x0 = 0; x0 < half; x0 += 256) {
                         uint32_t na_[4], nb_[4];
-                        apply_m_at4(la, lb, x0 + lane + S, S, Mc, F, na_, nb_);
+                        apply_m_strided<4>(la, lb, x0 + lane + S, 64, x0 + lane + S + 192, S, Mc, F, na_, nb_);
 #pragma unroll
                         for (int j = 0; j < 4; j++) {
                             const int64_t P = wlo + x0 + lane + 64 * j;
@@ -333,7 +333,7 @@ __global__ __launch_bounds__(GCD_THREADS) void gcd_pipe_kernel(GcdArgs G) {
                         __builtin_amdgcn_wave_barrier();
                         for (int x0 = 0; x0 < half; x0 += 256) {
                             uint32_t sa_[4], sb_[4];
-                            apply_m_at4(la, lb, x0 + lane + S, S, Mc, F, sa_, sb_);
+                            apply_m_strided<4>(la, lb, x0 + lane + S, 64, x0 + lane + S + 192, S, Mc, F, sa_, sb_);
 #pragma unroll
                             for (int j = 0; j < 4; j++) {
                                 SAn[wlo + x0 + lane + 64 * j] = sa_[j];
@@ -450,6 +450,9 @@ __device__ void gcd_instance(const GcdJob& J, int s, int64_t cap, uint32_t* smem
     // wave 0 runs the heads, wave 1 composes M, waves 2.. own the positions
     constexpr int NA = NT - 128;
     constexpr int PPA = (NT * PPT + NA - 1) / NA;
+    // positions per pass of the apply: fewer where 1024 threads leave 128
+    // VGPRs per lane
+    constexpr int AG = NT > 256 ? 2 : 4;
 
     const int64_t n = J.na > J.nb ? J.na : J.nb;
     int bad = n > cap;
@@ -565,11 +568,20 @@ __device__ void gcd_instance(const GcdJob& J, int s, int64_t cap, uint32_t* smem
                     __builtin_amdgcn_s_setprio(0);
                 }
             } else {
+                // G positions at a time share each read of M (a position
+                // above top is read at top; its sum is not stored)
 #pragma unroll
-                for (int j = 0; j < PPA; j++) {
-                    const int P = (tid - 128) + j * NA;
-                    nA[j] = nB[j] = 0u;
-                    if (P <= top) apply_m_at(A, B, P, res.S, Mc, F, nA[j], nB[j]);
+                for (int j0 = 0; j0 < PPA; j0 += AG) {
+                    const int P0 = (tid - 128) + j0 * NA;
+                    uint32_t ga[AG], gb[AG];
+#pragma unroll
+                    for (int j = 0; j < AG; j++) ga[j] = gb[j] = 0u;
+                    if (P0 <= top) apply_m_strided<AG>(A, B, P0, NA, (int)top, res.S, Mc, F, ga, gb);
+#pragma unroll
+                    for (int j = 0; j < AG && j0 + j < PPA; j++) {
+                        nA[j0 + j] = ga[j];
+                        nB[j0 + j] = gb[j];
+                    }
                 }
             }
             __syncthreads();

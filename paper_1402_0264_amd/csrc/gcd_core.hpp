@@ -310,48 +310,33 @@ __device__ void m_build_live(const StepDesc* desc, StepLog* L, const Field& F, u
     M[192 + lane] = de;
 }
 
-// New coefficients at one position: (A'[P], B'[P]) from the chunk-start
-// values A[P-k], B[P-k], k = 0..S, read through la/lb at local index x
-// (x - k >= 0 is guaranteed by the caller's staging).
-__device__ __forceinline__ void apply_m_at(const uint32_t* la, const uint32_t* lb, int x, int S, const uint32_t* M,
-                                           const Field& F, uint32_t& outA, uint32_t& outB) {
-    uint64_t accA = 0, accB = 0;
-    uint32_t cnt = 0;
-    const uint32_t half = F.fold_every / 2;
-    S = uni(S);
-    for (int k = 0; k <= S; k++) {
-        const uint32_t a = la[x - k], b = lb[x - k];
-        accA += (uint64_t)M[k] * a;
-        accA += (uint64_t)M[64 + k] * b;
-        accB += (uint64_t)M[128 + k] * a;
-        accB += (uint64_t)M[192 + k] * b;
-        if (++cnt == half) {
-            accA = fold(accA, F.c32);
-            accB = fold(accB, F.c32);
-            cnt = 0;
-        }
-    }
-    outA = reduce64(accA, F);
-    outB = reduce64(accB, F);
-}
-
-// apply_m_at for the four positions x, x + 64, x + 128 and x + 192 of one
-// lane: each coefficient of M read from LDS serves all four, and the four
-// sums give the loop independent work between its LDS reads.
-__device__ __forceinline__ void apply_m_at4(const uint32_t* la, const uint32_t* lb, int x, int S,
-                                            const uint32_t* M, const Field& F, uint32_t (&outA)[4],
-                                            uint32_t (&outB)[4]) {
-    uint64_t accA[4], accB[4];
+// New coefficients at G positions of one lane: (A'[P], B'[P]) is the sum
+// over k = 0..S of M's coefficients k times the chunk-start A[P-k], B[P-k],
+// read through la/lb at local index x + stride*j (j < G) clamped to xmax (a
+// clamped position's sum is not used; the caller's staging or padding
+// covers the indexes down to x - S). Each coefficient of M read from LDS
+// serves all G positions, and the G sums give the loop independent work
+// between its LDS reads.
+template <int G>
+__device__ __forceinline__ void apply_m_strided(const uint32_t* la, const uint32_t* lb, int x, int stride, int xmax,
+                                                int S, const uint32_t* M, const Field& F, uint32_t (&outA)[G],
+                                                uint32_t (&outB)[G]) {
+    uint64_t accA[G], accB[G];
+    int xs[G];
 #pragma unroll
-    for (int j = 0; j < 4; j++) accA[j] = accB[j] = 0;
+    for (int j = 0; j < G; j++) {
+        accA[j] = accB[j] = 0;
+        const int xj = x + stride * j;
+        xs[j] = xj < xmax ? xj : xmax;
+    }
     uint32_t cnt = 0;
     const uint32_t half = F.fold_every / 2;
     S = uni(S);
     for (int k = 0; k <= S; k++) {
         const uint32_t ma = M[k], mb = M[64 + k], mc = M[128 + k], md = M[192 + k];
 #pragma unroll
-        for (int j = 0; j < 4; j++) {
-            const uint32_t a = la[x + 64 * j - k], b = lb[x + 64 * j - k];
+        for (int j = 0; j < G; j++) {
+            const uint32_t a = la[xs[j] - k], b = lb[xs[j] - k];
             accA[j] += (uint64_t)ma * a;
             accA[j] += (uint64_t)mb * b;
             accB[j] += (uint64_t)mc * a;
@@ -359,7 +344,7 @@ __device__ __forceinline__ void apply_m_at4(const uint32_t* la, const uint32_t* 
         }
         if (++cnt == half) {
 #pragma unroll
-            for (int j = 0; j < 4; j++) {
+            for (int j = 0; j < G; j++) {
                 accA[j] = fold(accA[j], F.c32);
                 accB[j] = fold(accB[j], F.c32);
             }
@@ -367,7 +352,7 @@ __device__ __forceinline__ void apply_m_at4(const uint32_t* la, const uint32_t* 
         }
     }
 #pragma unroll
-    for (int j = 0; j < 4; j++) {
+    for (int j = 0; j < G; j++) {
         outA[j] = reduce64(accA[j], F);
         outB[j] = reduce64(accB[j], F);
     }
