@@ -287,12 +287,18 @@ __global__ __launch_bounds__(GCD_THREADS) void gcd_pipe_kernel(GcdArgs G) {
             if (wlo <= top) {
                 if (!res.big) {
                     const int S = res.S;
+                    // the extended variant (twice the apply) takes M's rows from
+                    // registers and reads only its windows from LDS; measured, the
+                    // plain one runs faster with M read from LDS
+                    uint32_t mreg[4];
+#pragma unroll
+                    for (int r = 0; r < 4; r++) mreg[r] = XG ? Mc[64 * r + lane] : 0u;
                     stage_pair(la, lb, Acur, Bcur, wlo - S, half + S);
                     __builtin_amdgcn_wave_barrier();
                     // half is a multiple of 256: four positions per lane at a time
                     for (int x0 = 0; x0 < half; x0 += 256) {
                         uint32_t na_[4], nb_[4];
-                        apply_m_strided<4>(la, lb, x0 + lane + S, 64, x0 + lane + S + 192, S, Mc, F, na_, nb_);
+                        apply_m_strided<4, XG>(la, lb, x0 + lane + S, 64, x0 + lane + S + 192, S, Mc, F, na_, nb_, mreg);
 #pragma unroll
                         for (int j = 0; j < 4; j++) {
                             const int64_t P = wlo + x0 + lane + 64 * j;
@@ -328,12 +334,15 @@ __global__ __launch_bounds__(GCD_THREADS) void gcd_pipe_kernel(GcdArgs G) {
                 if (wlo <= cdn) {
                     if (!res.big) {
                         const int S = res.S;
+                        uint32_t mreg[4];
+#pragma unroll
+                        for (int r = 0; r < 4; r++) mreg[r] = Mc[64 * r + lane];
                         __builtin_amdgcn_wave_barrier();
                         stage_pair(la, lb, SAc, SBc, wlo - S, half + S);
                         __builtin_amdgcn_wave_barrier();
                         for (int x0 = 0; x0 < half; x0 += 256) {
                             uint32_t sa_[4], sb_[4];
-                            apply_m_strided<4>(la, lb, x0 + lane + S, 64, x0 + lane + S + 192, S, Mc, F, sa_, sb_);
+                            apply_m_strided<4, true>(la, lb, x0 + lane + S, 64, x0 + lane + S + 192, S, Mc, F, sa_, sb_, mreg);
 #pragma unroll
                             for (int j = 0; j < 4; j++) {
                                 SAn[wlo + x0 + lane + 64 * j] = sa_[j];

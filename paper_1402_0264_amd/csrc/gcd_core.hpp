@@ -317,10 +317,13 @@ __device__ void m_build_live(const StepDesc* desc, StepLog* L, const Field& F, u
 // covers the indexes down to x - S). Each coefficient of M read from LDS
 // serves all G positions, and the G sums give the loop independent work
 // between its LDS reads.
-template <int G>
+// MREG: M's rows are taken from registers, mreg[r] holding row r's
+// coefficient k on lane k, by a lane read per coefficient instead of an LDS
+// read (M itself is then unused).
+template <int G, bool MREG = false>
 __device__ __forceinline__ void apply_m_strided(const uint32_t* la, const uint32_t* lb, int x, int stride, int xmax,
                                                 int S, const uint32_t* M, const Field& F, uint32_t (&outA)[G],
-                                                uint32_t (&outB)[G]) {
+                                                uint32_t (&outB)[G], const uint32_t* mreg = nullptr) {
     uint64_t accA[G], accB[G];
     int xs[G];
 #pragma unroll
@@ -333,7 +336,18 @@ __device__ __forceinline__ void apply_m_strided(const uint32_t* la, const uint32
     const uint32_t half = F.fold_every / 2;
     S = uni(S);
     for (int k = 0; k <= S; k++) {
-        const uint32_t ma = M[k], mb = M[64 + k], mc = M[128 + k], md = M[192 + k];
+        uint32_t ma, mb, mc, md;
+        if constexpr (MREG) {
+            ma = (uint32_t)__builtin_amdgcn_readlane((int)mreg[0], k);
+            mb = (uint32_t)__builtin_amdgcn_readlane((int)mreg[1], k);
+            mc = (uint32_t)__builtin_amdgcn_readlane((int)mreg[2], k);
+            md = (uint32_t)__builtin_amdgcn_readlane((int)mreg[3], k);
+        } else {
+            ma = M[k];
+            mb = M[64 + k];
+            mc = M[128 + k];
+            md = M[192 + k];
+        }
 #pragma unroll
         for (int j = 0; j < G; j++) {
             const uint32_t a = la[xs[j] - k], b = lb[xs[j] - k];
