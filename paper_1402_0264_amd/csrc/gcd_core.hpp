@@ -13,10 +13,11 @@
 //     index l + 64e below the leading one). A head entry stays exact while
 //     every entry it was computed from was loaded; the run stops before the
 //     next leading coefficient would be unknown, or when the total shift of
-//     the chunk would exceed MAXSHIFT. Each step is published when its head
-//     update is done, and a second wave (m_build_live) applies it to the 2x2
-//     matrix of polynomials M = [[alpha, beta], [gamma, delta]] (degree <=
-//     the total shift S; lane k holds coefficient k of each entry), so that
+//     the chunk would exceed MAXSHIFT. Each step is recorded as it starts
+//     and published with the next one (the last by the run's end count), and
+//     a second wave (m_build_live) applies it to the 2x2 matrix of
+//     polynomials M = [[alpha, beta], [gamma, delta]] (degree <= the total
+//     shift S; lane k holds coefficient k of each entry), so that
 //     (A', B') = M * (A, B) for the chunk-start A, B.
 //  2. apply: every coefficient position P of the new polynomials is an
 //     independent sum, A'[P] = sum_k alpha_k A[P-k] + beta_k B[P-k] (and
