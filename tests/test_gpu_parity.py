@@ -527,6 +527,41 @@ def test_xgcd_workload_32768_certificate():
         assert oracle.mul_coeff(hs, ha, p, int(k)) == int(host(sa)[k])
 
 
+def test_gcd_and_xgcd_grid_multi_pass_slices():
+    # degree 300000: more than 2 x 256 slices of 512 positions, so the
+    # cooperative grid takes slices of 1024 and each apply wave walks its
+    # half-slice in two passes of 256 positions. The oracle's gcd is too
+    # slow here: the planted monic g is the answer (u, v coprime with
+    # probability about 1 - 1/p), and s a + t b = g is checked in full on the
+    # device with sampled product coefficients against the oracle.
+    p = gen.P_A
+    pl = gen.planted_gcd(300000, 299999, 16, p, gen.Stream(gen.SEED_BASE + 61))
+    gd = pm.to_device(pl.g)
+    a = pm.mul(gd, pm.to_device(pl.u), p)
+    b = pm.mul(gd, pm.to_device(pl.v), p)
+    ha, hb = host(a), host(b)
+    rng = np.random.default_rng(61)
+    for k in rng.integers(0, ha.size, 4):
+        assert oracle.mul_coeff(pl.g, pl.u, p, int(k)) == int(ha[k])
+        assert oracle.mul_coeff(pl.g, pl.v, p, int(k)) == int(hb[k])
+    assert same(host(pm.gcd(a, b, p)), pl.g)
+    st = pm.last_gcd_stats()
+    assert st["chunks"] > 0 and st["steps"] > 0
+    g, s_, t_ = pm.xgcd(a, b, p)
+    assert same(host(g), pl.g)
+    assert s_.numel() - 1 < (b.numel() - 1) - (g.numel() - 1)
+    sa = pm.mul(s_, a, p)
+    tb = pm.mul(t_, b, p)
+    n = max(sa.numel(), tb.numel())
+    lhs = np.zeros(n, dtype=np.uint64)
+    lhs[:sa.numel()] += host(sa)
+    lhs[:tb.numel()] += host(tb)
+    lhs %= p
+    want = np.zeros(n, dtype=np.uint64)
+    want[:pl.g.size] = pl.g
+    assert np.array_equal(lhs, want)
+
+
 @pytest.mark.parametrize("p", [3, gen.P_A])
 def test_gcd_grid_big_steps_and_rescans(p):
     # the cooperative kernel at several blocks: degree gaps of 64-127 (no
