@@ -84,7 +84,9 @@ __device__ __forceinline__ void arrive_by_waves(CallInfo* info, unsigned nblocks
 }
 
 // The wait half: thread 0 waits until every block has arrived for
-// generation gen. Called by all threads of the block.
+// generation gen. Called by all threads of the block. Thread 0's agent-scope
+// acquire is the block's: the block barrier orders every other thread after
+// it (no fence per wave).
 __device__ __forceinline__ void wait_grid(CallInfo* info, unsigned nblocks, unsigned& gen) {
     if (nblocks > 1) {
         if (threadIdx.x == 0)
@@ -93,7 +95,6 @@ __device__ __forceinline__ void wait_grid(CallInfo* info, unsigned nblocks, unsi
         gen++;
     }
     __syncthreads();
-    __threadfence();
 }
 
 // The top 64 E entries of both operands after a chunk, from the chunk-start
