@@ -161,3 +161,72 @@ def sympy_poly(c, p: int):
 def from_sympy(P) -> list:
     co = [int(v) % P.get_modulus() for v in P.all_coeffs()]
     return trim(list(reversed(co)))
+
+
+def det_mod_p(rows: list, p: int) -> int:
+    """Determinant of a square matrix over GF(p) by Gaussian elimination."""
+    m = [[int(v) % p for v in r] for r in rows]
+    n = len(m)
+    det = 1
+    for col in range(n):
+        piv = next((r for r in range(col, n) if m[r][col]), None)
+        if piv is None:
+            return 0
+        if piv != col:
+            m[col], m[piv] = m[piv], m[col]
+            det = -det
+        det = det * m[col][col] % p
+        iv = pow(m[col][col], p - 2, p)
+        for r in range(col + 1, n):
+            if m[r][col]:
+                f = m[r][col] * iv % p
+                m[r] = [(x - f * y) % p for x, y in zip(m[r], m[col])]
+    return det % p
+
+
+def subresultant_degrees(a, b, p: int) -> list:
+    """The degrees j < deg b at which the j-th principal subresultant
+    coefficient of (a, b), deg a >= deg b >= 1, is non-zero, from highest to
+    lowest. psc_j is the determinant of the (m + n - 2j)-square matrix whose
+    rows are x^(n-j-1-i) a (i < n - j) and x^(m-j-1-i) b (i < m - j), each
+    written by the coefficients of degrees m + n - j - 1 down to j. By the
+    fundamental theorem of subresultants these are exactly the degrees of
+    the Euclidean remainders after a and b (linear algebra only: no
+    division of polynomials)."""
+    a, b = trim(a), trim(b)
+    m, n = len(a) - 1, len(b) - 1
+    assert m >= n >= 1
+    out = []
+    for j in range(n - 1, -1, -1):
+        size = m + n - 2 * j
+        rows = []
+        for poly, deg, count in ((a, m, n - j), (b, n, m - j)):
+            for i in range(count):
+                shift = count - 1 - i
+                row = [0] * size
+                for e, c in enumerate(poly):
+                    col = (m + n - j - 1) - (e + shift)
+                    if 0 <= col < size:
+                        row[col] = c
+                rows.append(row)
+        if det_mod_p(rows, p):
+            out.append(j)
+    return out
+
+
+def sympy_remainder_degrees(a, b, p: int) -> list:
+    """deg r0, deg r1, ..., -1 of the Euclidean remainder sequence, formed
+    with sympy's remainder over GF(p) (r0 the operand of higher degree, a on
+    equal degrees)."""
+    A, B = sympy_poly(a, p), sympy_poly(b, p)
+
+    def deg(P):
+        return -1 if P.is_zero else P.degree()
+
+    if deg(A) < deg(B):
+        A, B = B, A
+    out = [deg(A), deg(B)]
+    while not B.is_zero:
+        A, B = B, A.rem(B)
+        out.append(deg(B))
+    return out

@@ -353,6 +353,79 @@ def test_gcd_degree_sequence_and_counts(orc):
     assert stats.updates == sum(2 * (d + 1) for d in range(30, 300))
 
 
+def _counts_from_degrees(degs):
+    # the long division of r_(i-1) by r_i takes one step at every position
+    # from deg r_(i-1) down to deg r_i, each updating deg r_i + 1 coefficients
+    steps = updates = 0
+    for hi, lo in zip(degs[:-2], degs[1:-1]):
+        steps += hi - lo + 1
+        updates += (hi - lo + 1) * (lo + 1)
+    return steps, updates
+
+
+def _small_field_pair(st, da, db, p):
+    # uniform coefficients over a tiny field: remainders often lose several
+    # degrees at once, and leading coefficients vanish often
+    return st.uniform_poly(da, p), st.uniform_poly(db, p)
+
+
+@pytest.mark.parametrize("p", [3, 5, 7, gen.P_A])
+def test_gcd_degree_sequence_and_counts_against_sympy(orc, p):
+    """The oracle's degree sequence is sympy's Euclidean remainder sequence
+    over GF(p), and its step and update counts follow from that sequence by
+    the long division's step rule. At p = 3 and 5 most sequences skip
+    degrees, so the counts are checked beyond the generic case."""
+    st = gen.Stream(37 + p % 1000)
+    skipped = 0
+    for da, db in [(20, 19), (20, 20), (25, 12), (9, 30), (40, 39), (17, 1), (1, 1), (0, 6)]:
+        for _ in range(6 if p < 10 else 2):
+            a, b = _small_field_pair(st, da, db, p)
+            g, degs, stats = orc.gcd(a, b, p, with_info=True)
+            want = ck.sympy_remainder_degrees(a, b, p)
+            assert list(degs) == want, (p, da, db)
+            steps, updates = _counts_from_degrees(want)
+            assert (stats.steps, stats.updates) == (steps, updates)
+            assert stats.divisions == len(want) - 2
+            skipped += any(x - y > 1 for x, y in zip(want[1:-1], want[2:-1]))
+    if p < 10:
+        assert skipped > 5  # the non-generic sequences were exercised
+
+
+@pytest.mark.parametrize("p", [3, 5, gen.P_C])
+def test_gcd_degree_sequence_against_subresultants(orc, p):
+    """The remainder degrees after a and b are the j where the j-th principal
+    subresultant coefficient is non-zero (determinants of Sylvester
+    submatrices over GF(p): linear algebra, no polynomial division)."""
+    st = gen.Stream(38 + p % 1000)
+    for da, db in [(12, 11), (12, 12), (15, 7), (10, 3), (6, 5)]:
+        for _ in range(5):
+            a, b = _small_field_pair(st, da, db, p)
+            _, degs, _ = orc.gcd(a, b, p, with_info=True)
+            hi, lo = (a, b) if da >= db else (b, a)
+            assert list(degs[:2]) == [max(da, db), min(da, db)]
+            assert list(degs[2:-1]) == ck.subresultant_degrees(hi, lo, p) and degs[-1] == -1
+
+
+def test_euclid_step_tie_rule_worked_example(orc):
+    """The single Euclidean step follows the naive kernel's tie rule (reduce
+    a on equal degrees): each state of a five-step walk over F_5, worked by
+    hand in tests/golden/euclid_step_tie_f5.json."""
+    import json
+    import os
+    fx = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "euclid_step_tie_f5.json")))
+    p = fx["p"]
+    a = np.array(fx["a"], dtype=np.uint32)
+    b = np.array(fx["b"], dtype=np.uint32)
+    da, db = 2, 2
+    for want in fx["steps"]:
+        a, da, b, db, stepped = orc.euclid_step(a, da, b, db, p)
+        assert stepped
+        assert [int(x) for x in a] == want["a"] and da == want["da"]
+        assert [int(x) for x in b] == want["b"] and db == want["db"]
+    a, da, b, db, stepped = orc.euclid_step(a, da, b, db, p)
+    assert not stepped
+
+
 def test_gcd_degenerate(orc):
     p = gen.P_A
     z = np.zeros(0, dtype=np.uint32)
