@@ -144,6 +144,47 @@ pm_status poly_gcd_modp(const uint32_t *a, int64_t na, const uint32_t *b, int64_
                         uint32_t *g, int64_t g_cap, int64_t *ng, void *stream);
 
 /*
+ * The gcd of poly_gcd_modp together with the degree sequence of its
+ * Euclidean remainder sequence (Sec. 6): degs[0] = deg r0 (the operand of
+ * higher degree, a on equal degrees), degs[1] = deg r1, then the degree of
+ * each later remainder, ending with -1 for the zero remainder; with a zero
+ * operand it is (deg of the other, -1), and (-1, -1) for two zeros.
+ *   degs, degs_cap : host array; the first min(*n_degs, degs_cap) entries
+ *                    are written
+ *   n_degs         : host; the full length of the sequence
+ * The kernel logs the shift and the reduced operand of every division step
+ * it runs (Alg. 9's rule: the operand of higher degree, a on a tie); the
+ * host rebuilds each step's degrees from the log and checks them
+ * (PM_EDEVICE if the log is inconsistent). The remainders of the paper's
+ * step sequence are associates of the textbook ones with the same degrees,
+ * so this is the sequence of every correct Euclidean algorithm. Scratch:
+ * about 12 (na + nb) words for the log. Synchronous.
+ */
+pm_status poly_gcd_modp_degrees(const uint32_t *a, int64_t na, const uint32_t *b, int64_t nb, uint32_t p,
+                                uint32_t *g, int64_t g_cap, int64_t *ng, int64_t *degs, int64_t degs_cap,
+                                int64_t *n_degs, void *stream);
+
+/*
+ * The first k division steps of the naive Euclidean algorithm (Sec. 6.1,
+ * Alg. 9), fused s at a time as in poly_gcd_modp: a step reduces the
+ * operand of higher degree (a on equal degrees) by the other,
+ * X <- X - (lc X / lc Y) x^(deg X - deg Y) Y; positions whose coefficient is
+ * already zero are skipped, not counted. Both operands after the steps are
+ * returned made monic (the steps' own scaling is a unit, so this is
+ * canonical): x from a, y from b.
+ *   k          : steps to run (>= 0); fewer when an operand becomes zero
+ *   x, x_cap / y, y_cap : outputs (device), each needs deg + 1 words of its
+ *                operand after the steps (at most na and nb)
+ *   nx, ny     : host; their lengths (0 for a zero operand)
+ *   taken      : host; the steps run
+ * No leading division is taken apart (unlike poly_gcd_modp): every step is
+ * one of the fused chunks. Synchronous. Returns PM_EMODULUS for p = 2.
+ */
+pm_status poly_euclid_steps_modp(const uint32_t *a, int64_t na, const uint32_t *b, int64_t nb, uint32_t p,
+                                 int64_t k, uint32_t *x, int64_t x_cap, int64_t *nx, uint32_t *y, int64_t y_cap,
+                                 int64_t *ny, int64_t *taken, void *stream);
+
+/*
  * Extended Euclidean algorithm (the Bezout certificate of Sec. 6's gcd):
  * monic g = gcd(a, b) and cofactors s, t with s a + t b = g. Of all such
  * pairs it returns the unique one with deg s < deg b - deg g (s = 0 when

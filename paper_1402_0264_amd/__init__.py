@@ -119,6 +119,12 @@ def lib() -> ctypes.CDLL:
                                  _vp, ctypes.c_int64, _i64p, _vp, ctypes.c_int64, _i64p,
                                  _vp, ctypes.c_int64, _i64p, _vp]
     L.poly_xgcd_modp.restype = ctypes.c_int32
+    L.poly_gcd_modp_degrees.argtypes = [_vp, _i64, _vp, _i64, ctypes.c_uint32, _vp, _i64, _i64p, _i64p, _i64,
+                                        _i64p, _vp]
+    L.poly_gcd_modp_degrees.restype = ctypes.c_int32
+    L.poly_euclid_steps_modp.argtypes = [_vp, _i64, _vp, _i64, ctypes.c_uint32, _i64, _vp, _i64, _i64p, _vp,
+                                         _i64, _i64p, _i64p, _vp]
+    L.poly_euclid_steps_modp.restype = ctypes.c_int32
     L.pm_radix_sort_u32.argtypes = [_vp, _vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp]
     L.pm_radix_sort_u32.restype = ctypes.c_int32
     L.poly_gcd_modp_batch.argtypes = [ctypes.POINTER(GcdItem), ctypes.c_int32, ctypes.POINTER(GcdResult), _vp]
@@ -285,6 +291,40 @@ def gcd(a, b, p: int, stream=None, naive: bool = False):
     fn = lib().poly_gcd_modp_naive if naive else lib().poly_gcd_modp
     _check(fn(_dev_ptr(a), na, _dev_ptr(b), nb, p, g.data_ptr(), cap, ctypes.byref(ng), _stream_handle(stream)))
     return g[:ng.value]
+
+
+def gcd_degrees(a, b, p: int, stream=None):
+    """(g, degs): the monic gcd and the degree sequence of the Euclidean
+    remainder sequence (deg r0, deg r1, ..., -1), rebuilt from the kernel's
+    step log (poly_gcd_modp_degrees)."""
+    import numpy as np
+    torch = _torch()
+    a, b = _as_u32_tensor(a), _as_u32_tensor(b)
+    na, nb = a.numel(), b.numel()
+    cap = max(na, nb, 1)
+    g = torch.empty(cap, dtype=torch.int32, device=a.device if na else b.device)
+    degs = np.zeros(na + nb + 4, dtype=np.int64)
+    ng, nd = ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(lib().poly_gcd_modp_degrees(_dev_ptr(a), na, _dev_ptr(b), nb, p, g.data_ptr(), cap, ctypes.byref(ng),
+                                       degs.ctypes.data_as(_i64p), degs.size, ctypes.byref(nd),
+                                       _stream_handle(stream)))
+    return g[:ng.value], degs[:nd.value].copy()
+
+
+def euclid_steps(a, b, p: int, k: int, stream=None):
+    """(x, y, taken): the pair after the first k steps of the naive
+    Euclidean algorithm (poly_euclid_steps_modp), each made monic."""
+    torch = _torch()
+    a, b = _as_u32_tensor(a), _as_u32_tensor(b)
+    na, nb = a.numel(), b.numel()
+    dev = a.device if na else b.device
+    x = torch.empty(max(na, 1), dtype=torch.int32, device=dev)
+    y = torch.empty(max(nb, 1), dtype=torch.int32, device=dev)
+    nx, ny, taken = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(lib().poly_euclid_steps_modp(_dev_ptr(a), na, _dev_ptr(b), nb, p, k, x.data_ptr(), na,
+                                        ctypes.byref(nx), y.data_ptr(), nb, ctypes.byref(ny), ctypes.byref(taken),
+                                        _stream_handle(stream)))
+    return x[:nx.value], y[:ny.value], taken.value
 
 
 def xgcd(a, b, p: int, stream=None):

@@ -10,6 +10,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -852,19 +853,21 @@ namespace {
 // quotient alone (its shift is beyond what a chunk's matrix holds).
 constexpr int64_t GCD_LEAD_GAP = 128;
 
-// Scratch of the gcd's leading division (quotient, remainder, folded
-// operand), apart from the pool that the division and the gcd use.
+// Scratch apart from the pool that the division and the gcd use, one per
+// purpose: the gcd's leading division (quotient, remainder, folded operand;
+// AUX_LEAD) and the gcd's step log (AUX_TRACE).
 struct Aux {
     uint32_t* w = nullptr;
     int64_t cap = 0;
 };
-std::map<std::pair<int, hipStream_t>, Aux> g_aux;  // guarded by g_pool_mu
+enum { AUX_LEAD = 0, AUX_TRACE = 1 };
+std::map<std::tuple<int, hipStream_t, int>, Aux> g_aux;  // guarded by g_pool_mu
 
-pm_status aux_get(hipStream_t stream, int64_t words, uint32_t** out) {
+pm_status aux_get(hipStream_t stream, int64_t words, uint32_t** out, int key = AUX_LEAD) {
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
     std::lock_guard<std::mutex> lk(g_pool_mu);
-    Aux& X = g_aux[{dev, stream}];
+    Aux& X = g_aux[{dev, stream, key}];
     if (words > X.cap) {
         if (X.w) {
             HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
@@ -888,19 +891,81 @@ pm_status aux_get(hipStream_t stream, int64_t words, uint32_t** out) {
 // block keep the apply short (one block below 513 terms). The one-block
 // instance of the batch, which holds the pair in LDS, is for throughput
 // over many instances. Sets the call's counts.
+// The divisor degree of every step in a gcd step log (the layout of
+// pm::GcdTrace), appended to divs in step order. Each step's operand
+// degrees are rebuilt from the chunk's starting degrees and the shifts, and
+// checked: the reduced operand is the one of higher degree (a on a tie),
+// its degree falls, and every chunk ends at the next one's start. Returns
+// false when the log is incomplete or inconsistent.
+bool trace_divisor_degrees(const std::vector<int32_t>& log, int64_t chunk_cap, std::vector<int64_t>& divs) {
+    const int32_t nrec = log[0], nst = log[1];
+    if (log[2] != 0 || nrec < 1 || nrec > chunk_cap) return false;
+    const int32_t* rec = log.data() + pm::GCD_TRACE_HDR;
+    const int32_t* stp = rec + 4 * chunk_cap;
+    for (int32_t c = 0; c + 1 < nrec; c++) {
+        int64_t dA = rec[4 * c], dB = rec[4 * c + 1];
+        const int32_t first = rec[4 * c + 2], n = rec[4 * c + 3];
+        const int64_t eA = rec[4 * (c + 1)], eB = rec[4 * (c + 1) + 1];
+        if (first < 0 || n < 1 || first + n > nst) return false;
+        for (int32_t j = 0; j < n; j++) {
+            const int32_t d = stp[2 * (first + j)], which = stp[2 * (first + j) + 1];
+            const int64_t dX = which ? dB : dA, dY = which ? dA : dB;
+            const bool rule = which ? dB > dA : dA >= dB;
+            if (dY < 0 || !rule || dX - dY != d) return false;
+            divs.push_back(dY);
+            int64_t nd;
+            if (j + 1 < n) {
+                const int32_t d2 = stp[2 * (first + j + 1)], w2 = stp[2 * (first + j + 1) + 1];
+                nd = w2 == which ? dY + d2 : dY - d2;
+            } else {
+                nd = which ? eB : eA;
+            }
+            if (nd >= dX) return false;
+            (which ? dB : dA) = nd;
+        }
+        if (dA != eA || dB != eB) return false;
+    }
+    return true;
+}
+
+// The gcd of validated operands on the cooperative kernel, at every size:
+// one call's latency is its step chain, and slices of 512 positions per
+// block keep the apply short (one block below 513 terms). The one-block
+// instance of the batch, which holds the pair in LDS, is for throughput
+// over many instances. Sets the call's counts. With divs, the kernel also
+// logs its steps and the divisor degree of each is appended to divs.
 pm_status gcd_run(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, const pm::Field& F, uint32_t* g,
-                  int64_t g_cap, int64_t* ng, hipStream_t s) {
+                  int64_t g_cap, int64_t* ng, hipStream_t s, std::vector<int64_t>* divs = nullptr) {
     const int64_t n = na > nb ? na : nb;
     pm_params pp = params_now();
     pm::GcdPlan plan = pm::gcd_default_plan(n > 0 ? n : 1, num_cus(), pp.gcd_s);
     Pool* P = nullptr;
     pm_status st;
+    pm::GcdTrace tr{};
+    std::vector<int32_t> log;
+    if (divs) {
+        if (na + nb + 8 > INT32_MAX / 8) return fail(PM_EINVAL, "operands too long for the step log");
+        tr.chunk_cap = tr.step_cap = na + nb + 8;  // every chunk but the last runs a step
+        tr.max_steps = -1;
+        const int64_t words = pm::gcd_trace_words(tr.chunk_cap, tr.step_cap);
+        uint32_t* w = nullptr;
+        if ((st = aux_get(s, words, &w, AUX_TRACE))) return st;
+        tr.log = (int32_t*)w;
+        HIP_TRY(hipMemsetAsync(w, 0, pm::GCD_TRACE_HDR * sizeof(int32_t), s), "clear log");
+        log.resize((size_t)words);
+    }
     if ((st = pool_get(s, pm::gcd_scratch_words(n, plan), &P))) return st;
-    HIP_TRY(pm::gcd_launch(a, na, b, nb, F, g, g_cap, P->words, P->d_info, plan, s), "gcd launch");
+    HIP_TRY(pm::gcd_launch(a, na, b, nb, F, g, g_cap, P->words, P->d_info, plan, s, nullptr, divs ? &tr : nullptr),
+            "gcd launch");
+    if (divs)
+        HIP_TRY(hipMemcpyAsync(log.data(), tr.log, log.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s),
+                "copy log");
     if ((st = read_info(P, s))) return st;
     const pm::CallInfo I = *P->h_info;
     g_gcd_stats = pm_gcd_stats{I.steps, I.updates, I.chunks};
     if (I.status) return fail(I.status, "%s", status_text(I.status));
+    if (divs && !trace_divisor_degrees(log, tr.chunk_cap, *divs))
+        return fail(PM_EDEVICE, "the gcd's step log is inconsistent");
     *ng = I.n0;
     return PM_OK;
 }
@@ -913,7 +978,8 @@ pm_status gcd_run(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, 
 // the division stands for are counted as the steps would be: one per
 // position, deg Y + 1 updates each.
 pm_status gcd_lead_division(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, uint32_t p,
-                            const pm::Field& F, uint32_t* g, int64_t g_cap, int64_t* ng, hipStream_t s) {
+                            const pm::Field& F, uint32_t* g, int64_t g_cap, int64_t* ng, hipStream_t s,
+                            std::vector<int64_t>* divs = nullptr) {
     Pool* P = nullptr;
     pm_status st;
     if ((st = pool_get(s, 0, &P))) return st;
@@ -922,7 +988,7 @@ pm_status gcd_lead_division(const uint32_t* a, int64_t na, const uint32_t* b, in
     if (P->h_info->flags) return fail(PM_ERANGE, "%s", status_text(PM_ERANGE));
     const int64_t dA = P->h_info->deg_a, dB = P->h_info->deg_b;
     const int64_t gap = dA > dB ? dA - dB : dB - dA;
-    if (dA < 0 || dB < 0 || gap < GCD_LEAD_GAP) return gcd_run(a, na, b, nb, F, g, g_cap, ng, s);
+    if (dA < 0 || dB < 0 || gap < GCD_LEAD_GAP) return gcd_run(a, na, b, nb, F, g, g_cap, ng, s, divs);
     const bool redA = dA > dB;
     const uint32_t* X = redA ? a : b;
     const uint32_t* Y = redA ? b : a;
@@ -937,18 +1003,19 @@ pm_status gcd_lead_division(const uint32_t* a, int64_t na, const uint32_t* b, in
     int64_t nq = 0, nr = 0;
     if ((st = divrem_impl(X, dX + 1, Y, dY + 1, p, q, mu, &nq, r, dY + 1, &nr, s, nullptr))) return st;
     int64_t count = mu;
+    if (divs) divs->push_back(dY);  // every step of the division has Y as its divisor
     if (redA) {
-        st = gcd_run(r, nr, b, dB + 1, F, g, g_cap, ng, s);
+        st = gcd_run(r, nr, b, dB + 1, F, g, g_cap, ng, s, divs);
     } else {
         uint32_t q0 = 0;
         HIP_TRY(hipMemcpyAsync(&q0, q, sizeof(q0), hipMemcpyDeviceToHost, s), "copy q_0");
         HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
         if (q0 == 0) {
-            st = gcd_run(a, dA + 1, r, nr, F, g, g_cap, ng, s);
+            st = gcd_run(a, dA + 1, r, nr, F, g, g_cap, ng, s, divs);
         } else {
             count = mu - 1;  // position deg a is a's step (the tie)
             HIP_TRY(pm::fold_q0_launch(r, nr, q, a, dA + 1, fold, F, s), "fold launch");
-            st = gcd_run(a, dA + 1, fold, dA + 1, F, g, g_cap, ng, s);
+            st = gcd_run(a, dA + 1, fold, dA + 1, F, g, g_cap, ng, s, divs);
         }
     }
     g_gcd_stats.steps += count;
@@ -974,6 +1041,69 @@ pm_status poly_gcd_modp(const uint32_t* a, int64_t na, const uint32_t* b, int64_
     const int64_t gap = na > nb ? na - nb : nb - na;
     if (na > 0 && nb > 0 && gap >= GCD_LEAD_GAP) return gcd_lead_division(a, na, b, nb, p, F, g, g_cap, ng, s);
     return gcd_run(a, na, b, nb, F, g, g_cap, ng, s);
+}
+
+pm_status poly_gcd_modp_degrees(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, uint32_t p,
+                                uint32_t* g, int64_t g_cap, int64_t* ng, int64_t* degs, int64_t degs_cap,
+                                int64_t* n_degs, void* stream) {
+    if (!ng || !n_degs || degs_cap < 0 || (degs_cap > 0 && !degs)) return fail(PM_EINVAL, "null ng, n_degs or degs");
+    if (bad_len(a, na) || bad_len(b, nb)) return fail(PM_EINVAL, "null input or negative length");
+    if (g_cap < 0 || (g_cap > 0 && !g)) return fail(PM_EINVAL, "bad output buffer");
+    pm::Field F;
+    pm_status st = field_for(p, &F);
+    if (st) return st;
+    if (!redc_ok(p)) return fail(PM_EMODULUS, "p = 2 is not supported by the gcd");
+    hipStream_t s = (hipStream_t)stream;
+    g_gcd_stats = pm_gcd_stats{0, 0, 0};
+    // the trimmed degrees start the sequence
+    Pool* P = nullptr;
+    if ((st = pool_get(s, 0, &P))) return st;
+    HIP_TRY(pm::naive_prep_launch(a, na, b, nb, F, P->d_info, s), "degree scan");
+    if ((st = read_info(P, s))) return st;
+    if (P->h_info->flags) return fail(PM_ERANGE, "%s", status_text(PM_ERANGE));
+    const int64_t dA = P->h_info->deg_a, dB = P->h_info->deg_b;
+    std::vector<int64_t> divs;
+    const int64_t gap = na > nb ? na - nb : nb - na;
+    if (na > 0 && nb > 0 && gap >= GCD_LEAD_GAP) st = gcd_lead_division(a, na, b, nb, p, F, g, g_cap, ng, s, &divs);
+    else st = gcd_run(a, na, b, nb, F, g, g_cap, ng, s, &divs);
+    if (st) return st;
+    // deg r0, then each divisor's degree once (the remainders, in order), then
+    // the zero remainder that ends the sequence
+    std::vector<int64_t> seq{dA > dB ? dA : dB};
+    for (int64_t d : divs)
+        if (seq.size() == 1 || seq.back() != d) seq.push_back(d);
+    seq.push_back(-1);  // with a zero operand the sequence is (deg r0, -1)
+    *n_degs = (int64_t)seq.size();
+    for (int64_t i = 0; i < (int64_t)seq.size() && i < degs_cap; i++) degs[i] = seq[(size_t)i];
+    return PM_OK;
+}
+
+pm_status poly_euclid_steps_modp(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, uint32_t p,
+                                 int64_t k, uint32_t* x, int64_t x_cap, int64_t* nx, uint32_t* y, int64_t y_cap,
+                                 int64_t* ny, int64_t* taken, void* stream) {
+    if (!nx || !ny || !taken) return fail(PM_EINVAL, "null nx, ny or taken");
+    if (k < 0) return fail(PM_EINVAL, "negative step count");
+    if (bad_len(a, na) || bad_len(b, nb)) return fail(PM_EINVAL, "null input or negative length");
+    if (x_cap < 0 || (x_cap > 0 && !x) || y_cap < 0 || (y_cap > 0 && !y)) return fail(PM_EINVAL, "bad output buffer");
+    pm::Field F;
+    pm_status st = field_for(p, &F);
+    if (st) return st;
+    if (!redc_ok(p)) return fail(PM_EMODULUS, "p = 2 is not supported by the gcd");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = na > nb ? na : nb;
+    pm_params pp = params_now();
+    const pm::GcdPlan plan = pm::gcd_default_plan(n > 0 ? n : 1, num_cus(), pp.gcd_s);
+    Pool* P = nullptr;
+    if ((st = pool_get(s, pm::gcd_scratch_words(n, plan), &P))) return st;
+    const pm::GcdTrace tr{nullptr, 0, 0, k, y, y_cap};
+    HIP_TRY(pm::gcd_launch(a, na, b, nb, F, x, x_cap, P->words, P->d_info, plan, s, nullptr, &tr), "gcd launch");
+    if ((st = read_info(P, s))) return st;
+    const pm::CallInfo I = *P->h_info;
+    if (I.status) return fail(I.status, "%s", status_text(I.status));
+    *nx = I.n0;
+    *ny = I.n1;
+    *taken = I.run_steps;
+    return PM_OK;
 }
 
 }  // extern "C"

@@ -120,6 +120,7 @@ struct CallInfo {
     int64_t updates;    // coefficient updates, (deg divisor + 1) per step
     uint32_t bar_count; // grid barrier state (persistent kernels)
     uint32_t bar_gen;
+    int64_t run_steps;  // gcd: steps with a non-zero multiplier that were run
 };
 
 // Grid-wide barrier of a cooperative launch (all nblocks resident): one

@@ -45,7 +45,49 @@ struct GcdArgs {
     int64_t nsa, nsb;
     int64_t s_deg_cap;
     uint32_t* s_res;  // N words: the cofactor of the last non-zero remainder, scaled as g is
+    // diagnostics (GcdTrace): step log written by block 0, and a step limit
+    // after which both operands are written made monic (A to g, B to b_out)
+    int32_t* tlog;
+    int64_t tchunk_cap, tstep_cap;
+    int64_t max_steps;
+    uint32_t* b_out;
+    int64_t b_cap;
 };
+
+// Block 0 records a chunk whose head run is over (desc[0 .. n) final, behind
+// a block barrier): its starting degrees and its steps. Called by every
+// thread of every block with the same arguments; nrec and nst are the
+// block's running counts.
+__device__ __forceinline__ void trace_chunk(const GcdArgs& G, int32_t& nrec, int32_t& nst, int64_t dA, int64_t dB,
+                                            const StepDesc* desc, int n) {
+    if (!G.tlog || blockIdx.x != 0) return;
+    int32_t* hdr = G.tlog;
+    int32_t* rec = G.tlog + GCD_TRACE_HDR;
+    int32_t* stp = rec + 4 * G.tchunk_cap;
+    if (nrec >= G.tchunk_cap || (int64_t)nst + n > G.tstep_cap) {
+        if (threadIdx.x == 0) hdr[2] = 1;  // overflow: the log is incomplete
+        return;
+    }
+    if (threadIdx.x == 0) {
+        rec[4 * nrec + 0] = (int32_t)dA;
+        rec[4 * nrec + 1] = (int32_t)dB;
+        rec[4 * nrec + 2] = nst;
+        rec[4 * nrec + 3] = n;
+    }
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        stp[2 * (nst + i) + 0] = desc[i].d;
+        stp[2 * (nst + i) + 1] = desc[i].which;
+    }
+    nrec++;
+    nst += n;
+}
+
+// Steps the next head run may take under the step limit (G.s without one).
+__device__ __forceinline__ int steps_allowed(const GcdArgs& G, int64_t done) {
+    if (G.max_steps < 0) return G.s;
+    const int64_t left = G.max_steps - done;
+    return left <= 0 ? 0 : (left < G.s ? (int)left : G.s);
+}
 
 template <int E>
 __device__ __forceinline__ void load_heads(const uint32_t* A, const uint32_t* B, int64_t dA, int64_t dB,
@@ -223,6 +265,8 @@ __global__ __launch_bounds__(GCD_THREADS) void gcd_pipe_kernel(GcdArgs G) {
     int64_t cdeg = XG ? uni((G.nsa > G.nsb ? G.nsa : G.nsb) - 1) : 0;
     int cur = 0, mb = 0;
     int64_t steps = 0, chunks = 0, updates = 0;
+    int64_t run = 0;              // steps with a non-zero multiplier applied so far
+    int32_t t_rec = 0, t_st = 0;  // trace counts (block 0)
     const int64_t max_chunks = (dA > 0 ? dA : 0) + (dB > 0 ? dB : 0) + 4;
     bool ok = true;
     // chunk 0's steps and M, from the input operands
@@ -231,17 +275,20 @@ __global__ __launch_bounds__(GCD_THREADS) void gcd_pipe_kernel(GcdArgs G) {
             uint32_t hA[E], hB[E];
             load_heads<E>(A0, B0, dA, dB, hA, hB);
             int nst, big;
-            head_run_log<E>(hA, hB, (int)dA, (int)dB, G.s, F, desc, &s_log, &s_out[0], nst, big);
+            head_run_log<E>(hA, hB, (int)dA, (int)dB, steps_allowed(G, 0), F, desc, &s_log, &s_out[0], nst, big);
         } else if (wave == 1) {
             m_build_live(desc, &s_log, F, Mbuf);
         }
         __syncthreads();
         if (tid == 0) steplog_reset(&s_log);
         __syncthreads();
+        trace_chunk(G, t_rec, t_st, dA, dB, desc, uni(s_out[0].nsteps));
     }
     for (;;) {
         // state_c (cur) is complete; chunk c's steps are in s_out[mb], M[mb]
         if (dA < 0 || dB < 0) break;
+        // a chunk without steps only follows the step limit
+        if (G.max_steps >= 0 && uni(s_out[mb].nsteps) == 0) break;
         if (chunks >= max_chunks) { ok = false; break; }
         chunks++;
         const uint32_t* Acur = cur ? A1 : A0;
@@ -282,7 +329,8 @@ __global__ __launch_bounds__(GCD_THREADS) void gcd_pipe_kernel(GcdArgs G) {
                     hB[e] = hbuf[64 * (E + e) + lane];
                 }
                 int nst, big;
-                head_run_log<E>(hA, hB, (int)res.dA, (int)res.dB, G.s, F, desc, &s_log, &s_out[mb ^ 1], nst, big);
+                head_run_log<E>(hA, hB, (int)res.dA, (int)res.dB, steps_allowed(G, run + res.nsteps), F, desc,
+                                &s_log, &s_out[mb ^ 1], nst, big);
             }
         } else if (wave == 1) {
             if (pipe) m_build_live(desc, &s_log, F, Mn);
@@ -381,7 +429,9 @@ __global__ __launch_bounds__(GCD_THREADS) void gcd_pipe_kernel(GcdArgs G) {
         dB = res.dB;
         cdeg = cdn;
         steps += res.nsteps + res.zsteps;
+        run += res.nsteps;
         updates += res.upd;
+        if (pipe) trace_chunk(G, t_rec, t_st, dA, dB, desc, uni(s_out[mb ^ 1].nsteps));
         if (!pipe) {
             const uint32_t* An = cur ? A1 : A0;
             const uint32_t* Bn = cur ? B1 : B0;
@@ -405,7 +455,8 @@ __global__ __launch_bounds__(GCD_THREADS) void gcd_pipe_kernel(GcdArgs G) {
                     uint32_t hA[E], hB[E];
                     load_heads<E>(An, Bn, dA, dB, hA, hB);
                     int nst, big;
-                    head_run_log<E>(hA, hB, (int)dA, (int)dB, G.s, F, desc, &s_log, &s_out[mb ^ 1], nst, big);
+                    head_run_log<E>(hA, hB, (int)dA, (int)dB, steps_allowed(G, run), F, desc, &s_log,
+                                    &s_out[mb ^ 1], nst, big);
                 } else if (wave == 1) {
                     m_build_live(desc, &s_log, F, Mn);
                 }
@@ -413,8 +464,24 @@ __global__ __launch_bounds__(GCD_THREADS) void gcd_pipe_kernel(GcdArgs G) {
                 if (tid == 0) steplog_reset(&s_log);
             }
             __syncthreads();
+            if (dA >= 0 && dB >= 0) trace_chunk(G, t_rec, t_st, dA, dB, desc, uni(s_out[mb ^ 1].nsteps));
         }
         mb ^= 1;
+    }
+    if (G.tlog && blockIdx.x == 0 && tid == 0) {
+        // the end record (final degrees, no steps) and the header
+        if (t_rec < G.tchunk_cap) {
+            int32_t* rec = G.tlog + GCD_TRACE_HDR + 4 * t_rec;
+            rec[0] = (int32_t)dA;
+            rec[1] = (int32_t)dB;
+            rec[2] = t_st;
+            rec[3] = 0;
+            t_rec++;
+        } else {
+            G.tlog[2] = 1;
+        }
+        G.tlog[0] = t_rec;
+        G.tlog[1] = t_st;
     }
 
     // The last non-zero remainder, made monic.
@@ -423,6 +490,28 @@ __global__ __launch_bounds__(GCD_THREADS) void gcd_pipe_kernel(GcdArgs G) {
     const uint32_t* Rp = dA >= 0 ? Acur : Bcur;
     const int64_t dR = dA >= 0 ? dA : dB;
     int status = ok ? 0 : -6;  // PM_EDEVICE on a broken invariant
+    if (G.max_steps >= 0) {
+        // the pair after the limited steps, each made monic
+        if (status == 0 && (dA + 1 > G.g_cap || dB + 1 > G.b_cap)) status = -1;
+        if (status == 0 && dA >= 0) {
+            const uint32_t inv = invmod(Acur[dA], F);
+            for (int64_t P = lo + tid; P < hi && P <= dA; P += GCD_THREADS) G.g[P] = mulmod(Acur[P], inv, F);
+        }
+        if (status == 0 && dB >= 0) {
+            const uint32_t inv = invmod(Bcur[dB], F);
+            for (int64_t P = lo + tid; P < hi && P <= dB; P += GCD_THREADS) G.b_out[P] = mulmod(Bcur[P], inv, F);
+        }
+        if (blockIdx.x == 0 && tid == 0) {
+            G.info->status = status;
+            G.info->n0 = status == 0 ? dA + 1 : 0;
+            G.info->n1 = status == 0 ? dB + 1 : 0;
+            G.info->steps = steps;
+            G.info->chunks = chunks;
+            G.info->updates = updates;
+            G.info->run_steps = run;
+        }
+        return;
+    }
     if (status == 0 && dR + 1 > G.g_cap) status = -1;  // PM_EINVAL: g too small
     if (status == 0 && dR >= 0) {
         const uint32_t inv = invmod(Rp[dR], F);
@@ -440,6 +529,7 @@ __global__ __launch_bounds__(GCD_THREADS) void gcd_pipe_kernel(GcdArgs G) {
         G.info->steps = steps;
         G.info->chunks = chunks;
         G.info->updates = updates;
+        G.info->run_steps = run;
     }
 }
 
@@ -781,9 +871,10 @@ int64_t gcd_scratch_words(int64_t n, const GcdPlan& plan, bool cofactors) {
 
 hipError_t gcd_launch(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, const Field& F, uint32_t* g,
                       int64_t g_cap, uint32_t* scratch, CallInfo* info, const GcdPlan& plan, hipStream_t stream,
-                      const GcdCofactors* xg) {
+                      const GcdCofactors* xg, const GcdTrace* tr) {
     // each apply wave takes half a slice, four positions per lane at a time
     if (plan.slice <= 0 || plan.slice % 512 != 0) return hipErrorInvalidValue;
+    if (xg && tr) return hipErrorInvalidValue;  // the diagnostics are for the plain variant
     GcdArgs A{};
     A.a = a; A.b = b; A.na = na; A.nb = nb;
     A.N = gcd_positions(plan);
@@ -797,6 +888,15 @@ hipError_t gcd_launch(const uint32_t* a, int64_t na, const uint32_t* b, int64_t 
         A.sb0 = xg->sb0; A.nsb = xg->nsb;
         A.s_deg_cap = xg->deg_cap;
         A.s_res = xg->s_res;
+    }
+    A.max_steps = -1;
+    if (tr) {
+        A.tlog = tr->log;
+        A.tchunk_cap = tr->chunk_cap;
+        A.tstep_cap = tr->step_cap;
+        A.max_steps = tr->max_steps;
+        A.b_out = tr->b_out;
+        A.b_cap = tr->b_cap;
     }
     constexpr int E = 2;  // 128-entry heads (GcdPlan::head)
     void* args[] = {&A};

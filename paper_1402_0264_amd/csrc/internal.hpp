@@ -223,12 +223,36 @@ int64_t radix_scratch_words(int64_t n, int s, bool with_vals);
 hipError_t radix_sort_launch(const uint32_t* keys, const uint32_t* vals, int64_t n, int key_bits, int s,
                              uint32_t* keys_out, uint32_t* vals_out, uint32_t* scratch, hipStream_t stream);
 
+// Diagnostics of one gcd_launch (plain variant only):
+//  * log (optional): the steps of every chunk, written by block 0 once a
+//    chunk's head run is over. int32 words: a header {chunks, steps,
+//    overflow, 0}, then chunk_cap records {deg A, deg B at the chunk's
+//    start, index of its first step, its step count} (the last record, with
+//    no steps, holds the final degrees), then step_cap records {shift,
+//    which: 0 = A was reduced, 1 = B}. Steps with a zero multiplier are not
+//    run and not recorded.
+//  * max_steps >= 0: the kernel stops after that many run steps and writes
+//    both operands made monic, A to g (info->n0 = its length) and B to
+//    b_out (info->n1), instead of the gcd.
+struct GcdTrace {
+    int32_t* log;
+    int64_t chunk_cap;
+    int64_t step_cap;
+    int64_t max_steps;
+    uint32_t* b_out;
+    int64_t b_cap;
+};
+constexpr int GCD_TRACE_HDR = 4;
+inline int64_t gcd_trace_words(int64_t chunk_cap, int64_t step_cap) {
+    return GCD_TRACE_HDR + 4 * chunk_cap + 2 * step_cap;
+}
+
 // coefficient positions of the plan's grid (>= n)
 int64_t gcd_positions(const GcdPlan& plan);
 int64_t gcd_scratch_words(int64_t n, const GcdPlan& plan, bool cofactors = false);
 hipError_t gcd_launch(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb,
                       const Field& F, uint32_t* g, int64_t g_cap, uint32_t* scratch,
                       CallInfo* info, const GcdPlan& plan, hipStream_t stream,
-                      const GcdCofactors* xg = nullptr);
+                      const GcdCofactors* xg = nullptr, const GcdTrace* tr = nullptr);
 
 }  // namespace pm

@@ -157,17 +157,15 @@ def test_mul_product_2048():
     assert same(f, oracle.mul(a, b, gen.P_A))
 
 
-def test_mul_product_65536_sampled():
-    """Full size: outputs sampled one by one against the oracle's
-    definition, plus the evaluation identity at random points."""
+def test_mul_product_65536_full():
+    """Full size, every output coefficient against the oracle's product,
+    plus the evaluation identity at random points."""
     a, b = gen.product_65536()
     p = gen.P_A
     f = host(pm.mul(dev(a), dev(b), p))
     assert f.size == 131071
+    assert same(f, oracle.mul(a, b, p))
     st = gen.Stream(103)
-    ks = [0, 1, 2, 4095, 4096, 65534, 65535, 65536, 131069, 131070] + [st.uniform_int(0, 131070) for _ in range(54)]
-    for k in ks:
-        assert int(f[k]) == oracle.mul_coeff(a, b, p, k), k
     for _ in range(3):
         x = st.uniform_int(0, p - 1)
         assert ck.horner(f, x, p) == ck.horner(a, x, p) * ck.horner(b, x, p) % p
@@ -697,22 +695,26 @@ def test_mul_batch_graph_replay_and_status():
     b.close()
 
 
-def test_mul_batch_workload_4096_sampled():
-    """The 4096-product workload: every product checked at one random
-    point (f(x) = a(x) b(x)), 24 products checked in full."""
+def oracle_mul_many(pairs, p):
+    """The oracle's product of every pair, on a pool of host threads (the
+    C oracle runs without the interpreter lock)."""
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=min(16, max(1, len(pairs)))) as ex:
+        return list(ex.map(lambda ab: oracle.mul(ab[0], ab[1], p), pairs))
+
+
+def test_mul_batch_workload_4096_full():
+    """The 4096-product workload: every output coefficient of every product
+    against the oracle's product."""
     import torch
     bt = gen.batch_products()
     p = bt.p
     b = pm.MulBatch([(dev(a), dev(b_), p) for a, b_ in zip(bt.a, bt.b)])
     b.run()
     torch.cuda.synchronize()
-    st = gen.Stream(403)
+    want = oracle_mul_many(list(zip(bt.a, bt.b)), p)
     for i, f in enumerate(b.outputs):
-        fh = host(f)
-        x = st.uniform_int(0, p - 1)
-        assert ck.horner(fh, x, p) == ck.horner(bt.a[i], x, p) * ck.horner(bt.b[i], x, p) % p, i
-    for i in range(0, 4096, 171):
-        assert same(host(b.outputs[i]), oracle.mul(bt.a[i], bt.b[i], p)), i
+        assert same(host(f), want[i]), i
     b.close()
 
 
@@ -846,6 +848,43 @@ def test_server_batch_submission():
         srv.submit_many([(ok[0], ok[1], ok[2], 0), (ok[0], ok[1], 91, 1)])
     assert e.value.status == pm.PM_EMODULUS
     assert srv.pending() == 0
+    srv.close()
+
+
+def _capacity_requests():
+    """Instances at the largest served degree (D = 16384) and at the batch
+    capacity (17,408 terms), for both block shapes' edges: 4096 terms is the
+    256-thread shape's last size, 4097 the 1024-thread shape's first."""
+    st = gen.Stream(507)
+    cases = []
+    for D, dg, p in [(16384, 4096, gen.P_A), (16384, 0, gen.P_B), (17407, 1000, gen.P_C), (17407, 17000, gen.P_A),
+                     (4095, 1000, gen.P_B), (4096, 7, gen.P_A)]:
+        pl = gen.planted_gcd(D, D - 1, dg, p, st)
+        cases.append((oracle.mul(pl.g, pl.u, p), oracle.mul(pl.g, pl.v, p), p))
+    # uniform pairs of exactly the capacity (coprime with high probability)
+    a, b = st.uniform_poly(17407, gen.P_B), st.uniform_poly(17407, gen.P_B)
+    cases.append((a, b, gen.P_B))
+    return cases
+
+
+def test_gcd_batch_and_server_at_capacity():
+    reqs = _capacity_requests()
+    assert max(max(a.size, b.size) for a, b, _ in reqs) == pm.GCD_BATCH_MAX
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=8) as ex:
+        want = list(ex.map(lambda r: oracle.gcd(r[0], r[1], r[2], with_info=True), reqs))
+    for i, (g, r) in enumerate(pm.gcd_batch([(dev(a), dev(b), p) for a, b, p in reqs])):
+        wg, _, stats = want[i]
+        assert r["status"] == 0 and same(host(g), wg), i
+        assert r["steps"] == stats.steps and r["updates"] == stats.updates, i
+    srv = pm.Server()
+    srv.submit_many([(a, b, p, i) for i, (a, b, p) in enumerate(reqs)])
+    out = srv.drain()
+    assert sorted(c["tag"] for c in out) == list(range(len(reqs)))
+    for c in out:
+        wg, _, stats = want[c["tag"]]
+        assert c["status"] == 0 and same(c["g"], wg), c["tag"]
+        assert c["steps"] == stats.steps, c["tag"]
     srv.close()
 
 
