@@ -75,6 +75,26 @@ pm_status poly_mul_modp_async(const uint32_t *a, int64_t na, const uint32_t *b, 
                               uint32_t *f, int64_t f_cap, int64_t *d_nf, int32_t *d_status, void *stream);
 
 /*
+ * The asynchronous product for callers that cannot allocate device memory
+ * (code under hipGraph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): arguments, result and device-side checks as
+ * poly_mul_modp_async, but no call allocates or frees anything. The
+ * kernels' scratch (the partial sums of the addition phase) is a static
+ * device array of PM_NOALLOC_SCRATCH_WORDS words (64 MiB) that every device
+ * the library runs on holds until the process ends. The engine is the one
+ * poly_mul_modp_async picks, or else the VALU tiles, whichever plan's
+ * scratch fits; a product no plan fits returns PM_EINVAL before anything is
+ * enqueued (the matrix cores fit every square product up to about 300000
+ * terms per operand). All calls on one device share that device's array:
+ * two calls that overlap in time on one device (two streams, or two host
+ * threads) race and give wrong results; calls in order on one stream are
+ * safe. d_nf and d_status may be NULL.
+ */
+#define PM_NOALLOC_SCRATCH_WORDS (1 << 24)
+pm_status poly_mul_modp_noalloc(const uint32_t *a, int64_t na, const uint32_t *b, int64_t nb, uint32_t p,
+                                uint32_t *f, int64_t f_cap, int64_t *d_nf, int32_t *d_status, void *stream);
+
+/*
  * Batched products: many independent f_i = a_i * b_i (mixed lengths and
  * primes) in ONE persistent launch. The work is cut into output tiles of
  * 256*r coefficients, each summed over the whole of b_i in chunks of kc

@@ -47,6 +47,7 @@ class GcdResult(ctypes.Structure):
 
 
 GCD_BATCH_MAX = 17408
+NOALLOC_SCRATCH_WORDS = 1 << 24
 
 
 class MulItem(ctypes.Structure):
@@ -106,6 +107,8 @@ def lib() -> ctypes.CDLL:
     L.poly_mul_modp.restype = ctypes.c_int32
     L.poly_mul_modp_async.argtypes = [_vp, _i64, _vp, _i64, ctypes.c_uint32, _vp, _i64, _vp, _vp, _vp]
     L.poly_mul_modp_async.restype = ctypes.c_int32
+    L.poly_mul_modp_noalloc.argtypes = L.poly_mul_modp_async.argtypes
+    L.poly_mul_modp_noalloc.restype = ctypes.c_int32
     L.poly_divrem_modp.argtypes = [_vp, _i64, _vp, _i64, ctypes.c_uint32, _vp, _i64, _i64p, _vp, _i64,
                                    _i64p, _vp]
     L.poly_divrem_modp.restype = ctypes.c_int32
@@ -258,6 +261,17 @@ def mul_async(a, b, p: int, f, d_nf, d_status, stream=None):
     a, b = _as_u32_tensor(a), _as_u32_tensor(b)
     _check(lib().poly_mul_modp_async(_dev_ptr(a), a.numel(), _dev_ptr(b), b.numel(), p, f.data_ptr(),
                                      f.numel(), d_nf.data_ptr(), d_status.data_ptr(), _stream_handle(stream)))
+
+
+def mul_noalloc(a, b, p: int, f, d_nf=None, d_status=None, stream=None):
+    """Enqueue f = a*b with the library's static scratch
+    (poly_mul_modp_noalloc: nothing is allocated); d_nf (int64) and
+    d_status (int32), one element each, are optional device tensors."""
+    a, b = _as_u32_tensor(a), _as_u32_tensor(b)
+    _check(lib().poly_mul_modp_noalloc(_dev_ptr(a), a.numel(), _dev_ptr(b), b.numel(), p, f.data_ptr(),
+                                       f.numel(), d_nf.data_ptr() if d_nf is not None else None,
+                                       d_status.data_ptr() if d_status is not None else None,
+                                       _stream_handle(stream)))
 
 
 def divrem(a, b, p: int, stream=None, naive: bool = False):

@@ -404,6 +404,71 @@ pm_status poly_mul_modp_async(const uint32_t* a, int64_t na, const uint32_t* b, 
     return mul_enqueue(a, na, b, nb, F, f, d_nf, d_status, (hipStream_t)stream);
 }
 
+}  // extern "C"
+
+namespace {
+
+// ------------------------------------------- static scratch (no allocation)
+// The scratch of poly_mul_modp_noalloc: a fixed array in every device's
+// copy of the code object, held until the process ends. Host code never
+// passes `scratch` itself (on the host it is only a stand-in for the symbol)
+// but the device address hipGetSymbolAddress gives for the current device.
+static __device__ __align__(256) uint32_t scratch[PM_NOALLOC_SCRATCH_WORDS];
+
+std::mutex g_static_mu;
+std::map<int, uint32_t*> g_static_ptr;  // device -> address of its scratch
+
+pm_status static_scratch(uint32_t** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    auto it = g_static_ptr.find(dev);
+    if (it == g_static_ptr.end()) {
+        uint32_t* ptr = nullptr;
+        HIP_TRY(hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        if (!ptr) return fail(PM_EDEVICE, "no device address for the static scratch");
+        it = g_static_ptr.emplace(dev, ptr).first;
+    }
+    *out = it->second;
+    return PM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pm_status poly_mul_modp_noalloc(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, uint32_t p,
+                                uint32_t* f, int64_t f_cap, int64_t* d_nf, int32_t* d_status, void* stream) {
+    if (bad_len(a, na) || bad_len(b, nb)) return fail(PM_EINVAL, "null input or negative length");
+    int64_t need = (na > 0 && nb > 0) ? na + nb - 1 : 0;
+    if (need > 0 && (f == nullptr || f_cap < need))
+        return fail(PM_EINVAL, "f_cap %lld < na + nb - 1 = %lld", (long long)f_cap, (long long)need);
+    pm::Field F;
+    pm_status st = field_for(p, &F);
+    if (st) return st;
+    uint32_t* ws = nullptr;
+    if ((st = static_scratch(&ws))) return st;
+    hipStream_t s = (hipStream_t)stream;
+    order_operands(a, na, b, nb);
+    // the engine poly_mul_modp_async picks, else the VALU tiles, whichever
+    // plan's scratch fits the static array (the results are identical)
+    if (use_mfma(na, nb)) {
+        const pm::MxGeom g = pm::mx_geometry(na, nb, num_cus());
+        if (pm::mulx_scratch_words(g) <= PM_NOALLOC_SCRATCH_WORDS) {
+            HIP_TRY(pm::mulx_launch(a, na, b, nb, F, f, g, ws, d_nf, d_status, s), "mul launch");
+            return PM_OK;
+        }
+    }
+    const pm::MulPlan plan = mul_plan(na, nb);
+    const int64_t words = pm::mul_scratch_words(na, nb, plan);
+    if (words > PM_NOALLOC_SCRATCH_WORDS)
+        return fail(PM_EINVAL, "the product of %lld x %lld terms needs %lld scratch words, above the static %lld",
+                    (long long)na, (long long)nb, (long long)words, (long long)PM_NOALLOC_SCRATCH_WORDS);
+    HIP_TRY(pm::mul_launch(a, na, b, nb, F, f, plan, words > 0 ? ws : nullptr, d_nf, d_status, nullptr, -1, s),
+            "mul launch");
+    return PM_OK;
+}
+
 void pm_mul_batch_destroy(pm_mul_batch* B) {
     if (!B) return;
     int cur = 0;
