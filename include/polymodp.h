@@ -21,11 +21,14 @@
  *  - `stream` is a hipStream_t (NULL = the default stream). Work is enqueued
  *    on it in order; synchronous entry points wait for it before returning.
  *  - Ownership: the caller owns every buffer. Inputs are read only. Outputs
- *    must not overlap inputs. Scratch memory belongs to the library (one pool
- *    per device and stream, grown on demand and kept until pm_release).
+ *    (over their capacity) must not overlap inputs or each other: PM_EINVAL.
+ *    Scratch memory belongs to the library (one pool per device and stream,
+ *    grown on demand and kept until pm_release) unless the caller sets a
+ *    workspace for the stream (pm_set_workspace).
  *  - Errors: checks that need no device access (null pointers, negative
- *    lengths, capacities smaller than the given lengths require, a modulus
- *    that is not a prime below 2^30) are made before anything is enqueued.
+ *    lengths, capacities smaller than the given lengths require, outputs
+ *    overlapping inputs, a modulus that is not a prime below 2^30) are made
+ *    before anything is enqueued.
  *    Checks that need the data (coefficients >= p, a zero divisor, a
  *    capacity below what the true degrees require) are made on the device:
  *    synchronous calls return them, asynchronous calls write them to
@@ -148,6 +151,24 @@ pm_status poly_divrem_modp(const uint32_t *a, int64_t na, const uint32_t *b, int
                            void *stream);
 
 /*
+ * Asynchronous division: the q and r of poly_divrem_modp with nothing
+ * waiting for the device. The launch shapes are planned from the given
+ * lengths, so b must come without high zero coefficients (b[nb - 1] != 0,
+ * checked on the device: PM_EINVAL in d_status); a may have them.
+ *   q_cap >= na - nb + 1, r_cap >= min(na, nb - 1) (checked on the host);
+ *   q[deg a - deg b + 1 .. na - nb] is zeroed, r[0 .. min(na, nb - 1) - 1]
+ *   is written in full
+ *   d_nq, d_nr (int64), d_status (int32): device pointers, each may be
+ *   NULL, written by the last launch; lengths are 0 after an error
+ * nb = 0 returns PM_EDIVZERO before anything is enqueued; a coefficient
+ * >= p gives PM_ERANGE in d_status. No host synchronisation; no allocation
+ * once the stream's scratch exists (see pm_set_workspace).
+ */
+pm_status poly_divrem_modp_async(const uint32_t *a, int64_t na, const uint32_t *b, int64_t nb, uint32_t p,
+                                 uint32_t *q, int64_t q_cap, int64_t *d_nq, uint32_t *r, int64_t r_cap,
+                                 int64_t *d_nr, int32_t *d_status, void *stream);
+
+/*
  * Greatest common divisor by the Euclidean remainder sequence (Sec. 6),
  * returned monic; gcd(a, 0) = a made monic, gcd(0, 0) = 0.
  *   g, g_cap : output (device); needs deg gcd + 1 words, at most
@@ -158,10 +179,22 @@ pm_status poly_divrem_modp(const uint32_t *a, int64_t na, const uint32_t *b, int
  * the first division of the sequence runs as one poly_divrem_modp-style
  * division (the chunks would take each step of a long quotient alone);
  * pm_last_gcd_stats counts its steps position by position all the same.
- * Returns PM_ERANGE for a coefficient >= p, PM_EMODULUS for p = 2.
+ * Returns PM_ERANGE for a coefficient >= p.
  */
 pm_status poly_gcd_modp(const uint32_t *a, int64_t na, const uint32_t *b, int64_t nb, uint32_t p,
                         uint32_t *g, int64_t g_cap, int64_t *ng, void *stream);
+
+/*
+ * Asynchronous gcd: the monic g of poly_gcd_modp with nothing waiting for
+ * the device. d_ng (int64) and d_status (int32) are device pointers (each
+ * may be NULL); the length is 0 after an error. Every step runs in the
+ * fused chunks: there is no leading division, so a degree gap of k costs
+ * about k chunks (poly_gcd_modp divides first when k >= 128). No host
+ * synchronisation; no allocation once the stream's scratch exists (see
+ * pm_set_workspace).
+ */
+pm_status poly_gcd_modp_async(const uint32_t *a, int64_t na, const uint32_t *b, int64_t nb, uint32_t p,
+                              uint32_t *g, int64_t g_cap, int64_t *d_ng, int32_t *d_status, void *stream);
 
 /*
  * The gcd of poly_gcd_modp together with the degree sequence of its
@@ -198,7 +231,7 @@ pm_status poly_gcd_modp_degrees(const uint32_t *a, int64_t na, const uint32_t *b
  *   nx, ny     : host; their lengths (0 for a zero operand)
  *   taken      : host; the steps run
  * No leading division is taken apart (unlike poly_gcd_modp): every step is
- * one of the fused chunks. Synchronous. Returns PM_EMODULUS for p = 2.
+ * one of the fused chunks. Synchronous.
  */
 pm_status poly_euclid_steps_modp(const uint32_t *a, int64_t na, const uint32_t *b, int64_t nb, uint32_t p,
                                  int64_t k, uint32_t *x, int64_t x_cap, int64_t *nx, uint32_t *y, int64_t y_cap,
@@ -217,7 +250,7 @@ pm_status poly_euclid_steps_modp(const uint32_t *a, int64_t na, const uint32_t *
  * through every chunk's matrix; the cofactor is then reduced modulo b/g
  * when needed, and t = (g - s a)/b is one exact division (PM_EDEVICE if it
  * is not exact: an internal invariant). Host reads: a few per call.
- * Returns PM_ERANGE for a coefficient >= p, PM_EMODULUS for p = 2.
+ * Returns PM_ERANGE for a coefficient >= p.
  */
 pm_status poly_xgcd_modp(const uint32_t *a, int64_t na, const uint32_t *b, int64_t nb, uint32_t p,
                          uint32_t *g, int64_t g_cap, int64_t *ng, uint32_t *s, int64_t s_cap, int64_t *ns,
@@ -228,10 +261,10 @@ pm_status poly_xgcd_modp(const uint32_t *a, int64_t na, const uint32_t *b, int64
  * one division step per kernel launch, each launch a global synchronisation
  * (Sec. 3, naive division, Alg. 1/2; Sec. 6, naive gcd, Alg. 8/9, with the
  * exact inverse of the divisor's leading coefficient at every step).
- * Arguments, results and errors as poly_divrem_modp and poly_gcd_modp; the
- * gcd also accepts p = 2. The library's scratch holds a working copy of the
- * inputs. They cost deg a - deg b + 1 launches (division) and about
- * 2 (deg a + deg b) launches (gcd), and are not meant for production use.
+ * Arguments, results and errors as poly_divrem_modp and poly_gcd_modp.
+ * The library's scratch holds a working copy of the inputs. They cost
+ * deg a - deg b + 1 launches (division) and about 2 (deg a + deg b)
+ * launches (gcd), and are not meant for production use.
  */
 pm_status poly_divrem_modp_naive(const uint32_t *a, int64_t na, const uint32_t *b, int64_t nb, uint32_t p,
                                  uint32_t *q, int64_t q_cap, int64_t *nq, uint32_t *r, int64_t r_cap, int64_t *nr,
@@ -362,11 +395,13 @@ void pm_last_gcd_stats(pm_gcd_stats *out);
  *   gcd_s   : Euclidean steps fused per chunk (1..256; 0 = 128)
  *   mul_engine : which kernels compute a product (poly_mul_modp and
  *             poly_mul_modp_async): 0 = automatic (the matrix cores for
- *             products with n_a * n_b >= 2^22 and min(n_a, n_b) >= 256
+ *             products with n_a * n_b >= 40e6 and min(n_a, n_b) >= 256
  *             unless mul_s or mul_r is set), 1 = the VALU tile kernels
  *             (Sec. 5's layout, tuned by mul_s and mul_r), 2 = the matrix
- *             cores (int8 digit products; s fixed at 4096). Results are
- *             identical.
+ *             cores (int8 digit products; s fixed at 4096). The matrix
+ *             cores take a product only where their int32 digit sums stay
+ *             exact (pm_mul_plan); the VALU tiles take the rest. Results
+ *             are identical.
  * The settings are per process and apply to later calls.
  */
 typedef struct {
@@ -380,6 +415,59 @@ pm_status pm_set_params(const pm_params *params);
 void pm_get_params(pm_params *params);
 
 /*
+ * Loads tuned parameters from a text file (paper_1402_0264_amd.tune writes
+ * one): lines "name value" (or "name = value") for any of mul_s, mul_r,
+ * div_s, gcd_s and mul_engine; '#' starts a comment; names not given keep
+ * their current values. The values are checked as pm_set_params checks
+ * them, and on any error (unreadable file, unknown name, bad value) nothing
+ * changes and PM_EINVAL is returned.
+ */
+pm_status pm_autotune_load(const char *path);
+
+/*
+ * The plan poly_mul_modp and poly_mul_modp_async take for a product of
+ * na x nb terms on the current device under the current pm_params
+ * (diagnostics; nothing is enqueued): the engine (PM_MUL_VALU or
+ * PM_MUL_MFMA, 0 when an operand is empty); for the VALU tiles the outputs
+ * per thread r and the b-chunk s; for the matrix cores s = 4096, the
+ * work-groups and the most groups of 8 block offsets one work-group sums
+ * (at most 64, the bound that keeps the int32 digit sums exact); and the
+ * scratch words.
+ */
+enum { PM_MUL_AUTO = 0, PM_MUL_VALU = 1, PM_MUL_MFMA = 2 };
+typedef struct {
+    int32_t engine;
+    int32_t r;
+    int64_t s;
+    int64_t scratch_words;
+    int64_t work_groups;
+    int64_t max_share_groups;
+} pm_mul_plan_info;
+pm_status pm_mul_plan(int64_t na, int64_t nb, pm_mul_plan_info *out);
+
+/*
+ * Caller workspace. pm_set_workspace gives a stream on the current device
+ * a device buffer of `words` uint32 words (256-byte aligned, at least 64
+ * words) from which every later call on that stream takes its scratch and
+ * its device-side result record instead of the library's pool; a call that
+ * needs more returns PM_ENOMEM and allocates nothing. With a workspace of
+ * pm_workspace_size(op, na, nb) words (for the largest sizes to come) set,
+ * poly_mul_modp_async (PM_OP_MUL), poly_divrem_modp_async (PM_OP_DIVREM)
+ * and poly_gcd_modp_async (PM_OP_GCD) allocate nothing, also on their
+ * first call (inside hipGraph capture, for instance). The synchronous entry
+ * points still copy their results through a pinned host record, and the
+ * extended gcd, the gcd's step log and its leading division keep auxiliary
+ * buffers of the library. The sizes follow the current device and
+ * pm_params. pm_set_workspace waits for the stream and zeroes the first 64
+ * words; the caller keeps the buffer alive, and used by nothing else, while
+ * it is set. d_words = NULL with words = 0 returns the stream to the pool;
+ * pm_release drops every workspace.
+ */
+enum { PM_OP_MUL = 0, PM_OP_DIVREM = 1, PM_OP_GCD = 2 };
+pm_status pm_workspace_size(int32_t op, int64_t na, int64_t nb, int64_t *words);
+pm_status pm_set_workspace(void *stream, void *d_words, int64_t words);
+
+/*
  * Kernel timing (diagnostics). While enabled, every kernel launch of the
  * library is bracketed by two HIP events recorded on its launch stream
  * (no host synchronisation). pm_timing_read waits for the recorded launches
@@ -391,7 +479,9 @@ void pm_timing_enable(int on);
 pm_status pm_timing_read(const char *kernel, int64_t *launches, double *total_ms);
 void pm_timing_reset(void);
 
-/* Frees the scratch pool of every device and stream. */
+/* Frees the scratch pool of every device and stream, including buffers that
+ * larger calls outgrew (they are kept until here, since a captured graph
+ * may still use them), and drops every caller workspace. */
 void pm_release(void);
 
 /* Thread-local description of the last non-OK status. */

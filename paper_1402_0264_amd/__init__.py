@@ -85,6 +85,15 @@ class Completion(ctypes.Structure):
                 ("t_done_ms", ctypes.c_double)]
 
 
+class MulPlanInfo(ctypes.Structure):
+    _fields_ = [("engine", ctypes.c_int32), ("r", ctypes.c_int32), ("s", ctypes.c_int64),
+                ("scratch_words", ctypes.c_int64), ("work_groups", ctypes.c_int64),
+                ("max_share_groups", ctypes.c_int64)]
+
+
+PM_OP_MUL, PM_OP_DIVREM, PM_OP_GCD = 0, 1, 2
+
+
 class GcdStats(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int64), ("updates", ctypes.c_int64), ("chunks", ctypes.c_int64)]
 
@@ -176,6 +185,19 @@ def lib() -> ctypes.CDLL:
     L.pm_timing_reset.restype = None
     L.pm_timing_read.argtypes = [ctypes.c_char_p, _i64p, ctypes.POINTER(ctypes.c_double)]
     L.pm_timing_read.restype = ctypes.c_int32
+    L.poly_divrem_modp_async.argtypes = [_vp, _i64, _vp, _i64, ctypes.c_uint32, _vp, _i64, _vp, _vp, _i64, _vp, _vp,
+                                         _vp]
+    L.poly_divrem_modp_async.restype = ctypes.c_int32
+    L.poly_gcd_modp_async.argtypes = [_vp, _i64, _vp, _i64, ctypes.c_uint32, _vp, _i64, _vp, _vp, _vp]
+    L.poly_gcd_modp_async.restype = ctypes.c_int32
+    L.pm_workspace_size.argtypes = [ctypes.c_int32, _i64, _i64, _i64p]
+    L.pm_workspace_size.restype = ctypes.c_int32
+    L.pm_set_workspace.argtypes = [_vp, _vp, _i64]
+    L.pm_set_workspace.restype = ctypes.c_int32
+    L.pm_mul_plan.argtypes = [_i64, _i64, ctypes.POINTER(MulPlanInfo)]
+    L.pm_mul_plan.restype = ctypes.c_int32
+    L.pm_autotune_load.argtypes = [ctypes.c_char_p]
+    L.pm_autotune_load.restype = ctypes.c_int32
     L.pm_release.argtypes = []
     L.pm_release.restype = None
     L.pm_last_error.argtypes = []
@@ -291,6 +313,58 @@ def divrem(a, b, p: int, stream=None, naive: bool = False):
     _check(fn(_dev_ptr(a), na, _dev_ptr(b), nb, p, q.data_ptr(), qcap, ctypes.byref(nq), r.data_ptr(), rcap,
               ctypes.byref(nr), _stream_handle(stream)))
     return q[:nq.value], r[:nr.value]
+
+
+def divrem_async(a, b, p: int, q, r, d_nq=None, d_nr=None, d_status=None, stream=None):
+    """Enqueue the division into the device tensors q (at least
+    na - nb + 1 words) and r (at least min(na, nb - 1) words)
+    (poly_divrem_modp_async; b must have a non-zero top coefficient).
+    d_nq, d_nr (int64) and d_status (int32), one element each, are
+    optional device tensors written by the launch."""
+    a, b = _as_u32_tensor(a), _as_u32_tensor(b)
+    ptr = lambda t: t.data_ptr() if t is not None else None
+    _check(lib().poly_divrem_modp_async(_dev_ptr(a), a.numel(), _dev_ptr(b), b.numel(), p, _dev_ptr(q), q.numel(),
+                                        ptr(d_nq), _dev_ptr(r), r.numel(), ptr(d_nr), ptr(d_status),
+                                        _stream_handle(stream)))
+
+
+def gcd_async(a, b, p: int, g, d_ng=None, d_status=None, stream=None):
+    """Enqueue the monic gcd into the device tensor g (poly_gcd_modp_async);
+    d_ng (int64) and d_status (int32) are optional device tensors."""
+    a, b = _as_u32_tensor(a), _as_u32_tensor(b)
+    ptr = lambda t: t.data_ptr() if t is not None else None
+    _check(lib().poly_gcd_modp_async(_dev_ptr(a), a.numel(), _dev_ptr(b), b.numel(), p, _dev_ptr(g), g.numel(),
+                                     ptr(d_ng), ptr(d_status), _stream_handle(stream)))
+
+
+def workspace_size(op: int, na: int, nb: int) -> int:
+    """Words of workspace the asynchronous entry point of op (PM_OP_MUL,
+    PM_OP_DIVREM, PM_OP_GCD) needs at these sizes (pm_workspace_size)."""
+    w = ctypes.c_int64(0)
+    _check(lib().pm_workspace_size(op, na, nb, ctypes.byref(w)))
+    return w.value
+
+
+def set_workspace(buf, stream=None):
+    """Give the stream a caller-owned workspace (an int32 device tensor,
+    256-byte aligned), or return it to the library's pool with None
+    (pm_set_workspace)."""
+    if buf is None:
+        _check(lib().pm_set_workspace(_stream_handle(stream), None, 0))
+    else:
+        _check(lib().pm_set_workspace(_stream_handle(stream), buf.data_ptr(), buf.numel()))
+
+
+def mul_plan(na: int, nb: int) -> dict:
+    """The product plan for na x nb terms (pm_mul_plan; no device work)."""
+    info = MulPlanInfo()
+    _check(lib().pm_mul_plan(na, nb, ctypes.byref(info)))
+    return {f: getattr(info, f) for f, _ in MulPlanInfo._fields_}
+
+
+def autotune_load(path: str) -> None:
+    """Apply a parameter file written by tune.save_params (pm_autotune_load)."""
+    _check(lib().pm_autotune_load(os.fsencode(path)))
 
 
 def gcd(a, b, p: int, stream=None, naive: bool = False):

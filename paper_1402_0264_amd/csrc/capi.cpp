@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <atomic>
+#include <initializer_list>
 #include <map>
 #include <mutex>
 #include <string>
@@ -111,13 +112,19 @@ pm_status field_for(uint32_t p, pm::Field* out) {
     pm::Field F{};
     F.p = p;
     F.c32 = (uint32_t)((1ULL << 32) % p);
-    // -p^{-1} mod 2^32 by Newton iteration (p odd); p = 2 never uses REDC
+    // -p^{-1} mod 2^32 by Newton iteration (p odd). For p = 2 there is no
+    // such inverse; 2^31 makes the same REDC sequence return x mod 2 for any
+    // x < 2^32 (t = (x mod 2) 2^31, so (x + 2t) >> 32 = x mod 2), which
+    // covers every REDC input of the gcd at p = 2: sums of two products of
+    // residues below 2
     uint32_t inv = 1;
     if (p & 1) {
         inv = p;
         for (int i = 0; i < 5; i++) inv *= 2u - p * inv;
+        F.pinv_neg = (uint32_t)(0u - inv);
+    } else {
+        F.pinv_neg = 0x80000000u;
     }
-    F.pinv_neg = (uint32_t)(0u - inv);
     F.mu = ~0ULL / p;
     // after a fold the accumulator is below (2^32-1)*c32 + 2^32; each further
     // product is at most (p-1)^2
@@ -131,9 +138,6 @@ pm_status field_for(uint32_t p, pm::Field* out) {
     return PM_OK;
 }
 
-// REDC needs an odd modulus; for p = 2 the gcd kernel would not be exact.
-bool redc_ok(uint32_t p) { return (p & 1) != 0; }
-
 // ------------------------------------------------------------ parameters
 std::mutex g_param_mu;
 pm_params g_params = {0, 0, 0, 0, 0};
@@ -144,33 +148,54 @@ pm_params params_now() {
 }
 
 // ------------------------------------------------------------ scratch pool
+// Scratch of a call: the library's pool for its device and stream, or the
+// caller's workspace when one is set for the stream (pm_set_workspace). A
+// pool buffer that a larger call outgrows is retired, not freed: a graph
+// captured earlier may still hold its address, so retired buffers are freed
+// only by pm_release.
+constexpr int64_t INFO_WORDS = 64;  // the device CallInfo, rounded up to 256 bytes
+static_assert(sizeof(pm::CallInfo) <= INFO_WORDS * sizeof(uint32_t), "CallInfo too large");
+
 struct Pool {
-    pm::CallInfo* d_info = nullptr;  // device
-    pm::CallInfo* h_info = nullptr;  // pinned host
+    pm::CallInfo* d_info = nullptr;  // device: the call's results and barrier words
+    pm::CallInfo* h_info = nullptr;  // pinned host copy (synchronous calls)
     uint32_t* words = nullptr;       // device scratch
     int64_t cap = 0;
 };
 
+struct StreamState {
+    Pool own;                 // the library's buffers
+    Pool view;                // onto the caller's workspace
+    uint32_t* ws = nullptr;   // the caller's workspace (device), if set
+    int64_t ws_words = 0;
+};
+
 std::mutex g_pool_mu;
-std::map<std::pair<int, hipStream_t>, Pool> g_pools;
+std::map<std::pair<int, hipStream_t>, StreamState> g_pools;
+std::vector<void*> g_retired;  // outgrown device buffers, guarded by g_pool_mu
 
 pm_status pool_get(hipStream_t stream, int64_t words, Pool** out) {
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
     std::lock_guard<std::mutex> lk(g_pool_mu);
-    Pool& P = g_pools[{dev, stream}];
+    StreamState& S = g_pools[{dev, stream}];
+    if (S.ws) {
+        if (words > S.ws_words - INFO_WORDS)
+            return fail(PM_ENOMEM, "the stream's workspace holds %lld words; the call needs %lld",
+                        (long long)S.ws_words, (long long)(words + INFO_WORDS));
+        *out = &S.view;
+        return PM_OK;
+    }
+    Pool& P = S.own;
     if (!P.d_info) {
-        HIP_TRY(hipMalloc((void**)&P.d_info, sizeof(pm::CallInfo)), "hipMalloc(info)");
-        HIP_TRY(hipMemset(P.d_info, 0, sizeof(pm::CallInfo)), "hipMemset(info)");
+        HIP_TRY(hipMalloc((void**)&P.d_info, INFO_WORDS * sizeof(uint32_t)), "hipMalloc(info)");
+        HIP_TRY(hipMemset(P.d_info, 0, INFO_WORDS * sizeof(uint32_t)), "hipMemset(info)");
         HIP_TRY(hipHostMalloc((void**)&P.h_info, sizeof(pm::CallInfo), hipHostMallocDefault), "hipHostMalloc");
     }
     if (words > P.cap) {
-        if (P.words) {
-            HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
-            HIP_TRY(hipFree(P.words), "hipFree");
-            P.words = nullptr;
-            P.cap = 0;
-        }
+        if (P.words) g_retired.push_back(P.words);
+        P.words = nullptr;
+        P.cap = 0;
         int64_t want = words + words / 4 + 1024;
         if (hipMalloc((void**)&P.words, (size_t)want * sizeof(uint32_t)) != hipSuccess) {
             P.words = nullptr;
@@ -179,6 +204,36 @@ pm_status pool_get(hipStream_t stream, int64_t words, Pool** out) {
         P.cap = want;
     }
     *out = &P;
+    return PM_OK;
+}
+
+// Scratch apart from the pool that the division and the gcd use, one per
+// purpose: the gcd's leading division (quotient, remainder, folded operand;
+// AUX_LEAD) and the gcd's step log (AUX_TRACE).
+struct Aux {
+    uint32_t* w = nullptr;
+    int64_t cap = 0;
+};
+enum { AUX_LEAD = 0, AUX_TRACE = 1 };
+std::map<std::tuple<int, hipStream_t, int>, Aux> g_aux;  // guarded by g_pool_mu
+
+pm_status aux_get(hipStream_t stream, int64_t words, uint32_t** out, int key = AUX_LEAD) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    Aux& X = g_aux[{dev, stream, key}];
+    if (words > X.cap) {
+        if (X.w) g_retired.push_back(X.w);
+        X.w = nullptr;
+        X.cap = 0;
+        const int64_t want = words + words / 4 + 1024;
+        if (hipMalloc((void**)&X.w, (size_t)want * sizeof(uint32_t)) != hipSuccess) {
+            X.w = nullptr;
+            return fail(PM_ENOMEM, "cannot allocate %lld scratch words", (long long)want);
+        }
+        X.cap = want;
+    }
+    *out = X.w;
     return PM_OK;
 }
 
@@ -222,6 +277,29 @@ const char* status_text(pm_status st) {
 
 bool bad_len(const void* ptr, int64_t n) { return n < 0 || (n > 0 && ptr == nullptr); }
 
+// The words an argument covers: an input's length, an output's capacity.
+struct Span {
+    const void* p;
+    int64_t n;
+};
+
+bool spans_overlap(const Span& x, const Span& y) {
+    if (!x.p || !y.p || x.n <= 0 || y.n <= 0) return false;
+    const uintptr_t a = (uintptr_t)x.p, b = (uintptr_t)y.p;
+    return a < b + (uintptr_t)y.n * sizeof(uint32_t) && b < a + (uintptr_t)x.n * sizeof(uint32_t);
+}
+
+// Outputs may overlap neither the inputs nor each other (PM_EINVAL).
+pm_status check_aliasing(std::initializer_list<Span> outs, std::initializer_list<Span> ins) {
+    for (auto o = outs.begin(); o != outs.end(); ++o) {
+        for (const Span& i : ins)
+            if (spans_overlap(*o, i)) return fail(PM_EINVAL, "an output overlaps an input");
+        for (auto o2 = o + 1; o2 != outs.end(); ++o2)
+            if (spans_overlap(*o, *o2)) return fail(PM_EINVAL, "two outputs overlap");
+    }
+    return PM_OK;
+}
+
 // Ordered larger-first for the product kernel: the longer operand is staged
 // in LDS windows, the shorter one is walked step by step.
 void order_operands(const uint32_t*& a, int64_t& na, const uint32_t*& b, int64_t& nb) {
@@ -247,11 +325,20 @@ bool use_mfma(int64_t na, int64_t nb) {
     return lo >= 256 && (double)na * (double)nb >= 40.0e6;
 }
 
+// The matrix-core plan of a product (ordered operands) when that engine
+// takes it: use_mfma's choice, and only a plan whose int32 digit sums stay
+// exact (larger products go to the VALU tiles).
+bool mfma_plan(int64_t na, int64_t nb, int64_t nout, pm::MxGeom* g) {
+    if (!use_mfma(na, nb)) return false;
+    *g = pm::mx_geometry(na, nb, num_cus(), nout);
+    return pm::mx_exact(*g);
+}
+
 pm_status mul_enqueue(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, const pm::Field& F,
                       uint32_t* f, int64_t* d_nf, int32_t* d_status, hipStream_t stream) {
     order_operands(a, na, b, nb);
-    if (use_mfma(na, nb)) {
-        const pm::MxGeom g = pm::mx_geometry(na, nb, num_cus());
+    pm::MxGeom g;
+    if (mfma_plan(na, nb, -1, &g)) {
         Pool* P = nullptr;
         pm_status st = pool_get(stream, pm::mulx_scratch_words(g), &P);
         if (st) return st;
@@ -379,17 +466,55 @@ void pm_get_params(pm_params* params) {
 
 void pm_release(void) {
     std::lock_guard<std::mutex> lk(g_pool_mu);
+    int cur = 0;
+    (void)hipGetDevice(&cur);
     for (auto& kv : g_pools) {
-        int cur = 0;
-        (void)hipGetDevice(&cur);
         (void)hipSetDevice(kv.first.first);
         (void)hipStreamSynchronize(kv.first.second);
-        if (kv.second.words) (void)hipFree(kv.second.words);
-        if (kv.second.d_info) (void)hipFree(kv.second.d_info);
-        if (kv.second.h_info) (void)hipHostFree(kv.second.h_info);
-        (void)hipSetDevice(cur);
+        Pool& P = kv.second.own;
+        if (P.words) (void)hipFree(P.words);
+        if (P.d_info) (void)hipFree(P.d_info);
+        if (P.h_info) (void)hipHostFree(P.h_info);
+        if (kv.second.view.h_info) (void)hipHostFree(kv.second.view.h_info);
     }
+    (void)hipDeviceSynchronize();
+    for (void* w : g_retired) (void)hipFree(w);
+    g_retired.clear();
+    for (auto& kv : g_aux)
+        if (kv.second.w) (void)hipFree(kv.second.w);
+    g_aux.clear();
+    (void)hipSetDevice(cur);
     g_pools.clear();
+}
+
+pm_status pm_set_workspace(void* stream, void* d_words, int64_t words) {
+    if (words < 0 || (words > 0 && !d_words)) return fail(PM_EINVAL, "null workspace or negative size");
+    if (words > 0 && words < INFO_WORDS)
+        return fail(PM_EINVAL, "a workspace needs at least %lld words", (long long)INFO_WORDS);
+    if (((uintptr_t)d_words & 255) != 0) return fail(PM_EINVAL, "the workspace must be 256-byte aligned");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    StreamState& S = g_pools[{dev, s}];
+    // calls already enqueued on the stream may still use the old scratch
+    HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+    if (words == 0) {
+        S.ws = nullptr;
+        S.ws_words = 0;
+        return PM_OK;
+    }
+    if (!S.view.h_info)
+        HIP_TRY(hipHostMalloc((void**)&S.view.h_info, sizeof(pm::CallInfo), hipHostMallocDefault), "hipHostMalloc");
+    // the call results and the grid barrier words start at zero
+    HIP_TRY(hipMemsetAsync(d_words, 0, INFO_WORDS * sizeof(uint32_t), s), "hipMemsetAsync(workspace)");
+    HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+    S.ws = (uint32_t*)d_words;
+    S.ws_words = words;
+    S.view.d_info = (pm::CallInfo*)d_words;
+    S.view.words = (uint32_t*)d_words + INFO_WORDS;
+    S.view.cap = words - INFO_WORDS;
+    return PM_OK;
 }
 
 pm_status poly_mul_modp_async(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, uint32_t p,
@@ -398,6 +523,7 @@ pm_status poly_mul_modp_async(const uint32_t* a, int64_t na, const uint32_t* b, 
     int64_t need = (na > 0 && nb > 0) ? na + nb - 1 : 0;
     if (need > 0 && (f == nullptr || f_cap < need))
         return fail(PM_EINVAL, "f_cap %lld < na + nb - 1 = %lld", (long long)f_cap, (long long)need);
+    if (check_aliasing({{f, need}}, {{a, na}, {b, nb}})) return PM_EINVAL;
     pm::Field F;
     pm_status st = field_for(p, &F);
     if (st) return st;
@@ -443,6 +569,7 @@ pm_status poly_mul_modp_noalloc(const uint32_t* a, int64_t na, const uint32_t* b
     int64_t need = (na > 0 && nb > 0) ? na + nb - 1 : 0;
     if (need > 0 && (f == nullptr || f_cap < need))
         return fail(PM_EINVAL, "f_cap %lld < na + nb - 1 = %lld", (long long)f_cap, (long long)need);
+    if (check_aliasing({{f, need}}, {{a, na}, {b, nb}})) return PM_EINVAL;
     pm::Field F;
     pm_status st = field_for(p, &F);
     if (st) return st;
@@ -452,8 +579,8 @@ pm_status poly_mul_modp_noalloc(const uint32_t* a, int64_t na, const uint32_t* b
     order_operands(a, na, b, nb);
     // the engine poly_mul_modp_async picks, else the VALU tiles, whichever
     // plan's scratch fits the static array (the results are identical)
-    if (use_mfma(na, nb)) {
-        const pm::MxGeom g = pm::mx_geometry(na, nb, num_cus());
+    pm::MxGeom g;
+    if (mfma_plan(na, nb, -1, &g)) {
         if (pm::mulx_scratch_words(g) <= PM_NOALLOC_SCRATCH_WORDS) {
             HIP_TRY(pm::mulx_launch(a, na, b, nb, F, f, g, ws, d_nf, d_status, s), "mul launch");
             return PM_OK;
@@ -497,6 +624,8 @@ pm_status pm_mul_batch_create(const pm_mul_item* items, int32_t count, int32_t r
         if (bad_len(it.a, it.na) || bad_len(it.b, it.nb)) return fail(PM_EINVAL, "item %d: bad input", i);
         const int64_t need = (it.na > 0 && it.nb > 0) ? it.na + it.nb - 1 : 0;
         if (need > 0 && (!it.f || it.f_cap < need)) return fail(PM_EINVAL, "item %d: f_cap < na + nb - 1", i);
+        if (check_aliasing({{it.f, need}}, {{it.a, it.na}, {it.b, it.nb}}))
+            return fail(PM_EINVAL, "item %d: the output overlaps an input", i);
         pm::Field F;
         pm_status st = field_for(it.p, &F);
         if (st) return st;
@@ -575,6 +704,7 @@ pm_status poly_mul_modp(const uint32_t* a, int64_t na, const uint32_t* b, int64_
     int64_t need = (na > 0 && nb > 0) ? na + nb - 1 : 0;
     if (need > 0 && (f == nullptr || f_cap < need))
         return fail(PM_EINVAL, "f_cap %lld < na + nb - 1 = %lld", (long long)f_cap, (long long)need);
+    if (check_aliasing({{f, need}}, {{a, na}, {b, nb}})) return PM_EINVAL;
     pm::Field F;
     pm_status st = field_for(p, &F);
     if (st) return st;
@@ -592,6 +722,49 @@ pm_status poly_mul_modp(const uint32_t* a, int64_t na, const uint32_t* b, int64_
 
 namespace {
 
+// The remainder of a division once q is known: r_k = a_k - (q*b)_k for
+// k < nout (nout = deg b). Only b_0 .. b_{nout-1} and q_0 .. q_{nout-1}
+// reach those exponents, so the product takes nout coefficients of b and
+// nq <= nout of q. Returns the pool it used in *P.
+void remainder_shape(const uint32_t*& x, int64_t& nx, const uint32_t*& y, int64_t& ny, const uint32_t* b,
+                     const uint32_t* q, int64_t nq, int64_t nout) {
+    x = b;
+    nx = nout;
+    y = q;
+    ny = nq;
+    order_operands(x, nx, y, ny);
+}
+
+int64_t remainder_scratch_words(int64_t nq, int64_t nout) {
+    if (nq <= 0 || nout <= 0) return 0;
+    const uint32_t *x = nullptr, *y = nullptr;
+    int64_t nx = 0, ny = 0;
+    remainder_shape(x, nx, y, ny, nullptr, nullptr, nq, nout);
+    pm::MxGeom g;
+    if (mfma_plan(nx, ny, nout, &g)) return pm::mulx_scratch_words(g);
+    return pm::mul_scratch_words(nx, ny, mul_plan(nx, ny));
+}
+
+pm_status remainder_enqueue(const uint32_t* a, const uint32_t* b, const uint32_t* q, int64_t nq, int64_t nout,
+                            const pm::Field& F, uint32_t* r, hipStream_t s, Pool** P) {
+    const uint32_t *x, *y;
+    int64_t nx, ny;
+    remainder_shape(x, nx, y, ny, b, q, nq, nout);
+    pm_status st;
+    pm::MxGeom g;
+    if (mfma_plan(nx, ny, nout, &g)) {
+        if ((st = pool_get(s, pm::mulx_scratch_words(g), P))) return st;
+        HIP_TRY(pm::mulx_launch(x, nx, y, ny, F, r, g, (*P)->words, nullptr, nullptr, s, a, nout),
+                "remainder launch");
+    } else {
+        const pm::MulPlan plan = mul_plan(nx, ny);
+        if ((st = pool_get(s, pm::mul_scratch_words(nx, ny, plan), P))) return st;
+        HIP_TRY(pm::mul_launch(x, nx, y, ny, F, r, plan, (*P)->words, nullptr, nullptr, a, nout, s),
+                "remainder launch");
+    }
+    return PM_OK;
+}
+
 // The division of poly_divrem_modp; also reports deg a and deg b (degs[0],
 // degs[1]) when degs is given.
 pm_status divrem_impl(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, uint32_t p, uint32_t* q,
@@ -601,6 +774,7 @@ pm_status divrem_impl(const uint32_t* a, int64_t na, const uint32_t* b, int64_t 
     if (bad_len(a, na) || bad_len(b, nb)) return fail(PM_EINVAL, "null input or negative length");
     if (q_cap < 0 || r_cap < 0 || (q_cap > 0 && !q) || (r_cap > 0 && !r))
         return fail(PM_EINVAL, "bad output buffer");
+    if (check_aliasing({{q, q_cap}, {r, r_cap}}, {{a, na}, {b, nb}})) return PM_EINVAL;
     if (nb == 0) return fail(PM_EDIVZERO, "division by the zero polynomial");
     if (na - nb + 1 > q_cap) return fail(PM_EINVAL, "q_cap %lld < na - nb + 1", (long long)q_cap);
     pm::Field F;
@@ -636,21 +810,7 @@ pm_status divrem_impl(const uint32_t* a, int64_t na, const uint32_t* b, int64_t 
         *nr = 0;
         return PM_OK;
     }
-    // r_k = a_k - (q*b)_k for k < deg b: only b_0 .. b_{deg b - 1} and
-    // q_0 .. q_{deg b - 1} reach those exponents
-    const uint32_t *x = b, *y = q;
-    int64_t nx = db, ny = mu < db ? mu : db;
-    order_operands(x, nx, y, ny);
-    if (use_mfma(nx, ny)) {
-        const pm::MxGeom g = pm::mx_geometry(nx, ny, num_cus(), db);
-        if ((st = pool_get(s, pm::mulx_scratch_words(g), &P))) return st;
-        HIP_TRY(pm::mulx_launch(x, nx, y, ny, F, r, g, P->words, nullptr, nullptr, s, a, db), "remainder launch");
-    } else {
-        pm::MulPlan plan = mul_plan(nx, ny);
-        int64_t words = pm::mul_scratch_words(nx, ny, plan);
-        if ((st = pool_get(s, words, &P))) return st;
-        HIP_TRY(pm::mul_launch(x, nx, y, ny, F, r, plan, P->words, nullptr, nullptr, a, db, s), "remainder launch");
-    }
+    if ((st = remainder_enqueue(a, b, q, mu < db ? mu : db, db, F, r, s, &P))) return st;
     HIP_TRY(pm::trim_launch(r, db, P->d_info, s), "trim launch");
     if ((st = read_info(P, s))) return st;
     *nr = P->h_info->n1;
@@ -673,6 +833,7 @@ pm_status poly_divrem_modp_naive(const uint32_t* a, int64_t na, const uint32_t* 
     if (bad_len(a, na) || bad_len(b, nb)) return fail(PM_EINVAL, "null input or negative length");
     if (q_cap < 0 || r_cap < 0 || (q_cap > 0 && !q) || (r_cap > 0 && !r))
         return fail(PM_EINVAL, "bad output buffer");
+    if (check_aliasing({{q, q_cap}, {r, r_cap}}, {{a, na}, {b, nb}})) return PM_EINVAL;
     if (nb == 0) return fail(PM_EDIVZERO, "division by the zero polynomial");
     if (na - nb + 1 > q_cap) return fail(PM_EINVAL, "q_cap %lld < na - nb + 1", (long long)q_cap);
     pm::Field F;
@@ -721,6 +882,7 @@ pm_status poly_gcd_modp_naive(const uint32_t* a, int64_t na, const uint32_t* b, 
     if (!ng) return fail(PM_EINVAL, "null ng");
     if (bad_len(a, na) || bad_len(b, nb)) return fail(PM_EINVAL, "null input or negative length");
     if (g_cap < 0 || (g_cap > 0 && !g)) return fail(PM_EINVAL, "bad output buffer");
+    if (check_aliasing({{g, g_cap}}, {{a, na}, {b, nb}})) return PM_EINVAL;
     pm::Field F;
     pm_status st = field_for(p, &F);
     if (st) return st;
@@ -775,13 +937,14 @@ pm_status gcd_batch_jobs(const pm_gcd_item* items, int32_t count, std::vector<pm
         const pm_gcd_item& it = items[i];
         if (bad_len(it.a, it.na) || bad_len(it.b, it.nb) || it.g_cap < 0 || (it.g_cap > 0 && !it.g))
             return fail(PM_EINVAL, "item %d: bad pointer or length", i);
+        if (check_aliasing({{it.g, it.g_cap}}, {{it.a, it.na}, {it.b, it.nb}}))
+            return fail(PM_EINVAL, "item %d: the output overlaps an input", i);
         int64_t n = it.na > it.nb ? it.na : it.nb;
         if (n > PM_GCD_BATCH_MAX)
             return fail(PM_EINVAL, "item %d: %lld terms exceed the batch limit", i, (long long)n);
         pm::Field F;
         pm_status st = field_for(it.p, &F);
         if (st) return st;
-        if (!redc_ok(it.p)) return fail(PM_EMODULUS, "item %d: p = 2 is not supported by the gcd", i);
         jobs[i] = pm::GcdJob{it.a, it.b, it.na, it.nb, it.g, it.g_cap, nullptr, F, 0, 0};
         (n <= pm::gcd_batch_cap(0) ? small : large).push_back(i);
     }
@@ -917,39 +1080,6 @@ namespace {
 // Euclidean division: the chunked steps would take each step of a long
 // quotient alone (its shift is beyond what a chunk's matrix holds).
 constexpr int64_t GCD_LEAD_GAP = 128;
-
-// Scratch apart from the pool that the division and the gcd use, one per
-// purpose: the gcd's leading division (quotient, remainder, folded operand;
-// AUX_LEAD) and the gcd's step log (AUX_TRACE).
-struct Aux {
-    uint32_t* w = nullptr;
-    int64_t cap = 0;
-};
-enum { AUX_LEAD = 0, AUX_TRACE = 1 };
-std::map<std::tuple<int, hipStream_t, int>, Aux> g_aux;  // guarded by g_pool_mu
-
-pm_status aux_get(hipStream_t stream, int64_t words, uint32_t** out, int key = AUX_LEAD) {
-    int dev = 0;
-    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
-    std::lock_guard<std::mutex> lk(g_pool_mu);
-    Aux& X = g_aux[{dev, stream, key}];
-    if (words > X.cap) {
-        if (X.w) {
-            HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
-            HIP_TRY(hipFree(X.w), "hipFree");
-            X.w = nullptr;
-            X.cap = 0;
-        }
-        const int64_t want = words + words / 4 + 1024;
-        if (hipMalloc((void**)&X.w, (size_t)want * sizeof(uint32_t)) != hipSuccess) {
-            X.w = nullptr;
-            return fail(PM_ENOMEM, "cannot allocate %lld scratch words", (long long)want);
-        }
-        X.cap = want;
-    }
-    *out = X.w;
-    return PM_OK;
-}
 
 // The gcd of validated operands on the cooperative kernel, at every size:
 // one call's latency is its step chain, and slices of 512 positions per
@@ -1097,10 +1227,10 @@ pm_status poly_gcd_modp(const uint32_t* a, int64_t na, const uint32_t* b, int64_
     if (!ng) return fail(PM_EINVAL, "null ng");
     if (bad_len(a, na) || bad_len(b, nb)) return fail(PM_EINVAL, "null input or negative length");
     if (g_cap < 0 || (g_cap > 0 && !g)) return fail(PM_EINVAL, "bad output buffer");
+    if (check_aliasing({{g, g_cap}}, {{a, na}, {b, nb}})) return PM_EINVAL;
     pm::Field F;
     pm_status st = field_for(p, &F);
     if (st) return st;
-    if (!redc_ok(p)) return fail(PM_EMODULUS, "p = 2 is not supported by the gcd");
     hipStream_t s = (hipStream_t)stream;
     g_gcd_stats = pm_gcd_stats{0, 0, 0};
     const int64_t gap = na > nb ? na - nb : nb - na;
@@ -1114,10 +1244,10 @@ pm_status poly_gcd_modp_degrees(const uint32_t* a, int64_t na, const uint32_t* b
     if (!ng || !n_degs || degs_cap < 0 || (degs_cap > 0 && !degs)) return fail(PM_EINVAL, "null ng, n_degs or degs");
     if (bad_len(a, na) || bad_len(b, nb)) return fail(PM_EINVAL, "null input or negative length");
     if (g_cap < 0 || (g_cap > 0 && !g)) return fail(PM_EINVAL, "bad output buffer");
+    if (check_aliasing({{g, g_cap}}, {{a, na}, {b, nb}})) return PM_EINVAL;
     pm::Field F;
     pm_status st = field_for(p, &F);
     if (st) return st;
-    if (!redc_ok(p)) return fail(PM_EMODULUS, "p = 2 is not supported by the gcd");
     hipStream_t s = (hipStream_t)stream;
     g_gcd_stats = pm_gcd_stats{0, 0, 0};
     // the trimmed degrees start the sequence
@@ -1150,10 +1280,10 @@ pm_status poly_euclid_steps_modp(const uint32_t* a, int64_t na, const uint32_t* 
     if (k < 0) return fail(PM_EINVAL, "negative step count");
     if (bad_len(a, na) || bad_len(b, nb)) return fail(PM_EINVAL, "null input or negative length");
     if (x_cap < 0 || (x_cap > 0 && !x) || y_cap < 0 || (y_cap > 0 && !y)) return fail(PM_EINVAL, "bad output buffer");
+    if (check_aliasing({{x, x_cap}, {y, y_cap}}, {{a, na}, {b, nb}})) return PM_EINVAL;
     pm::Field F;
     pm_status st = field_for(p, &F);
     if (st) return st;
-    if (!redc_ok(p)) return fail(PM_EMODULUS, "p = 2 is not supported by the gcd");
     hipStream_t s = (hipStream_t)stream;
     const int64_t n = na > nb ? na : nb;
     pm_params pp = params_now();
@@ -1209,10 +1339,10 @@ pm_status poly_xgcd_modp(const uint32_t* a, int64_t na, const uint32_t* b, int64
     if (bad_len(a, na) || bad_len(b, nb)) return fail(PM_EINVAL, "null input or negative length");
     if (g_cap < 0 || (g_cap > 0 && !g) || s_cap < 0 || (s_cap > 0 && !s_out) || t_cap < 0 || (t_cap > 0 && !t_out))
         return fail(PM_EINVAL, "bad output buffer");
+    if (check_aliasing({{g, g_cap}, {s_out, s_cap}, {t_out, t_cap}}, {{a, na}, {b, nb}})) return PM_EINVAL;
     pm::Field F;
     pm_status st = field_for(p, &F);
     if (st) return st;
-    if (!redc_ok(p)) return fail(PM_EMODULUS, "p = 2 is not supported by the gcd");
     hipStream_t hs = (hipStream_t)stream;
     g_gcd_stats = pm_gcd_stats{0, 0, 0};
     *ng = *ns = *nt = 0;
@@ -1339,6 +1469,148 @@ pm_status poly_xgcd_modp(const uint32_t* a, int64_t na, const uint32_t* b, int64
     *ns = nsf;
     *nt = ntf;
     return PM_OK;
+}
+
+pm_status poly_divrem_modp_async(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, uint32_t p,
+                                 uint32_t* q, int64_t q_cap, int64_t* d_nq, uint32_t* r, int64_t r_cap,
+                                 int64_t* d_nr, int32_t* d_status, void* stream) {
+    if (bad_len(a, na) || bad_len(b, nb)) return fail(PM_EINVAL, "null input or negative length");
+    if (q_cap < 0 || r_cap < 0 || (q_cap > 0 && !q) || (r_cap > 0 && !r))
+        return fail(PM_EINVAL, "bad output buffer");
+    if (nb == 0) return fail(PM_EDIVZERO, "division by the zero polynomial");
+    // the launch shapes come from the given lengths: with b[nb - 1] != 0
+    // (checked on the device) the quotient has at most na - nb + 1 terms and
+    // the remainder at most min(na, nb - 1)
+    const int64_t mu_plan = na - nb + 1 > 0 ? na - nb + 1 : 0;
+    const int64_t r_need = na < nb - 1 ? na : nb - 1;
+    if (q_cap < mu_plan) return fail(PM_EINVAL, "q_cap %lld < na - nb + 1", (long long)q_cap);
+    if (r_cap < r_need) return fail(PM_EINVAL, "r_cap %lld < min(na, nb - 1)", (long long)r_cap);
+    if (check_aliasing({{q, q_cap}, {r, r_cap}}, {{a, na}, {b, nb}})) return PM_EINVAL;
+    pm::Field F;
+    pm_status st = field_for(p, &F);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t nq_prod = mu_plan < nb - 1 ? mu_plan : nb - 1;
+    int64_t words = pm::divrem_head_words(na);
+    if (mu_plan > 0) words = std::max(words, remainder_scratch_words(nq_prod, nb - 1));
+    Pool* P = nullptr;
+    if ((st = pool_get(s, words, &P))) return st;
+    pm::CallInfo* info = P->d_info;
+    const pm_params pp = params_now();
+    HIP_TRY(pm::divrem_head_launch(a, na, b, nb, F, q, q_cap, r_cap, P->words, info, pp.div_s > 0 ? pp.div_s : 64,
+                                   num_cus(), s),
+            "divrem head launch");
+    HIP_TRY(pm::divrem_async_fix_launch(q, mu_plan, b, nb, info, s), "quotient fix launch");
+    if (mu_plan == 0) {
+        // na < nb: deg a < deg b for every normalised b, so r = a
+        if (na > 0) HIP_TRY(hipMemcpyAsync(r, a, (size_t)na * 4, hipMemcpyDeviceToDevice, s), "copy r");
+        HIP_TRY(pm::trim_launch(r, na, info, s), "trim launch");
+    } else {
+        // stream order: the product's scratch may reuse the head's (same buffer)
+        Pool* P2 = nullptr;
+        if (nq_prod > 0 && (st = remainder_enqueue(a, b, q, nq_prod, nb - 1, F, r, s, &P2))) return st;
+        HIP_TRY(pm::trim_launch(r, nb - 1, info, s), "trim launch");
+    }
+    HIP_TRY(pm::info_export_launch(info, d_nq, d_nr, d_status, s), "export launch");
+    return PM_OK;
+}
+
+pm_status poly_gcd_modp_async(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, uint32_t p, uint32_t* g,
+                              int64_t g_cap, int64_t* d_ng, int32_t* d_status, void* stream) {
+    if (bad_len(a, na) || bad_len(b, nb)) return fail(PM_EINVAL, "null input or negative length");
+    if (g_cap < 0 || (g_cap > 0 && !g)) return fail(PM_EINVAL, "bad output buffer");
+    if (check_aliasing({{g, g_cap}}, {{a, na}, {b, nb}})) return PM_EINVAL;
+    pm::Field F;
+    pm_status st = field_for(p, &F);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = na > nb ? na : nb;
+    const pm::GcdPlan plan = pm::gcd_default_plan(n > 0 ? n : 1, num_cus(), params_now().gcd_s);
+    Pool* P = nullptr;
+    if ((st = pool_get(s, pm::gcd_scratch_words(n, plan), &P))) return st;
+    HIP_TRY(pm::gcd_launch(a, na, b, nb, F, g, g_cap, P->words, P->d_info, plan, s), "gcd launch");
+    HIP_TRY(pm::info_export_launch(P->d_info, d_ng, nullptr, d_status, s), "export launch");
+    return PM_OK;
+}
+
+pm_status pm_workspace_size(int32_t op, int64_t na, int64_t nb, int64_t* words) {
+    if (!words || na < 0 || nb < 0) return fail(PM_EINVAL, "null words or negative length");
+    int64_t w = 0;
+    if (op == PM_OP_MUL) {
+        const uint32_t *x = nullptr, *y = nullptr;
+        int64_t nx = na, ny = nb;
+        order_operands(x, nx, y, ny);
+        pm::MxGeom g;
+        if (nx > 0 && ny > 0)
+            w = mfma_plan(nx, ny, -1, &g) ? pm::mulx_scratch_words(g) : pm::mul_scratch_words(nx, ny, mul_plan(nx, ny));
+    } else if (op == PM_OP_DIVREM) {
+        w = pm::divrem_head_words(na);
+        const int64_t mu_plan = na - nb + 1;
+        if (nb > 1 && mu_plan > 0) w = std::max(w, remainder_scratch_words(std::min(mu_plan, nb - 1), nb - 1));
+    } else if (op == PM_OP_GCD) {
+        const int64_t n = na > nb ? na : nb;
+        w = pm::gcd_scratch_words(n, pm::gcd_default_plan(n > 0 ? n : 1, num_cus(), params_now().gcd_s));
+    } else {
+        return fail(PM_EINVAL, "unknown operation %d", op);
+    }
+    *words = INFO_WORDS + w;
+    return PM_OK;
+}
+
+pm_status pm_mul_plan(int64_t na, int64_t nb, pm_mul_plan_info* out) {
+    if (!out || na < 0 || nb < 0) return fail(PM_EINVAL, "null out or negative length");
+    *out = pm_mul_plan_info{0, 0, 0, 0, 0, 0};
+    const uint32_t *x = nullptr, *y = nullptr;
+    int64_t nx = na, ny = nb;
+    order_operands(x, nx, y, ny);
+    if (nx <= 0 || ny <= 0) return PM_OK;
+    pm::MxGeom g;
+    if (mfma_plan(nx, ny, -1, &g)) {
+        out->engine = PM_MUL_MFMA;
+        out->s = 4096;
+        out->scratch_words = pm::mulx_scratch_words(g);
+        out->work_groups = g.G;
+        out->max_share_groups = g.maxgrp;
+        return PM_OK;
+    }
+    const pm::MulPlan plan = mul_plan(nx, ny);
+    out->engine = PM_MUL_VALU;
+    out->r = plan.r;
+    out->s = plan.kc;
+    out->scratch_words = pm::mul_scratch_words(nx, ny, plan);
+    return PM_OK;
+}
+
+pm_status pm_autotune_load(const char* path) {
+    if (!path) return fail(PM_EINVAL, "null path");
+    FILE* fh = fopen(path, "r");
+    if (!fh) return fail(PM_EINVAL, "cannot open %s", path);
+    pm_params q = params_now();
+    char line[256];
+    int lineno = 0;
+    pm_status st = PM_OK;
+    while (st == PM_OK && fgets(line, sizeof line, fh)) {
+        lineno++;
+        char* c = strchr(line, '#');
+        if (c) *c = 0;
+        for (char* t = line; *t; t++)
+            if (*t == '=' || *t == ':' || *t == ',') *t = ' ';
+        char key[64];
+        long long v = 0;
+        const int got = sscanf(line, "%63s %lld", key, &v);
+        if (got <= 0) continue;  // blank or comment
+        if (got != 2) { st = fail(PM_EINVAL, "%s:%d: expected a name and an integer", path, lineno); break; }
+        if (v < INT32_MIN || v > INT32_MAX) { st = fail(PM_EINVAL, "%s:%d: value out of range", path, lineno); break; }
+        if (!strcmp(key, "mul_s")) q.mul_s = (int32_t)v;
+        else if (!strcmp(key, "mul_r")) q.mul_r = (int32_t)v;
+        else if (!strcmp(key, "div_s")) q.div_s = (int32_t)v;
+        else if (!strcmp(key, "gcd_s")) q.gcd_s = (int32_t)v;
+        else if (!strcmp(key, "mul_engine")) q.mul_engine = (int32_t)v;
+        else st = fail(PM_EINVAL, "%s:%d: unknown parameter %s", path, lineno, key);
+    }
+    fclose(fh);
+    if (st) return st;
+    return pm_set_params(&q);  // checks every value; nothing changes on an error
 }
 
 pm_status pm_radix_sort_u32(const uint32_t* keys, const uint32_t* vals, int64_t n, int32_t key_bits, int32_t s,

@@ -60,7 +60,9 @@ __device__ __forceinline__ uint64_t fold(uint64_t acc, uint32_t c32) {
 }
 
 // Montgomery reduction: returns x * 2^-32 mod p for x < p * 2^32 / 1.5
-// (callers pass x < 2p^2, p < 2^30), as a canonical residue.
+// (callers pass x < 2p^2, p < 2^30), as a canonical residue. For p = 2 the
+// host sets pinv_neg = 2^31, and the same steps return x mod 2 for
+// x < 2^32 (the only unit mod 2 is 1, so that is the scaled step's value).
 __device__ __forceinline__ uint32_t redc(uint64_t x, const Field& F) {
     uint32_t t = (uint32_t)x * F.pinv_neg;
     uint64_t s = x + (uint64_t)t * F.p;     // divisible by 2^32, no overflow

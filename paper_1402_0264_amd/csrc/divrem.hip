@@ -474,6 +474,29 @@ __global__ __launch_bounds__(256) void sub_kernel(const uint32_t* x, int64_t nx,
         out[i] = submod(i < nx ? x[i] : 0u, i < ny ? y[i] : 0u, p);
 }
 
+// Between the quotient and the remainder product of the asynchronous
+// division, whose product shape is planned from the given lengths: q is
+// zeroed past the true quotient length up to the q_plan words the product
+// reads, and a divisor whose given top coefficient b[nb - 1] is zero is
+// refused (the product would miss the true degree of b).
+__global__ __launch_bounds__(256) void divrem_async_fix_kernel(uint32_t* q, int64_t q_plan, const uint32_t* b,
+                                                               int64_t nb, CallInfo* info) {
+    const int64_t mu = info->n0;  // 0 after an error
+    for (int64_t i = mu + (int64_t)blockIdx.x * 256 + threadIdx.x; i < q_plan; i += (int64_t)gridDim.x * 256)
+        q[i] = 0u;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && info->status == 0 && nb > 0 && b[nb - 1] == 0u)
+        info->status = -1;  // PM_EINVAL
+}
+
+// An asynchronous call's results, from the call's device record to the
+// caller's device words (any of them may be null); lengths are 0 on error.
+__global__ void info_export_kernel(const CallInfo* info, int64_t* d_n0, int64_t* d_n1, int32_t* d_status) {
+    const int32_t st = info->status;
+    if (d_status) *d_status = st;
+    if (d_n0) *d_n0 = st == 0 ? info->n0 : 0;
+    if (d_n1) *d_n1 = st == 0 ? info->n1 : 0;
+}
+
 __global__ __launch_bounds__(256) void trim_kernel(const uint32_t* r, int64_t n, CallInfo* info) {
     if (threadIdx.x < 64) {
         int64_t d = top_nonzero_wave(r, n);
@@ -562,6 +585,20 @@ hipError_t sub_launch(const uint32_t* x, int64_t nx, const uint32_t* y, int64_t 
                       uint32_t p, hipStream_t stream) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(sub_kernel, dim3(elementwise_grid(n)), dim3(256), 0, stream, x, nx, y, ny, n, out, p);
+    return hipGetLastError();
+}
+
+hipError_t divrem_async_fix_launch(uint32_t* q, int64_t q_plan, const uint32_t* b, int64_t nb, CallInfo* info,
+                                   hipStream_t stream) {
+    hipLaunchKernelGGL(divrem_async_fix_kernel, dim3(elementwise_grid(q_plan)), dim3(256), 0, stream, q, q_plan, b,
+                       nb, info);
+    return hipGetLastError();
+}
+
+hipError_t info_export_launch(const CallInfo* info, int64_t* d_n0, int64_t* d_n1, int32_t* d_status,
+                              hipStream_t stream) {
+    if (!d_n0 && !d_n1 && !d_status) return hipSuccess;
+    hipLaunchKernelGGL(info_export_kernel, dim3(1), dim3(1), 0, stream, info, d_n0, d_n1, d_status);
     return hipGetLastError();
 }
 

@@ -89,13 +89,19 @@ struct MxGeom {
     int64_t na, nb;   // a: the plain side, b: the Toeplitz side
     int64_t nab;      // 64-coefficient blocks of a, rounded so that offset ranges start on groups of 8
     int64_t nJ;       // block offsets of b, rounded up to a multiple of 8
-    int64_t nkr;      // output ranges of 2048
+    int64_t nkr;      // output ranges of 4096
     int64_t itot;     // (range, group of 8 offsets) iterations
     int64_t G;        // work-groups (one share each)
     int64_t maxseg;   // most ranges one share touches
+    int64_t maxgrp;   // most groups one share sums
 };
 // nout > 0: only the ranges holding outputs below nout are planned.
 MxGeom mx_geometry(int64_t na, int64_t nb, int num_cus, int64_t nout = -1);
+// The int32 digit sums of a plan are exact: no share sums more than 64
+// groups of 8 block offsets (|sum| < 512 * 64 * 2^14 = 2^29). Products too
+// large for the planner's cap on work-groups fail this and go to the VALU
+// tiles; mulx_launch refuses them.
+bool mx_exact(const MxGeom& g);
 int64_t mulx_scratch_words(const MxGeom& g);
 // f = a*b for na, nb >= 1 and p < 2^30; out_len/out_status as mul_launch.
 // With sub_from, f[k] = sub_from[k] - (a*b)[k]; with nout > 0 only f[k] for
@@ -122,6 +128,15 @@ inline int64_t divrem_head_words(int64_t na) {
 hipError_t divrem_head_launch(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb,
                               const Field& F, uint32_t* q, int64_t q_cap, int64_t r_cap,
                               uint32_t* head, CallInfo* info, int s, int num_cus, hipStream_t stream);
+// Asynchronous division, between the quotient and the remainder product:
+// q[i] = 0 for info->n0 <= i < q_plan, and PM_EINVAL in info->status when
+// b[nb - 1] == 0.
+hipError_t divrem_async_fix_launch(uint32_t* q, int64_t q_plan, const uint32_t* b, int64_t nb, CallInfo* info,
+                                   hipStream_t stream);
+// *d_status = info->status, *d_n0 = info->n0, *d_n1 = info->n1 (lengths 0
+// on error); null pointers are skipped.
+hipError_t info_export_launch(const CallInfo* info, int64_t* d_n0, int64_t* d_n1, int32_t* d_status,
+                              hipStream_t stream);
 // info->n1 = 1 + (largest k < n with r[k] != 0), or 0.
 hipError_t trim_launch(const uint32_t* r, int64_t n, CallInfo* info, hipStream_t stream);
 // out[i] = -x[i] for i < n (out[0] = 0 when drop0)

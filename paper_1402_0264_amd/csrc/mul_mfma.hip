@@ -544,23 +544,28 @@ MxGeom mx_plan(int64_t na, int64_t nb, int num_cus, int64_t nout) {
     if (G > g.itot) G = g.itot;
     if (G > (INT64_C(1) << 20)) G = INT64_C(1) << 20;
     g.G = G;
-    int64_t ms = 1;
+    int64_t ms = 1, mg = 0;
     for (int64_t w = 0; w < G; w++) {
         const int64_t a = mx_share_begin(g, w), b = mx_share_begin(g, w + 1);
         if (a >= b) continue;
         const int64_t s = mx_range_of(g, b - 1) - mx_range_of(g, a) + 1;
         if (s > ms) ms = s;
+        if (b - a > mg) mg = b - a;
     }
     g.maxseg = ms;
+    g.maxgrp = mg;
     return g;
 }
 }  // namespace
+
+bool mx_exact(const MxGeom& g) { return g.maxgrp <= MX_MAXGRP; }
 
 int64_t mulx_scratch_words(const MxGeom& g) { return g.G * g.maxseg * MX_RANGE + g.G; }
 
 hipError_t mulx_launch(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, const Field& F, uint32_t* f,
                        const MxGeom& g, uint32_t* scratch, int64_t* out_len, int32_t* out_status,
                        hipStream_t stream, const uint32_t* sub_from, int64_t nout) {
+    if (!mx_exact(g)) return hipErrorInvalidValue;  // the int32 digit sums could overflow
     MxArgs A{};
     A.a = a;
     A.b = b;

@@ -146,6 +146,23 @@ def tune_gcd_batch(items, candidates=GCD_S_CANDIDATES, reps: int = 2, use_cache:
     return rec
 
 
+PARAM_NAMES = ("mul_s", "mul_r", "div_s", "gcd_s", "mul_engine")
+
+
+def save_params(path: str, params: dict) -> None:
+    """Write tuned parameters (pm_params names, e.g. params_of(tune_mul(...)))
+    as the text file the library's pm_autotune_load applies."""
+    lines = ["# polymodp parameters (pm_autotune_load): name value"]
+    for k, v in params.items():
+        if k not in PARAM_NAMES:
+            raise ValueError("unknown parameter %r" % k)
+        lines.append("%s %d" % (k, int(v)))
+    tmp = path + ".tmp%d" % os.getpid()
+    with open(tmp, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    os.replace(tmp, path)
+
+
 def params_of(rec: dict) -> dict:
     """pm.set_params keywords for a tune_mul result."""
     import paper_1402_0264_amd as pm
