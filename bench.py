@@ -12,14 +12,21 @@ over K steps after W warm-up steps.
 
 Beside it, in the same line:
   roofline      the dominant kernel of the engine that ran (matrix cores:
-                mulx_kernel, 16 int8 digit products per coefficient product,
-                against the dense int8 MFMA peak; VALU tiles: mul_tile_kernel,
-                one 32x32->64-bit multiply-add per coefficient product,
-                against the VALU multiply-add peak): algorithmic operations
-                per launch over its average duration (HIP events around each
-                launch on its stream, same timed steps);
+                mulx_kernel, the method's work of one multiply-add (2
+                operations) per coefficient product against the dense int8
+                MFMA peak, and apart from it the MFMA digit utilisation (16
+                int8 digit products per coefficient product); VALU tiles:
+                mul_tile_kernel, one 32x32->64-bit multiply-add per
+                coefficient product against the VALU multiply-add peak):
+                algorithmic operations per launch over its average duration
+                (HIP events around each launch on its stream, same timed
+                steps), and the measured HBM traffic over the algorithmic
+                bytes;
   cpu_baseline  the CPU oracle timed on this host on a bounded sample of the
-                same product (single thread);
+                same product (single thread), with the CPU model and counts;
+  cpu_baselines the oracle on the other workloads: the gcd and division
+                (one thread), the batched products and the served gcds
+                (one thread on a sample, and a thread pool over instances);
   batched_4096  4096 independent products (degrees log-uniform in [32, 8192])
                 in one persistent launch replayed from a captured graph,
                 tile shape from the autotuner, beside the same products as
@@ -63,6 +70,8 @@ PEAK_MULMOD_PER_S = 256 * 64 * 2.4e9
 PEAK_INT8_OPS_PER_S = 5.0e15
 # int8 digit products per coefficient product on the matrix cores (4 x 4 digits)
 DIGIT_PRODUCTS = 16
+# HBM bytes the degree-65535 product must move: both inputs read, f written once
+ALGO_BYTES_65536 = 4 * (65536 + 65536 + 131071)
 KERNEL_SOURCES = {"mulx_kernel": ("mul_mfma.hip", "common.hpp", "internal.hpp"),
                   "mul_tile_kernel": ("mul.hip", "common.hpp", "internal.hpp")}
 
@@ -114,6 +123,94 @@ def time_steps(fn, steps: int, warmup: int):
     return e0.elapsed_time(e1)
 
 
+def cpu_info() -> dict:
+    """The host the CPU baselines ran on: model name, logical CPUs, the
+    CPUs this process may use, and the pool size the baselines use (the
+    box's thread budget, OMP_NUM_THREADS, when set)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    pool = int(os.environ.get("OMP_NUM_THREADS") or 0) or avail
+    return {"cpu_model": model, "nproc": os.cpu_count(), "cpus_available": avail, "pool_threads": min(pool, avail)}
+
+
+def _pool_map(fn, items, threads: int):
+    """fn over items on a thread pool (the oracle's ctypes calls release
+    the GIL, so the threads run on separate cores)."""
+    import concurrent.futures as cf
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        return list(ex.map(fn, items))
+
+
+def cpu_baselines(reqs, threads: int) -> dict:
+    """The oracle (plain C, no tuning) on the other workloads: one thread,
+    and a pool of `threads` threads over independent instances (batched
+    products, served gcds). Bounded samples where the whole would take
+    minutes; each entry says what it timed."""
+    import oracle
+    from paper_1402_0264_amd import gen
+    oracle.lib()
+    out = {}
+    pl = gen.gcd_32768()
+    p = pl.p
+    a, b = oracle.mul(pl.g, pl.u, p), oracle.mul(pl.g, pl.v, p)
+    t0 = time.perf_counter()
+    g, degs, stats = oracle.gcd(a, b, p, with_info=True)
+    t = time.perf_counter() - t0
+    out["gcd_32768"] = {"kind": "oracle", "threads": 1, "ms": round(t * 1e3, 1), "gcds_per_s": round(1 / t, 3),
+                        "updates": int(stats.updates), "updates_per_s": round(stats.updates / t, 1),
+                        "sample": "the whole gcd (Euclid, one remainder at a time)"}
+    st = gen.Stream(gen.SEED_BASE + 6)
+    da, db = st.uniform_poly(65535, gen.P_A), st.uniform_poly(32767, gen.P_A)
+    t0 = time.perf_counter()
+    oracle.divrem(da, db, gen.P_A)
+    t = time.perf_counter() - t0
+    upd = (da.size - db.size + 1) * db.size
+    out["divrem_65536"] = {"kind": "oracle", "threads": 1, "ms": round(t * 1e3, 1),
+                           "updates_per_s": round(upd / t, 1), "sample": "the whole division"}
+    bt = gen.batch_products()
+    pairs = list(zip(bt.a, bt.b))
+    sample = pairs[::16]
+    work = float(sum(x.size * y.size for x, y in sample))
+    t0 = time.perf_counter()
+    for x, y in sample:
+        oracle.mul(x, y, bt.p)
+    t1 = time.perf_counter() - t0
+    work_all = float(sum(x.size * y.size for x, y in pairs))
+    t0 = time.perf_counter()
+    _pool_map(lambda xy: oracle.mul(xy[0], xy[1], bt.p), pairs, threads)
+    tp = time.perf_counter() - t0
+    out["batched_4096"] = {"kind": "oracle",
+                           "single_thread": {"mulmods_per_s": round(work / t1, 1),
+                                             "sample": "every 16th of the 4096 products (%d), %.3g mulmods"
+                                                       % (len(sample), work)},
+                           "pool": {"threads": threads, "ms": round(tp * 1e3, 1),
+                                    "mulmods_per_s": round(work_all / tp, 1), "sample": "all 4096 products"}}
+    if reqs:
+        one = reqs[:32]
+        t0 = time.perf_counter()
+        for x, y, q, *_ in one:
+            oracle.gcd(x, y, q)
+        t1 = time.perf_counter() - t0
+        many = reqs[:512]
+        t0 = time.perf_counter()
+        _pool_map(lambda r: oracle.gcd(r[0], r[1], r[2]), many, threads)
+        tp = time.perf_counter() - t0
+        out["served"] = {"kind": "oracle",
+                         "single_thread": {"gcds_per_s": round(len(one) / t1, 2),
+                                           "sample": "the first %d requests of the trace, one after another" % len(one)},
+                         "pool": {"threads": threads, "gcds_per_s": round(len(many) / tp, 2),
+                                  "sample": "the first %d requests of the trace on the pool" % len(many)}}
+    return out
+
+
 def cpu_baseline(a, b, p: int, seconds: float) -> dict:
     """The oracle (plain C, one thread) on sampled output coefficients of the
     same product; each f_k is computed in full by the schoolbook definition."""
@@ -132,9 +229,11 @@ def cpu_baseline(a, b, p: int, seconds: float) -> dict:
         el = time.perf_counter() - t0
         if el >= seconds:
             break
-    return {"value": terms / el, "unit": "mulmods/s", "cores": 1, "kind": "oracle",
-            "sample": "%d output coefficients f_k of the degree-65535 product, k uniform, "
-                      "%d coefficient products in %.1f s" % (n, terms, el)}
+    rec = {"value": terms / el, "unit": "mulmods/s", "cores": 1, "kind": "oracle",
+           "sample": "%d output coefficients f_k of the degree-65535 product, k uniform, "
+                     "%d coefficient products in %.1f s" % (n, terms, el)}
+    rec.update(cpu_info())
+    return rec
 
 
 def bench_batched(reps: int) -> dict:
@@ -197,9 +296,19 @@ def _pct(xs, q):
     return xs[max(0, min(len(xs) - 1, int(round(q * len(xs) + 0.5)) - 1))]
 
 
+_SERVED = {}
+
+
 def served_inputs(count: int):
     """The served trace's requests as host arrays; a = g*u and b = g*v are
-    formed with the library's batched product."""
+    formed with the library's batched product (built once per count)."""
+    if count in _SERVED:
+        return _SERVED[count]
+    _SERVED[count] = _served_inputs(count)
+    return _SERVED[count]
+
+
+def _served_inputs(count: int):
     import torch
     import paper_1402_0264_amd as pm
     from paper_1402_0264_amd import gen
@@ -220,11 +329,12 @@ def served_inputs(count: int):
     return reqs
 
 
-def bench_batched_gcd(reqs, one_call_sample: int = 256, reps: int = 3) -> dict:
+def bench_batched_gcd(reqs, one_call_sample: int = 256, reps: int = 3, served=None) -> dict:
     """The served trace's requests as one prepared batch (pm_gcd_batch_*):
     s picked by the autotuner, the run captured in a CUDA graph and
     replayed; beside it, the first requests of the same list as one
     synchronous poly_gcd_modp call each."""
+    import numpy as np
     import torch
     import paper_1402_0264_amd as pm
     from paper_1402_0264_amd import tune
@@ -260,6 +370,11 @@ def bench_batched_gcd(reqs, one_call_sample: int = 256, reps: int = 3) -> dict:
     torch.cuda.synchronize()
     t_one = (time.perf_counter() - t0) / k
     same = all(torch.equal(g1, res[i][0]) for i, g1 in enumerate(singles))
+    # every gcd the server returned for the same requests equals the batch's
+    served_same = None
+    if served is not None:
+        served_same = len(served) == len(res) and all(
+            np.array_equal(served[i], pm.to_numpy(g)) for i, (g, _) in enumerate(res))
     batch.close()
     updates = sum(r["updates"] for _, r in res)
     return {"workload": "the served trace's %d requests (D log-uniform in [64, 16384], three primes) "
@@ -268,20 +383,23 @@ def bench_batched_gcd(reqs, one_call_sample: int = 256, reps: int = 3) -> dict:
             "gcds_per_s": round(len(items) / (ms * 1e-3), 1), "updates_per_s": round(updates / (ms * 1e-3), 1),
             "one_call_per_instance_gcds_per_s": round(1.0 / t_one, 1), "one_call_sample": k,
             "speedup_vs_one_call_per_instance": round((len(items) / (ms * 1e-3)) * t_one, 1),
-            "all_ok": ok, "sample_equals_one_call": same}
+            "all_ok": ok, "sample_equals_one_call": same, "served_results_equal_batch": served_same}
 
 
-def run_server_trace(reqs, scale: float):
+def run_server_trace(reqs, scale: float, keep: bool = False):
     """Submit each request at arrival * scale seconds (the requests that have
     arrived by each pass of the loop go in one submit_many call); returns
-    latencies (ms) and the span from the first arrival to the last
-    completion."""
+    latencies (ms, in completion order, with each one's op), the span from
+    the first arrival to the last completion, and with `keep` the
+    completions by request index. A request is (a, b, p, arrival, D, k) for
+    a gcd, with a seventh element True for a division."""
     import paper_1402_0264_amd as pm
     srv = pm.Server()
     t0 = time.perf_counter()
     i = done = 0
     lat = []
     first = last = None
+    kept = {}
     deadline = time.perf_counter() + 600.0
     while done < len(reqs):
         now = time.perf_counter() - t0
@@ -289,18 +407,21 @@ def run_server_trace(reqs, scale: float):
             raise TimeoutError("served trace did not finish")
         due = []
         while i < len(reqs) and reqs[i][3] * scale <= now:  # every request that has arrived, one call
-            due.append((reqs[i][0], reqs[i][1], reqs[i][2], i))
+            r = reqs[i]
+            due.append((r[0], r[1], r[2], i, len(r) > 6 and r[6]))
             i += 1
         srv.submit_many(due)
         for c in srv.poll():
             if c["status"] != 0:
                 raise RuntimeError("served request %d failed: %d" % (c["tag"], c["status"]))
-            lat.append(c["t_done_ms"] - c["t_submit_ms"])
+            lat.append((c["t_done_ms"] - c["t_submit_ms"], c["op"]))
             first = c["t_submit_ms"] if first is None else min(first, c["t_submit_ms"])
             last = c["t_done_ms"] if last is None else max(last, c["t_done_ms"])
+            if keep:
+                kept[c["tag"]] = c
             done += 1
     srv.close()
-    return lat, (last - first) / 1e3
+    return lat, (last - first) / 1e3, kept
 
 
 def run_one_call_trace(reqs, scale: float):
@@ -327,12 +448,13 @@ def bench_served(n_req: int, warm: int, load: float, baseline: bool, loads=(0.5,
     t_first = reqs[0][3]
     reqs = [(a, b, p, arr - t_first, D, k) for a, b, p, arr, D, k in reqs]
     run_server_trace(warm_reqs, 0.0)
-    lat_sat, span_sat = run_server_trace(reqs, 0.0)      # everything arrives at once
+    lat_sat, span_sat, kept = run_server_trace(reqs, 0.0, keep=True)  # everything arrives at once
     sat = len(reqs) / span_sat
     mean_gap = reqs[-1][3] / max(len(reqs) - 1, 1)         # of the rate-1 trace
     rate = load * sat
     scale = 1.0 / (rate * mean_gap)
-    lat, span = run_server_trace(reqs, scale)
+    lat, span, _ = run_server_trace(reqs, scale)
+    lat = [x for x, _ in lat]
     out = {"workload": "%d gcd requests, D log-uniform in [64, 16384], deg b = D-1, planted gcd degree "
                        "uniform in [0, D/4], p in {469762049, 998244353, 167772161}" % len(reqs),
            "saturated_gcds_per_s": round(sat, 1),
@@ -343,7 +465,8 @@ def bench_served(n_req: int, warm: int, load: float, baseline: bool, loads=(0.5,
     sweep = [{"load": load, "gcds_per_s": out["gcds_per_s"], "p50_ms": out["p50_ms"], "p99_ms": out["p99_ms"]}]
     for ld in loads:
         sc = 1.0 / (ld * sat * mean_gap)
-        l2, sp2 = run_server_trace(reqs, sc)
+        l2, sp2, _ = run_server_trace(reqs, sc)
+        l2 = [x for x, _ in l2]
         sweep.append({"load": ld, "gcds_per_s": round(len(reqs) / sp2, 1), "p50_ms": round(_pct(l2, 0.50), 3),
                       "p99_ms": round(_pct(l2, 0.99), 3)})
     out["loads"] = sorted(sweep, key=lambda x: x["load"])
@@ -356,7 +479,69 @@ def bench_served(n_req: int, warm: int, load: float, baseline: bool, loads=(0.5,
         out["throughput_ratio"] = round(out["gcds_per_s"] / out["one_call_per_instance"]["gcds_per_s"], 2)
         out["p99_ratio_one_call_over_served"] = round(out["one_call_per_instance"]["p99_ms"] / out["p99_ms"], 2)
     torch.cuda.synchronize()
+    out["_results"] = {t: c["g"] for t, c in kept.items()}  # checked against the batch, then dropped
     return out
+
+
+def bench_served_mixed(n_req: int, warm: int, load: float) -> dict:
+    """A Poisson stream of gcd and division requests (a quarter divisions:
+    a of degree D, b of degree D/2) through the same server: saturated
+    requests/s, then p50/p99 per kind at `load` of that rate. Every
+    division is checked against the oracle (on a thread pool), every gcd
+    against the prepared batch's result for the same pair."""
+    import numpy as np
+    import torch
+    import oracle
+    import paper_1402_0264_amd as pm
+    from paper_1402_0264_amd import gen
+    trace = gen.served_mixed_trace(n_req + warm, rate=1.0)
+    gi = [i for i, r in enumerate(trace) if isinstance(r, gen.Request)]
+    items = []
+    for i in gi:
+        g = pm.to_device(trace[i].factors.g)
+        items += [(g, pm.to_device(trace[i].factors.u), trace[i].p), (g, pm.to_device(trace[i].factors.v), trace[i].p)]
+    prods = []
+    for lo in range(0, len(items), 1024):
+        b = pm.MulBatch(items[lo:lo + 1024])
+        b.run()
+        torch.cuda.synchronize()
+        prods += [pm.to_numpy(f) for f in b.outputs]
+        b.close()
+    reqs = []
+    j = 0
+    for r in trace:
+        if isinstance(r, gen.Request):
+            reqs.append((prods[2 * j], prods[2 * j + 1], r.p, r.arrival, r.D, r.k, False))
+            j += 1
+        else:
+            reqs.append((r.a, r.b, r.p, r.arrival, r.D, 0, True))
+    warm_reqs, reqs = reqs[:warm], reqs[warm:]
+    t_first = reqs[0][3]
+    reqs = [(a, b, p, arr - t_first, D, k, d) for a, b, p, arr, D, k, d in reqs]
+    run_server_trace(warm_reqs, 0.0)
+    lat_sat, span_sat, kept = run_server_trace(reqs, 0.0, keep=True)
+    sat = len(reqs) / span_sat
+    mean_gap = reqs[-1][3] / max(len(reqs) - 1, 1)
+    lat, span, _ = run_server_trace(reqs, 1.0 / (load * sat * mean_gap))
+    gl = [x for x, op in lat if op != pm.PM_OP_DIVREM]
+    dl = [x for x, op in lat if op == pm.PM_OP_DIVREM]
+    # checks: divisions against the oracle, gcds against the prepared batch
+    divs = [i for i, r in enumerate(reqs) if r[6]]
+    threads = cpu_info()["pool_threads"]
+    want = _pool_map(lambda i: oracle.divrem(reqs[i][0], reqs[i][1], reqs[i][2]), divs, threads)
+    div_ok = all(np.array_equal(kept[i]["q"], w[0]) and np.array_equal(kept[i]["r"], w[1])
+                 for i, w in zip(divs, want))
+    gcds = [i for i, r in enumerate(reqs) if not r[6]]
+    res = pm.gcd_batch([(pm.to_device(reqs[i][0]), pm.to_device(reqs[i][1]), reqs[i][2]) for i in gcds])
+    gcd_ok = all(r["status"] == 0 and np.array_equal(kept[i]["g"], pm.to_numpy(g)) for i, (g, r) in zip(gcds, res))
+    return {"workload": "%d requests, a quarter of them divisions (deg a = D, deg b = D/2) and the rest gcds as "
+                        "in the served trace, D log-uniform in [64, 16384], three primes" % len(reqs),
+            "divisions": len(divs), "gcds": len(gcds),
+            "saturated_requests_per_s": round(sat, 1), "load": load,
+            "requests_per_s": round(len(reqs) / span, 1),
+            "gcd_p50_ms": round(_pct(gl, 0.50), 3), "gcd_p99_ms": round(_pct(gl, 0.99), 3),
+            "divrem_p50_ms": round(_pct(dl, 0.50), 3), "divrem_p99_ms": round(_pct(dl, 0.99), 3),
+            "divisions_equal_oracle": bool(div_ok), "gcds_equal_batch": bool(gcd_ok)}
 
 
 def bench_product_2048(reps: int) -> dict:
@@ -558,16 +743,24 @@ def main() -> int:
     tile_avg_ms = ms_tile / max(n_tile, 1)
     achieved = work / (tile_avg_ms * 1e-3)
     if mfma:
-        ops = 2.0 * DIGIT_PRODUCTS * work
-        roof = {"bound": "mfma", "achieved": round(ops / (tile_avg_ms * 1e-3) / 1e12, 1),
+        # the method's work: one multiply-add (2 operations) per coefficient
+        # product, against the dense int8 matrix-core peak; the matrix cores
+        # spend 16 int8 digit products on each, reported apart as their use
+        ops = 2.0 * work
+        roof = {"bound": "mfma", "achieved": round(ops / (tile_avg_ms * 1e-3) / 1e12, 2),
                 "peak": round(PEAK_INT8_OPS_PER_S / 1e12, 1), "unit": "TOP/s",
-                "frac": round(ops / (tile_avg_ms * 1e-3) / PEAK_INT8_OPS_PER_S, 4)}
+                "frac": round(ops / (tile_avg_ms * 1e-3) / PEAK_INT8_OPS_PER_S, 4),
+                "mfma_digit_utilisation": round(2.0 * DIGIT_PRODUCTS * work / (tile_avg_ms * 1e-3)
+                                                / PEAK_INT8_OPS_PER_S, 4)}
     else:
         roof = {"bound": "alu", "achieved": round(achieved / 1e12, 3),
                 "peak": round(PEAK_MULMOD_PER_S / 1e12, 3), "unit": "Tmulmod/s",
                 "frac": round(achieved / PEAK_MULMOD_PER_S, 4)}
-    roof.update({"traffic": traffic_for(kernel), "kernel": kernel, "kernel_avg_ms": round(tile_avg_ms, 5),
-                 "kernel_Tmulmod_per_s": round(achieved / 1e12, 2), "launches": n_tile})
+    traffic = traffic_for(kernel)
+    roof.update({"traffic": traffic, "kernel": kernel, "kernel_avg_ms": round(tile_avg_ms, 5),
+                 "kernel_Tmulmod_per_s": round(achieved / 1e12, 2), "launches": n_tile,
+                 "algorithmic_bytes": ALGO_BYTES_65536,
+                 "traffic_over_algorithmic": round(traffic / ALGO_BYTES_65536, 2) if traffic else None})
     if n_red:  # the VALU engine's addition phase carries timing events; the matrix cores' does not
         roof["reduce_avg_ms"] = round(ms_red / n_red, 5)
     out = {
@@ -599,10 +792,19 @@ def main() -> int:
         out["gcd_32768"] = bench_gcd(args.gcd_reps)
     if not args.no_served:
         out["served"] = bench_served(args.served_requests, 128, 0.8, not args.no_served_baseline)
+    if not args.no_served:
+        out["served_mixed"] = bench_served_mixed(args.served_requests, 128, 0.8)
     if not args.no_batched:
-        out["batched_gcd"] = bench_batched_gcd(served_inputs(args.served_requests))
+        # the served measurement's requests (after its warm-up ones), so the
+        # server's results can be compared one by one
+        out["batched_gcd"] = bench_batched_gcd(served_inputs(args.served_requests + 128)[128:],
+                                               served=out.get("served", {}).pop("_results", None))
+    if "served" in out:
+        out["served"].pop("_results", None)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(a_np, b_np, p, args.cpu_seconds)
+        reqs = None if args.no_served else served_inputs(args.served_requests + 128)[128:]
+        out["cpu_baselines"] = cpu_baselines(reqs, out["cpu_baseline"]["pool_threads"])
     print(json.dumps(out), flush=True)
     return 0
 

@@ -299,6 +299,7 @@ typedef struct {
     int64_t chunks;   /* fused chunks                                     */
     int32_t status;   /* PM_OK or the item's device-side error            */
     int32_t done;     /* 1 once the item finished                         */
+    int64_t nr;       /* 0 (the server's division requests use it)        */
 } pm_gcd_result;
 pm_status poly_gcd_modp_batch(const pm_gcd_item *items, int32_t count, pm_gcd_result *results, void *stream);
 /*
@@ -320,55 +321,78 @@ pm_status pm_gcd_batch_results(pm_gcd_batch *batch, pm_gcd_result *results, void
 void pm_gcd_batch_destroy(pm_gcd_batch *batch);
 
 /*
- * GCD server with continuous batching. Requests of mixed degree (up to
- * PM_GCD_BATCH_MAX terms) and prime are queued by pm_server_submit (inputs
- * are copied; the caller may reuse its arrays at once). pm_server_submit
- * and pm_server_poll admit queued requests in arrival order while a slot
- * (max_inflight) and room in the resident-input budget (arena_words) are
- * free; admitted requests are published to the GPU at once, their inputs
- * staged in pinned memory mapped into the device's address space.
- * pm_server_poll returns the requests that finished since the last poll.
- * A persistent worker kernel (one block per CU) runs the published
- * requests one block each, taking the next one as soon as it finishes, so
- * requests join and leave the GPU individually. Each request's remainder
- * sequence stays in its block's LDS until its monic gcd is written to the
- * caller's host buffer g (done by the time the completion is returned).
- * The worker stops by itself after an idle period and is relaunched when
- * work arrives; pm_server_destroy stops it and waits for it.
+ * Server with continuous batching of gcd and division requests. Requests
+ * of mixed degree (up to PM_GCD_BATCH_MAX terms per operand), prime and
+ * kind are queued by pm_server_submit (inputs are copied; the caller may
+ * reuse its arrays at once). pm_server_submit and pm_server_poll admit
+ * queued requests in arrival order while a slot (max_inflight) and room in
+ * the device-memory arena (arena_words) for the request's inputs, and in
+ * the host output arena for its outputs, are free. An admitted request's
+ * inputs are copied into the device arena (one copy per admission pass on
+ * a copy stream); the request is published to the GPU once its copy has
+ * completed. pm_server_poll returns the requests that finished since the
+ * last poll.
+ * Two persistent worker kernels run the published requests, one thread-
+ * block each, taking the next one as soon as one finishes, so requests
+ * join and leave the GPU individually: requests whose operands fit 4096
+ * terms go to blocks of 256 threads (several per CU), larger ones to
+ * blocks of 1024 threads (one per CU). Each request's remainder sequence
+ * (or division) stays in its block's LDS until its results are written to
+ * the caller's host buffers (done by the time the completion is returned).
+ * The workers stop by themselves after an idle period and are relaunched
+ * when work arrives (the 1024-thread worker first, so that the other
+ * fills the CUs it leaves); pm_server_destroy stops them and waits.
  * Not thread-safe: one host thread drives a server. Times are milliseconds
  * on the server's steady clock.
  */
 typedef struct pm_server pm_server;
 typedef struct {
-    int32_t max_inflight;  /* requests admitted at once (0 = 1024)             */
-    int32_t streams;       /* unused, 0                                        */
-    int64_t arena_words;   /* budget of resident input words (0 = 32 Mi)       */
-    int32_t s;             /* Euclidean steps fused per chunk (0 = 128)        */
-    int32_t reserved;
+    int32_t max_inflight;  /* requests admitted at once (0 = 4096)                       */
+    int32_t large_blocks;  /* blocks of the 1024-thread worker (0 = 7/8 of the CUs)      */
+    int64_t arena_words;   /* device words for resident inputs (0 = 32 Mi, or less when
+                            * the device has less than 8 times that free); the host
+                            * output arena has as many words                              */
+    int32_t s;             /* Euclidean steps fused per chunk (0 = 128)                   */
+    int32_t small_blocks;  /* blocks of the 256-thread worker (0 = fill the other CUs,
+                            * -1 = none: every request on the 1024-thread worker)         */
 } pm_server_opts;
+/* A request: op PM_OP_GCD (or 0) asks for the monic gcd of a and b, written
+ * to g; PM_OP_DIVREM asks for the division of a by b (Sec. 3's problem:
+ * a = q b + r, deg r < deg b), q written to g and r to r. */
 typedef struct {
     const uint32_t *a;     /* host arrays */
     int64_t na;
     const uint32_t *b;
     int64_t nb;
     uint32_t p;
-    uint32_t *g;           /* host output, g_cap words */
+    uint32_t *g;           /* host output, g_cap words: the gcd, or q      */
     int64_t g_cap;
     uint64_t tag;          /* returned in the completion */
+    int32_t op;            /* PM_OP_GCD (0 also) or PM_OP_DIVREM          */
+    int32_t reserved;
+    uint32_t *r;           /* division: host output r, r_cap words        */
+    int64_t r_cap;
 } pm_gcd_request;
+typedef pm_gcd_request pm_request;
 typedef struct {
     uint64_t ticket;
     uint64_t tag;
     int32_t status;
-    int32_t reserved;
-    int64_t ng;
+    int32_t op;            /* the request's op                           */
+    int64_t ng;            /* length of the gcd, or of q                 */
     int64_t steps;
     int64_t updates;
     double t_submit_ms;    /* pm_server_submit                          */
-    double t_start_ms;     /* admitted and published to the GPU         */
+    double t_start_ms;     /* published to the GPU                      */
     double t_done_ms;      /* seen finished by pm_server_poll           */
+    int64_t nr;            /* division: length of r                     */
 } pm_completion;
 pm_status pm_server_create(const pm_server_opts *opts, pm_server **out);
+/* Errors found on the host (bad buffers, a request above PM_GCD_BATCH_MAX
+ * terms or above the whole arena, a modulus that is not a prime below 2^30,
+ * b = 0 with nb = 0 for a division) return at once and queue nothing;
+ * errors found on the device (a coefficient >= p, a zero divisor, outputs
+ * too short for the true degrees) come back in the completion's status. */
 pm_status pm_server_submit(pm_server *srv, const pm_gcd_request *req, uint64_t *ticket);
 /* count requests in one call (tickets: count entries, or NULL); all are
  * checked first, so an error queues none of them. The requests of one call

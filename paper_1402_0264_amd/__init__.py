@@ -43,7 +43,8 @@ class GcdItem(ctypes.Structure):
 
 class GcdResult(ctypes.Structure):
     _fields_ = [("ng", ctypes.c_int64), ("steps", ctypes.c_int64), ("updates", ctypes.c_int64),
-                ("chunks", ctypes.c_int64), ("status", ctypes.c_int32), ("done", ctypes.c_int32)]
+                ("chunks", ctypes.c_int64), ("status", ctypes.c_int32), ("done", ctypes.c_int32),
+                ("nr", ctypes.c_int64)]
 
 
 GCD_BATCH_MAX = 17408
@@ -56,33 +57,35 @@ class MulItem(ctypes.Structure):
 
 
 class ServerOpts(ctypes.Structure):
-    _fields_ = [("max_inflight", ctypes.c_int32), ("streams", ctypes.c_int32), ("arena_words", ctypes.c_int64),
-                ("s", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+    _fields_ = [("max_inflight", ctypes.c_int32), ("large_blocks", ctypes.c_int32), ("arena_words", ctypes.c_int64),
+                ("s", ctypes.c_int32), ("small_blocks", ctypes.c_int32)]
 
 
 class GcdRequest(ctypes.Structure):
     _fields_ = [("a", ctypes.c_void_p), ("na", ctypes.c_int64), ("b", ctypes.c_void_p), ("nb", ctypes.c_int64),
                 ("p", ctypes.c_uint32), ("g", ctypes.c_void_p), ("g_cap", ctypes.c_int64),
-                ("tag", ctypes.c_uint64)]
+                ("tag", ctypes.c_uint64), ("op", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("r", ctypes.c_void_p), ("r_cap", ctypes.c_int64)]
 
 
 # pm_gcd_request as a numpy record (same field offsets as GcdRequest)
 
 def _req_dtype():
     import numpy as np
-    return np.dtype({"names": ["a", "na", "b", "nb", "p", "g", "g_cap", "tag"],
-                     "formats": ["<u8", "<i8", "<u8", "<i8", "<u4", "<u8", "<i8", "<u8"],
+    return np.dtype({"names": ["a", "na", "b", "nb", "p", "g", "g_cap", "tag", "op", "r", "r_cap"],
+                     "formats": ["<u8", "<i8", "<u8", "<i8", "<u4", "<u8", "<i8", "<u8", "<i4", "<u8", "<i8"],
                      "offsets": [GcdRequest.a.offset, GcdRequest.na.offset, GcdRequest.b.offset,
                                  GcdRequest.nb.offset, GcdRequest.p.offset, GcdRequest.g.offset,
-                                 GcdRequest.g_cap.offset, GcdRequest.tag.offset],
+                                 GcdRequest.g_cap.offset, GcdRequest.tag.offset, GcdRequest.op.offset,
+                                 GcdRequest.r.offset, GcdRequest.r_cap.offset],
                      "itemsize": ctypes.sizeof(GcdRequest)})
 
 
 class Completion(ctypes.Structure):
     _fields_ = [("ticket", ctypes.c_uint64), ("tag", ctypes.c_uint64), ("status", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("ng", ctypes.c_int64), ("steps", ctypes.c_int64),
+                ("op", ctypes.c_int32), ("ng", ctypes.c_int64), ("steps", ctypes.c_int64),
                 ("updates", ctypes.c_int64), ("t_submit_ms", ctypes.c_double), ("t_start_ms", ctypes.c_double),
-                ("t_done_ms", ctypes.c_double)]
+                ("t_done_ms", ctypes.c_double), ("nr", ctypes.c_int64)]
 
 
 class MulPlanInfo(ctypes.Structure):
@@ -573,39 +576,35 @@ def gcd_batch(pairs, stream=None):
 
 
 class Server:
-    """Continuous-batching gcd server (pm_server_*). Inputs and outputs are
-    host numpy arrays; ``submit`` returns a ticket, ``poll`` returns the
-    finished requests as dicts with the monic gcd ``g``."""
+    """Continuous-batching server of gcd and division requests (pm_server_*).
+    Inputs and outputs are host numpy arrays; ``submit`` returns a ticket,
+    ``poll`` returns the finished requests as dicts: the monic gcd ``g``, or
+    for a division (``divrem=True``) the quotient ``q`` and remainder ``r``."""
 
-    def __init__(self, max_inflight: int = 0, streams: int = 0, arena_words: int = 0, s: int = 0):
+    def __init__(self, max_inflight: int = 0, large_blocks: int = 0, arena_words: int = 0, s: int = 0,
+                 small_blocks: int = 0):
         self.handle = ctypes.c_void_p()
-        _check(lib().pm_server_create(ctypes.byref(ServerOpts(max_inflight, streams, arena_words, s, 0)),
+        _check(lib().pm_server_create(ctypes.byref(ServerOpts(max_inflight, large_blocks, arena_words, s,
+                                                              small_blocks)),
                                       ctypes.byref(self.handle)))
         self._out = {}
         self._buf = (Completion * 512)()
 
-    def submit(self, a, b, p: int, tag: int = 0) -> int:
-        import numpy as np
-        a = np.ascontiguousarray(np.asarray(a, dtype=np.uint32))
-        b = np.ascontiguousarray(np.asarray(b, dtype=np.uint32))
-        g = np.zeros(max(a.size, b.size, 1), dtype=np.uint32)
-        req = GcdRequest(a.ctypes.data if a.size else None, a.size, b.ctypes.data if b.size else None, b.size, p,
-                         g.ctypes.data, g.size, tag)
-        t = ctypes.c_uint64(0)
-        _check(lib().pm_server_submit(self.handle, ctypes.byref(req), ctypes.byref(t)))
-        self._out[t.value] = g
-        return t.value
+    def submit(self, a, b, p: int, tag: int = 0, divrem: bool = False) -> int:
+        return self.submit_many([(a, b, p, tag, divrem)])[0]
 
     def submit_many(self, reqs) -> list:
-        """Submits [(a, b, p, tag), ...] in one call; returns the tickets. The
-        request records are built as one numpy array with the layout of
-        pm_gcd_request, and the outputs are views of one buffer."""
+        """Submits [(a, b, p, tag[, divrem]), ...] in one call; returns the
+        tickets. The request records are built as one numpy array with the
+        layout of pm_gcd_request, and the outputs are views of one buffer
+        (g, or q then r: max(na, nb) words each)."""
         import numpy as np
         n = len(reqs)
         if n == 0:
             return []
         ins = []
-        for a, b, p, tag in reqs:
+        for r in reqs:
+            a, b = r[0], r[1]
             if not (isinstance(a, np.ndarray) and a.dtype == np.uint32 and a.flags.c_contiguous):
                 a = np.ascontiguousarray(np.asarray(a, dtype=np.uint32))
             if not (isinstance(b, np.ndarray) and b.dtype == np.uint32 and b.flags.c_contiguous):
@@ -613,25 +612,31 @@ class Server:
             ins.append((a, b))
         na = np.fromiter((x[0].size for x in ins), dtype=np.int64, count=n)
         nb = np.fromiter((x[1].size for x in ins), dtype=np.int64, count=n)
+        div = np.fromiter((bool(r[4]) if len(r) > 4 else False for r in reqs), dtype=bool, count=n)
         cap = np.maximum(np.maximum(na, nb), 1)
+        words = np.where(div, 2 * cap, cap)
         offs = np.zeros(n, dtype=np.int64)
-        np.cumsum(cap[:-1], out=offs[1:])
-        gbuf = np.zeros(int(offs[-1] + cap[-1]), dtype=np.uint32)
+        np.cumsum(words[:-1], out=offs[1:])
+        gbuf = np.zeros(int(offs[-1] + words[-1]), dtype=np.uint32)
         rec = np.zeros(n, dtype=_req_dtype())
         rec["a"] = np.fromiter((x[0].ctypes.data if x[0].size else 0 for x in ins), dtype=np.uint64, count=n)
         rec["na"] = na
         rec["b"] = np.fromiter((x[1].ctypes.data if x[1].size else 0 for x in ins), dtype=np.uint64, count=n)
         rec["nb"] = nb
         rec["p"] = np.fromiter((r[2] for r in reqs), dtype=np.uint32, count=n)
-        rec["g"] = gbuf.ctypes.data + 4 * offs.astype(np.uint64)
+        base = np.uint64(gbuf.ctypes.data)
+        rec["g"] = base + 4 * offs.astype(np.uint64)
         rec["g_cap"] = cap
         rec["tag"] = np.fromiter((r[3] for r in reqs), dtype=np.uint64, count=n)
+        rec["op"] = np.where(div, PM_OP_DIVREM, PM_OP_GCD)
+        rec["r"] = np.where(div, base + 4 * (offs + cap).astype(np.uint64), np.uint64(0))
+        rec["r_cap"] = np.where(div, cap, 0)
         tickets = np.zeros(n, dtype=np.uint64)
         _check(lib().pm_server_submit_batch(self.handle, ctypes.cast(rec.ctypes.data, ctypes.POINTER(GcdRequest)),
                                             n, ctypes.cast(tickets.ctypes.data, ctypes.POINTER(ctypes.c_uint64))))
         for i in range(n):
-            o = int(offs[i])
-            self._out[int(tickets[i])] = gbuf[o:o + int(cap[i])]
+            o, c = int(offs[i]), int(cap[i])
+            self._out[int(tickets[i])] = (gbuf[o:o + c], gbuf[o + c:o + 2 * c] if div[i] else None)
         return [int(t) for t in tickets]
 
     def poll(self) -> list:
@@ -640,10 +645,16 @@ class Server:
         done = []
         for i in range(n.value):
             c = self._buf[i]
-            g = self._out.pop(c.ticket)
-            done.append({"ticket": c.ticket, "tag": c.tag, "status": c.status, "g": g[:c.ng].copy(),
-                         "steps": c.steps, "updates": c.updates, "t_submit_ms": c.t_submit_ms,
-                         "t_start_ms": c.t_start_ms, "t_done_ms": c.t_done_ms})
+            g, r = self._out.pop(c.ticket)
+            d = {"ticket": c.ticket, "tag": c.tag, "status": c.status, "op": c.op, "steps": c.steps,
+                 "updates": c.updates, "t_submit_ms": c.t_submit_ms, "t_start_ms": c.t_start_ms,
+                 "t_done_ms": c.t_done_ms}
+            if c.op == PM_OP_DIVREM:
+                d["q"] = g[:c.ng].copy()
+                d["r"] = r[:c.nr].copy()
+            else:
+                d["g"] = g[:c.ng].copy()
+            done.append(d)
         return done
 
     def pending(self) -> int:

@@ -766,9 +766,152 @@ __device__ void gcd_instance(const GcdJob& J, int s, int64_t cap, uint32_t* smem
     if (tid == 0) {
         J.out->status = status;
         J.out->ng = status == 0 ? dR + 1 : 0;
+        J.out->nr = 0;
         J.out->steps = steps;
         J.out->updates = updates;
         J.out->chunks = chunks;
+        __threadfence_system();
+        __hip_atomic_store(&J.out->done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
+// One Euclidean division (Sec. 3) on the calling block, both operands in
+// LDS (a request of the server). The quotient comes s = 64 terms per chunk,
+// from the top down: the chunk's terms u_i = q_(jtop - i) solve the
+// triangular system sum_(k<=i) beta_(i-k) u_k = v_i on the chunk's current
+// head values v, with beta_d = b[deg b - d], so u = G v mod x^64 where G is
+// the inverse of sum beta_d x^d (64 serial steps on one wave, once); then
+// every position of a below the chunk takes the chunk's terms at once:
+// a[x] -= sum_i u_i b[x - jtop + i]. What remains below deg b is r. Writes
+// q to J.g, r to J.r and the result record (lengths, steps = the quotient's
+// positions, updates = steps * (deg b + 1)).
+template <int NT>
+__device__ void div_instance(const GcdJob& J, int64_t cap, uint32_t* smem) {
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const Field F = J.F;
+    uint32_t* A = smem + PADLO;      // cap words (+PADLO zeros below)
+    uint32_t* B = A + cap + PADLO;   // cap words (+PADLO zeros below)
+    uint32_t* sG = B + cap;          // 64: G_k
+    uint32_t* sU = sG + 64;          // 64: the chunk's quotient terms
+    __shared__ int64_t s_deg[2];
+    const int64_t n = J.na > J.nb ? J.na : J.nb;
+    int bad = n > cap;
+    if (tid < PADLO) { A[tid - PADLO] = 0u; B[tid - PADLO] = 0u; }
+    for (int64_t i = tid; i < cap; i += NT) {
+        uint32_t x, y;
+        if (J.fresh) {
+            x = i < J.na ? __hip_atomic_load(J.a + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) : 0u;
+            y = i < J.nb ? __hip_atomic_load(J.b + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) : 0u;
+        } else {
+            x = i < J.na ? J.a[i] : 0u;
+            y = i < J.nb ? J.b[i] : 0u;
+        }
+        bad |= (x >= F.p) | (y >= F.p);
+        A[i] = x;
+        B[i] = y;
+    }
+    bad = __syncthreads_or(bad);
+    int64_t da = -1, db = -1;
+    if (!bad) {
+        if (wave < 2) {
+            const int64_t d = top_nonzero_wave(wave == 0 ? A : B, cap);
+            if (lane == 0) s_deg[wave] = d;
+        }
+        __syncthreads();
+        da = uni(s_deg[0]);
+        db = uni(s_deg[1]);
+    }
+    int status = bad ? (n > cap ? -1 : -3) : 0;       // PM_EINVAL / PM_ERANGE
+    if (status == 0 && db < 0) status = -4;           // PM_EDIVZERO
+    const int64_t mu = (status == 0 && da >= db) ? da - db + 1 : 0;
+    const int64_t nr_max = da < db ? da + 1 : db;
+    if (status == 0 && (mu > J.g_cap || nr_max > J.r_cap)) status = -1;  // PM_EINVAL
+    if (status == 0 && mu > 0) {
+        // G = (sum_(d<64) beta_d x^d)^(-1) mod x^64: lane k holds the pending
+        // coefficient of x^k of the series 1 being divided
+        if (wave == 0) {
+            const uint32_t beta = lane <= db ? B[db - lane] : 0u;
+            sU[lane] = beta;
+            const uint32_t inv = invmod(B[db], F);
+            uint32_t val = lane == 0 ? 1u : 0u;
+            for (int j = 0; j < 64; j++) {
+                const uint32_t gj = mulmod((uint32_t)__builtin_amdgcn_readlane((int)val, j), inv, F);
+                if (lane > j) val = submod(val, mulmod(gj, sU[lane - j], F), F.p);
+                if (lane == j) sG[j] = gj;
+            }
+        }
+        __syncthreads();
+        const uint32_t half = F.fold_every / 2;
+        for (int64_t jtop = mu - 1; jtop >= 0; jtop -= 64) {
+            const int S = (int)(jtop + 1 < 64 ? jtop + 1 : 64);
+            const int64_t top = jtop + db;  // a-position of q_jtop
+            if (wave == 0) {
+                // u_i = sum_(k<=i) G_(i-k) v_k, v_k = a[top - k]
+                const uint32_t v = lane < S ? A[top - lane] : 0u;
+                uint64_t acc = 0;
+                uint32_t cnt = 0;
+                for (int k = 0; k < S; k++) {
+                    const uint32_t vk = (uint32_t)__builtin_amdgcn_readlane((int)v, k);
+                    if (lane >= k) acc += (uint64_t)sG[lane - k] * vk;
+                    if (++cnt == half) {
+                        acc = fold(acc, F.c32);
+                        cnt = 0;
+                    }
+                }
+                const uint32_t u = lane < S ? reduce64(acc, F) : 0u;
+                sU[lane] = u;
+                if (lane < S) J.g[jtop - lane] = u;
+            }
+            __syncthreads();
+            // positions jtop - S + 1 .. top - S below the chunk; b is zero
+            // outside 0..db (PADLO zeros below, zeros loaded above)
+            // the loop runs the same passes on every lane of a wave (the lane
+            // reads of u need every lane active) and only the store is
+            // guarded; a lane past the last position computes a clamped one
+            const uint32_t u_reg = sU[lane];
+            const int64_t lo = jtop - S + 1 > 0 ? jtop - S + 1 : 0, hi = top - S;
+            for (int64_t x0 = lo + (tid - lane); x0 <= hi; x0 += NT) {
+                const int64_t x = x0 + lane;
+                const uint32_t* bw = B + ((x <= hi ? x : hi) - jtop);
+                uint64_t acc = 0;
+                uint32_t cnt = 0;
+                for (int i = 0; i < S; i++) {
+                    const uint32_t ui = (uint32_t)__builtin_amdgcn_readlane((int)u_reg, i);
+                    acc += (uint64_t)ui * bw[i];
+                    if (++cnt == half) {
+                        acc = fold(acc, F.c32);
+                        cnt = 0;
+                    }
+                }
+                const uint32_t d = reduce64(acc, F);
+                if (x <= hi) A[x] = submod(A[x], d, F.p);
+            }
+            __syncthreads();
+        }
+    }
+    // r: what remains of a below deg b (all of a when deg a < deg b)
+    int64_t nr = 0;
+    if (status == 0) {
+        if (wave == 0) {
+            const int64_t d = top_nonzero_wave(A, nr_max);
+            if (lane == 0) s_deg[0] = d;
+        }
+        __syncthreads();
+        nr = uni(s_deg[0]) + 1;
+        for (int64_t i = tid; i < nr; i += NT) J.r[i] = A[i];
+    }
+    // q and r may live in host memory (the server's completion buffers):
+    // every thread's stores are made visible before `done` is raised
+    __threadfence_system();
+    __syncthreads();
+    if (tid == 0) {
+        J.out->status = status;
+        J.out->ng = status == 0 ? mu : 0;
+        J.out->nr = status == 0 ? nr : 0;
+        J.out->steps = mu;
+        J.out->updates = mu * (db + 1);
+        J.out->chunks = (mu + 63) / 64;
         __threadfence_system();
         __hip_atomic_store(&J.out->done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
@@ -791,10 +934,11 @@ __global__ __launch_bounds__(NT) void gcd_batch_kernel(const GcdJob* jobs, const
 template <int NT, int PPT, int E>
 __global__ __launch_bounds__(NT) void gcd_worker_kernel(const GcdJob* jobs, const uint32_t* order, uint32_t order_cap,
                                                         const uint32_t* tail, const uint32_t* stop, uint32_t* head,
-                                                        int s, int64_t cap, uint64_t idle_ticks) {
+                                                        uint32_t* started, int s, int64_t cap, uint64_t idle_ticks) {
     extern __shared__ uint32_t smem[];
     __shared__ int64_t s_job;
     __shared__ GcdJob s_J;
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(started, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     for (;;) {
         if (threadIdx.x == 0) {
             int64_t got = -1;
@@ -829,7 +973,8 @@ __global__ __launch_bounds__(NT) void gcd_worker_kernel(const GcdJob* jobs, cons
         }
         __syncthreads();
         const GcdJob J = s_J;
-        gcd_instance<NT, PPT, E>(J, s, cap, smem);
+        if (J.op == JOB_DIVREM) div_instance<NT>(J, cap, smem);
+        else gcd_instance<NT, PPT, E>(J, s, cap, smem);
         __syncthreads();
     }
 }
@@ -915,20 +1060,39 @@ hipError_t gcd_launch(const uint32_t* a, int64_t na, const uint32_t* b, int64_t 
 
 int64_t gcd_batch_cap(int kind) { return kind == 0 ? 256 * 16 : 1024 * 17; }
 
-hipError_t gcd_worker_launch(const GcdJob* jobs, const uint32_t* order, uint32_t order_cap, const uint32_t* tail,
-                             const uint32_t* stop, uint32_t* head, int s, int blocks, double idle_seconds,
-                             hipStream_t stream) {
-    const int64_t cap = gcd_batch_cap(1);
+int gcd_worker_blocks_per_cu(int kind) {
+    int v = 0;
+    hipError_t e;
+    if (kind == 0)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, (const void*)gcd_worker_kernel<256, 16, 2>, 256,
+                                                         batch_lds_bytes<256, 16, 2>(gcd_batch_cap(0)));
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, (const void*)gcd_worker_kernel<1024, 17, 2>, 1024,
+                                                         batch_lds_bytes<1024, 17, 2>(gcd_batch_cap(1)));
+    return e == hipSuccess && v > 0 ? v : 1;
+}
+
+hipError_t gcd_worker_launch(int kind, const GcdJob* jobs, const uint32_t* order, uint32_t order_cap,
+                             const uint32_t* tail, const uint32_t* stop, uint32_t* head, uint32_t* started, int s,
+                             int blocks, double idle_seconds, hipStream_t stream) {
     int dev = 0, khz = 0;
     (void)hipGetDevice(&dev);
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0) khz = 100000;
     const uint64_t ticks = (uint64_t)(idle_seconds * 1e3 * khz);
     // 128-entry heads for any s: a chunk has at most 2(S+1) <= 128 steps,
     // which consume about 64 entries of each head (a shorter run is still
-    // exact), and 1024 threads leave 128 VGPRs per lane
-    size_t lds = batch_lds_bytes<1024, 17, 2>(cap);
-    hipLaunchKernelGGL((gcd_worker_kernel<1024, 17, 2>), dim3(blocks), dim3(1024), lds, stream, jobs, order,
-                       order_cap, tail, stop, head, s, cap, ticks);
+    // exact); 1024 threads leave 128 VGPRs per lane
+    if (kind == 0) {
+        const int64_t cap = gcd_batch_cap(0);
+        const size_t lds = batch_lds_bytes<256, 16, 2>(cap);
+        hipLaunchKernelGGL((gcd_worker_kernel<256, 16, 2>), dim3(blocks), dim3(256), lds, stream, jobs, order,
+                           order_cap, tail, stop, head, started, s, cap, ticks);
+    } else {
+        const int64_t cap = gcd_batch_cap(1);
+        const size_t lds = batch_lds_bytes<1024, 17, 2>(cap);
+        hipLaunchKernelGGL((gcd_worker_kernel<1024, 17, 2>), dim3(blocks), dim3(1024), lds, stream, jobs, order,
+                           order_cap, tail, stop, head, started, s, cap, ticks);
+    }
     return hipGetLastError();
 }
 

@@ -177,28 +177,33 @@ struct GcdPlan {
 // Per-instance results of the batched gcd kernel (device or host-mapped
 // memory). `done` is set last, with release order, when the instance ends.
 struct GcdResult {
-    int64_t ng;
+    int64_t ng;       // gcd: length of g; division: length of q
     int64_t steps;
     int64_t updates;
     int64_t chunks;
     int32_t status;
     int32_t done;
+    int64_t nr;       // division: length of r
 };
 
-// One instance of the batched gcd: inputs, output and where to report.
+// One instance of the batched gcd (or, for the server, one division):
+// inputs, outputs and where to report.
 struct GcdJob {
     const uint32_t* a;
     const uint32_t* b;
     int64_t na, nb;
-    uint32_t* g;
+    uint32_t* g;      // gcd: g; division: q
     int64_t g_cap;
     GcdResult* out;
     Field F;
     // 1 when a and b were written by another agent (a copy engine) after
     // the running kernel started: they are then read past the caches
     int32_t fresh;
-    int32_t pad;
+    int32_t op;       // JOB_GCD or JOB_DIVREM
+    uint32_t* r;      // division: the remainder
+    int64_t r_cap;
 };
+enum { JOB_GCD = 0, JOB_DIVREM = 1 };
 
 // Capacity (max(na, nb)) of the two batched kernel shapes: kind 0 = 256
 // threads, kind 1 = 1024 threads.
@@ -208,14 +213,18 @@ int64_t gcd_batch_cap(int kind);
 // capacity of `kind`.
 hipError_t gcd_batch_launch(const GcdJob* d_jobs, const int32_t* d_order, int njobs, int kind, int s,
                             hipStream_t stream);
-// Persistent worker (1024 threads, capacity gcd_batch_cap(1)): blocks claim
-// sequence numbers h < *tail from *head and run jobs[order[h % order_cap]]
-// (order_cap a power of two). tail, stop, order and jobs live in pinned host
-// memory written by the host; head in device memory, zero at first. Exits
-// when stop is raised with nothing left, or after idle_seconds without work.
-hipError_t gcd_worker_launch(const GcdJob* jobs, const uint32_t* order, uint32_t order_cap, const uint32_t* tail,
-                             const uint32_t* stop, uint32_t* head, int s, int blocks, double idle_seconds,
-                             hipStream_t stream);
+// Persistent worker of the server, of block shape `kind` (as
+// gcd_batch_cap): blocks claim sequence numbers h < *tail from *head and
+// run jobs[order[h % order_cap]] (order_cap a power of two), a gcd or a
+// division (GcdJob::op). tail, stop, order, jobs and started live in pinned
+// host memory written by the host; head in device memory, zero at first.
+// Every block adds 1 to *started when it begins. Exits when stop is raised
+// with nothing left, or after idle_seconds without work.
+hipError_t gcd_worker_launch(int kind, const GcdJob* jobs, const uint32_t* order, uint32_t order_cap,
+                             const uint32_t* tail, const uint32_t* stop, uint32_t* head, uint32_t* started, int s,
+                             int blocks, double idle_seconds, hipStream_t stream);
+// Blocks of one worker shape that fit a CU beside nothing else.
+int gcd_worker_blocks_per_cu(int kind);
 constexpr int GCD_THREADS = 256;
 GcdPlan gcd_default_plan(int64_t n, int num_cus, int s);
 // The extended gcd's cofactor tracking: the cofactor of the caller's a in

@@ -1,25 +1,33 @@
-// serve.cpp -- continuous-batching gcd server (pm_server_* in polymodp.h).
+// serve.cpp -- continuous-batching server of gcd and division requests
+// (pm_server_* in polymodp.h).
 //
-// A persistent worker kernel (one 1024-thread block per CU) takes requests
-// one at a time from a queue the host publishes in pinned memory: block b
-// claims sequence number h (an atomic on a device counter), reads the slot
-// of request h, runs the whole remainder sequence with both polynomials in
-// its LDS, writes the monic gcd and the result into the slot's pinned
-// buffers and raises the slot's `done` flag (system-scope release), then
-// claims the next one. Requests therefore join and leave the GPU one by one:
-// nothing waits for a batch or a launch to finish.
+// Two persistent worker kernels take requests one at a time from rings the
+// host publishes in pinned memory: the 1024-thread worker (one block per
+// CU, operands up to 17408 terms) and the 256-thread worker (several blocks
+// per CU, operands up to 4096 terms). A block claims sequence number h of
+// its ring (an atomic on a device counter), reads the job record of h, runs
+// the whole remainder sequence (or the division) with both operands in its
+// LDS, writes the results into the request's pinned output buffers and
+// raises the request's `done` flag (system-scope release), then claims the
+// next one. Requests therefore join and leave the GPU one by one: nothing
+// waits for a batch or a launch to finish.
 //
 // The host side (pm_server_submit and pm_server_poll, called by one thread):
 //  1. poll harvests finished slots (done flag, acquire) and frees them;
 //  2. submit and poll admit queued requests in FIFO order (the requests of
-//     one batch call longest first) while a slot and room in the
-//     resident-input budget are free: the inputs go into the slot's pinned
-//     staging buffer (mapped into the device's address space), and the
-//     request is published at once by raising the shared tail (release);
-//     the claiming block reads the inputs once, past the caches, straight
-//     into its LDS (copies queued on a stream would wait behind the
-//     worker's own blocks, which hold the CUs);
-//  3. makes sure the worker runs (it stops by itself after an idle period).
+//     one batch call longest first) while a slot, room in the device input
+//     arena and room in the pinned output arena are free: the inputs are
+//     copied into the arena's pinned mirror, and one copy per contiguous
+//     run of the admission pass moves them to device memory on the copy
+//     stream, followed by an event;
+//  3. the requests of a pass are published (their ring entries written and
+//     the ring's tail raised, release) once its event has completed; the
+//     claiming block reads the inputs past the caches (the copy engine
+//     wrote them after the worker started);
+//  4. makes sure the workers run (they stop by themselves after an idle
+//     period): the 1024-thread worker is launched first and waited for
+//     until all its blocks have started, so that the 256-thread worker,
+//     launched next, takes only the CUs it leaves.
 // All device and pinned memory is allocated by pm_server_create.
 #include <hip/hip_runtime.h>
 
@@ -41,35 +49,40 @@ int server_num_cus();
 
 namespace {
 
-// Sequence numbers index the order ring modulo ORDER_CAP. A block reads
-// order[h] right after claiming h; the host can only overwrite that entry
-// after publishing h + ORDER_CAP, which needs ORDER_CAP - max_inflight
-// further requests to finish in between, so the entry is always intact.
+// Sequence numbers index a ring modulo ORDER_CAP. A block reads its ring
+// entry right after claiming it; the host can only overwrite that entry
+// after publishing ORDER_CAP more requests on the ring, which needs
+// ORDER_CAP - max_inflight of them to finish in between, so it is intact.
 constexpr uint32_t ORDER_CAP = 1u << 16;
 constexpr double IDLE_SECONDS = 0.5;
+constexpr int NKIND = 2;  // worker shapes: 0 = 256 threads, 1 = 1024 threads
+constexpr int EVENTS = 64;
 
 struct Pending {
     uint64_t ticket;
     uint64_t tag;
+    int32_t op;
     std::vector<uint32_t> ab;  // a then b
     int64_t na, nb;
-    uint32_t* g_user;
-    int64_t g_cap;
+    uint32_t *g_user, *r_user;
+    int64_t g_cap, r_cap;
     pm::Field F;
     double t_submit;
 };
 
 struct Slot {
     bool busy = false;
+    int kind = 1;
+    int32_t op = pm::JOB_GCD;
     uint64_t ticket = 0, tag = 0;
-    int64_t arena_off = 0, arena_len = 0;
-    uint32_t* g_user = nullptr;
-    int64_t g_cap = 0;
+    int64_t in_off = 0, in_len = 0, out_off = 0, out_len = 0, r_off = 0;
+    bool published = false;
+    uint32_t *g_user = nullptr, *r_user = nullptr;
+    int64_t g_cap = 0, r_cap = 0;
     double t_submit = 0, t_start = 0;
 };
 
-// First-fit allocator over [0, cap) words with coalescing (64-word grain):
-// the budget of input words resident for admitted requests.
+// First-fit allocator over [0, cap) words with coalescing (64-word grain).
 class Arena {
 public:
     explicit Arena(int64_t cap) { free_[0] = cap & ~INT64_C(63); }
@@ -108,28 +121,52 @@ private:
     std::map<int64_t, int64_t> free_;
 };
 
+// One worker shape: its kernel's stream, ring and claim counter.
+struct Worker {
+    int blocks = 0;
+    int64_t cap = 0;
+    hipStream_t stream = nullptr;
+    bool launched = false;
+    uint32_t* d_head = nullptr;   // device: next sequence number to claim
+    uint32_t* h_order = nullptr;  // pinned: ORDER_CAP slot ids
+    uint32_t tail = 0;            // host copy of the published tail
+    int64_t inflight = 0;
+};
+
+// The requests of one admission pass, published when their copy is done.
+struct Pass {
+    hipEvent_t done;
+    std::vector<int> slots;
+};
+
+// Pinned control words: the published tail of each ring, the stop flag and
+// each worker's count of started blocks.
+enum { CTL_TAIL0 = 0, CTL_TAIL1 = 1, CTL_STOP = 2, CTL_STARTED0 = 3, CTL_STARTED1 = 4, CTL_WORDS = 8 };
+
 }  // namespace
 
 struct pm_server {
     pm_server_opts opt{};
     int device = 0;
-    int64_t cap = 0;  // words per input polynomial and per output of a slot
-    hipStream_t worker_stream = nullptr;
-    bool worker_launched = false;
-    uint32_t* d_head = nullptr;
-    Arena* arena = nullptr;
+    Worker w[NKIND];
+    hipStream_t copy_stream = nullptr;
+    uint32_t* d_in = nullptr;            // device input arena (arena_words)
+    uint32_t* h_mirror = nullptr;        // pinned, the inputs as staged for the copy
+    uint32_t* h_out = nullptr;           // pinned output arena (arena_words)
+    Arena* in_arena = nullptr;
+    Arena* out_arena = nullptr;
     pm::GcdJob* h_jobs = nullptr;        // pinned, one per slot
     pm::GcdResult* h_results = nullptr;  // pinned, one per slot
-    uint32_t* h_in = nullptr;            // pinned, 2*cap words per slot
-    uint32_t* h_g = nullptr;             // pinned, cap words per slot
-    uint32_t* h_order = nullptr;         // pinned, ORDER_CAP slot ids
-    uint32_t* h_ctl = nullptr;           // pinned: [0] tail, [1] stop
-    uint32_t tail = 0;
+    uint32_t* h_ctl = nullptr;           // pinned control words
     std::vector<Slot> slots;
     std::vector<int> free_slots;
     std::deque<Pending> queue;
+    std::deque<Pass> passes;             // copies in flight, oldest first
+    std::vector<hipEvent_t> free_events;
+    std::vector<int> staged;             // slots placed in the current pass
+    std::vector<std::pair<int64_t, int64_t>> runs;  // its input ranges (offset, words)
     uint64_t next_ticket = 1;
-    int64_t inflight = 0;
+    int64_t inflight = 0;                // admitted (staged, copied or on the GPU)
     std::chrono::steady_clock::time_point t0;
     double now_ms() const {
         return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -143,160 +180,227 @@ void destroy(pm_server* S) {
     int cur = 0;
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(S->device);
-    if (S->h_ctl) __atomic_store_n(&S->h_ctl[1], 1u, __ATOMIC_RELEASE);  // stop the worker
-    if (S->worker_stream) (void)hipStreamSynchronize(S->worker_stream);
-    if (S->worker_stream) (void)hipStreamDestroy(S->worker_stream);
-    if (S->d_head) (void)hipFree(S->d_head);
-    for (void* p : {(void*)S->h_jobs, (void*)S->h_results, (void*)S->h_in, (void*)S->h_g, (void*)S->h_order,
-                    (void*)S->h_ctl})
+    if (S->h_ctl) __atomic_store_n(&S->h_ctl[CTL_STOP], 1u, __ATOMIC_RELEASE);  // stop the workers
+    for (Worker& W : S->w) {
+        if (W.stream) (void)hipStreamSynchronize(W.stream);
+        if (W.stream) (void)hipStreamDestroy(W.stream);
+        if (W.d_head) (void)hipFree(W.d_head);
+        if (W.h_order) (void)hipHostFree(W.h_order);
+    }
+    if (S->copy_stream) (void)hipStreamSynchronize(S->copy_stream);
+    for (Pass& P : S->passes) (void)hipEventDestroy(P.done);
+    for (hipEvent_t e : S->free_events) (void)hipEventDestroy(e);
+    if (S->copy_stream) (void)hipStreamDestroy(S->copy_stream);
+    if (S->d_in) (void)hipFree(S->d_in);
+    for (void* p : {(void*)S->h_mirror, (void*)S->h_out, (void*)S->h_jobs, (void*)S->h_results, (void*)S->h_ctl})
         if (p) (void)hipHostFree(p);
-    delete S->arena;
+    delete S->in_arena;
+    delete S->out_arena;
     (void)hipSetDevice(cur);
     delete S;
 }
 
-pm_status ensure_worker(pm_server* S) {
-    if (S->worker_launched && hipStreamQuery(S->worker_stream) == hipErrorNotReady) return PM_OK;
-    const int blocks = pm::server_num_cus();
-    if (pm::gcd_worker_launch(S->h_jobs, S->h_order, ORDER_CAP, &S->h_ctl[0], &S->h_ctl[1], S->d_head, S->opt.s,
-                              blocks, IDLE_SECONDS, S->worker_stream) != hipSuccess)
+int kind_of(const pm_server* S, int64_t na, int64_t nb) {
+    const int64_t n = na > nb ? na : nb;
+    return (S->w[0].blocks > 0 && n <= S->w[0].cap) ? 0 : 1;
+}
+
+// Output words a request needs in the pinned output arena.
+int64_t out_words(int32_t op, int64_t na, int64_t nb) { return op == pm::JOB_DIVREM ? na + nb : (na > nb ? na : nb); }
+
+pm_status launch_worker(pm_server* S, int k) {
+    Worker& W = S->w[k];
+    uint32_t* started = &S->h_ctl[k == 0 ? CTL_STARTED0 : CTL_STARTED1];
+    __atomic_store_n(started, 0u, __ATOMIC_RELAXED);
+    const uint32_t* tail = &S->h_ctl[k == 0 ? CTL_TAIL0 : CTL_TAIL1];
+    if (pm::gcd_worker_launch(k, S->h_jobs, W.h_order, ORDER_CAP, tail, &S->h_ctl[CTL_STOP], W.d_head, started,
+                              S->opt.s, W.blocks, IDLE_SECONDS, W.stream) != hipSuccess)
         return pm::server_fail(PM_EDEVICE, "worker launch");
-    S->worker_launched = true;
+    W.launched = true;
+    if (k == 1) {
+        // every block of the 1024-thread worker holds its CU before the other
+        // worker's blocks are placed (bounded wait: another process's work
+        // may hold the GPU)
+        const auto t = std::chrono::steady_clock::now();
+        while (__atomic_load_n(started, __ATOMIC_ACQUIRE) < (uint32_t)W.blocks &&
+               std::chrono::steady_clock::now() - t < std::chrono::seconds(2))
+            ;
+    }
     return PM_OK;
 }
 
-// Puts one request into slot si at arena offset off: inputs into the slot's
-// pinned staging, the job record, and the next entry of the order ring
-// (published by the caller with one store of the tail).
-void place(pm_server* S, int si, int64_t off, uint64_t ticket, uint64_t tag, const uint32_t* a, int64_t na,
-           const uint32_t* b, int64_t nb, uint32_t* g_user, int64_t g_cap, const pm::Field& F, double t_submit,
-           double t_start) {
+bool running(const Worker& W) { return W.launched && hipStreamQuery(W.stream) == hipErrorNotReady; }
+
+// Makes sure the workers that have work run: the 1024-thread one first
+// whenever the 256-thread one is (re)launched, so that the latter never
+// spreads over CUs the former needs.
+pm_status ensure_workers(pm_server* S) {
+    const bool need0 = S->w[0].blocks > 0 && S->w[0].inflight > 0;
+    const bool need1 = S->w[1].inflight > 0;
+    const bool run0 = running(S->w[0]);
+    if ((need1 || (need0 && !run0)) && !running(S->w[1])) {
+        pm_status st = launch_worker(S, 1);
+        if (st) return st;
+    }
+    if (need0 && !run0) return launch_worker(S, 0);
+    return PM_OK;
+}
+
+// Puts one request into slot si: its inputs into the pinned mirror at its
+// arena offset, its job record, and the slot into the current pass.
+void place(pm_server* S, int si, int64_t in_off, int64_t out_off, uint64_t ticket, uint64_t tag, int32_t op,
+           const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, uint32_t* g_user, int64_t g_cap,
+           uint32_t* r_user, int64_t r_cap, const pm::Field& F, double t_submit) {
     Slot& sl = S->slots[si];
     sl.busy = true;
+    sl.kind = kind_of(S, na, nb);
+    sl.op = op;
     sl.ticket = ticket;
     sl.tag = tag;
-    sl.arena_off = off;
-    sl.arena_len = na + nb;
+    sl.in_off = in_off;
+    sl.in_len = na + nb;
+    sl.out_off = out_off;
+    sl.out_len = out_words(op, na, nb);
+    sl.r_off = out_off + na;  // a division's r follows its q
+    sl.published = false;
     sl.g_user = g_user;
     sl.g_cap = g_cap;
+    sl.r_user = r_user;
+    sl.r_cap = r_cap;
     sl.t_submit = t_submit;
-    sl.t_start = t_start;
+    sl.t_start = 0;
     std::memset(&S->h_results[si], 0, sizeof(pm::GcdResult));
-    uint32_t* stage = S->h_in + (int64_t)si * 2 * S->cap;
+    uint32_t* stage = S->h_mirror + in_off;
     if (na) std::memcpy(stage, a, (size_t)na * 4);
     if (nb) std::memcpy(stage + na, b, (size_t)nb * 4);
-    S->h_jobs[si] = pm::GcdJob{stage, stage + na, na, nb, S->h_g + (int64_t)si * S->cap, S->cap,
-                               &S->h_results[si], F, 1, 0};
-    S->h_order[S->tail & (ORDER_CAP - 1)] = (uint32_t)si;
-    S->tail++;
+    const uint32_t* da = S->d_in + in_off;
+    uint32_t* out = S->h_out + out_off;
+    // outputs: the gcd, or q then r, each within the request's own words
+    const int64_t gw = op == pm::JOB_DIVREM ? na : sl.out_len;
+    S->h_jobs[si] = pm::GcdJob{da, da + na, na, nb, out, std::min(g_cap, gw), &S->h_results[si], F, 1,
+                               op, op == pm::JOB_DIVREM ? out + na : nullptr,
+                               op == pm::JOB_DIVREM ? std::min(r_cap, nb) : 0};
+    if (!S->runs.empty() && S->runs.back().first + S->runs.back().second == in_off)
+        S->runs.back().second += Arena::grain(na + nb);
+    else
+        S->runs.push_back({in_off, Arena::grain(na + nb)});
+    S->staged.push_back(si);
+    S->w[sl.kind].inflight++;
     S->inflight++;
 }
 
-// Admits queued requests in FIFO order while a slot and room in the budget
-// are free and publishes them. With `check`, also makes sure the worker runs
-// (a query of its stream); without it, only a worker never launched is
-// started, and the next poll relaunches one that has left.
-pm_status admit(pm_server* S, bool check) {
-    bool published = __atomic_load_n(&S->h_ctl[0], __ATOMIC_RELAXED) != S->tail;  // direct placements
+// Publishes the passes whose copies have completed, oldest first.
+void publish_ready(pm_server* S) {
+    bool any[NKIND] = {false, false};
     const double t = S->now_ms();
+    while (!S->passes.empty() && hipEventQuery(S->passes.front().done) == hipSuccess) {
+        Pass P = std::move(S->passes.front());
+        S->passes.pop_front();
+        for (int si : P.slots) {
+            Slot& sl = S->slots[si];
+            Worker& W = S->w[sl.kind];
+            sl.t_start = t;
+            sl.published = true;
+            W.h_order[W.tail & (ORDER_CAP - 1)] = (uint32_t)si;
+            W.tail++;
+            any[sl.kind] = true;
+        }
+        S->free_events.push_back(P.done);
+    }
+    for (int k = 0; k < NKIND; k++)
+        if (any[k]) __atomic_store_n(&S->h_ctl[k == 0 ? CTL_TAIL0 : CTL_TAIL1], S->w[k].tail, __ATOMIC_RELEASE);
+}
+
+// Ends the current admission pass: its input runs are copied to the device
+// and an event marks when they are there.
+pm_status close_pass(pm_server* S) {
+    if (S->staged.empty()) return PM_OK;
+    for (const auto& run : S->runs)
+        if (hipMemcpyAsync(S->d_in + run.first, S->h_mirror + run.first, (size_t)run.second * 4,
+                           hipMemcpyHostToDevice, S->copy_stream) != hipSuccess)
+            return pm::server_fail(PM_EDEVICE, "input copy");
+    S->runs.clear();
+    if (S->free_events.empty()) {
+        // all events in use: the oldest pass must finish first
+        if (hipEventSynchronize(S->passes.front().done) != hipSuccess)
+            return pm::server_fail(PM_EDEVICE, "copy event");
+        publish_ready(S);
+    }
+    hipEvent_t e = S->free_events.back();
+    S->free_events.pop_back();
+    if (hipEventRecord(e, S->copy_stream) != hipSuccess) return pm::server_fail(PM_EDEVICE, "copy event");
+    S->passes.push_back(Pass{e, std::move(S->staged)});
+    S->staged.clear();
+    return PM_OK;
+}
+
+// Admits queued requests in FIFO order while a slot and arena room are
+// free, starts their copy, publishes what has arrived, and makes sure the
+// workers run.
+pm_status admit(pm_server* S) {
     while (!S->queue.empty() && !S->free_slots.empty()) {
         Pending& P = S->queue.front();
-        const int64_t len = P.na + P.nb;
-        int64_t off = 0;
-        if (!S->arena->alloc(len, &off)) break;  // FIFO: wait for room, no overtaking
+        int64_t in_off = 0, out_off = 0;
+        if (!S->in_arena->alloc(P.na + P.nb, &in_off)) break;  // FIFO: wait for room, no overtaking
+        if (!S->out_arena->alloc(out_words(P.op, P.na, P.nb), &out_off)) {
+            S->in_arena->release(in_off, P.na + P.nb);
+            break;
+        }
         const int si = S->free_slots.back();
         S->free_slots.pop_back();
-        place(S, si, off, P.ticket, P.tag, P.ab.data(), P.na, P.ab.data() + P.na, P.nb, P.g_user, P.g_cap, P.F,
-              P.t_submit, t);
+        place(S, si, in_off, out_off, P.ticket, P.tag, P.op, P.ab.data(), P.na, P.ab.data() + P.na, P.nb, P.g_user,
+              P.g_cap, P.r_user, P.r_cap, P.F, P.t_submit);
         S->queue.pop_front();
-        published = true;
     }
-    if (published) __atomic_store_n(&S->h_ctl[0], S->tail, __ATOMIC_RELEASE);
-    // (re)launch the worker whenever published work may be waiting and the
-    // previous worker has left (it leaves after an idle period)
-    if (S->inflight > 0 && (check || !S->worker_launched)) return ensure_worker(S);
-    return PM_OK;
+    pm_status st = close_pass(S);
+    if (st) return st;
+    publish_ready(S);
+    return ensure_workers(S);
 }
 
-}  // namespace
-
-extern "C" {
-
-pm_status pm_server_create(const pm_server_opts* opts, pm_server** out) {
-    if (!out) return pm::server_fail(PM_EINVAL, "null output");
-    pm_server* S = new pm_server();
-    if (opts) S->opt = *opts;
-    if (S->opt.max_inflight <= 0) S->opt.max_inflight = 1024;
-    if (S->opt.max_inflight > (int32_t)(ORDER_CAP / 4)) S->opt.max_inflight = (int32_t)(ORDER_CAP / 4);
-    if (S->opt.arena_words <= 0) S->opt.arena_words = INT64_C(32) << 20;
-    if (S->opt.s < 0 || S->opt.s > 256) {
-        delete S;
-        return pm::server_fail(PM_EINVAL, "s must be in [0, 256]");
-    }
-    if (S->opt.s == 0) S->opt.s = 128;
-    (void)hipGetDevice(&S->device);
-    S->t0 = std::chrono::steady_clock::now();
-    S->cap = pm::gcd_batch_cap(1);
-    const size_t M = (size_t)S->opt.max_inflight;
-    hipError_t e = hipStreamCreateWithFlags(&S->worker_stream, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipMalloc((void**)&S->d_head, sizeof(uint32_t));
-    if (e == hipSuccess) e = hipMemset(S->d_head, 0, sizeof(uint32_t));
-    if (e == hipSuccess) e = hipHostMalloc((void**)&S->h_jobs, M * sizeof(pm::GcdJob), hipHostMallocDefault);
-    if (e == hipSuccess) e = hipHostMalloc((void**)&S->h_results, M * sizeof(pm::GcdResult), hipHostMallocDefault);
-    if (e == hipSuccess) e = hipHostMalloc((void**)&S->h_in, M * 2 * S->cap * sizeof(uint32_t), hipHostMallocDefault);
-    if (e == hipSuccess) e = hipHostMalloc((void**)&S->h_g, M * S->cap * sizeof(uint32_t), hipHostMallocDefault);
-    if (e == hipSuccess) e = hipHostMalloc((void**)&S->h_order, ORDER_CAP * sizeof(uint32_t), hipHostMallocDefault);
-    if (e == hipSuccess) e = hipHostMalloc((void**)&S->h_ctl, 2 * sizeof(uint32_t), hipHostMallocDefault);
-    if (e == hipSuccess) e = hipDeviceSynchronize();
-    if (e != hipSuccess) {
-        destroy(S);
-        return pm::server_fail(PM_ENOMEM, "cannot allocate the server's buffers");
-    }
-    std::memset(S->h_results, 0, M * sizeof(pm::GcdResult));
-    std::memset(S->h_order, 0, ORDER_CAP * sizeof(uint32_t));
-    S->h_ctl[0] = 0;
-    S->h_ctl[1] = 0;
-    S->arena = new Arena(S->opt.arena_words);
-    S->slots.resize(M);
-    for (int i = (int)M - 1; i >= 0; i--) S->free_slots.push_back(i);
-    *out = S;
-    return PM_OK;
-}
-
-void pm_server_destroy(pm_server* S) { destroy(S); }
-
-}  // extern "C"
-
-namespace {
-
-pm_status enqueue(pm_server* S, const pm_gcd_request* r, uint64_t* ticket) {
-    if (!r) return pm::server_fail(PM_EINVAL, "null request");
+// Host checks of one request; *op gets the job kind.
+pm_status check_request(const pm_server* S, const pm_gcd_request* r, pm::Field* F, int32_t* op) {
+    if (r->op != 0 && r->op != PM_OP_GCD && r->op != PM_OP_DIVREM)
+        return pm::server_fail(PM_EINVAL, "op must be PM_OP_GCD or PM_OP_DIVREM");
+    *op = r->op == PM_OP_DIVREM ? pm::JOB_DIVREM : pm::JOB_GCD;
     if (r->na < 0 || r->nb < 0 || (r->na > 0 && !r->a) || (r->nb > 0 && !r->b) || r->g_cap < 0 ||
         (r->g_cap > 0 && !r->g))
         return pm::server_fail(PM_EINVAL, "bad request buffers");
+    if (*op == pm::JOB_DIVREM && (r->r_cap < 0 || (r->r_cap > 0 && !r->r)))
+        return pm::server_fail(PM_EINVAL, "bad remainder buffer");
     const int64_t n = r->na > r->nb ? r->na : r->nb;
-    if (n > S->cap) return pm::server_fail(PM_EINVAL, "request exceeds PM_GCD_BATCH_MAX terms");
-    if (Arena::grain(r->na + r->nb) > S->opt.arena_words)
-        return pm::server_fail(PM_ENOMEM, "request larger than the whole resident-input budget");
+    if (n > S->w[1].cap) return pm::server_fail(PM_EINVAL, "request exceeds PM_GCD_BATCH_MAX terms");
+    if (Arena::grain(r->na + r->nb) > S->opt.arena_words ||
+        Arena::grain(out_words(*op, r->na, r->nb)) > S->opt.arena_words)
+        return pm::server_fail(PM_ENOMEM, "request larger than the whole arena");
+    if (*op == pm::JOB_DIVREM && r->nb == 0) return pm::server_fail(PM_EDIVZERO, "division by the zero polynomial");
+    return pm::server_field(r->p, F);
+}
+
+pm_status enqueue(pm_server* S, const pm_gcd_request* r, uint64_t* ticket) {
     pm::Field F;
-    pm_status st = pm::server_field(r->p, &F);
+    int32_t op = 0;
+    pm_status st = check_request(S, r, &F, &op);
     if (st) return st;
-    if ((r->p & 1u) == 0) return pm::server_fail(PM_EMODULUS, "p = 2 is not supported by the gcd");
-    int64_t off = 0;
-    if (S->queue.empty() && !S->free_slots.empty() && S->arena->alloc(r->na + r->nb, &off)) {
-        // nothing waits ahead of it: straight from the caller's arrays into a
-        // slot (published by the caller's next admission pass)
-        const int si = S->free_slots.back();
-        S->free_slots.pop_back();
-        const uint64_t t = S->next_ticket++;
-        const double now = S->now_ms();
-        place(S, si, off, t, r->tag, r->a, r->na, r->b, r->nb, r->g, r->g_cap, F, now, now);
-        if (ticket) *ticket = t;
-        return PM_OK;
+    int64_t in_off = 0, out_off = 0;
+    if (S->queue.empty() && !S->free_slots.empty() && S->in_arena->alloc(r->na + r->nb, &in_off)) {
+        if (S->out_arena->alloc(out_words(op, r->na, r->nb), &out_off)) {
+            // nothing waits ahead of it: straight from the caller's arrays
+            // into the pass being built
+            const int si = S->free_slots.back();
+            S->free_slots.pop_back();
+            const uint64_t t = S->next_ticket++;
+            place(S, si, in_off, out_off, t, r->tag, op, r->a, r->na, r->b, r->nb, r->g, r->g_cap, r->r, r->r_cap, F,
+                  S->now_ms());
+            if (ticket) *ticket = t;
+            return PM_OK;
+        }
+        S->in_arena->release(in_off, r->na + r->nb);
     }
     Pending P;
     P.ticket = S->next_ticket++;
     P.tag = r->tag;
+    P.op = op;
     P.na = r->na;
     P.nb = r->nb;
     P.ab.resize((size_t)(r->na + r->nb));
@@ -304,6 +408,8 @@ pm_status enqueue(pm_server* S, const pm_gcd_request* r, uint64_t* ticket) {
     if (r->nb) std::memcpy(P.ab.data() + r->na, r->b, (size_t)r->nb * 4);
     P.g_user = r->g;
     P.g_cap = r->g_cap;
+    P.r_user = r->r;
+    P.r_cap = r->r_cap;
     P.F = F;
     P.t_submit = S->now_ms();
     if (ticket) *ticket = P.ticket;
@@ -315,31 +421,100 @@ pm_status enqueue(pm_server* S, const pm_gcd_request* r, uint64_t* ticket) {
 
 extern "C" {
 
+pm_status pm_server_create(const pm_server_opts* opts, pm_server** out) {
+    if (!out) return pm::server_fail(PM_EINVAL, "null output");
+    *out = nullptr;
+    pm_server_opts o{};
+    if (opts) o = *opts;
+    if (o.s < 0 || o.s > 256) return pm::server_fail(PM_EINVAL, "s must be in [0, 256]");
+    if (o.max_inflight < 0 || o.large_blocks < 0 || o.small_blocks < -1 || o.arena_words < 0)
+        return pm::server_fail(PM_EINVAL, "negative option");
+    pm_server* S = new pm_server();
+    if (o.max_inflight == 0) o.max_inflight = 4096;
+    if (o.max_inflight > (int32_t)(ORDER_CAP / 4)) o.max_inflight = (int32_t)(ORDER_CAP / 4);
+    if (o.s == 0) o.s = 128;
+    (void)hipGetDevice(&S->device);
+    // the input arena is budgeted from the device's free memory
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+        delete S;
+        return pm::server_fail(PM_EDEVICE, "hipMemGetInfo");
+    }
+    const int64_t free_words = (int64_t)(free_b / 4);
+    if (o.arena_words == 0) o.arena_words = std::min<int64_t>(INT64_C(32) << 20, free_words / 8);
+    if (o.arena_words > free_words / 2) {
+        delete S;
+        return pm::server_fail(PM_ENOMEM, "arena_words above half the device's free memory");
+    }
+    const int cus = pm::server_num_cus();
+    if (o.large_blocks == 0) o.large_blocks = cus - cus / 8;
+    if (o.large_blocks > cus) o.large_blocks = cus;
+    if (o.small_blocks == 0) o.small_blocks = (cus - o.large_blocks) * pm::gcd_worker_blocks_per_cu(0);
+    if (o.small_blocks < 0) o.small_blocks = 0;
+    S->opt = o;
+    S->t0 = std::chrono::steady_clock::now();
+    S->w[0].blocks = o.small_blocks;
+    S->w[0].cap = pm::gcd_batch_cap(0);
+    S->w[1].blocks = o.large_blocks;
+    S->w[1].cap = pm::gcd_batch_cap(1);
+    const size_t M = (size_t)o.max_inflight;
+    hipError_t e = hipSuccess;
+    for (Worker& W : S->w) {
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&W.stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipMalloc((void**)&W.d_head, sizeof(uint32_t));
+        if (e == hipSuccess) e = hipMemset(W.d_head, 0, sizeof(uint32_t));
+        if (e == hipSuccess) e = hipHostMalloc((void**)&W.h_order, ORDER_CAP * sizeof(uint32_t), hipHostMallocDefault);
+        if (e == hipSuccess) std::memset(W.h_order, 0, ORDER_CAP * sizeof(uint32_t));
+    }
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->copy_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipMalloc((void**)&S->d_in, (size_t)o.arena_words * 4);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&S->h_mirror, (size_t)o.arena_words * 4, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&S->h_out, (size_t)o.arena_words * 4, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&S->h_jobs, M * sizeof(pm::GcdJob), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&S->h_results, M * sizeof(pm::GcdResult), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&S->h_ctl, CTL_WORDS * sizeof(uint32_t), hipHostMallocDefault);
+    for (int i = 0; i < EVENTS && e == hipSuccess; i++) {
+        hipEvent_t ev;
+        e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e == hipSuccess) S->free_events.push_back(ev);
+    }
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        destroy(S);
+        return pm::server_fail(PM_ENOMEM, "cannot allocate the server's buffers");
+    }
+    std::memset(S->h_results, 0, M * sizeof(pm::GcdResult));
+    std::memset(S->h_ctl, 0, CTL_WORDS * sizeof(uint32_t));
+    S->in_arena = new Arena(o.arena_words);
+    S->out_arena = new Arena(o.arena_words);
+    S->slots.resize(M);
+    for (int i = (int)M - 1; i >= 0; i--) S->free_slots.push_back(i);
+    *out = S;
+    return PM_OK;
+}
+
+void pm_server_destroy(pm_server* S) { destroy(S); }
+
 pm_status pm_server_submit(pm_server* S, const pm_gcd_request* r, uint64_t* ticket) {
     if (!S || !r) return pm::server_fail(PM_EINVAL, "null argument");
     pm_status st = enqueue(S, r, ticket);
     if (st) return st;
-    return admit(S, false);  // on the GPU at once when a slot is free
+    return admit(S);  // on the GPU as soon as its copy is done, when a slot is free
 }
 
 pm_status pm_server_submit_batch(pm_server* S, const pm_gcd_request* reqs, int32_t count, uint64_t* tickets) {
     if (!S || count < 0 || (count > 0 && !reqs)) return pm::server_fail(PM_EINVAL, "null argument");
     // every request is checked before any is queued: a bad one queues none
     for (int32_t i = 0; i < count; i++) {
-        const pm_gcd_request* r = &reqs[i];
-        const int64_t n = r->na > r->nb ? r->na : r->nb;
-        if (r->na < 0 || r->nb < 0 || (r->na > 0 && !r->a) || (r->nb > 0 && !r->b) || r->g_cap < 0 ||
-            (r->g_cap > 0 && !r->g) || n > S->cap || Arena::grain(r->na + r->nb) > S->opt.arena_words)
-            return pm::server_fail(PM_EINVAL, "bad request in the batch");
         pm::Field F;
-        pm_status st = pm::server_field(r->p, &F);
+        int32_t op = 0;
+        pm_status st = check_request(S, &reqs[i], &F, &op);
         if (st) return st;
-        if ((r->p & 1u) == 0) return pm::server_fail(PM_EMODULUS, "p = 2 is not supported by the gcd");
     }
     // The requests of one call arrive together, so they may start in any
-    // order: longest first (work ~ na * nb), which keeps the largest
-    // remainder sequences, each bound by its own step chain on one CU, from
-    // starting last and setting the span.
+    // order: longest first (work ~ na * nb), which keeps the largest, each
+    // bound by its own step chain on one CU, from starting last and setting
+    // the span.
     std::vector<int32_t> order((size_t)count);
     for (int32_t i = 0; i < count; i++) order[(size_t)i] = i;
     std::stable_sort(order.begin(), order.end(), [reqs](int32_t x, int32_t y) {
@@ -350,11 +525,11 @@ pm_status pm_server_submit_batch(pm_server* S, const pm_gcd_request* reqs, int32
         pm_status st = enqueue(S, &reqs[i], tickets ? &tickets[i] : nullptr);
         if (st) return st;
         if ((k & 15) == 15) {  // the first requests start while the rest are copied
-            st = admit(S, false);
+            st = admit(S);
             if (st) return st;
         }
     }
-    return admit(S, false);
+    return admit(S);
 }
 
 int64_t pm_server_pending(pm_server* S) { return S ? (int64_t)S->queue.size() + S->inflight : 0; }
@@ -362,37 +537,39 @@ int64_t pm_server_pending(pm_server* S) { return S ? (int64_t)S->queue.size() + 
 pm_status pm_server_poll(pm_server* S, pm_completion* out, int32_t max, int32_t* n) {
     if (!S || !n || (max > 0 && !out)) return pm::server_fail(PM_EINVAL, "null argument");
     *n = 0;
+    publish_ready(S);
     // 1. harvest
     for (int si = 0; si < S->opt.max_inflight && *n < max; si++) {
         Slot& sl = S->slots[si];
-        if (!sl.busy) continue;
+        if (!sl.busy || !sl.published) continue;
         pm::GcdResult* R = &S->h_results[si];
         if (__atomic_load_n(&R->done, __ATOMIC_ACQUIRE) == 0) continue;
         pm_completion& c = out[(*n)++];
         c.ticket = sl.ticket;
         c.tag = sl.tag;
         c.status = R->status;
-        c.reserved = 0;
+        c.op = sl.op == pm::JOB_DIVREM ? PM_OP_DIVREM : PM_OP_GCD;
         c.ng = R->status == 0 ? R->ng : 0;
+        c.nr = R->status == 0 && sl.op == pm::JOB_DIVREM ? R->nr : 0;
         c.steps = R->steps;
         c.updates = R->updates;
         c.t_submit_ms = sl.t_submit;
         c.t_start_ms = sl.t_start;
         c.t_done_ms = S->now_ms();
+        const uint32_t* res = S->h_out + sl.out_off;
         if (c.status == 0) {
-            if (c.ng > sl.g_cap) {
-                c.status = PM_EINVAL;
-                c.ng = 0;
-            } else if (c.ng > 0) {
-                std::memcpy(sl.g_user, S->h_g + (int64_t)si * S->cap, (size_t)c.ng * 4);
-            }
+            // the device checked the capacities the job record gave it
+            if (c.ng > 0) std::memcpy(sl.g_user, res, (size_t)c.ng * 4);
+            if (c.nr > 0) std::memcpy(sl.r_user, S->h_out + sl.r_off, (size_t)c.nr * 4);
         }
-        S->arena->release(sl.arena_off, sl.arena_len);
+        S->in_arena->release(sl.in_off, sl.in_len);
+        S->out_arena->release(sl.out_off, sl.out_len);
+        S->w[sl.kind].inflight--;
         S->inflight--;
         sl.busy = false;
         S->free_slots.push_back(si);
     }
-    return admit(S, true);
+    return admit(S);
 }
 
 }  // extern "C"

@@ -184,3 +184,36 @@ def served_trace(count: int, rate: float, lo: int = 64, hi: int = 16384,
         k = st.uniform_int(0, D // 4)
         reqs.append(Request(t, p, D, k, planted_gcd(D, D - 1, k, p, st)))
     return reqs
+
+
+@dataclass
+class DivisionRequest:
+    arrival: float
+    p: int
+    D: int          # deg a
+    a: np.ndarray
+    b: np.ndarray   # degree floor(D / 2)
+
+
+def served_mixed_trace(count: int, rate: float, div_share: float = 0.25, lo: int = 64, hi: int = 16384,
+                       seed: int = SEED_BASE + 7) -> list:
+    """Poisson stream of gcd and division requests. Per request, in this
+    order: the inter-arrival gap, the prime index, the kind (a division with
+    probability div_share), D log-uniform in [lo, hi]; then for a gcd the
+    draws of served_trace (k, g, u, v), for a division a of degree D and b
+    of degree floor(D/2), uniform with non-zero leading coefficients."""
+    st = Stream(seed)
+    t = 0.0
+    reqs = []
+    for _ in range(count):
+        t += st.exponential(rate)
+        p = PRIMES[st.index(len(PRIMES))]
+        div = st.unit() < div_share
+        D = st.log_uniform_int(lo, hi)
+        if div:
+            a = st.uniform_poly(D, p)
+            reqs.append(DivisionRequest(t, p, D, a, st.uniform_poly(D // 2, p)))
+        else:
+            k = st.uniform_int(0, D // 4)
+            reqs.append(Request(t, p, D, k, planted_gcd(D, D - 1, k, p, st)))
+    return reqs

@@ -908,6 +908,116 @@ def test_server_admission_waits_for_memory_and_slots():
     srv.close()
 
 
+def _division_requests(count, seed, lo=8, hi=6000):
+    """Division requests: a of degree D log-uniform in [lo, hi], b of a
+    degree uniform in [0, D], uniform residues, three primes."""
+    st = gen.Stream(seed)
+    reqs = []
+    for _ in range(count):
+        p = gen.PRIMES[st.index(3)]
+        D = st.log_uniform_int(lo, hi)
+        db = st.uniform_int(0, D)
+        reqs.append((st.uniform_poly(D, p), st.uniform_poly(db, p), p))
+    return reqs
+
+
+def _check_division(c, a, b, p):
+    wq, wr = oracle.divrem(a, b, p)
+    assert c["status"] == 0 and c["op"] == pm.PM_OP_DIVREM, c["tag"]
+    assert same(c["q"], wq) and same(c["r"], wr), c["tag"]
+    nzb = np.nonzero(b)[0]
+    db1 = int(nzb[-1]) + 1 if nzb.size else 0  # deg b + 1: high zeros do not count
+    assert c["steps"] == wq.size and c["updates"] == wq.size * db1, c["tag"]
+
+
+def test_server_division_requests():
+    # both worker shapes (up to 4096 terms on the 256-thread blocks), the
+    # capacity, long and short quotients, deg a < deg b, constant divisors,
+    # and division requests with high zeros
+    reqs = _division_requests(40, 511) + _division_requests(4, 512, lo=5000, hi=17407)
+    st = gen.Stream(513)
+    p = gen.P_B
+    a = st.uniform_poly(17406, p)
+    z = np.zeros(30, dtype=np.uint32)
+    reqs += [(a, st.uniform_poly(8000, p), p), (a, st.uniform_poly(0, p), p), (a[:4096], a[:4096], p),
+             (a[:100], st.uniform_poly(3000, p), p), (np.zeros(0, np.uint32), a[:50], p),
+             (np.concatenate([a[:700], z]), np.concatenate([a[:300], z]), p),
+             (st.uniform_poly(4095, 2), st.uniform_poly(2000, 2), 2)]
+    srv = pm.Server()
+    srv.submit_many([(x, y, q, i, True) for i, (x, y, q) in enumerate(reqs)])
+    out = srv.drain()
+    assert sorted(c["tag"] for c in out) == list(range(len(reqs)))
+    for c in out:
+        _check_division(c, *reqs[c["tag"]])
+    # device errors come back in the completion; b = 0 given empty on the host
+    bad = a[:60].copy()
+    bad[9] = p + 3
+    srv.submit_many([(a[:60], np.zeros(8, np.uint32), p, 0, True), (bad, a[:20], p, 1, True)])
+    st_by_tag = {c["tag"]: c["status"] for c in srv.drain()}
+    assert st_by_tag == {0: pm.PM_EDIVZERO, 1: pm.PM_ERANGE}
+    with pytest.raises(pm.PolyModPError) as e:
+        srv.submit(a[:60], np.zeros(0, np.uint32), p, divrem=True)
+    assert e.value.status == pm.PM_EDIVZERO
+    srv.close()
+
+
+def test_server_gcd_and_division_same_alone_and_in_the_mix():
+    gcds = _served_requests(30, 514) + _served_requests(3, 515, lo=5000, hi=16000)
+    divs = _division_requests(30, 516) + _division_requests(2, 517, lo=5000, hi=16000)
+    mix = [(a, b, p, False) for a, b, p in gcds] + [(a, b, p, True) for a, b, p in divs]
+    # gcds and divisions interleaved in submission order
+    ng = len(gcds)
+    idx = [j for pair in zip(range(ng), range(ng, len(mix))) for j in pair]
+    idx += [j for j in range(len(mix)) if j not in set(idx)]
+    srv = pm.Server()
+    done = {}
+    # three waves while polling: later requests join a GPU already working
+    for w in range(3):
+        srv.submit_many([(mix[i][0], mix[i][1], mix[i][2], i, mix[i][3]) for i in idx[w::3]])
+        for c in srv.poll():
+            done[c["tag"]] = c
+    for c in srv.drain():
+        done[c["tag"]] = c
+    assert len(done) == len(mix)
+    for i, (a, b, p, div) in enumerate(mix):
+        if div:
+            _check_division(done[i], a, b, p)
+        else:
+            assert done[i]["status"] == 0 and same(done[i]["g"], oracle.gcd(a, b, p)), i
+    srv.close()
+    # alone: a fresh server per request, results and counts identical
+    for i in [0, len(gcds) - 1, len(gcds), len(mix) - 1]:
+        a, b, p, div = mix[i]
+        solo = pm.Server()
+        solo.submit(a, b, p, tag=i, divrem=div)
+        c = solo.drain()[0]
+        key = ("q", "r") if div else ("g",)
+        assert all(same(c[k], done[i][k]) for k in key) and c["steps"] == done[i]["steps"], i
+        solo.close()
+
+
+def test_server_worker_shapes_give_identical_results():
+    # every request on the 1024-thread worker, the default split, and a
+    # small split with few blocks of each shape: the same results
+    reqs = _served_requests(24, 519, lo=30, hi=9000)
+    divs = _division_requests(8, 520, lo=30, hi=9000)
+    subs = [(a, b, p, i, False) for i, (a, b, p) in enumerate(reqs)]
+    subs += [(a, b, p, len(reqs) + i, True) for i, (a, b, p) in enumerate(divs)]
+    results = []
+    for opts in [dict(small_blocks=-1), dict(), dict(large_blocks=4, small_blocks=6)]:
+        srv = pm.Server(**opts)
+        srv.submit_many(subs)
+        out = {c["tag"]: c for c in srv.drain()}
+        srv.close()
+        results.append(out)
+    for i, (a, b, p) in enumerate(reqs):
+        assert same(results[0][i]["g"], oracle.gcd(a, b, p)), i
+    for out in results[1:]:
+        for t, c in results[0].items():
+            keys = ("q", "r") if c["op"] == pm.PM_OP_DIVREM else ("g",)
+            assert all(same(out[t][k], c[k]) for k in keys) and out[t]["steps"] == c["steps"], t
+
+
 # ------------------------------------------------------------- radix sort
 def _sort_inputs(st, n, kind):
     if kind == "uniform":
