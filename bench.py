@@ -386,7 +386,7 @@ def bench_batched_gcd(reqs, one_call_sample: int = 256, reps: int = 3, served=No
             "all_ok": ok, "sample_equals_one_call": same, "served_results_equal_batch": served_same}
 
 
-def run_server_trace(reqs, scale: float, keep: bool = False):
+def run_server_trace(reqs, scale: float, keep: bool = False, **opts):
     """Submit each request at arrival * scale seconds (the requests that have
     arrived by each pass of the loop go in one submit_many call); returns
     latencies (ms, in completion order, with each one's op), the span from
@@ -394,7 +394,7 @@ def run_server_trace(reqs, scale: float, keep: bool = False):
     completions by request index. A request is (a, b, p, arrival, D, k) for
     a gcd, with a seventh element True for a division."""
     import paper_1402_0264_amd as pm
-    srv = pm.Server()
+    srv = pm.Server(**opts)
     t0 = time.perf_counter()
     i = done = 0
     lat = []
@@ -450,6 +450,9 @@ def bench_served(n_req: int, warm: int, load: float, baseline: bool, loads=(0.5,
     run_server_trace(warm_reqs, 0.0)
     lat_sat, span_sat, kept = run_server_trace(reqs, 0.0, keep=True)  # everything arrives at once
     sat = len(reqs) / span_sat
+    # the same, with the inputs read by the workers from pinned host memory
+    # instead of copied to the device arena
+    _, span_host, _ = run_server_trace(reqs, 0.0, staging=2)
     mean_gap = reqs[-1][3] / max(len(reqs) - 1, 1)         # of the rate-1 trace
     rate = load * sat
     scale = 1.0 / (rate * mean_gap)
@@ -458,6 +461,7 @@ def bench_served(n_req: int, warm: int, load: float, baseline: bool, loads=(0.5,
     out = {"workload": "%d gcd requests, D log-uniform in [64, 16384], deg b = D-1, planted gcd degree "
                        "uniform in [0, D/4], p in {469762049, 998244353, 167772161}" % len(reqs),
            "saturated_gcds_per_s": round(sat, 1),
+           "saturated_gcds_per_s_inputs_in_host_memory": round(len(reqs) / span_host, 1),
            "offered_rate_per_s": round(rate, 1), "load": load,
            "gcds_per_s": round(len(reqs) / span, 1),
            "p50_ms": round(_pct(lat, 0.50), 3), "p99_ms": round(_pct(lat, 0.99), 3),

@@ -328,15 +328,16 @@ void pm_gcd_batch_destroy(pm_gcd_batch *batch);
  * queued requests in arrival order while a slot (max_inflight) and room in
  * the device-memory arena (arena_words) for the request's inputs, and in
  * the host output arena for its outputs, are free. An admitted request's
- * inputs are copied into the device arena (one copy per admission pass on
- * a copy stream); the request is published to the GPU once its copy has
- * completed. pm_server_poll returns the requests that finished since the
- * last poll.
+ * inputs are copied into the device arena (one copy per contiguous run of
+ * an admission pass, on an SDMA engine, so that the copies need no CU);
+ * the request is published to the GPU once its copy has completed.
+ * pm_server_poll returns the requests that finished since the last poll.
  * Two persistent worker kernels run the published requests, one thread-
  * block each, taking the next one as soon as one finishes, so requests
- * join and leave the GPU individually: requests whose operands fit 4096
- * terms go to blocks of 256 threads (several per CU), larger ones to
- * blocks of 1024 threads (one per CU). Each request's remainder sequence
+ * join and leave the GPU individually: blocks of 1024 threads (one per
+ * CU) take any request, and when large_blocks leaves CUs free, blocks of
+ * 256 threads (several per CU) take those whose operands fit 4096 terms.
+ * Each request's remainder sequence
  * (or division) stays in its block's LDS until its results are written to
  * the caller's host buffers (done by the time the completion is returned).
  * The workers stop by themselves after an idle period and are relaunched
@@ -348,13 +349,18 @@ void pm_gcd_batch_destroy(pm_gcd_batch *batch);
 typedef struct pm_server pm_server;
 typedef struct {
     int32_t max_inflight;  /* requests admitted at once (0 = 4096)                       */
-    int32_t large_blocks;  /* blocks of the 1024-thread worker (0 = 7/8 of the CUs)      */
+    int32_t large_blocks;  /* blocks of the 1024-thread worker (0 = one per CU)          */
     int64_t arena_words;   /* device words for resident inputs (0 = 32 Mi, or less when
                             * the device has less than 8 times that free); the host
                             * output arena has as many words                              */
     int32_t s;             /* Euclidean steps fused per chunk (0 = 128)                   */
     int32_t small_blocks;  /* blocks of the 256-thread worker (0 = fill the other CUs,
                             * -1 = none: every request on the 1024-thread worker)         */
+    int32_t staging;       /* where the workers read inputs: 0 = the device arena when an
+                            * SDMA engine can fill it, else pinned host memory; 1 = the
+                            * device arena (PM_EDEVICE without an SDMA engine); 2 = the
+                            * pinned host mirror, read over the bus                        */
+    int32_t reserved;
 } pm_server_opts;
 /* A request: op PM_OP_GCD (or 0) asks for the monic gcd of a and b, written
  * to g; PM_OP_DIVREM asks for the division of a by b (Sec. 3's problem:

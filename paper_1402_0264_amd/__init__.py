@@ -58,7 +58,8 @@ class MulItem(ctypes.Structure):
 
 class ServerOpts(ctypes.Structure):
     _fields_ = [("max_inflight", ctypes.c_int32), ("large_blocks", ctypes.c_int32), ("arena_words", ctypes.c_int64),
-                ("s", ctypes.c_int32), ("small_blocks", ctypes.c_int32)]
+                ("s", ctypes.c_int32), ("small_blocks", ctypes.c_int32), ("staging", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class GcdRequest(ctypes.Structure):
@@ -582,10 +583,10 @@ class Server:
     for a division (``divrem=True``) the quotient ``q`` and remainder ``r``."""
 
     def __init__(self, max_inflight: int = 0, large_blocks: int = 0, arena_words: int = 0, s: int = 0,
-                 small_blocks: int = 0):
+                 small_blocks: int = 0, staging: int = 0):
         self.handle = ctypes.c_void_p()
         _check(lib().pm_server_create(ctypes.byref(ServerOpts(max_inflight, large_blocks, arena_words, s,
-                                                              small_blocks)),
+                                                              small_blocks, staging, 0)),
                                       ctypes.byref(self.handle)))
         self._out = {}
         self._buf = (Completion * 512)()

@@ -23,6 +23,8 @@ CALIB_SRC = os.path.join(PKG, "calib_src")
 CALIB_LIB = os.path.join(PKG, "libpolymodp_calib.so")
 ARCH = "gfx950"
 
+# ROCr, for the server's SDMA copies (hsa_amd_memory_async_copy_on_engine)
+LIBS = ["-L/opt/rocm/lib", "-lhsa-runtime64"]
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           "--offload-arch=" + ARCH, "-I", os.path.join(ROOT, "include")]
@@ -50,7 +52,7 @@ def _compile(src: str) -> str:
 
 def _link(objs: list, out: str) -> None:
     tmp = out + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), "-shared", "-fPIC", "--offload-arch=" + ARCH, "-Wl,-z,defs", "-o", tmp] + objs
+    cmd = [hipcc(), "-shared", "-fPIC", "--offload-arch=" + ARCH, "-Wl,-z,defs", "-o", tmp] + objs + LIBS
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed: %s\n%s" % (" ".join(cmd), r.stderr))

@@ -943,7 +943,7 @@ def test_server_division_requests():
              (a[:100], st.uniform_poly(3000, p), p), (np.zeros(0, np.uint32), a[:50], p),
              (np.concatenate([a[:700], z]), np.concatenate([a[:300], z]), p),
              (st.uniform_poly(4095, 2), st.uniform_poly(2000, 2), 2)]
-    srv = pm.Server()
+    srv = pm.Server(large_blocks=128)  # the small requests on 256-thread blocks
     srv.submit_many([(x, y, q, i, True) for i, (x, y, q) in enumerate(reqs)])
     out = srv.drain()
     assert sorted(c["tag"] for c in out) == list(range(len(reqs)))
@@ -997,14 +997,16 @@ def test_server_gcd_and_division_same_alone_and_in_the_mix():
 
 
 def test_server_worker_shapes_give_identical_results():
-    # every request on the 1024-thread worker, the default split, and a
-    # small split with few blocks of each shape: the same results
+    # every request on the 1024-thread worker (the default), a split that
+    # gives the small requests to 256-thread blocks on 64 CUs, few blocks of
+    # each shape, and the inputs read from pinned host memory instead of
+    # the device arena: the same results
     reqs = _served_requests(24, 519, lo=30, hi=9000)
     divs = _division_requests(8, 520, lo=30, hi=9000)
     subs = [(a, b, p, i, False) for i, (a, b, p) in enumerate(reqs)]
     subs += [(a, b, p, len(reqs) + i, True) for i, (a, b, p) in enumerate(divs)]
     results = []
-    for opts in [dict(small_blocks=-1), dict(), dict(large_blocks=4, small_blocks=6)]:
+    for opts in [dict(), dict(large_blocks=192), dict(large_blocks=4, small_blocks=6), dict(staging=2)]:
         srv = pm.Server(**opts)
         srv.submit_many(subs)
         out = {c["tag"]: c for c in srv.drain()}
