@@ -27,6 +27,8 @@
 // applying the recorded steps one by one.
 #pragma once
 
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace pm {
@@ -117,16 +119,13 @@ __device__ __forceinline__ void count_zero_steps(StepLog* L, int dX, int dY, int
     L->zupd += (int64_t)z * (dY + 1);
 }
 
-// Head run by one whole wave. hA/hB: the heads (entry i = coefficient of
-// x^(deg - i)), exact for i < 64*E. Each step reduces the operand of higher
-// degree (A on a tie). The run keeps the heads and their scalar state by
-// role, X the operand reduced next and Y the other, so a step reads no
-// select; the roles swap when the degrees cross. Each step is published in
-// desc[] for the M builder on another wave (m_build_live).
-// Returns the chunk summary through *out (lane 0 writes) and the step
-// count and big flag in n_out / big_out; a big step is desc[0].
+// Head run in the heads' own layout (entry i = coefficient of x^(deg - i)),
+// the form head_run_log takes for a first step whose shift exceeds
+// GCD_MAXSHIFT (big): the two heads then cannot share one window. Each step
+// reduces the operand of higher degree (A on a tie) and shifts the result
+// by its degree drop. Same results and outputs as head_run_log.
 template <int E>
-__device__ void head_run_log(const uint32_t (&hA)[E], const uint32_t (&hB)[E], int dA, int dB, int s,
+__device__ void head_run_rel(const uint32_t (&hA)[E], const uint32_t (&hB)[E], int dA, int dB, int s,
                              const Field& F, StepDesc* desc, StepLog* L, ChunkOut* out, int& n_out,
                              int& big_out) {
     const int lane = threadIdx.x & 63;
@@ -251,6 +250,301 @@ __device__ void head_run_log(const uint32_t (&hA)[E], const uint32_t (&hB)[E], i
         out->unkA = unkA;
         out->unkB = unkB;
         out->big = big;
+        out->zsteps = L->zs;
+        if (!(unkA | unkB)) {
+            out->zX = -1;
+            out->zY = -1;
+        }
+        __hip_atomic_store(&L->end, n, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+}
+
+// Entries of a window of E registers (entry k = 64e + lane) moved down by d
+// (out[k] = in[k + d], 0 past the end), 0 <= d < 64.
+template <int E>
+__device__ __forceinline__ void window_down(const uint32_t (&in)[E], int d, uint32_t (&out)[E]) {
+    const int lane = threadIdx.x & 63;
+    if (d == 0) {
+#pragma unroll
+        for (int e = 0; e < E; e++) out[e] = in[e];
+    } else if (d == 1) {
+#pragma unroll
+        for (int e = 0; e < E; e++)
+            out[e] = lanes_down1(in[e], e + 1 < E ? (uint32_t)__builtin_amdgcn_readlane((int)in[e + 1], 0) : 0u);
+    } else {
+        const int src = ((lane + d) & 63) << 2;
+        const bool low = lane + d < 64;
+#pragma unroll
+        for (int e = 0; e < E; e++) {
+            const uint32_t a = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)in[e]);
+            const uint32_t b = e + 1 < E ? (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)in[e + 1]) : 0u;
+            out[e] = low ? a : b;
+        }
+    }
+}
+
+// Entries moved up by g (out[k] = in[k - g], 0 below g), 0 <= g < 64.
+template <int E>
+__device__ __forceinline__ void window_up(const uint32_t (&in)[E], int g, uint32_t (&out)[E]) {
+    const int lane = threadIdx.x & 63;
+    const int src = ((lane - g) & 63) << 2;
+    const bool high = lane >= g;
+#pragma unroll
+    for (int e = 0; e < E; e++) {
+        const uint32_t a = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)in[e]);
+        const uint32_t b = e > 0 ? (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)in[e - 1]) : 0u;
+        out[e] = high ? a : b;
+    }
+}
+
+// Entry k (uniform, 0 <= k < 64E) of a window, to every lane.
+template <int E>
+__device__ __forceinline__ uint32_t window_at(const uint32_t (&r)[E], int k) {
+    uint32_t v = r[0];
+#pragma unroll
+    for (int e = 1; e < E; e++)
+        if ((k >> 6) == e) v = r[e];
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, k & 63);
+}
+
+// The first entry k with lo < k < hi and r[k] != 0, or -1 (uniform bounds).
+template <int E>
+__device__ __forceinline__ int window_first_nonzero(const uint32_t (&r)[E], int lo, int hi) {
+    const int lane = threadIdx.x & 63;
+    int found = -1;
+#pragma unroll
+    for (int e = E - 1; e >= 0; e--) {
+        const int k = 64 * e + lane;
+        const unsigned long long m = __ballot(r[e] != 0u && k > lo && k < hi);
+        if (m) found = 64 * e + (int)__builtin_ctzll(m);
+    }
+    return found;
+}
+
+// Head run by one whole wave. hA/hB: the heads (entry i = coefficient of
+// x^(deg - i)), exact for i < 64*E. Each step reduces the operand of higher
+// degree (A on a tie) by the other, X <- REDC(lc(Y) X + (p - lc(X)) x^d Y).
+// The run holds both operands in one window of 64E entries, entry k being
+// the coefficient of x^(base - k) with base the higher starting degree, so
+// a step's shift d moves Y by d entries (none for d = 0, one DPP lane shift
+// for d = 1), the new leading coefficient is read in place and the roles
+// change without moving data. An entry is exact below its operand's limit
+// (V): X's new limit is min(V_X, V_Y - d). A step whose new leading
+// coefficient lies at or beyond the limit ends the run with its degree
+// unknown. The descriptors gather in lanes (step j in lane j mod 64) and go
+// to desc[] every 8 steps, each flush published to the M builder on
+// another wave (m_build_live) through L->prog, the last by L->end.
+// Returns the chunk summary through *out (lane 0 writes) and the step
+// count and big flag in n_out / big_out; a big step is desc[0].
+template <int E>
+__device__ void head_run_log(const uint32_t (&hA)[E], const uint32_t (&hB)[E], int dA, int dB, int s,
+                             const Field& F, StepDesc* desc, StepLog* L, ChunkOut* out, int& n_out,
+                             int& big_out) {
+    const int lane = threadIdx.x & 63;
+    constexpr int H = 64 * E;
+    s = uni(s);
+    dA = uni(dA);
+    dB = uni(dB);
+    {
+        const int dX = dA >= dB ? dA : dB, dY = dA >= dB ? dB : dA;
+        if (s > 0 && dY >= 0 && dX - dY > GCD_MAXSHIFT) {
+            head_run_rel<E>(hA, hB, dA, dB, s, F, desc, L, out, n_out, big_out);
+            return;
+        }
+    }
+    int n = 0, S = 0, unkA = 0, unkB = 0, flushed = 0;
+    int64_t upd = 0;
+    uint32_t wm1 = 0u, wm2 = 0u, wd = 0u;  // descriptors not yet flushed (wd: d | which << 16)
+    uint32_t rA[E], rB[E];
+    int VA = H, VB = H, base = 0;
+    uint32_t lcA = (uint32_t)__builtin_amdgcn_readfirstlane((int)hA[0]);
+    uint32_t lcB = (uint32_t)__builtin_amdgcn_readfirstlane((int)hB[0]);
+    // desc[j] for flushed <= j < upto, from lane j mod 64, then published
+    auto flush = [&](int upto) {
+        const int j = flushed + ((lane - flushed) & 63);
+        if (j < upto) desc[j] = StepDesc{wm1, wm2, (int32_t)(wd & 0xffffu), (int32_t)(wd >> 16)};
+        flushed = upto;
+        if (lane == 0) __hip_atomic_store(&L->prog, upto, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    };
+    if (s > 0 && dA >= 0 && dB >= 0) {
+        // the window: the operand of higher degree as it is, the other moved
+        // up by the degree gap
+        base = dA >= dB ? dA : dB;
+        if (dA >= dB) {
+#pragma unroll
+            for (int e = 0; e < E; e++) rA[e] = hA[e];
+            window_up<E>(hB, dA - dB, rB);
+        } else {
+#pragma unroll
+            for (int e = 0; e < E; e++) rB[e] = hB[e];
+            window_up<E>(hA, dB - dA, rA);
+        }
+        // A step's new leading coefficient when entry kX + 1 did not give it
+        // (it vanished, or it is not exact): the first non-zero exact entry
+        // below the old leading one, X = 0, or an unknown degree (the run
+        // ends). Sets dX, lcX and the zero-multiplier steps.
+        auto resolve = [&](auto role, int dXo, int dY, int VX, int kX) {
+            constexpr bool XA = decltype(role)::value;
+            const uint32_t(&X)[E] = XA ? rA : rB;
+            const int v = VX - kX;
+            int nd;
+            uint32_t nlc = 0u;
+            const int k = window_first_nonzero<E>(X, kX + 1, VX);
+            if (k >= 0) {
+                nd = base - k;
+                nlc = window_at<E>(X, k);
+                if (lane == 0) count_zero_steps(L, dXo, dY, nd);
+            } else {
+                // every exact entry below the old leading one vanished
+                nd = dXo - v;
+                if (nd < 0) {
+                    nd = -1;
+                    if (lane == 0) count_zero_steps(L, dXo, dY, nd);
+                } else {
+                    (XA ? unkA : unkB) = 1;
+                    if (lane == 0) {  // the zero steps wait for the true degree
+                        out->zX = dXo;
+                        out->zY = dY;
+                    }
+                }
+            }
+            (XA ? dA : dB) = nd;
+            (XA ? lcA : lcB) = nlc;
+        };
+        // The step's descriptor into lane n mod 64 (flushed every 8 steps).
+        auto record = [&](uint32_t m1, uint32_t m2, int d, int which) {
+            const bool mine = lane == (n & 63);
+            wm1 = mine ? m1 : wm1;
+            wm2 = mine ? m2 : wm2;
+            wd = mine ? (uint32_t)(d | (which << 16)) : wd;
+        };
+        // One step with X = A (XA) or X = B; d >= 0. Each role has its own
+        // copy of the step, so a step moves no data between the operands.
+        auto step = [&](auto role) {
+            constexpr bool XA = decltype(role)::value;
+            uint32_t(&X)[E] = XA ? rA : rB;
+            const uint32_t(&Y)[E] = XA ? rB : rA;
+            const int dX = XA ? dA : dB;
+            const int dY = XA ? dB : dA;
+            int& VX = XA ? VA : VB;
+            const int VY = XA ? VB : VA;
+            const uint32_t lcX = XA ? lcA : lcB;
+            const uint32_t lcY = XA ? lcB : lcA;
+            const int d = dX - dY;
+            const uint32_t m1 = lcY;
+            const uint32_t m2 = F.p - lcX;
+            record(m1, m2, d, XA ? 0 : 1);
+            uint32_t ys[E];
+            window_down<E>(Y, d, ys);
+#pragma unroll
+            for (int e = 0; e < E; e++) X[e] = redc((uint64_t)m1 * X[e] + (uint64_t)m2 * ys[e], F);
+            VX = VX < VY - d ? VX : VY - d;
+            n++;
+            S += d;
+            upd += dY + 1;
+            const int kX = base - dX;
+            const int v = VX - kX;  // exact entries from the old leading one on
+            const uint32_t nlc = v >= 2 ? window_at<E>(X, kX + 1) : 0u;
+            if (__builtin_expect(nlc != 0u, 1)) {
+                (XA ? dA : dB) = dX - 1;
+                (XA ? lcA : lcB) = nlc;
+            } else {
+                resolve(role, dX, dY, VX, kX);
+            }
+        };
+        for (;;) {
+            // Rounds of the generic pattern from a tie deg A = deg B = D: A is
+            // reduced by B (no shift) down to D - 1, then B by x A (shift 1)
+            // down to D - 1, a tie again. A round takes 2 steps and 1 of the
+            // shift budget; it is exact when its two new leading entries are
+            // (k + 2 < min(V_A, V_B), k = base - D), and the counts of all its
+            // rounds are settled at once. A vanishing leading entry ends the
+            // rounds after its step, through resolve.
+            if (dA == dB && dA >= 0) {
+                const int D0 = dA;
+                int k = base - D0;
+                int rounds = 0;
+                for (;;) {
+                    const int minV = VA < VB ? VA : VB;
+                    if (!(n + 2 <= s && S + rounds + 1 <= GCD_MAXSHIFT && k + 2 < minV)) break;
+                    // A <- REDC(lcB A + (p - lcA) B)
+                    uint32_t m1 = lcB, m2 = F.p - lcA;
+                    record(m1, m2, 0, 0);
+#pragma unroll
+                    for (int e = 0; e < E; e++) rA[e] = redc((uint64_t)m1 * rA[e] + (uint64_t)m2 * rB[e], F);
+                    VA = minV;
+                    n++;
+                    const uint32_t la = window_at<E>(rA, k + 1);
+                    if (__builtin_expect(la == 0u, 0)) {
+                        // the rounds before, then this step with X = A at the tie D
+                        const int D = D0 - rounds;
+                        upd += (int64_t)rounds * (2 * D0 + 1) - (int64_t)rounds * (rounds - 1) + (D + 1);
+                        S += rounds;
+                        dA = dB = D;
+                        resolve(std::true_type{}, D, D, VA, k);
+                        rounds = -1;
+                        break;
+                    }
+                    lcA = la;
+                    // B <- REDC(lcA B + (p - lcB) x A), deg B = deg A + 1
+                    m1 = lcA;
+                    m2 = F.p - lcB;
+                    record(m1, m2, 1, 1);
+                    uint32_t ys[E];
+                    window_down<E>(rA, 1, ys);
+#pragma unroll
+                    for (int e = 0; e < E; e++) rB[e] = redc((uint64_t)m1 * rB[e] + (uint64_t)m2 * ys[e], F);
+                    VB = VB < VA - 1 ? VB : VA - 1;
+                    n++;
+                    const uint32_t lb = window_at<E>(rB, k + 1);
+                    if (__builtin_expect(lb == 0u, 0)) {
+                        // the rounds before, this round's A step (to D - 1), then
+                        // this step with X = B of degree D, Y = A of degree D - 1
+                        const int D = D0 - rounds;
+                        upd += (int64_t)rounds * (2 * D0 + 1) - (int64_t)rounds * (rounds - 1) + (D + 1) + D;
+                        S += rounds + 1;
+                        dA = D - 1;
+                        dB = D;
+                        resolve(std::false_type{}, D, D - 1, VB, k);
+                        rounds = -1;
+                        break;
+                    }
+                    lcB = lb;
+                    rounds++;
+                    k++;
+                    if (n - flushed >= 8) flush(n);
+                }
+                if (rounds > 0) {
+                    // sum over the rounds of (D + 1) + D, D = D0, D0 - 1, ...
+                    upd += (int64_t)rounds * (2 * D0 + 1) - (int64_t)rounds * (rounds - 1);
+                    S += rounds;
+                    dA = dB = D0 - rounds;
+                }
+                if (n - flushed >= 8) flush(n);
+                const int ndX = dA >= dB ? dA : dB, ndY = dA >= dB ? dB : dA;
+                if (((s - 1 - n) | ndY | (GCD_MAXSHIFT - S - (ndX - ndY)) | -(unkA | unkB)) < 0) break;
+            }
+            if (dA >= dB) step(std::true_type{});  // A on a tie
+            else step(std::false_type{});
+            if (n - flushed >= 8) flush(n);
+            // the next step: steps left, both operands non-zero, its shift
+            // within the chunk's matrix, and every degree known
+            const int ndX = dA >= dB ? dA : dB, ndY = dA >= dB ? dB : dA;
+            if (((s - 1 - n) | ndY | (GCD_MAXSHIFT - S - (ndX - ndY)) | -(unkA | unkB)) < 0) break;
+        }
+    }
+    flush(n);
+    n_out = n;
+    big_out = 0;
+    if (lane == 0) {
+        out->dA = dA;
+        out->dB = dB;
+        out->upd = upd + L->zupd;
+        out->nsteps = n;
+        out->S = S;
+        out->unkA = unkA;
+        out->unkB = unkB;
+        out->big = 0;
         out->zsteps = L->zs;
         if (!(unkA | unkB)) {
             out->zX = -1;
