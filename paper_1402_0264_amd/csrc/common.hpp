@@ -59,15 +59,17 @@ __device__ __forceinline__ uint64_t fold(uint64_t acc, uint32_t c32) {
     return (uint64_t)(uint32_t)(acc >> 32) * c32 + (uint32_t)acc;
 }
 
-// Montgomery reduction: returns x * 2^-32 mod p for x < p * 2^32 / 1.5
-// (callers pass x < 2p^2, p < 2^30), as a canonical residue. For p = 2 the
-// host sets pinv_neg = 2^31, and the same steps return x mod 2 for
+// Montgomery reduction: returns x * 2^-32 mod p as a canonical residue for
+// x < p * 2^32 (p < 2^30). Larger x below 6p^2 (the gcd's sums of three
+// products of entries kept below 2p) give a congruent value below 1.5p. For
+// p = 2 the host sets pinv_neg = 2^31, and the same steps return x mod 2 for
 // x < 2^32 (the only unit mod 2 is 1, so that is the scaled step's value).
 __device__ __forceinline__ uint32_t redc(uint64_t x, const Field& F) {
     uint32_t t = (uint32_t)x * F.pinv_neg;
     uint64_t s = x + (uint64_t)t * F.p;     // divisible by 2^32, no overflow
-    uint32_t u = (uint32_t)(s >> 32);       // < 1.5 p
-    return u >= F.p ? u - F.p : u;
+    uint32_t u = (uint32_t)(s >> 32);       // < 2p for x < p 2^32
+    uint32_t v = u - F.p;                   // wraps above u when u < p
+    return v < u ? v : u;
 }
 
 // x^e mod p by square and multiply (Fermat inverse: e = p - 2).

@@ -76,7 +76,7 @@ __device__ __forceinline__ void trace_chunk(const GcdArgs& G, int32_t& nrec, int
     }
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
         stp[2 * (nst + i) + 0] = desc[i].d;
-        stp[2 * (nst + i) + 1] = desc[i].which;
+        stp[2 * (nst + i) + 1] = desc[i].which & 1;  // 2: the first step of a round, X = A
     }
     nrec++;
     nst += n;
@@ -89,13 +89,15 @@ __device__ __forceinline__ int steps_allowed(const GcdArgs& G, int64_t done) {
     return left <= 0 ? 0 : (left < G.s ? (int)left : G.s);
 }
 
+// The heads of A and B in the head run's interleaved layout: entry i (the
+// coefficient of x^(deg - i)) in lane i / E of element i % E.
 template <int E>
 __device__ __forceinline__ void load_heads(const uint32_t* A, const uint32_t* B, int64_t dA, int64_t dB,
                                            uint32_t (&hA)[E], uint32_t (&hB)[E]) {
     const int lane = threadIdx.x & 63;
 #pragma unroll
     for (int e = 0; e < E; e++) {
-        const int64_t i = lane + 64 * e;
+        const int64_t i = E * lane + e;
         hA[e] = dA - i >= 0 ? A[dA - i] : 0u;
         hB[e] = dB - i >= 0 ? B[dB - i] : 0u;
     }
@@ -325,8 +327,8 @@ __global__ __launch_bounds__(GCD_THREADS) void gcd_pipe_kernel(GcdArgs G) {
                 uint32_t hA[E], hB[E];
 #pragma unroll
                 for (int e = 0; e < E; e++) {
-                    hA[e] = hbuf[64 * e + lane];
-                    hB[e] = hbuf[64 * (E + e) + lane];
+                    hA[e] = hbuf[E * lane + e];
+                    hB[e] = hbuf[64 * E + E * lane + e];
                 }
                 int nst, big;
                 head_run_log<E>(hA, hB, (int)res.dA, (int)res.dB, steps_allowed(G, run + res.nsteps), F, desc,
@@ -660,8 +662,8 @@ __device__ void gcd_instance(const GcdJob& J, int s, int64_t cap, uint32_t* smem
                     uint32_t hA[E], hB[E];
 #pragma unroll
                     for (int e = 0; e < E; e++) {
-                        hA[e] = hbuf[64 * e + lane];
-                        hB[e] = hbuf[64 * (E + e) + lane];
+                        hA[e] = hbuf[E * lane + e];
+                        hB[e] = hbuf[64 * E + E * lane + e];
                     }
                     int nst, big;
                     head_run_log<E>(hA, hB, (int)res.dA, (int)res.dB, s, F, desc, &s_log, &s_out[mb ^ 1], nst, big);

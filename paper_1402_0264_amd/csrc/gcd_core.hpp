@@ -69,12 +69,6 @@ __device__ __forceinline__ uint32_t lanes_down1(uint32_t x, uint32_t in63) {
     return (threadIdx.x & 63) == 63 ? in63 : y;
 }
 
-// lane i <- lane i-1 of x (lane 0 <- 0)
-__device__ __forceinline__ uint32_t lanes_up1(uint32_t x) {
-    uint32_t y = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x138 /* wave_shr:1 */, 0xf, 0xf, false);
-    return (threadIdx.x & 63) == 0 ? 0u : y;
-}
-
 // lane i <- lane i-d (0 for i < d), any 0 <= d < 64
 __device__ __forceinline__ uint32_t lanes_up(uint32_t x, int d) {
     const int lane = threadIdx.x & 63;
@@ -259,81 +253,115 @@ __device__ void head_run_rel(const uint32_t (&hA)[E], const uint32_t (&hB)[E], i
     }
 }
 
-// Entries of a window of E registers (entry k = 64e + lane) moved down by d
-// (out[k] = in[k + d], 0 past the end), 0 <= d < 64.
-template <int E>
-__device__ __forceinline__ void window_down(const uint32_t (&in)[E], int d, uint32_t (&out)[E]) {
-    const int lane = threadIdx.x & 63;
-    if (d == 0) {
-#pragma unroll
-        for (int e = 0; e < E; e++) out[e] = in[e];
-    } else if (d == 1) {
-#pragma unroll
-        for (int e = 0; e < E; e++)
-            out[e] = lanes_down1(in[e], e + 1 < E ? (uint32_t)__builtin_amdgcn_readlane((int)in[e + 1], 0) : 0u);
-    } else {
-        const int src = ((lane + d) & 63) << 2;
-        const bool low = lane + d < 64;
-#pragma unroll
-        for (int e = 0; e < E; e++) {
-            const uint32_t a = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)in[e]);
-            const uint32_t b = e + 1 < E ? (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)in[e + 1]) : 0u;
-            out[e] = low ? a : b;
-        }
-    }
+// ---------------------------------------------------------------- windows
+// A window of E registers holds 64E entries interleaved: entry i is in lane
+// i / E of register i % E, so moving every entry by one place is a register
+// rename plus one DPP lane shift.
+
+// llvm.amdgcn.writelane: the value (uniform) into one lane (uniform) of old
+extern "C" __device__ int pm_writelane_i32(int value, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
+
+__device__ __forceinline__ uint32_t writelane(uint32_t old, uint32_t value, int lane) {
+    return (uint32_t)pm_writelane_i32((int)value, lane, (int)old);
 }
 
-// Entries moved up by g (out[k] = in[k - g], 0 below g), 0 <= g < 64.
+// lane i <- lane i+1 of x (lane 63 <- 0)
+__device__ __forceinline__ uint32_t lanes_next(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x130 /* wave_shl:1 */, 0xf, 0xf, true);
+}
+
+// lane i <- lane i-1 of x (lane 0 <- 0)
+__device__ __forceinline__ uint32_t lanes_prev(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x138 /* wave_shr:1 */, 0xf, 0xf, true);
+}
+
+// A residue below 2p made canonical.
+__device__ __forceinline__ uint32_t canon(uint32_t x, uint32_t p) {
+    const uint32_t y = x - p;
+    return y < x ? y : x;
+}
+
+// REDC without its final subtraction: x < p 2^32 gives a value < 2p
+// congruent to x 2^-32 (for p = 2, x < 2^32: x mod 2, as redc).
+__device__ __forceinline__ uint32_t redc_lazy(uint64_t x, const Field& F) {
+    const uint32_t t = (uint32_t)x * F.pinv_neg;
+    return (uint32_t)((x + (uint64_t)t * F.p) >> 32);
+}
+
+// out[i] = in[i + 1] (0 enters at the end)
 template <int E>
-__device__ __forceinline__ void window_up(const uint32_t (&in)[E], int g, uint32_t (&out)[E]) {
+__device__ __forceinline__ void window_next(const uint32_t (&in)[E], uint32_t (&out)[E]) {
+#pragma unroll
+    for (int e = 0; e + 1 < E; e++) out[e] = in[e + 1];
+    out[E - 1] = lanes_next(in[0]);
+}
+
+// out[i] = in[i + delta], 0 where i + delta is outside the window
+// (uniform delta, |delta| < 64E)
+template <int E>
+__device__ __forceinline__ void window_shift(const uint32_t (&in)[E], int delta, uint32_t (&out)[E]) {
     const int lane = threadIdx.x & 63;
-    const int src = ((lane - g) & 63) << 2;
-    const bool high = lane >= g;
 #pragma unroll
     for (int e = 0; e < E; e++) {
-        const uint32_t a = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)in[e]);
-        const uint32_t b = e > 0 ? (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)in[e - 1]) : 0u;
-        out[e] = high ? a : b;
+        // source entry E lane + e + delta = E (lane + q) + r
+        const int t = e + delta;
+        const int q = t >= 0 ? t / E : -((E - 1 - t) / E);
+        const int r = t - E * q;
+        uint32_t src = in[0];
+#pragma unroll
+        for (int j = 1; j < E; j++)
+            if (r == j) src = in[j];
+        const int sl = lane + q;
+        const uint32_t v = (uint32_t)__builtin_amdgcn_ds_bpermute((sl & 63) << 2, (int)src);
+        out[e] = (sl >= 0 && sl < 64) ? v : 0u;
     }
 }
 
 // Entry k (uniform, 0 <= k < 64E) of a window, to every lane.
 template <int E>
 __device__ __forceinline__ uint32_t window_at(const uint32_t (&r)[E], int k) {
+    const unsigned u = (unsigned)k;
     uint32_t v = r[0];
 #pragma unroll
     for (int e = 1; e < E; e++)
-        if ((k >> 6) == e) v = r[e];
-    return (uint32_t)__builtin_amdgcn_readlane((int)v, k & 63);
+        if (u % E == (unsigned)e) v = r[e];
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)(u / E));
 }
 
-// The first entry k with lo < k < hi and r[k] != 0, or -1 (uniform bounds).
+// The first entry k with lo < k < hi and r[k] != 0, or -1 (uniform bounds;
+// canonical entries).
 template <int E>
 __device__ __forceinline__ int window_first_nonzero(const uint32_t (&r)[E], int lo, int hi) {
     const int lane = threadIdx.x & 63;
     int found = -1;
 #pragma unroll
-    for (int e = E - 1; e >= 0; e--) {
-        const int k = 64 * e + lane;
+    for (int e = 0; e < E; e++) {
+        const int k = E * lane + e;
         const unsigned long long m = __ballot(r[e] != 0u && k > lo && k < hi);
-        if (m) found = 64 * e + (int)__builtin_ctzll(m);
+        if (m) {
+            const int c = E * (int)__builtin_ctzll(m) + e;
+            found = (found < 0 || c < found) ? c : found;
+        }
     }
     return found;
 }
 
-// Head run by one whole wave. hA/hB: the heads (entry i = coefficient of
-// x^(deg - i)), exact for i < 64*E. Each step reduces the operand of higher
-// degree (A on a tie) by the other, X <- REDC(lc(Y) X + (p - lc(X)) x^d Y).
-// The run holds both operands in one window of 64E entries, entry k being
-// the coefficient of x^(base - k) with base the higher starting degree, so
-// a step's shift d moves Y by d entries (none for d = 0, one DPP lane shift
-// for d = 1), the new leading coefficient is read in place and the roles
-// change without moving data. An entry is exact below its operand's limit
-// (V): X's new limit is min(V_X, V_Y - d). A step whose new leading
-// coefficient lies at or beyond the limit ends the run with its degree
-// unknown. The descriptors gather in lanes (step j in lane j mod 64) and go
-// to desc[] every 8 steps, each flush published to the M builder on
-// another wave (m_build_live) through L->prog, the last by L->end.
+// Head run by one whole wave. hA/hB: the heads, entry i = coefficient of
+// x^(deg - i) in the interleaved layout, exact for i < 64E. Each step
+// reduces the operand of higher degree (A on a tie) by the other,
+// X <- REDC(lc(Y) X + (p - lc(X)) x^d Y). The run holds both operands in one
+// window, entry k being the coefficient of x^(base - k) with base the higher
+// starting degree, so a step's shift d moves Y by d entries, the new leading
+// coefficient is read in place and the roles change without moving data.
+// An entry is exact below its operand's limit (V): X's new limit is
+// min(V_X, V_Y - d). A step whose new leading coefficient lies at or beyond
+// the limit ends the run with its degree unknown. Entries are kept below 2p
+// (reduced lazily); leading coefficients and multipliers are canonical.
+// The descriptors gather in lanes (step j in lane j mod 64) and go to
+// desc[] every 8 steps or so, each flush published to the M builder on
+// another wave (m_build_live) through L->prog, the last by L->end. A step
+// recorded with which = 2 is an A step with d = 0 whose next record is a B
+// step with d = 1 (a round, composed at once by the M builder).
 // Returns the chunk summary through *out (lane 0 writes) and the step
 // count and big flag in n_out / big_out; a big step is desc[0].
 template <int E>
@@ -348,13 +376,33 @@ __device__ void head_run_log(const uint32_t (&hA)[E], const uint32_t (&hB)[E], i
     {
         const int dX = dA >= dB ? dA : dB, dY = dA >= dB ? dB : dA;
         if (s > 0 && dY >= 0 && dX - dY > GCD_MAXSHIFT) {
-            head_run_rel<E>(hA, hB, dA, dB, s, F, desc, L, out, n_out, big_out);
+            // the relative form takes the heads with entry i in lane i mod 64
+            // of register i / 64
+            uint32_t cA[E], cB[E];
+#pragma unroll
+            for (int c = 0; c < E; c++) {
+                const int i = lane + 64 * c;
+                uint32_t va = 0u, vb = 0u;
+#pragma unroll
+                for (int j = 0; j < E; j++) {
+                    const uint32_t a = (uint32_t)__builtin_amdgcn_ds_bpermute((i / E) << 2, (int)hA[j]);
+                    const uint32_t b = (uint32_t)__builtin_amdgcn_ds_bpermute((i / E) << 2, (int)hB[j]);
+                    va = i % E == j ? a : va;
+                    vb = i % E == j ? b : vb;
+                }
+                cA[c] = va;
+                cB[c] = vb;
+            }
+            head_run_rel<E>(cA, cB, dA, dB, s, F, desc, L, out, n_out, big_out);
             return;
         }
     }
     int n = 0, S = 0, unkA = 0, unkB = 0, flushed = 0;
     int64_t upd = 0;
-    uint32_t wm1 = 0u, wm2 = 0u, wd = 0u;  // descriptors not yet flushed (wd: d | which << 16)
+    // Descriptors not yet flushed, step j in lane j mod 64: wm1 = m1 | kind
+    // << 30 (m1 < p < 2^30), wm2 = m2, wd = d for kinds 0 and 1. Kinds: 0 X =
+    // A, 1 X = B, 2 a round's A step (d = 0), 3 a round's B step (d = 1).
+    uint32_t wm1 = 0u, wm2 = 0u, wd = 0u;
     uint32_t rA[E], rB[E];
     int VA = H, VB = H, base = 0;
     uint32_t lcA = (uint32_t)__builtin_amdgcn_readfirstlane((int)hA[0]);
@@ -362,7 +410,12 @@ __device__ void head_run_log(const uint32_t (&hA)[E], const uint32_t (&hB)[E], i
     // desc[j] for flushed <= j < upto, from lane j mod 64, then published
     auto flush = [&](int upto) {
         const int j = flushed + ((lane - flushed) & 63);
-        if (j < upto) desc[j] = StepDesc{wm1, wm2, (int32_t)(wd & 0xffffu), (int32_t)(wd >> 16)};
+        if (j < upto) {
+            const uint32_t kind = wm1 >> 30;
+            const int which = kind == 2u ? 2 : (int)(kind & 1u);
+            const int d = kind >= 2u ? (int)kind - 2 : (int)wd;
+            desc[j] = StepDesc{wm1 & 0x3fffffffu, wm2, d, which};
+        }
         flushed = upto;
         if (lane == 0) __hip_atomic_store(&L->prog, upto, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
     };
@@ -373,11 +426,11 @@ __device__ void head_run_log(const uint32_t (&hA)[E], const uint32_t (&hB)[E], i
         if (dA >= dB) {
 #pragma unroll
             for (int e = 0; e < E; e++) rA[e] = hA[e];
-            window_up<E>(hB, dA - dB, rB);
+            window_shift<E>(hB, -(dA - dB), rB);
         } else {
 #pragma unroll
             for (int e = 0; e < E; e++) rB[e] = hB[e];
-            window_up<E>(hA, dB - dA, rA);
+            window_shift<E>(hA, -(dB - dA), rA);
         }
         // A step's new leading coefficient when entry kX + 1 did not give it
         // (it vanished, or it is not exact): the first non-zero exact entry
@@ -385,7 +438,9 @@ __device__ void head_run_log(const uint32_t (&hA)[E], const uint32_t (&hB)[E], i
         // ends). Sets dX, lcX and the zero-multiplier steps.
         auto resolve = [&](auto role, int dXo, int dY, int VX, int kX) {
             constexpr bool XA = decltype(role)::value;
-            const uint32_t(&X)[E] = XA ? rA : rB;
+            uint32_t(&X)[E] = XA ? rA : rB;
+#pragma unroll
+            for (int e = 0; e < E; e++) X[e] = canon(X[e], F.p);
             const int v = VX - kX;
             int nd;
             uint32_t nlc = 0u;
@@ -411,12 +466,11 @@ __device__ void head_run_log(const uint32_t (&hA)[E], const uint32_t (&hB)[E], i
             (XA ? dA : dB) = nd;
             (XA ? lcA : lcB) = nlc;
         };
-        // The step's descriptor into lane n mod 64 (flushed every 8 steps).
-        auto record = [&](uint32_t m1, uint32_t m2, int d, int which) {
-            const bool mine = lane == (n & 63);
-            wm1 = mine ? m1 : wm1;
-            wm2 = mine ? m2 : wm2;
-            wd = mine ? (uint32_t)(d | (which << 16)) : wd;
+        // The step's descriptor into lane n mod 64 (d only for kinds 0, 1).
+        auto record = [&](uint32_t m1, uint32_t m2, uint32_t kind) {
+            const int l = n & 63;
+            wm1 = writelane(wm1, m1 | (kind << 30), l);
+            wm2 = writelane(wm2, m2, l);
         };
         // One step with X = A (XA) or X = B; d >= 0. Each role has its own
         // copy of the step, so a step moves no data between the operands.
@@ -433,9 +487,18 @@ __device__ void head_run_log(const uint32_t (&hA)[E], const uint32_t (&hB)[E], i
             const int d = dX - dY;
             const uint32_t m1 = lcY;
             const uint32_t m2 = F.p - lcX;
-            record(m1, m2, d, XA ? 0 : 1);
+            record(m1, m2, XA ? 0u : 1u);
+            wd = writelane(wd, (uint32_t)d, n & 63);
             uint32_t ys[E];
-            window_down<E>(Y, d, ys);
+            if (d == 0) {
+#pragma unroll
+                for (int e = 0; e < E; e++) ys[e] = Y[e];
+            } else if (d == 1) {
+                window_next<E>(Y, ys);
+            } else {
+                window_shift<E>(Y, d, ys);
+            }
+            // entries below 2p in, canonical out
 #pragma unroll
             for (int e = 0; e < E; e++) X[e] = redc((uint64_t)m1 * X[e] + (uint64_t)m2 * ys[e], F);
             VX = VX < VY - d ? VX : VY - d;
@@ -464,49 +527,42 @@ __device__ void head_run_log(const uint32_t (&hA)[E], const uint32_t (&hB)[E], i
                 const int D0 = dA;
                 int k = base - D0;
                 int rounds = 0;
-                for (;;) {
-                    const int minV = VA < VB ? VA : VB;
-                    if (!(n + 2 <= s && S + rounds + 1 <= GCD_MAXSHIFT && k + 2 < minV)) break;
+                int why = 0;  // 1: A's new leading entry vanished, 2: B's
+                uint32_t la = 0u;
+                // Round r leaves V_A = minV0 - r and V_B = minV0 - r - 1, so
+                // the limits on the rounds are known up front: the steps
+                // left, the shift budget, and exactness (k + 2 < minV).
+                const int minV0 = VA < VB ? VA : VB;
+                int R = (s - n) / 2;
+                R = R < GCD_MAXSHIFT - S ? R : GCD_MAXSHIFT - S;
+                R = R < (minV0 - k - 1) / 2 ? R : (minV0 - k - 1) / 2;
+                for (int r = 0; r < R; r++) {
+                    const int minV = minV0 - r;
                     // A <- REDC(lcB A + (p - lcA) B)
-                    uint32_t m1 = lcB, m2 = F.p - lcA;
-                    record(m1, m2, 0, 0);
+                    const uint32_t m1 = uni(lcB), m2 = F.p - uni(lcA);
+                    record(m1, m2, 2u);
 #pragma unroll
                     for (int e = 0; e < E; e++) rA[e] = redc((uint64_t)m1 * rA[e] + (uint64_t)m2 * rB[e], F);
-                    VA = minV;
                     n++;
-                    const uint32_t la = window_at<E>(rA, k + 1);
+                    VA = minV;
+                    la = window_at<E>(rA, k + 1);
                     if (__builtin_expect(la == 0u, 0)) {
-                        // the rounds before, then this step with X = A at the tie D
-                        const int D = D0 - rounds;
-                        upd += (int64_t)rounds * (2 * D0 + 1) - (int64_t)rounds * (rounds - 1) + (D + 1);
-                        S += rounds;
-                        dA = dB = D;
-                        resolve(std::true_type{}, D, D, VA, k);
-                        rounds = -1;
+                        why = 1;
                         break;
                     }
-                    lcA = la;
                     // B <- REDC(lcA B + (p - lcB) x A), deg B = deg A + 1
-                    m1 = lcA;
-                    m2 = F.p - lcB;
-                    record(m1, m2, 1, 1);
-                    uint32_t ys[E];
-                    window_down<E>(rA, 1, ys);
+                    const uint32_t n2 = F.p - m1;
+                    record(la, n2, 3u);
+                    uint32_t xa[E];
+                    window_next<E>(rA, xa);
 #pragma unroll
-                    for (int e = 0; e < E; e++) rB[e] = redc((uint64_t)m1 * rB[e] + (uint64_t)m2 * ys[e], F);
-                    VB = VB < VA - 1 ? VB : VA - 1;
+                    for (int e = 0; e < E; e++) rB[e] = redc((uint64_t)la * rB[e] + (uint64_t)n2 * xa[e], F);
                     n++;
+                    VB = minV - 1;
                     const uint32_t lb = window_at<E>(rB, k + 1);
+                    lcA = la;
                     if (__builtin_expect(lb == 0u, 0)) {
-                        // the rounds before, this round's A step (to D - 1), then
-                        // this step with X = B of degree D, Y = A of degree D - 1
-                        const int D = D0 - rounds;
-                        upd += (int64_t)rounds * (2 * D0 + 1) - (int64_t)rounds * (rounds - 1) + (D + 1) + D;
-                        S += rounds + 1;
-                        dA = D - 1;
-                        dB = D;
-                        resolve(std::false_type{}, D, D - 1, VB, k);
-                        rounds = -1;
+                        why = 2;
                         break;
                     }
                     lcB = lb;
@@ -514,11 +570,25 @@ __device__ void head_run_log(const uint32_t (&hA)[E], const uint32_t (&hB)[E], i
                     k++;
                     if (n - flushed >= 8) flush(n);
                 }
-                if (rounds > 0) {
-                    // sum over the rounds of (D + 1) + D, D = D0, D0 - 1, ...
-                    upd += (int64_t)rounds * (2 * D0 + 1) - (int64_t)rounds * (rounds - 1);
-                    S += rounds;
-                    dA = dB = D0 - rounds;
+                // the complete rounds: the sum over them of (D + 1) + D,
+                // D = D0, D0 - 1, ...
+                upd += (int64_t)rounds * (2 * D0 + 1) - (int64_t)rounds * (rounds - 1);
+                S += rounds;
+                const int D = D0 - rounds;
+                dA = dB = D;
+                if (why == 1) {
+                    // the A step at the tie D stands alone (kind 0, d = 0)
+                    wm1 = writelane(wm1, lcB, (n - 1) & 63);
+                    wd = writelane(wd, 0u, (n - 1) & 63);
+                    upd += D + 1;
+                    resolve(std::true_type{}, D, D, VA, k);
+                } else if (why == 2) {
+                    // the round's A step (to D - 1), then B of degree D by
+                    // x A of degree D - 1
+                    upd += (D + 1) + D;
+                    S += 1;
+                    dA = D - 1;
+                    resolve(std::false_type{}, D, D - 1, VB, k);
                 }
                 if (n - flushed >= 8) flush(n);
                 const int ndX = dA >= dB ? dA : dB, ndY = dA >= dB ? dB : dA;
@@ -554,12 +624,13 @@ __device__ void head_run_log(const uint32_t (&hA)[E], const uint32_t (&hB)[E], i
     }
 }
 
-// One step on M's rows: (P, Q) <- m1 (P, Q) + m2 x^d (R, T).
+// One step on M's rows: (P, Q) <- REDC(m1 (P, Q) + m2 x^d (R, T)); rows
+// below 2p in, canonical out.
 __device__ __forceinline__ void m_row_step(uint32_t& P, uint32_t& Q, uint32_t R, uint32_t T, uint32_t m1,
                                            uint32_t m2, int d, const Field& F) {
     if (d == 1) {
-        R = lanes_up1(R);
-        T = lanes_up1(T);
+        R = lanes_prev(R);
+        T = lanes_prev(T);
     } else if (d != 0) {
         R = lanes_up(R, d);
         T = lanes_up(T, d);
@@ -571,8 +642,11 @@ __device__ __forceinline__ void m_row_step(uint32_t& P, uint32_t& Q, uint32_t R,
 // Composes M from the steps of a head run while it goes on (one whole
 // wave, lane k = coefficient k of alpha, beta, gamma, delta): each published
 // step (rows of X) <- REDC(m1 (rows of X) + m2 x^d (rows of Y)) is applied
-// as soon as it appears. Writes M to LDS as 4 rows of 64 words. Waits only
-// on the head run, which never waits on it.
+// as soon as it appears, a round (a record with which = 2 and the next) as
+// one update of both rows from the rows before it, with the head run's c1,
+// c2. The published records are read a batch at a time, record k + j on
+// lane j. Entries stay below 2p until the end. Writes M to LDS as 4 rows of
+// 64 canonical words. Waits only on the head run, which never waits on it.
 __device__ void m_build_live(const StepDesc* desc, StepLog* L, const Field& F, uint32_t* M) {
     const int lane = threadIdx.x & 63;
     uint32_t al = lane == 0 ? 1u : 0u, be = 0u, ga = 0u, de = lane == 0 ? 1u : 0u;
@@ -584,25 +658,45 @@ __device__ void m_build_live(const StepDesc* desc, StepLog* L, const Field& F, u
         const int avail =
             end >= 0 ? end : uni(__hip_atomic_load(&L->prog, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP));
         if (k < avail) {
-            StepDesc D = desc[k];
-            for (;;) {
-                // the next published record is read while this one is applied
-                const StepDesc Dn = desc[k + 1 < avail ? k + 1 : k];
-                const uint32_t m1 = uni(D.m1), m2 = uni(D.m2);
-                const int d = uni(D.d);
-                if (uni(D.which) == 0) m_row_step(al, be, ga, de, m1, m2, d, F);
-                else m_row_step(ga, de, al, be, m1, m2, d, F);
-                if (++k >= avail) break;
-                D = Dn;
+            const int cnt = avail - k < 64 ? avail - k : 64;
+            StepDesc D{0u, 0u, 0, 0};
+            if (lane < cnt) D = desc[k + lane];
+            int i = 0;
+            while (i < cnt) {
+                const uint32_t m1 = (uint32_t)__builtin_amdgcn_readlane((int)D.m1, i);
+                const uint32_t m2 = (uint32_t)__builtin_amdgcn_readlane((int)D.m2, i);
+                const int w = __builtin_amdgcn_readlane(D.which, i);
+                if (w == 2 && i + 1 < cnt) {
+                    const uint32_t n1 = (uint32_t)__builtin_amdgcn_readlane((int)D.m1, i + 1);
+                    const uint32_t n2 = (uint32_t)__builtin_amdgcn_readlane((int)D.m2, i + 1);
+                    const uint32_t cv = redc((uint64_t)(lane == 0 ? m1 : m2) * n2, F);
+                    const uint32_t c1 = (uint32_t)__builtin_amdgcn_readlane((int)cv, 0);
+                    const uint32_t c2 = (uint32_t)__builtin_amdgcn_readlane((int)cv, 1);
+                    const uint32_t xal = lanes_prev(al), xbe = lanes_prev(be);
+                    const uint32_t xga = lanes_prev(ga), xde = lanes_prev(de);
+                    const uint32_t nga = redc((uint64_t)n1 * ga + (uint64_t)c1 * xal + (uint64_t)c2 * xga, F);
+                    const uint32_t nde = redc((uint64_t)n1 * de + (uint64_t)c1 * xbe + (uint64_t)c2 * xde, F);
+                    al = redc_lazy((uint64_t)m1 * al + (uint64_t)m2 * ga, F);
+                    be = redc_lazy((uint64_t)m1 * be + (uint64_t)m2 * de, F);
+                    ga = nga;
+                    de = nde;
+                    i += 2;
+                } else {
+                    const int d = __builtin_amdgcn_readlane(D.d, i);
+                    if ((w & 1) == 0) m_row_step(al, be, ga, de, m1, m2, d, F);
+                    else m_row_step(ga, de, al, be, m1, m2, d, F);
+                    i += 1;
+                }
             }
+            k += cnt;
         }
         if (end >= 0 && k >= end) break;
         if (k >= avail) __builtin_amdgcn_s_sleep(1);
     }
-    M[lane] = al;
-    M[64 + lane] = be;
-    M[128 + lane] = ga;
-    M[192 + lane] = de;
+    M[lane] = canon(al, F.p);
+    M[64 + lane] = canon(be, F.p);
+    M[128 + lane] = canon(ga, F.p);
+    M[192 + lane] = canon(de, F.p);
 }
 
 // New coefficients at G positions of one lane: (A'[P], B'[P]) is the sum
