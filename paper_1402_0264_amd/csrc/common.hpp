@@ -129,25 +129,30 @@ struct CallInfo {
 
 // Grid-wide barrier of a cooperative launch (all nblocks resident): one
 // arrival counter and a generation word in device memory (CallInfo). gen
-// is the caller's copy of the generation, read once at kernel start.
+// is the caller's copy of the generation, read once at kernel start. Every
+// wave waits for its own stores to reach the L2; thread 0 then releases the
+// block's stores with one agent-scope fence (a fence per wave writes back
+// the XCD's L2 once per wave, and those queue), arrives, polls with plain
+// coherent loads and acquires once for the block.
 __device__ __forceinline__ void grid_sync(CallInfo* info, unsigned nblocks, unsigned& gen) {
-    __threadfence();
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (nblocks > 1) {
         if (threadIdx.x == 0) {
+            __threadfence();
             unsigned arrived = atomicAdd(&info->bar_count, 1u);
             if (arrived == nblocks - 1) {
                 atomicExch(&info->bar_count, 0u);
                 __threadfence();
                 atomicAdd(&info->bar_gen, 1u);
             } else {
-                while (__hip_atomic_load(&info->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen)
+                while (__hip_atomic_load(&info->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen)
                     __builtin_amdgcn_s_sleep(1);
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             }
         }
         gen++;
         __syncthreads();
-        __threadfence();
     }
 }
 

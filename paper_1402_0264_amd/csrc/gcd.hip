@@ -107,12 +107,15 @@ __device__ __forceinline__ void load_heads(const uint32_t* A, const uint32_t* B,
 // The arrive half of a grid barrier, called by each of the block's nwaves
 // arriving waves once they are done with the chunk-start operands (and
 // their writes of the new ones are issued): the last of them to arrive (an
-// LDS counter) arrives for the block. With fence = true the wave first
-// releases its stores at agent scope: required of a wave that wrote device
-// memory; a wave that only read it (its loads already consumed) may skip it.
+// LDS counter) arrives for the block. A wave that wrote device memory
+// (wrote = true) first waits until its stores have reached the L2; the
+// last arriver then releases the whole block's stores with one agent-scope
+// fence. (A fence per wave costs far more: each writes back the XCD's whole
+// L2, and those of all the waves on an XCD queue behind each other.) A wave
+// that only read (its loads already consumed) needs no wait.
 __device__ __forceinline__ void arrive_by_waves(CallInfo* info, unsigned nblocks, uint32_t* s_arrive, int nwaves,
-                                                bool fence) {
-    if (fence) __threadfence();
+                                                bool wrote) {
+    if (wrote) __builtin_amdgcn_s_waitcnt(0);
     if ((threadIdx.x & 63) == 0) {
         const uint32_t before = atomicAdd(s_arrive, 1u);
         if (before == (uint32_t)nwaves - 1) {
@@ -131,14 +134,17 @@ __device__ __forceinline__ void arrive_by_waves(CallInfo* info, unsigned nblocks
 }
 
 // The wait half: thread 0 waits until every block has arrived for
-// generation gen. Called by all threads of the block. Thread 0's agent-scope
-// acquire is the block's: the block barrier orders every other thread after
-// it (no fence per wave).
+// generation gen. Called by all threads of the block. Thread 0 polls with
+// plain coherent loads and then acquires once at agent scope; that acquire
+// is the block's: the block barrier orders every other thread after it (no
+// fence per wave).
 __device__ __forceinline__ void wait_grid(CallInfo* info, unsigned nblocks, unsigned& gen) {
     if (nblocks > 1) {
-        if (threadIdx.x == 0)
-            while (__hip_atomic_load(&info->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen)
+        if (threadIdx.x == 0) {
+            while (__hip_atomic_load(&info->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen)
                 __builtin_amdgcn_s_sleep(1);
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
         gen++;
     }
     __syncthreads();
@@ -318,11 +324,9 @@ __global__ __launch_bounds__(GCD_THREADS) void gcd_pipe_kernel(GcdArgs G) {
         }
         if (pipe) heads_after_chunk<E>(Acur, Bcur, res.dA, res.dB, res.S, Mc, F, hw, hbuf);
         if (wave == 0) {
-            // done with state c (the windows were read before the block's barrier)
-            // wave 0 wrote nothing here and needs no fence; measured, the plain
-            // variant still runs faster with one (17.6 against 18.5 ms at
-            // degree 32768) and the extended one without (20.2 against 21.6)
-            arrive_by_waves(G.info, G.groups, &s_arrive, NARRIVE, !XG);
+            // done with state c (the windows were read before the block's
+            // barrier); wave 0 wrote nothing here
+            arrive_by_waves(G.info, G.groups, &s_arrive, NARRIVE, false);
             if (pipe) {
                 uint32_t hA[E], hB[E];
 #pragma unroll

@@ -790,20 +790,35 @@ __device__ __forceinline__ void stage_pair(uint32_t* la, uint32_t* lb, const uin
 
 // One new coefficient: sum_k Ma[k] la[x-k] + Mb[k] lb[x-k], k = 0..S (one
 // row of M applied at local index x; x - k >= 0 guaranteed by the caller).
+// Four accumulators (even and odd k, each row) keep the multiply-adds
+// independent so the LDS reads of later terms overlap them; each is folded
+// after fold_every products, and the four folded sums (each below 2^32 p,
+// p < 2^30) add without overflow.
 __device__ __forceinline__ uint32_t apply_row_at(const uint32_t* la, const uint32_t* lb, int x, int S,
                                                  const uint32_t* Ma, const uint32_t* Mb, const Field& F) {
-    uint64_t acc = 0;
+    uint64_t a0 = 0, a1 = 0, b0 = 0, b1 = 0;
     uint32_t cnt = 0;
-    const uint32_t half = F.fold_every / 2;
-    for (int k = 0; k <= S; k++) {
-        acc += (uint64_t)Ma[k] * la[x - k];
-        acc += (uint64_t)Mb[k] * lb[x - k];
-        if (++cnt == half) {
-            acc = fold(acc, F.c32);
+    const uint32_t fe = F.fold_every;
+    int k = 0;
+#pragma unroll 4
+    for (; k + 1 <= S; k += 2) {
+        a0 += (uint64_t)Ma[k] * la[x - k];
+        b0 += (uint64_t)Mb[k] * lb[x - k];
+        a1 += (uint64_t)Ma[k + 1] * la[x - k - 1];
+        b1 += (uint64_t)Mb[k + 1] * lb[x - k - 1];
+        if (++cnt == fe) {
+            a0 = fold(a0, F.c32);
+            b0 = fold(b0, F.c32);
+            a1 = fold(a1, F.c32);
+            b1 = fold(b1, F.c32);
             cnt = 0;
         }
     }
-    return reduce64(acc, F);
+    if (k <= S) {  // after the loop cnt < fe: one more product fits
+        a0 += (uint64_t)Ma[k] * la[x - k];
+        b0 += (uint64_t)Mb[k] * lb[x - k];
+    }
+    return reduce64(fold(a0, F.c32) + fold(b0, F.c32) + fold(a1, F.c32) + fold(b1, F.c32), F);
 }
 
 }  // namespace pm
