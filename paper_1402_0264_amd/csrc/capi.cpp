@@ -39,7 +39,10 @@ struct pm_mul_batch {
     uint32_t fold_min = 1u << 30;
     pm::MulItem* d_items = nullptr;
     pm::MulTask* d_tasks = nullptr;
-    uint32_t* d_counters = nullptr;
+    uint32_t* d_counters = nullptr;  // the VALU kernel's task queue (two words)
+    int n_mx_tasks = 0;               // items on the matrix cores: one task per output range
+    pm::MxItem* d_mx_items = nullptr;
+    pm::MxTask* d_mx_tasks = nullptr;
 };
 
 namespace {
@@ -605,8 +608,23 @@ void pm_mul_batch_destroy(pm_mul_batch* B) {
     if (B->d_items) (void)hipFree(B->d_items);
     if (B->d_tasks) (void)hipFree(B->d_tasks);
     if (B->d_counters) (void)hipFree(B->d_counters);
+    if (B->d_mx_items) (void)hipFree(B->d_mx_items);
+    if (B->d_mx_tasks) (void)hipFree(B->d_mx_tasks);
     (void)hipSetDevice(cur);
     delete B;
+}
+
+// Which engine a batch item goes to: the matrix cores when the estimated
+// cycles of its range tasks on one CU (block offsets at about 2048 cycles
+// each, half the MFMA peak, plus staging and epilogue per task) undercut
+// the VALU tiles' (about 25 multiply-adds per cycle per CU, measured on the
+// batch), or always under PM_MUL_MFMA; never past the exactness bound.
+bool batch_on_matrix_cores(const pm::MxItem& it, int64_t nkr, int engine) {
+    if (engine == PM_MUL_VALU || it.nb > pm::MX_BATCH_MAXB) return false;
+    if (engine == PM_MUL_MFMA) return true;
+    double mx = 0;
+    for (int64_t kr = 0; kr < nkr; kr++) mx += 2048.0 * (double)pm::mx_batch_offsets(it, kr) + 4000.0;
+    return mx < (double)it.na * (double)it.nb / 25.0;
 }
 
 pm_status pm_mul_batch_create(const pm_mul_item* items, int32_t count, int32_t r, int32_t kc, pm_mul_batch** out) {
@@ -617,8 +635,11 @@ pm_status pm_mul_batch_create(const pm_mul_item* items, int32_t count, int32_t r
     if (kc < r) return fail(PM_EINVAL, "kc must be at least r");
     std::vector<pm::MulItem> host((size_t)count);
     std::vector<std::pair<int64_t, pm::MulTask>> tasks;
+    std::vector<pm::MxItem> mx_items;
+    std::vector<std::pair<int64_t, pm::MxTask>> mx_tasks;
     uint32_t fold_min = 1u << 30;
     const int64_t T = pm::mul_batch_tile(r);
+    const int engine = params_now().mul_engine;
     for (int32_t i = 0; i < count; i++) {
         const pm_mul_item& it = items[i];
         if (bad_len(it.a, it.na) || bad_len(it.b, it.nb)) return fail(PM_EINVAL, "item %d: bad input", i);
@@ -635,11 +656,29 @@ pm_status pm_mul_batch_create(const pm_mul_item* items, int32_t count, int32_t r
         order_operands(x, nx, y, ny);
         host[i] = pm::MulItem{x, y, it.f, nx, ny, F};
         if (need == 0) continue;
+        if (ny <= pm::MX_BATCH_MAXB) {
+            pm::MxItem mi;
+            const int64_t nkr = pm::mx_batch_item(x, nx, y, ny, it.f, F, &mi);
+            if (batch_on_matrix_cores(mi, nkr, engine)) {
+                const int32_t idx = (int32_t)mx_items.size();
+                mx_items.push_back(mi);
+                for (int64_t kr = 0; kr < nkr; kr++)
+                    mx_tasks.push_back({pm::mx_batch_offsets(mi, kr), pm::MxTask{idx, (int32_t)kr}});
+                continue;
+            }
+        }
         const int64_t tiles = (need + T - 1) / T;
         if (tiles > INT32_MAX) return fail(PM_EINVAL, "item %d too large", i);
         for (int64_t t = 0; t < tiles; t++) tasks.push_back({T * ny, pm::MulTask{i, (int32_t)t}});
     }
-    if (tasks.size() > (size_t)INT32_MAX) return fail(PM_EINVAL, "too many tasks");
+    if (tasks.size() > (size_t)INT32_MAX || mx_tasks.size() > (size_t)INT32_MAX)
+        return fail(PM_EINVAL, "too many tasks");
+    std::stable_sort(mx_tasks.begin(), mx_tasks.end(),
+                     [](const std::pair<int64_t, pm::MxTask>& u, const std::pair<int64_t, pm::MxTask>& v) {
+                         return u.first > v.first;
+                     });
+    std::vector<pm::MxTask> mtv(mx_tasks.size());
+    for (size_t i = 0; i < mx_tasks.size(); i++) mtv[i] = mx_tasks[i].second;
     // longest first: a greedy queue then ends with the short tasks
     std::stable_sort(tasks.begin(), tasks.end(),
                      [](const std::pair<int64_t, pm::MulTask>& u, const std::pair<int64_t, pm::MulTask>& v) {
@@ -657,6 +696,10 @@ pm_status pm_mul_batch_create(const pm_mul_item* items, int32_t count, int32_t r
     hipError_t e = hipSuccess;
     if (count > 0) e = hipMalloc((void**)&B->d_items, host.size() * sizeof(pm::MulItem));
     if (e == hipSuccess && !tv.empty()) e = hipMalloc((void**)&B->d_tasks, tv.size() * sizeof(pm::MulTask));
+    B->n_mx_tasks = (int)mtv.size();
+    if (e == hipSuccess && !mx_items.empty())
+        e = hipMalloc((void**)&B->d_mx_items, mx_items.size() * sizeof(pm::MxItem));
+    if (e == hipSuccess && !mtv.empty()) e = hipMalloc((void**)&B->d_mx_tasks, mtv.size() * sizeof(pm::MxTask));
     if (e == hipSuccess) e = hipMalloc((void**)&B->d_counters, 2 * sizeof(uint32_t));
     if (e != hipSuccess) {
         pm_mul_batch_destroy(B);
@@ -665,6 +708,10 @@ pm_status pm_mul_batch_create(const pm_mul_item* items, int32_t count, int32_t r
     if (count > 0) e = hipMemcpy(B->d_items, host.data(), host.size() * sizeof(pm::MulItem), hipMemcpyHostToDevice);
     if (e == hipSuccess && !tv.empty())
         e = hipMemcpy(B->d_tasks, tv.data(), tv.size() * sizeof(pm::MulTask), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !mx_items.empty())
+        e = hipMemcpy(B->d_mx_items, mx_items.data(), mx_items.size() * sizeof(pm::MxItem), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !mtv.empty())
+        e = hipMemcpy(B->d_mx_tasks, mtv.data(), mtv.size() * sizeof(pm::MxTask), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(B->d_counters, 0, 2 * sizeof(uint32_t));
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
@@ -679,6 +726,8 @@ pm_status pm_mul_batch_run(pm_mul_batch* B, int32_t* d_status, void* stream) {
     if (!B) return fail(PM_EINVAL, "null batch");
     hipStream_t s = (hipStream_t)stream;
     if (d_status) HIP_TRY(pm::mul_batch_check_launch(B->d_items, B->count, d_status, s), "batch check launch");
+    HIP_TRY(pm::mulx_batch_launch(B->d_mx_items, B->d_mx_tasks, B->n_mx_tasks, num_cus(), s),
+            "batch launch (matrix cores)");
     HIP_TRY(pm::mul_batch_launch(B->d_items, B->d_tasks, B->ntasks, B->r, B->kc, B->fold_min, B->d_counters,
                                  num_cus(), s),
             "batch launch");

@@ -102,6 +102,34 @@ MxGeom mx_geometry(int64_t na, int64_t nb, int num_cus, int64_t nout = -1);
 // large for the planner's cap on work-groups fail this and go to the VALU
 // tiles; mulx_launch refuses them.
 bool mx_exact(const MxGeom& g);
+
+// Batched matrix-core product: one item per product whose shorter operand
+// (b) holds at most MX_BATCH_MAXB coefficients, one task per output range
+// of 4096 outputs; a task sums every block offset of its range (at most
+// 512, which keeps the int32 digit sums exact) and writes f directly.
+constexpr int64_t MX_BATCH_MAXB = 512 * 64 - 64;
+struct MxItem {
+    const uint32_t* a;  // the longer operand
+    const uint32_t* b;
+    uint32_t* f;
+    int64_t na, nb;
+    int64_t nab, nJ;    // MxGeom's rounded block counts
+    Field F;
+    uint32_t w[7];      // 256^e mod p
+    uint32_t c63;       // 2^63 mod p
+};
+struct MxTask {
+    int32_t item;
+    int32_t kr;
+};
+// Fills an item (na >= nb >= 1, nb <= MX_BATCH_MAXB); returns its ranges.
+int64_t mx_batch_item(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, uint32_t* f, const Field& F,
+                      MxItem* out);
+// Block offsets range kr of an item sums (its share of the work).
+int64_t mx_batch_offsets(const MxItem& it, int64_t kr);
+// Tasks sorted longest first; no counters (a static assignment).
+hipError_t mulx_batch_launch(const MxItem* d_items, const MxTask* d_tasks, int ntasks, int num_cus,
+                             hipStream_t stream);
 int64_t mulx_scratch_words(const MxGeom& g);
 // f = a*b for na, nb >= 1 and p < 2^30; out_len/out_status as mul_launch.
 // With sub_from, f[k] = sub_from[k] - (a*b)[k]; with nout > 0 only f[k] for

@@ -279,8 +279,14 @@ __device__ __forceinline__ uint32_t smod(int64_t x, const MxArgs& A) {
     return r >= A.c63 ? r - A.c63 : r + A.F.p - A.c63;
 }
 
-__global__ __launch_bounds__(MX_THREADS, 1) void mulx_kernel(MxArgs A) {
-    __shared__ __attribute__((aligned(16))) uint8_t lds[MX_LDS_BYTES];
+// The LDS addresses of a lane: bwin, its Toeplitz window (copy o = 3 - ul
+// of digit plane j; at offset jj the 32 bytes from bwin + (JC - jj)*64 hold
+// row tile t in dwords 3-t .. 6-t), and acol, its a columns (plane i, block
+// 32wk + m + 8q + JC - 1 - jj, k-slot group g).
+struct MxLane {
+    int bwin, acol, q;
+};
+__device__ __forceinline__ MxLane mx_lane() {
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int wu = wave & 3, wk = wave >> 2;  // u slice [16wu, +16), block half [32wk, +32)
@@ -288,22 +294,149 @@ __global__ __launch_bounds__(MX_THREADS, 1) void mulx_kernel(MxArgs A) {
     const int rl = lane & 15;           // row (A side) / column (B side) of the 16x16 tile
     const int ul = rl >> 2, dj = rl & 3;   // A side: output u = 16*wu + 4t + ul, digit j of b
     const int q = rl >> 2, di = rl & 3;    // B side: block K = K0 + 32*wk + m + 8q, digit i of a
+    return MxLane{MX_LDS_B + (4 * (3 - ul) + dj) * MX_BPL - 16 - 16 * wu + 16 * g,
+                  MX_LDS_A + di * MX_APL + 16 * g + 32 * wk * MX_T, q};
+}
+
+// Accumulates the digit sums of output range K0 (= 64 kr) over the block
+// offsets [Ja, Jend) (whole groups of 8) into acc, staging a and b a
+// JC-offset chunk at a time. Called by the whole work-group; returns the
+// range-check bits of the staged coefficients.
+__device__ __forceinline__ uint32_t mx_range(const MxArgs& A, uint8_t* lds, const MxLane& L, int64_t K0, int64_t Ja,
+                                             int64_t Jend, v4i (&acc)[4][8]) {
+    const int bwin = L.bwin, acol = L.acol, q = L.q;
+    uint32_t bad = 0;
+#pragma unroll
+    for (int t = 0; t < 4; t++)
+#pragma unroll
+        for (int m = 0; m < 8; m++) acc[t][m] = v4i{0, 0, 0, 0};
+
+    for (int64_t Js = Ja; Js < Jend; Js += MX_JC) {
+        const int ngrp = (int)((Jend - Js < MX_JC ? Jend - Js : MX_JC) / MX_GRP);
+        const int last = ngrp * MX_GRP - 1;
+        __syncthreads();  // the previous stage is no longer read
+        bad |= mx_stage(A, lds, K0, Js);
+        __syncthreads();
+        v4i B[8];
+#pragma unroll
+        for (int m = 0; m < 8; m++) B[m] = ld_b128(lds, acol + (m + 8 * q + MX_JC - 1) * MX_T);
+        // two Toeplitz windows, used alternately: offset jj reads window
+        // jj mod 2 while the next offset's window loads into the other
+        v4i Wa0 = ld_b128(lds, bwin + MX_JC * MX_T), Wa1 = ld_b128(lds, bwin + MX_JC * MX_T + 16);
+        v4i Wb0 = Wa0, Wb1 = Wa1;
+
+        for (int grp = 0; grp < ngrp; grp++) {
+#pragma unroll
+            for (int ph = 0; ph < MX_GRP; ph++) {
+                const int jj = grp * MX_GRP + ph;
+                const int jn = jj < last ? jj + 1 : last;  // next offset (clamped, stays in the stage)
+                // new column for tile 0 at the next offset (only the q = 0
+                // lanes keep it; the others take tile 7's q - 1 part)
+                const v4i fresh = ld_b128(lds, acol + (MX_JC - 1 - jn) * MX_T);
+                const v4i C0 = (ph & 1) ? Wb0 : Wa0, C1 = (ph & 1) ? Wb1 : Wa1;
+                if (ph & 1) {
+                    Wa0 = ld_b128(lds, bwin + (MX_JC - jn) * MX_T);
+                    Wa1 = ld_b128(lds, bwin + (MX_JC - jn) * MX_T + 16);
+                } else {
+                    Wb0 = ld_b128(lds, bwin + (MX_JC - jn) * MX_T);
+                    Wb1 = ld_b128(lds, bwin + (MX_JC - jn) * MX_T + 16);
+                }
+                // the three reads above stay ahead of this offset's MFMAs: they
+                // are used one step later (window) or after all 32 (fresh)
+                __builtin_amdgcn_sched_barrier(0);
+                const v4i At[4] = {v4i{C0[3], C1[0], C1[1], C1[2]}, v4i{C0[2], C0[3], C1[0], C1[1]},
+                                   v4i{C0[1], C0[2], C0[3], C1[0]}, C0};
+#pragma unroll
+                for (int t = 0; t < 4; t++)
+#pragma unroll
+                    for (int m = 0; m < 8; m++)
+                        acc[t][m] = __builtin_amdgcn_mfma_i32_16x16x64_i8(At[t], B[(m - ph) & 7], acc[t][m], 0, 0, 0);
+                const int slot = (7 - ph) & 7;
+#pragma unroll
+                for (int c = 0; c < 4; c++)
+                    B[slot][c] = __builtin_amdgcn_update_dpp(fresh[c], B[slot][c], 0x114 /* row_shr:4 */, 0xf, 0xf,
+                                                             false);
+                // keep each offset's tile assembly after the previous
+                // offset's MFMAs, so its LDS reads have a whole step to land
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    }
+    return bad;
+}
+
+// Epilogue: f[64K + u] = sum_{i,j} 256^(i+j) C_ij. Lane (u, K, i) holds C_ij
+// for j = 0..3 of every column tile; the four lanes i of a quad share (u,
+// K). Through a wave-private LDS exchange, lane i of a quad collects the
+// 16 C_ij of column tile m0 + i, forms the 7 diagonal sums S_s = sum over
+// i + j = s of C_ij in int32 (|S_s| <= 4 * 2^29), and then sum_s w_s S_s in
+// int64 (16 products below 2^59: below 2^63), reduced modulo p once. The
+// residues of the range go to LDS and leave in coalesced 16-byte stores:
+// out[x] for x < nlim, x = (K - K0)*64 + u. Called by the whole work-group
+// after its last MFMA; reuses the staging LDS.
+constexpr int MX_EX_STRIDE = 20;  // words per lane in the exchange (16, padded)
+constexpr int MX_EPI_EX = 0;
+constexpr int MX_EPI_RES = MX_EPI_EX + (MX_THREADS / 64) * 64 * MX_EX_STRIDE * 4;
+static_assert(MX_EPI_RES + MX_RANGE * 4 <= MX_LDS_BYTES, "epilogue LDS");
+
+__device__ __forceinline__ void mx_epilogue(const MxArgs& A, const v4i (&acc)[4][8], uint8_t* lds, uint32_t* out,
+                                            int64_t nlim) {
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int wu = wave & 3, wk = wave >> 2;
+    const int rl = lane & 15;
+    const int q = rl >> 2, di = rl & 3;
+    uint32_t* ex = (uint32_t*)(lds + MX_EPI_EX) + wave * 64 * MX_EX_STRIDE;
+    uint32_t* res = (uint32_t*)(lds + MX_EPI_RES);
+    const int qbase = lane & ~3;
+    __syncthreads();  // every wave is done with the staged operands
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+#pragma unroll
+        for (int m0 = 0; m0 < 8; m0 += 4) {
+#pragma unroll
+            for (int dm = 0; dm < 4; dm++) *(v4i*)(ex + lane * MX_EX_STRIDE + 4 * dm) = acc[t][m0 + dm];
+            __builtin_amdgcn_wave_barrier();
+            v4i C[4];
+#pragma unroll
+            for (int i = 0; i < 4; i++) C[i] = *(const v4i*)(ex + (qbase + i) * MX_EX_STRIDE + 4 * di);
+            __builtin_amdgcn_wave_barrier();
+            const int32_t S[7] = {C[0][0],
+                                  C[0][1] + C[1][0],
+                                  C[0][2] + C[1][1] + C[2][0],
+                                  C[0][3] + C[1][2] + C[2][1] + C[3][0],
+                                  C[1][3] + C[2][2] + C[3][1],
+                                  C[2][3] + C[3][2],
+                                  C[3][3]};
+            int64_t v = 0;
+#pragma unroll
+            for (int e = 0; e < 7; e++) v += (int64_t)A.w[e] * S[e];
+            res[(32 * wk + m0 + di + 8 * q) * MX_T + 16 * wu + 4 * t + (lane >> 4)] = smod(v, A);
+        }
+    }
+    __syncthreads();
+    const bool vec = ((uintptr_t)out & 15) == 0;
+    for (int x = 4 * tid; x < MX_RANGE; x += 4 * MX_THREADS) {
+        const uint4 r = *(const uint4*)(res + x);
+        if (vec && x + 3 < nlim) {
+            *(uint4*)(out + x) = r;
+        } else {
+            if (x < nlim) out[x] = r.x;
+            if (x + 1 < nlim) out[x + 1] = r.y;
+            if (x + 2 < nlim) out[x + 2] = r.z;
+            if (x + 3 < nlim) out[x + 3] = r.w;
+        }
+    }
+}
+
+__global__ __launch_bounds__(MX_THREADS, 1) void mulx_kernel(MxArgs A) {
+    __shared__ __attribute__((aligned(16))) uint8_t lds[MX_LDS_BYTES];
+    const int tid = threadIdx.x;
     const MxGeom& G = A.g;
+    const MxLane L = mx_lane();
     const int64_t w = blockIdx.x;
     const int64_t Ia = mx_share_begin(G, w), Ib = mx_share_begin(G, w + 1);
     uint32_t bad = 0;
-
-    // Toeplitz window of this lane: copy o = 3 - ul of digit plane j; at
-    // offset jj the 32 bytes from bwin + (JC - jj)*64 hold row tile t in
-    // dwords 3-t .. 6-t.
-    const int bwin = MX_LDS_B + (4 * (3 - ul) + dj) * MX_BPL - 16 - 16 * wu + 16 * g;
-    // a columns: plane i, block (32wk + m + 8q + JC - 1 - jj), k-slot group g
-    const int acol = MX_LDS_A + di * MX_APL + 16 * g + 32 * wk * MX_T;
-    // weights 256^(i+j) mod p of this lane's digit i, for j = 0..3
-    uint32_t wl[4];
-#pragma unroll
-    for (int j = 0; j < 4; j++) wl[j] = A.w[di + j];
-
     int64_t I = Ia;
     int64_t kr = Ia < Ib ? mx_range_of(G, Ia) : 0;
     int seg = 0;
@@ -313,99 +446,66 @@ __global__ __launch_bounds__(MX_THREADS, 1) void mulx_kernel(MxArgs A) {
         const int64_t Iend = Ib < S1 ? Ib : S1;
         const int64_t Ja = mx_lo(G, kr) + MX_GRP * (I - S0);
         const int64_t Jend = mx_lo(G, kr) + MX_GRP * (Iend - S0);
-        const int64_t K0 = kr * MX_KW;
-
         v4i acc[4][8];
-#pragma unroll
-        for (int t = 0; t < 4; t++)
-#pragma unroll
-            for (int m = 0; m < 8; m++) acc[t][m] = v4i{0, 0, 0, 0};
-
-        for (int64_t Js = Ja; Js < Jend; Js += MX_JC) {
-            const int ngrp = (int)((Jend - Js < MX_JC ? Jend - Js : MX_JC) / MX_GRP);
-            const int last = ngrp * MX_GRP - 1;
-            __syncthreads();  // the previous stage is no longer read
-            bad |= mx_stage(A, lds, K0, Js);
-            __syncthreads();
-
-            v4i B[8];
-#pragma unroll
-            for (int m = 0; m < 8; m++) B[m] = ld_b128(lds, acol + (m + 8 * q + MX_JC - 1) * MX_T);
-            // two Toeplitz windows, used alternately: offset jj reads window
-            // jj mod 2 while the next offset's window loads into the other
-            v4i Wa0 = ld_b128(lds, bwin + MX_JC * MX_T), Wa1 = ld_b128(lds, bwin + MX_JC * MX_T + 16);
-            v4i Wb0 = Wa0, Wb1 = Wa1;
-
-            for (int grp = 0; grp < ngrp; grp++) {
-#pragma unroll
-                for (int ph = 0; ph < MX_GRP; ph++) {
-                    const int jj = grp * MX_GRP + ph;
-                    const int jn = jj < last ? jj + 1 : last;  // next offset (clamped, stays in the stage)
-                    // new column for tile 0 at the next offset (only the q = 0
-                    // lanes keep it; the others take tile 7's q - 1 part)
-                    const v4i fresh = ld_b128(lds, acol + (MX_JC - 1 - jn) * MX_T);
-                    const v4i C0 = (ph & 1) ? Wb0 : Wa0, C1 = (ph & 1) ? Wb1 : Wa1;
-                    if (ph & 1) {
-                        Wa0 = ld_b128(lds, bwin + (MX_JC - jn) * MX_T);
-                        Wa1 = ld_b128(lds, bwin + (MX_JC - jn) * MX_T + 16);
-                    } else {
-                        Wb0 = ld_b128(lds, bwin + (MX_JC - jn) * MX_T);
-                        Wb1 = ld_b128(lds, bwin + (MX_JC - jn) * MX_T + 16);
-                    }
-                    // the three reads above stay ahead of this offset's MFMAs: they
-                    // are used one step later (window) or after all 32 (fresh)
-                    __builtin_amdgcn_sched_barrier(0);
-                    const v4i At[4] = {v4i{C0[3], C1[0], C1[1], C1[2]}, v4i{C0[2], C0[3], C1[0], C1[1]},
-                                       v4i{C0[1], C0[2], C0[3], C1[0]}, C0};
-#pragma unroll
-                    for (int t = 0; t < 4; t++)
-#pragma unroll
-                        for (int m = 0; m < 8; m++)
-                            acc[t][m] = __builtin_amdgcn_mfma_i32_16x16x64_i8(At[t], B[(m - ph) & 7], acc[t][m],
-                                                                              0, 0, 0);
-                    const int slot = (7 - ph) & 7;
-#pragma unroll
-                    for (int c = 0; c < 4; c++)
-                        B[slot][c] = __builtin_amdgcn_update_dpp(fresh[c], B[slot][c], 0x114 /* row_shr:4 */, 0xf,
-                                                                 0xf, false);
-                    // keep each offset's tile assembly after the previous
-                    // offset's MFMAs, so its LDS reads have a whole step to land
-                    __builtin_amdgcn_sched_barrier(0);
-                }
-            }
-        }
-
-        // Epilogue: f[64K + u] = sum_{i,j} 256^(i+j) C_ij. Lane (u, K, i)
-        // holds C_ij for j = 0..3 of four column tiles m0 + dm. Each weighted
-        // sum v = sum_j w_(i+j) C_ij is exact in int64 and below 2^61 in
-        // magnitude (|C| < 2^29 for at most 512 offsets, w < 2^30), so the four
-        // lanes i of a quad are added exactly before any reduction; lane i then
-        // reduces the sum of tile m0 + i once and stores it at position
-        // (K - K0)*64 + u of the range.
-        uint32_t* out = A.part + ((w * G.maxseg + seg) * MX_RANGE);
-#pragma unroll
-        for (int t = 0; t < 4; t++) {
-#pragma unroll
-            for (int m0 = 0; m0 < 8; m0 += 4) {
-                int64_t keep = 0;
-#pragma unroll
-                for (int dm = 0; dm < 4; dm++) {
-                    const v4i c = acc[t][m0 + dm];
-                    int64_t v = (int64_t)wl[0] * c[0] + (int64_t)wl[1] * c[1] + (int64_t)wl[2] * c[2] +
-                                (int64_t)wl[3] * c[3];
-                    v += quad_xor1(v);
-                    v += quad_xor2(v);
-                    if (dm == di) keep = v;
-                }
-                out[(32 * wk + m0 + di + 8 * q) * MX_T + 16 * wu + 4 * t + (lane >> 4)] = smod(keep, A);
-            }
-        }
+        bad |= mx_range(A, lds, L, kr * MX_KW, Ja, Jend, acc);
+        // this share's partial sums of range kr (canonical residues)
+        mx_epilogue(A, acc, lds, A.part + ((w * G.maxseg + seg) * MX_RANGE), MX_RANGE);
         I = Iend;
         kr++;
         seg++;
     }
     bad = __syncthreads_or(bad);
     if (tid == 0) A.flags[w] = bad;
+}
+
+// ------------------------------------------------------------------ batched
+// Persistent matrix-core product of many independent pairs (one launch):
+// each task is one output range of 4096 outputs of one product, summed over
+// every block offset of b that meets it (at most 512: b is the shorter
+// operand and holds at most 32704 coefficients, so the int32 digit sums stay
+// exact), and reduced straight into f. The host sorts the tasks longest
+// first; work-group w takes tasks w, 2G - 1 - w, 2G + w, ... (rounds of G
+// in alternating directions, which evens out the sums), and loads each
+// next task's descriptor while it works on the current one. No counters:
+// the launch can be replayed (e.g. from a hipGraph) as it is.
+__device__ __forceinline__ int mx_batch_task_at(int round) {
+    const int G = (int)gridDim.x, w = (int)blockIdx.x;
+    return round * G + ((round & 1) ? G - 1 - w : w);
+}
+
+__global__ __launch_bounds__(MX_THREADS, 1) void mulx_batch_kernel(const MxItem* __restrict__ items,
+                                                                   const MxTask* __restrict__ tasks, int ntasks) {
+    __shared__ __attribute__((aligned(16))) uint8_t lds[MX_LDS_BYTES];
+    int round = 0;
+    int t = mx_batch_task_at(0);
+    if (t >= ntasks) return;
+    MxTask tk = tasks[t];
+    while (t < ntasks) {
+        const int tn = mx_batch_task_at(round + 1);
+        const MxTask tkn = tasks[tn < ntasks ? tn : t];  // the next task's descriptor, in flight meanwhile
+        const MxItem& it = items[tk.item];
+        MxArgs A{};
+        A.a = it.a;
+        A.b = it.b;
+        A.g.na = it.na;
+        A.g.nb = it.nb;
+        A.g.nab = it.nab;
+        A.g.nJ = it.nJ;
+        A.F = it.F;
+#pragma unroll
+        for (int e = 0; e < 7; e++) A.w[e] = it.w[e];
+        A.c63 = it.c63;
+        A.a_vec = ((uintptr_t)it.a & 15) == 0;
+        A.b_vec = ((uintptr_t)it.b & 15) == 0;
+        const int64_t kr = tk.kr;
+        v4i acc[4][8];
+        (void)mx_range(A, lds, mx_lane(), kr * MX_KW, mx_lo(A.g, kr), mx_hi(A.g, kr), acc);
+        const int64_t k0 = kr * MX_RANGE;
+        mx_epilogue(A, acc, lds, it.f + k0, it.na + it.nb - 1 - k0);
+        tk = tkn;
+        t = tn;
+        round++;
+    }
 }
 
 // Addition phase: work-group (kr, c) adds, for outputs 1024c .. 1024c+1023
@@ -561,6 +661,43 @@ MxGeom mx_plan(int64_t na, int64_t nb, int num_cus, int64_t nout) {
 bool mx_exact(const MxGeom& g) { return g.maxgrp <= MX_MAXGRP; }
 
 int64_t mulx_scratch_words(const MxGeom& g) { return g.G * g.maxseg * MX_RANGE + g.G; }
+
+int64_t mx_batch_item(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, uint32_t* f, const Field& F,
+                      MxItem* out) {
+    MxItem it{};
+    it.a = a;
+    it.b = b;
+    it.f = f;
+    it.na = na;
+    it.nb = nb;
+    const int64_t nab = (na + MX_T - 1) / MX_T;
+    const int64_t nJ = (nb + 62) / MX_T + 1;
+    const int64_t c = (1 - nab) >= 0 ? (1 - nab) / MX_GRP * MX_GRP : -((nab - 1 + MX_GRP - 1) / MX_GRP * MX_GRP);
+    it.nab = 1 - c;
+    it.nJ = (nJ + MX_GRP - 1) / MX_GRP * MX_GRP;
+    it.F = F;
+    for (int e = 0; e < 7; e++) it.w[e] = (uint32_t)host_powmod(256, e, F.p);
+    it.c63 = (uint32_t)host_powmod(2, 63, F.p);
+    *out = it;
+    return (nJ + nab - 1 + MX_KW - 1) / MX_KW;
+}
+
+int64_t mx_batch_offsets(const MxItem& it, int64_t kr) {
+    MxGeom g{};
+    g.nab = it.nab;
+    g.nJ = it.nJ;
+    return mx_hi(g, kr) - mx_lo(g, kr);
+}
+
+hipError_t mulx_batch_launch(const MxItem* d_items, const MxTask* d_tasks, int ntasks, int num_cus,
+                             hipStream_t stream) {
+    if (ntasks <= 0) return hipSuccess;
+    int grid = mx_blocks_per_cu() * num_cus;
+    if (grid > ntasks) grid = ntasks;
+    TimingScope ts("mulx_batch_kernel", stream);
+    hipLaunchKernelGGL(mulx_batch_kernel, dim3((unsigned)grid), dim3(MX_THREADS), 0, stream, d_items, d_tasks, ntasks);
+    return hipGetLastError();
+}
 
 hipError_t mulx_launch(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, const Field& F, uint32_t* f,
                        const MxGeom& g, uint32_t* scratch, int64_t* out_len, int32_t* out_status,

@@ -664,6 +664,47 @@ def test_mul_batch_matches_oracle(r, kc):
     b.close()
 
 
+def _edge_batch_items():
+    """Ragged and degenerate shapes for the batch engines: single
+    coefficients, lengths on and beside the 64-coefficient blocks and the
+    4096-output ranges, one operand far longer than the other, the longest
+    shorter operand the matrix cores take (32704) and one past it, and
+    p = 2 and 3."""
+    st = gen.Stream(gen.SEED_BASE + 407)
+    shapes = [(1, 1), (1, 5), (7, 1), (63, 64), (64, 65), (65, 63), (4096, 1), (4095, 2), (4097, 64),
+              (2049, 2048), (3000, 3001), (8192, 8192), (8193, 257), (20000, 300), (32704, 40),
+              (40, 32704), (32705, 32705), (5000, 4100), (129, 127), (256, 256), (1000, 1024)]
+    items = []
+    for i, (na, nb) in enumerate(shapes):
+        p = (2, 3, gen.P_A, 998244353)[i % 4]
+        items.append((st.uniform_poly(na - 1, p), st.uniform_poly(nb - 1, p), p))
+    # every coefficient 0x808080 (signed digits -128, -127, -127, 1) at the
+    # longest b the matrix cores take: digit sums at the int32 bound
+    w = np.full(32704, 0x808080, dtype=np.uint32)
+    items.append((w, w.copy(), gen.P_A))
+    return items
+
+
+@pytest.mark.parametrize("engine", [pm.MUL_AUTO, pm.MUL_VALU, pm.MUL_MFMA])
+def test_mul_batch_engines_match_oracle(engine):
+    """The batch with every item on the VALU tiles, on the matrix cores
+    where they apply, and split by the cost model: each output element
+    against the oracle's product."""
+    import torch
+    items = _edge_batch_items() + _batch_items(80, 1, 9000, 408)
+    pm.set_params(mul_engine=engine)
+    try:
+        b = pm.MulBatch([(dev(a), dev(b_), p) for a, b_, p in items])
+    finally:
+        pm.set_params()
+    b.run()
+    torch.cuda.synchronize()
+    want = oracle_mul_many([(a, b_) for a, b_, _ in items], None, [p for _, _, p in items])
+    for i, f in enumerate(b.outputs):
+        assert same(host(f), want[i]), (engine, i, items[i][0].size, items[i][1].size)
+    b.close()
+
+
 def test_mul_batch_graph_replay_and_status():
     import torch
     items = _batch_items(60, 1, 2000, 402)
@@ -695,12 +736,14 @@ def test_mul_batch_graph_replay_and_status():
     b.close()
 
 
-def oracle_mul_many(pairs, p):
-    """The oracle's product of every pair, on a pool of host threads (the
-    C oracle runs without the interpreter lock)."""
+def oracle_mul_many(pairs, p, primes=None):
+    """The oracle's product of every pair (modulo p, or primes[i] for pair
+    i), on a pool of host threads (the C oracle runs without the
+    interpreter lock)."""
     from concurrent.futures import ThreadPoolExecutor
+    ps = primes if primes is not None else [p] * len(pairs)
     with ThreadPoolExecutor(max_workers=min(16, max(1, len(pairs)))) as ex:
-        return list(ex.map(lambda ab: oracle.mul(ab[0], ab[1], p), pairs))
+        return list(ex.map(lambda i: oracle.mul(pairs[i][0], pairs[i][1], ps[i]), range(len(pairs))))
 
 
 def test_mul_batch_workload_4096_full():
