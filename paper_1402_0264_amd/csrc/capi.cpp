@@ -39,10 +39,15 @@ struct pm_mul_batch {
     uint32_t fold_min = 1u << 30;
     pm::MulItem* d_items = nullptr;
     pm::MulTask* d_tasks = nullptr;
-    uint32_t* d_counters = nullptr;  // the VALU kernel's task queue (two words)
     int n_mx_tasks = 0;               // items on the matrix cores: one task per output range
     pm::MxItem* d_mx_items = nullptr;
     pm::MxTask* d_mx_tasks = nullptr;
+    // With both kinds of tasks and r = 4, the VALU tiles run on a second
+    // stream beside the matrix cores, one work-group per CU (it fits beside
+    // the matrix-core work-group: VGPRs, LDS and waves); side joins the
+    // caller's stream through the two events, so a capture takes both.
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 namespace {
@@ -607,9 +612,11 @@ void pm_mul_batch_destroy(pm_mul_batch* B) {
     (void)hipDeviceSynchronize();
     if (B->d_items) (void)hipFree(B->d_items);
     if (B->d_tasks) (void)hipFree(B->d_tasks);
-    if (B->d_counters) (void)hipFree(B->d_counters);
     if (B->d_mx_items) (void)hipFree(B->d_mx_items);
     if (B->d_mx_tasks) (void)hipFree(B->d_mx_tasks);
+    if (B->ev_fork) (void)hipEventDestroy(B->ev_fork);
+    if (B->ev_join) (void)hipEventDestroy(B->ev_join);
+    if (B->side) (void)hipStreamDestroy(B->side);
     (void)hipSetDevice(cur);
     delete B;
 }
@@ -700,7 +707,6 @@ pm_status pm_mul_batch_create(const pm_mul_item* items, int32_t count, int32_t r
     if (e == hipSuccess && !mx_items.empty())
         e = hipMalloc((void**)&B->d_mx_items, mx_items.size() * sizeof(pm::MxItem));
     if (e == hipSuccess && !mtv.empty()) e = hipMalloc((void**)&B->d_mx_tasks, mtv.size() * sizeof(pm::MxTask));
-    if (e == hipSuccess) e = hipMalloc((void**)&B->d_counters, 2 * sizeof(uint32_t));
     if (e != hipSuccess) {
         pm_mul_batch_destroy(B);
         return fail(PM_ENOMEM, "batch tables: %s", hipGetErrorString(e));
@@ -712,7 +718,11 @@ pm_status pm_mul_batch_create(const pm_mul_item* items, int32_t count, int32_t r
         e = hipMemcpy(B->d_mx_items, mx_items.data(), mx_items.size() * sizeof(pm::MxItem), hipMemcpyHostToDevice);
     if (e == hipSuccess && !mtv.empty())
         e = hipMemcpy(B->d_mx_tasks, mtv.data(), mtv.size() * sizeof(pm::MxTask), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemset(B->d_counters, 0, 2 * sizeof(uint32_t));
+    if (e == hipSuccess && B->r == 4 && B->ntasks > 0 && B->n_mx_tasks > 0) {
+        e = hipStreamCreateWithFlags(&B->side, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&B->ev_fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&B->ev_join, hipEventDisableTiming);
+    }
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         pm_mul_batch_destroy(B);
@@ -726,10 +736,21 @@ pm_status pm_mul_batch_run(pm_mul_batch* B, int32_t* d_status, void* stream) {
     if (!B) return fail(PM_EINVAL, "null batch");
     hipStream_t s = (hipStream_t)stream;
     if (d_status) HIP_TRY(pm::mul_batch_check_launch(B->d_items, B->count, d_status, s), "batch check launch");
+    if (B->side) {
+        HIP_TRY(hipEventRecord(B->ev_fork, s), "batch fork");
+        HIP_TRY(hipStreamWaitEvent(B->side, B->ev_fork, 0), "batch fork");
+        HIP_TRY(pm::mulx_batch_launch(B->d_mx_items, B->d_mx_tasks, B->n_mx_tasks, num_cus(), s),
+                "batch launch (matrix cores)");
+        HIP_TRY(pm::mul_batch_launch(B->d_items, B->d_tasks, B->ntasks, B->r, B->kc, B->fold_min, num_cus(),
+                                     B->side, 1),
+                "batch launch");
+        HIP_TRY(hipEventRecord(B->ev_join, B->side), "batch join");
+        HIP_TRY(hipStreamWaitEvent(s, B->ev_join, 0), "batch join");
+        return PM_OK;
+    }
     HIP_TRY(pm::mulx_batch_launch(B->d_mx_items, B->d_mx_tasks, B->n_mx_tasks, num_cus(), s),
             "batch launch (matrix cores)");
-    HIP_TRY(pm::mul_batch_launch(B->d_items, B->d_tasks, B->ntasks, B->r, B->kc, B->fold_min, B->d_counters,
-                                 num_cus(), s),
+    HIP_TRY(pm::mul_batch_launch(B->d_items, B->d_tasks, B->ntasks, B->r, B->kc, B->fold_min, num_cus(), s),
             "batch launch");
     return PM_OK;
 }

@@ -75,10 +75,12 @@ struct MulTask {
 int64_t mul_batch_tile(int r);
 // Chunk length the batched kernel uses for a requested kc.
 int64_t mul_batch_kc(int r, int64_t kc);
-// d_counters: two words, zero before the first launch (the kernel leaves
-// them zero). fold_min: the smallest Field::fold_every over the items.
+// Tasks sorted longest first (a static assignment, no counters).
+// fold_min: the smallest Field::fold_every over the items.
+// blocks_per_cu > 0 caps the persistent grid (e.g. one block per CU beside
+// other work); 0 fills the device.
 hipError_t mul_batch_launch(const MulItem* d_items, const MulTask* d_tasks, int ntasks, int r, int64_t kc,
-                            uint32_t fold_min, uint32_t* d_counters, int num_cus, hipStream_t stream);
+                            uint32_t fold_min, int num_cus, hipStream_t stream, int blocks_per_cu = 0);
 hipError_t mul_batch_check_launch(const MulItem* d_items, int count, int32_t* d_status, hipStream_t stream);
 
 // Product on the matrix cores (mul_mfma.hip): int8 digit products of the

@@ -231,25 +231,25 @@ int64_t effective_kc(const MulPlan& plan, int64_t nb) {
 // Persistent product of many independent pairs (one launch): each task is
 // one output tile of T = 256*R outputs of one product, summed over all of b
 // in chunks of kc coefficients with the sums kept in registers (no partial
-// rows). Thread-blocks take tasks from a queue (one atomic counter) in the
-// order of the task table, which the host sorts longest first; the last
-// block to leave resets the counters, so the launch can be replayed (e.g.
-// from a hipGraph) without any memset.
+// rows). The host sorts the tasks longest first; thread-block w takes tasks
+// w, 2G - 1 - w, 2G + w, ... (rounds of G in alternating directions) and
+// loads each next task's descriptor while it works on the current one. No
+// counters: the launch can be replayed (e.g. from a hipGraph) as it is.
 template <int R, int FOLD>
 __global__ __launch_bounds__(MUL_THREADS) void mul_batch_kernel(const MulItem* __restrict__ items,
                                                                 const MulTask* __restrict__ tasks, int ntasks,
-                                                                int64_t kc, uint32_t* counters) {
+                                                                int64_t kc) {
     extern __shared__ uint32_t lds[];
-    __shared__ int s_task;
     constexpr int T = MUL_THREADS * R;
     const int tid = threadIdx.x;
-    for (;;) {
-        if (tid == 0) s_task = (int)atomicAdd(&counters[0], 1u);
-        __syncthreads();
-        const int t = s_task;
-        __syncthreads();
-        if (t >= ntasks) break;
-        const MulTask tk = tasks[t];
+    const int G = (int)gridDim.x, w = (int)blockIdx.x;
+    int round = 0;
+    int t = w;
+    if (t >= ntasks) return;
+    MulTask tk = tasks[t];
+    while (t < ntasks) {
+        const int tn = (round + 1) * G + (((round + 1) & 1) ? G - 1 - w : w);
+        const MulTask tkn = tasks[tn < ntasks ? tn : t];  // the next task's descriptor, in flight meanwhile
         const MulItem it = items[tk.item];
         const int64_t K0 = (int64_t)tk.tile * T;
         const int64_t nf = it.na + it.nb - 1;
@@ -269,12 +269,9 @@ __global__ __launch_bounds__(MUL_THREADS) void mul_batch_kernel(const MulItem* _
 #pragma unroll
         for (int r = 0; r < R; r++)
             if (kt + r < nf) it.f[kt + r] = reduce64(acc[r], it.F);
-    }
-    if (tid == 0) {
-        if (atomicAdd(&counters[1], 1u) == gridDim.x - 1) {
-            atomicExch(&counters[0], 0u);
-            atomicExch(&counters[1], 0u);
-        }
+        tk = tkn;
+        t = tn;
+        round++;
     }
 }
 
@@ -289,22 +286,22 @@ __global__ __launch_bounds__(256) void mul_batch_check_kernel(const MulItem* __r
 }
 
 template <int R, int FOLD>
-hipError_t launch_batch(const MulItem* items, const MulTask* tasks, int ntasks, int64_t kc, uint32_t* counters,
-                        int grid, hipStream_t stream) {
+hipError_t launch_batch(const MulItem* items, const MulTask* tasks, int ntasks, int64_t kc, int grid,
+                        hipStream_t stream) {
     size_t lds = (size_t)tile_lds_bytes(R, kc);
     hipLaunchKernelGGL((mul_batch_kernel<R, FOLD>), dim3(grid), dim3(MUL_THREADS), lds, stream, items, tasks, ntasks,
-                       kc, counters);
+                       kc);
     return hipGetLastError();
 }
 
 template <int R>
 hipError_t launch_batch_fold(uint32_t fold_min, const MulItem* items, const MulTask* tasks, int ntasks, int64_t kc,
-                             uint32_t* counters, int grid, hipStream_t stream) {
-    if (fold_min >= 128) return launch_batch<R, 128>(items, tasks, ntasks, kc, counters, grid, stream);
-    if (fold_min >= 64) return launch_batch<R, 64>(items, tasks, ntasks, kc, counters, grid, stream);
-    if (fold_min >= 32) return launch_batch<R, 32>(items, tasks, ntasks, kc, counters, grid, stream);
-    if (fold_min >= 16) return launch_batch<R, 16>(items, tasks, ntasks, kc, counters, grid, stream);
-    return launch_batch<R, 8>(items, tasks, ntasks, kc, counters, grid, stream);
+                             int grid, hipStream_t stream) {
+    if (fold_min >= 128) return launch_batch<R, 128>(items, tasks, ntasks, kc, grid, stream);
+    if (fold_min >= 64) return launch_batch<R, 64>(items, tasks, ntasks, kc, grid, stream);
+    if (fold_min >= 32) return launch_batch<R, 32>(items, tasks, ntasks, kc, grid, stream);
+    if (fold_min >= 16) return launch_batch<R, 16>(items, tasks, ntasks, kc, grid, stream);
+    return launch_batch<R, 8>(items, tasks, ntasks, kc, grid, stream);
 }
 
 template <int R>
@@ -344,7 +341,7 @@ int64_t mul_batch_kc(int r, int64_t kc) {
 }
 
 hipError_t mul_batch_launch(const MulItem* d_items, const MulTask* d_tasks, int ntasks, int r, int64_t kc,
-                            uint32_t fold_min, uint32_t* d_counters, int num_cus, hipStream_t stream) {
+                            uint32_t fold_min, int num_cus, hipStream_t stream, int blocks_per_cu) {
     if (ntasks <= 0) return hipSuccess;
     kc = mul_batch_kc(r, kc);
     int per_cu = 1, grid;
@@ -354,13 +351,14 @@ hipError_t mul_batch_launch(const MulItem* d_items, const MulTask* d_tasks, int 
         case 16: per_cu = batch_blocks_per_cu<16>(kc); break;
         default: return hipErrorInvalidValue;
     }
+    if (blocks_per_cu > 0 && per_cu > blocks_per_cu) per_cu = blocks_per_cu;
     grid = per_cu * num_cus;
     if (grid > ntasks) grid = ntasks;
     TimingScope ts("mul_batch_kernel", stream);
     switch (r) {
-        case 4: return launch_batch_fold<4>(fold_min, d_items, d_tasks, ntasks, kc, d_counters, grid, stream);
-        case 8: return launch_batch_fold<8>(fold_min, d_items, d_tasks, ntasks, kc, d_counters, grid, stream);
-        default: return launch_batch_fold<16>(fold_min, d_items, d_tasks, ntasks, kc, d_counters, grid, stream);
+        case 4: return launch_batch_fold<4>(fold_min, d_items, d_tasks, ntasks, kc, grid, stream);
+        case 8: return launch_batch_fold<8>(fold_min, d_items, d_tasks, ntasks, kc, grid, stream);
+        default: return launch_batch_fold<16>(fold_min, d_items, d_tasks, ntasks, kc, grid, stream);
     }
 }
 
