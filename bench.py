@@ -684,6 +684,7 @@ def main() -> int:
     ap.add_argument("--gcd-reps", type=int, default=5)
     ap.add_argument("--no-div", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-batched-gcd", action="store_true", help="skip the prepared gcd batch")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--served-requests", type=int, default=2048)
     ap.add_argument("--no-served-baseline", action="store_true")
@@ -798,7 +799,7 @@ def main() -> int:
         out["served"] = bench_served(args.served_requests, 128, 0.8, not args.no_served_baseline)
     if not args.no_served:
         out["served_mixed"] = bench_served_mixed(args.served_requests, 128, 0.8)
-    if not args.no_batched:
+    if not args.no_batched and not args.no_batched_gcd:
         # the served measurement's requests (after its warm-up ones), so the
         # server's results can be compared one by one
         out["batched_gcd"] = bench_batched_gcd(served_inputs(args.served_requests + 128)[128:],

@@ -311,8 +311,12 @@ __device__ __forceinline__ uint32_t mx_range(const MxArgs& A, uint8_t* lds, cons
 #pragma unroll
         for (int m = 0; m < 8; m++) acc[t][m] = v4i{0, 0, 0, 0};
 
-    for (int64_t Js = Ja; Js < Jend; Js += MX_JC) {
-        const int ngrp = (int)((Jend - Js < MX_JC ? Jend - Js : MX_JC) / MX_GRP);
+    // block offsets fit in 32 bits (at most nb / 64 + 1); 32-bit loop
+    // bounds keep their compares on the scalar unit
+    const int ja = (int)Ja, jend = (int)Jend;
+    for (int js = ja; js < jend; js += MX_JC) {
+        const int64_t Js = js;
+        const int ngrp = (jend - js < MX_JC ? jend - js : MX_JC) / MX_GRP;
         const int last = ngrp * MX_GRP - 1;
         __syncthreads();  // the previous stage is no longer read
         bad |= mx_stage(A, lds, K0, Js);
@@ -437,22 +441,22 @@ __global__ __launch_bounds__(MX_THREADS, 1) void mulx_kernel(MxArgs A) {
     const int64_t w = blockIdx.x;
     const int64_t Ia = mx_share_begin(G, w), Ib = mx_share_begin(G, w + 1);
     uint32_t bad = 0;
-    int64_t I = Ia;
+    // the share's groups counted from Ia (at most MX_MAXGRP: 32-bit counts
+    // keep the loop's compares on the scalar unit)
+    const int nshare = (int)(Ib - Ia);
     int64_t kr = Ia < Ib ? mx_range_of(G, Ia) : 0;
     int seg = 0;
-    while (I < Ib) {
+    for (int done = 0; done < nshare; seg++, kr++) {
+        const int64_t I = Ia + done;
         const int64_t S0 = mx_prefix(G, kr);
-        const int64_t S1 = S0 + mx_groups(G, kr);
-        const int64_t Iend = Ib < S1 ? Ib : S1;
+        const int64_t left = S0 + mx_groups(G, kr) - I;  // groups of range kr from I on
+        const int take = left < nshare - done ? (int)left : nshare - done;
         const int64_t Ja = mx_lo(G, kr) + MX_GRP * (I - S0);
-        const int64_t Jend = mx_lo(G, kr) + MX_GRP * (Iend - S0);
         v4i acc[4][8];
-        bad |= mx_range(A, lds, L, kr * MX_KW, Ja, Jend, acc);
+        bad |= mx_range(A, lds, L, kr * MX_KW, Ja, Ja + MX_GRP * take, acc);
         // this share's partial sums of range kr (canonical residues)
         mx_epilogue(A, acc, lds, A.part + ((w * G.maxseg + seg) * MX_RANGE), MX_RANGE);
-        I = Iend;
-        kr++;
-        seg++;
+        done += take;
     }
     bad = __syncthreads_or(bad);
     if (tid == 0) A.flags[w] = bad;

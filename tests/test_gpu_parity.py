@@ -736,6 +736,38 @@ def test_mul_batch_graph_replay_and_status():
     b.close()
 
 
+def test_mul_batch_two_engines_side_stream_in_a_graph():
+    """r = 4 with items for both engines: the VALU tiles run on the batch's
+    second stream beside the matrix cores, joined back by events. Captured
+    in a graph and replayed three times (outputs cleared between, the
+    program's own work and syncs between replays); every replay against the
+    oracle element by element."""
+    import torch
+    items = _batch_items(40, 2000, 9000, 409) + _batch_items(120, 1, 400, 410)
+    b = pm.MulBatch([(dev(a), dev(b_), p) for a, b_, p in items], 4, 512)
+    want = oracle_mul_many([(a, b_) for a, b_, _ in items], None, [p for _, _, p in items])
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        b.run(stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    for i, f in enumerate(b.outputs):
+        assert same(host(f), want[i]), ("eager", i)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        b.run()
+    for rep in range(3):
+        for f in b.outputs:
+            f.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for i, f in enumerate(b.outputs):
+            assert same(host(f), want[i]), (rep, i)
+    b.close()
+
+
 def oracle_mul_many(pairs, p, primes=None):
     """The oracle's product of every pair (modulo p, or primes[i] for pair
     i), on a pool of host threads (the C oracle runs without the
