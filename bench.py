@@ -28,9 +28,10 @@ Beside it, in the same line:
                 (one thread), the batched products and the served gcds
                 (one thread on a sample, and a thread pool over instances);
   batched_4096  4096 independent products (degrees log-uniform in [32, 8192])
-                in one persistent launch replayed from a captured graph,
-                tile shape from the autotuner, beside the same products as
-                4096 separate calls on the same stream;
+                as one prepared batch replayed from a captured graph (the
+                larger items on the matrix cores, the rest on the VALU tiles
+                beside them; tile shape from the autotuner), beside the same
+                products as 4096 separate calls on the same stream;
   product_2048  the degree-2047 product: single-call host latency, and the
                 steady rate of 100 calls captured in one graph and replayed;
   divrem_65536  Euclidean division with a long quotient: degree 65535 by
@@ -47,7 +48,9 @@ Beside it, in the same line:
                 continuous-batching server: saturated GCDs/s, then p50/p99
                 latency at 0.8 of that rate (and at 0.5, 1.0, 1.2), beside
                 the same trace served one synchronous call per request (FIFO)
-                at 0.8.
+                at 0.8;
+  served_mixed  the same kind of trace with a quarter of the requests
+                Euclidean divisions: saturated requests/s, p50/p99 of each.
 """
 from __future__ import annotations
 
