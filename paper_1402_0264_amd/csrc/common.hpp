@@ -125,6 +125,8 @@ struct CallInfo {
     uint32_t bar_count; // grid barrier state (persistent kernels)
     uint32_t bar_gen;
     int64_t run_steps;  // gcd: steps with a non-zero multiplier that were run
+    uint32_t mult;      // naive gcd: the multiplier of the next step
+    uint32_t pad;
 };
 
 // Grid-wide barrier of a cooperative launch (all nblocks resident): one

@@ -4,9 +4,12 @@
 // over the program parameter s; the fused kernels (divrem.hip, gcd.hip) are
 // the optimized algorithms.
 //
-// Every step reads the leading coefficient it cancels before any thread of
-// the launch writes: the cancelled position itself is never written by the
-// step (it is dead afterwards), so no thread of any block can see it change.
+// A step's multiplier is formed apart from its update, by the launch before
+// it: the division's next quotient term by the thread that updates the next
+// leading position, the gcd's next multiplier by the one-wave rescan that
+// finds the new degree. A step launch then only subtracts a multiple of the
+// divisor, grid-striding over its coefficients; every position it writes is
+// written by one thread and read by no other.
 #include "internal.hpp"
 
 namespace pm {
@@ -41,44 +44,72 @@ __global__ __launch_bounds__(256) void naive_prep_kernel(const uint32_t* a, int6
     }
 }
 
-// One step of the naive division (Alg. 2) at head position i of the working
-// copy w of a: c = w[i] lc(b)^{-1} is the quotient coefficient q[i - db],
-// and w[i - db + j] -= c b[j] for j < db (position i, j = db, cancels).
+// Division step at head position i (Alg. 1/2): with c = q[i - db], the
+// quotient term of position i (formed by the launch before), the positions
+// i - db + j, j < db, lose c b[j]; the thread that updates position i - 1,
+// the next step's leading position, also forms its term q[i - 1 - db] =
+// w[i - 1] lc(b)^-1 from its own new value. For db = 0 nothing is updated
+// and the next term is w[i - 1] lc(b)^-1 as it stands.
 __global__ __launch_bounds__(256) void naive_div_step_kernel(uint32_t* w, const uint32_t* b, int64_t db, int64_t i,
                                                              uint32_t inv, uint32_t* q, Field F) {
-    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const uint32_t c = mulmod(w[i], inv, F);
-    if (j == 0) q[i - db] = c;
-    if (j < db) {
-        uint32_t* x = w + (i - db + j);
-        *x = submod(*x, mulmod(c, b[j], F), F.p);
+    const uint32_t c = q[i - db];
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < db; j += stride) {
+        const int64_t x = i - db + j;
+        const uint32_t v = submod(w[x], mulmod(c, b[j], F), F.p);
+        w[x] = v;
+        if (j == db - 1 && i - 1 >= db) q[i - 1 - db] = mulmod(v, inv, F);
     }
+    if (db == 0 && i >= 1 && blockIdx.x == 0 && threadIdx.x == 0) q[i - 1] = mulmod(w[i - 1], inv, F);
+}
+
+// The first quotient term, q[da - db] = w[da] lc(b)^-1. One thread.
+__global__ __launch_bounds__(64) void naive_div_first_kernel(const uint32_t* w, int64_t da, int64_t db, uint32_t inv,
+                                                             uint32_t* q, Field F) {
+    if (threadIdx.x == 0) q[da - db] = mulmod(w[da], inv, F);
+}
+
+// The multiplier of the next gcd step (Alg. 9), lc(X) lc(Y)^-1 with X the
+// operand of higher degree (A on a tie), into info->mult. One thread.
+__device__ __forceinline__ void naive_gcd_next_mult(const uint32_t* A, const uint32_t* B, int64_t dA, int64_t dB,
+                                                    const Field& F, CallInfo* info) {
+    if (dA < 0 || dB < 0) return;
+    const bool redA = dA >= dB;
+    const uint32_t lx = redA ? A[dA] : B[dB];
+    const uint32_t ly = redA ? B[dB] : A[dA];
+    info->mult = mulmod(lx, invmod(ly, F), F);
+}
+
+__global__ __launch_bounds__(64) void naive_gcd_mult_kernel(const uint32_t* A, const uint32_t* B, Field F,
+                                                            CallInfo* info) {
+    if (threadIdx.x == 0) naive_gcd_next_mult(A, B, info->deg_a, info->deg_b, F, info);
 }
 
 // One step of the naive gcd (Alg. 9) on the working copies A, B with the
 // degrees in info: X, the operand of higher degree (A on a tie), loses
-// c x^d Y with c = lc(X) / lc(Y), d = deg X - deg Y. Position deg X cancels
-// and is left for naive_gcd_rescan_kernel.
+// c x^d Y, c = info->mult, d = deg X - deg Y (grid-stride over the
+// coefficients of Y below its leading one). Position deg X cancels and is
+// left for naive_gcd_rescan_kernel.
 __global__ __launch_bounds__(256) void naive_gcd_step_kernel(uint32_t* A, uint32_t* B, Field F, CallInfo* info) {
     const int64_t dA = info->deg_a, dB = info->deg_b;
     if (dA < 0 || dB < 0) return;
     const bool redA = dA >= dB;
     uint32_t* X = redA ? A : B;
     const uint32_t* Y = redA ? B : A;
-    const int64_t dX = redA ? dA : dB, dY = redA ? dB : dA;
-    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (j >= dY) return;
-    const uint32_t c = mulmod(X[dX], invmod(Y[dY], F), F);
-    X[j + dX - dY] = submod(X[j + dX - dY], mulmod(c, Y[j], F), F.p);
+    const int64_t d = redA ? dA - dB : dB - dA, dY = redA ? dB : dA;
+    const uint32_t c = info->mult;
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < dY; j += stride)
+        X[j + d] = submod(X[j + d], mulmod(c, Y[j], F), F.p);
 }
 
 // After a step: clears X's cancelled leading coefficient, finds X's new
-// degree below it, and counts the step and its updates (deg Y + 1). The
-// positions between the old and the new leading coefficient that are still
-// at or above deg Y are steps too, each with a zero multiplier (the long
-// division visits every position, Alg. 1/2): they are counted, not run.
-// One wave.
-__global__ __launch_bounds__(64) void naive_gcd_rescan_kernel(uint32_t* A, uint32_t* B, CallInfo* info) {
+// degree below it, counts the step and its updates (deg Y + 1), and forms
+// the next step's multiplier. The positions between the old and the new
+// leading coefficient that are still at or above deg Y are steps too, each
+// with a zero multiplier (the long division visits every position, Alg.
+// 1/2): they are counted, not run. One wave.
+__global__ __launch_bounds__(64) void naive_gcd_rescan_kernel(uint32_t* A, uint32_t* B, Field F, CallInfo* info) {
     const int64_t dA = info->deg_a, dB = info->deg_b;
     if (dA < 0 || dB < 0) return;
     const bool redA = dA >= dB;
@@ -93,6 +124,7 @@ __global__ __launch_bounds__(64) void naive_gcd_rescan_kernel(uint32_t* A, uint3
         const int64_t zero = dX - 1 - floor_ > 0 ? dX - 1 - floor_ : 0;
         info->steps += 1 + zero;
         info->updates += (1 + zero) * (dY + 1);
+        naive_gcd_next_mult(A, B, redA ? nd : dA, redA ? dB : nd, F, info);
     }
 }
 
@@ -124,8 +156,10 @@ hipError_t naive_prep_launch(const uint32_t* a, int64_t na, const uint32_t* b, i
 
 hipError_t naive_divrem_launch(uint32_t* w, const uint32_t* b, int64_t da, int64_t db, uint32_t inv, uint32_t* q,
                                const Field& F, hipStream_t stream) {
-    const unsigned grid = grid_for(db);
+    unsigned grid = grid_for(db);
+    if (grid > 1024) grid = 1024;
     TimingScope ts("naive_div_step_kernel", stream);
+    hipLaunchKernelGGL(naive_div_first_kernel, dim3(1), dim3(64), 0, stream, w, da, db, inv, q, F);
     for (int64_t i = da; i >= db; i--) {
         hipLaunchKernelGGL(naive_div_step_kernel, dim3(grid), dim3(256), 0, stream, w, b, db, i, inv, q, F);
         hipError_t e = hipGetLastError();
@@ -136,10 +170,12 @@ hipError_t naive_divrem_launch(uint32_t* w, const uint32_t* b, int64_t da, int64
 
 hipError_t naive_gcd_steps_launch(uint32_t* A, uint32_t* B, int64_t n, int64_t count, const Field& F,
                                   CallInfo* info, hipStream_t stream) {
-    const unsigned grid = grid_for(n);
+    unsigned grid = grid_for(n);
+    if (grid > 1024) grid = 1024;
+    hipLaunchKernelGGL(naive_gcd_mult_kernel, dim3(1), dim3(64), 0, stream, A, B, F, info);
     for (int64_t k = 0; k < count; k++) {
         hipLaunchKernelGGL(naive_gcd_step_kernel, dim3(grid), dim3(256), 0, stream, A, B, F, info);
-        hipLaunchKernelGGL(naive_gcd_rescan_kernel, dim3(1), dim3(64), 0, stream, A, B, info);
+        hipLaunchKernelGGL(naive_gcd_rescan_kernel, dim3(1), dim3(64), 0, stream, A, B, F, info);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
