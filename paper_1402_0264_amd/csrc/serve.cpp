@@ -417,6 +417,25 @@ pm_status ensure_workers(pm_server* S) {
     return PM_OK;
 }
 
+// Writes one word of every page of a new pinned buffer, on several host
+// threads. The runtime maps such memory into the process lazily: the first
+// write to each page takes a page fault, and left to the admission copies
+// those faults ran them at about 3.6 GB/s (28 GB/s once mapped).
+void prefault(void* p, size_t bytes) {
+    constexpr size_t PAGE = 4096;
+    volatile char* base = (volatile char*)p;
+    const size_t pages = (bytes + PAGE - 1) / PAGE;
+    const unsigned hc = std::thread::hardware_concurrency();
+    const size_t nt = std::min<size_t>(pages / 1024 + 1, std::min(8u, hc > 1 ? hc : 1u));
+    auto touch = [=](size_t t) {
+        for (size_t i = t; i < pages; i += nt) base[i * PAGE] = 0;
+    };
+    std::vector<std::thread> th;
+    for (size_t t = 1; t < nt; t++) th.emplace_back(touch, t);
+    touch(0);
+    for (auto& x : th) x.join();
+}
+
 // Puts one request into slot si: its inputs into the pinned mirror at its
 // arena offset, its job record, and the slot into the current pass.
 void place(pm_server* S, int si, int64_t in_off, int64_t out_off, uint64_t ticket, uint64_t tag, int32_t op,
@@ -739,6 +758,8 @@ pm_status pm_server_create(const pm_server_opts* opts, pm_server** out) {
     }
     std::memset(S->h_results, 0, M * sizeof(pm::GcdResult));
     std::memset(S->h_ctl, 0, CTL_WORDS * sizeof(uint32_t));
+    prefault(S->h_mirror, (size_t)o.arena_words * 4);
+    prefault(S->h_out, (size_t)o.arena_words * 4);
     S->in_arena = new Arena(o.arena_words);
     S->out_arena = new Arena(o.arena_words);
     S->slots.resize(M);
