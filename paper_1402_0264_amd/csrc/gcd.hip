@@ -559,12 +559,17 @@ __device__ void gcd_instance(const GcdJob& J, int s, int64_t cap, uint32_t* smem
     __shared__ ChunkOut s_out[2];
     __shared__ int64_t s_deg[2];
     __shared__ StepLog s_log;
-    // wave 0 runs the heads, wave 1 composes M, waves 2.. own the positions
+    // wave 0 runs the heads, wave 1 composes M, waves 2.. own the positions.
+    // The 1024-thread shape gives each lane four consecutive positions per
+    // pass (NP passes) and slides a window down A and B (apply_m_window4:
+    // its apply is bound by VALU, not LDS, reads). The 256-thread shape
+    // keeps the strided passes of AG positions, which need fewer registers
+    // and so let two blocks share a CU.
     constexpr int NA = NT - 128;
-    constexpr int PPA = (NT * PPT + NA - 1) / NA;
-    // positions per pass of the apply: fewer where 1024 threads leave 128
-    // VGPRs per lane
-    constexpr int AG = NT > 256 ? 2 : 4;
+    constexpr bool WIN = NT > 256;
+    constexpr int NP = (NT * PPT + 4 * NA - 1) / (4 * NA);
+    constexpr int AG = 4;
+    constexpr int PPA = WIN ? 4 * NP : (NT * PPT + NA - 1) / NA;
 
     const int64_t n = J.na > J.nb ? J.na : J.nb;
     int bad = n > cap;
@@ -679,8 +684,20 @@ __device__ void gcd_instance(const GcdJob& J, int s, int64_t cap, uint32_t* smem
                     m_build_live(desc, &s_log, F, Mn);
                     __builtin_amdgcn_s_setprio(0);
                 }
+            } else if constexpr (WIN) {
+#pragma unroll
+                for (int t = 0; t < NP; t++) {
+                    const int x = 4 * (tid - 128) + 4 * NA * t;
+                    uint32_t ga[4] = {0u, 0u, 0u, 0u}, gb[4] = {0u, 0u, 0u, 0u};
+                    if (x <= top) apply_m_window4(A, B, x, res.S, Mc, F, ga, gb);
+#pragma unroll
+                    for (int j = 0; j < 4; j++) {
+                        nA[4 * t + j] = ga[j];
+                        nB[4 * t + j] = gb[j];
+                    }
+                }
             } else {
-                // G positions at a time share each read of M (a position
+                // AG positions at a time share each read of M (a position
                 // above top is read at top; its sum is not stored)
 #pragma unroll
                 for (int j0 = 0; j0 < PPA; j0 += AG) {
@@ -701,7 +718,8 @@ __device__ void gcd_instance(const GcdJob& J, int s, int64_t cap, uint32_t* smem
             if (wave >= 2) {
 #pragma unroll
                 for (int j = 0; j < PPA; j++) {
-                    const int P = (tid - 128) + j * NA;
+                    // position of result j: four consecutive per pass, or strided
+                    const int P = WIN ? 4 * (tid - 128) + 4 * NA * (j / 4) + (j % 4) : (tid - 128) + j * NA;
                     if (P <= top) {
                         A[P] = P <= res.dA ? nA[j] : 0u;
                         B[P] = P <= res.dB ? nB[j] : 0u;
@@ -926,7 +944,7 @@ __device__ void div_instance(const GcdJob& J, int64_t cap, uint32_t* smem) {
 template <int NT, int PPT, int E>
 __global__ __launch_bounds__(NT) void gcd_batch_kernel(const GcdJob* jobs, const int32_t* order, int njobs,
                                                        int s, int64_t cap) {
-    extern __shared__ uint32_t smem[];
+    extern __shared__ __align__(16) uint32_t smem[];  // 16-byte reads of A and B
     if ((int)blockIdx.x >= njobs) return;
     const int jid = order ? order[blockIdx.x] : (int)blockIdx.x;
     const GcdJob J = jobs[jid];
@@ -941,7 +959,7 @@ template <int NT, int PPT, int E>
 __global__ __launch_bounds__(NT) void gcd_worker_kernel(const GcdJob* jobs, const uint32_t* order, uint32_t order_cap,
                                                         const uint32_t* tail, const uint32_t* stop, uint32_t* head,
                                                         uint32_t* started, int s, int64_t cap, uint64_t idle_ticks) {
-    extern __shared__ uint32_t smem[];
+    extern __shared__ __align__(16) uint32_t smem[];  // 16-byte reads of A and B
     __shared__ int64_t s_job;
     __shared__ GcdJob s_J;
     if (threadIdx.x == 0) __hip_atomic_fetch_add(started, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);

@@ -761,6 +761,70 @@ __device__ __forceinline__ void apply_m_strided(const uint32_t* la, const uint32
     }
 }
 
+// New coefficients at the four consecutive positions x..x+3 of one lane (x
+// a multiple of 4, la and lb 16-byte aligned): (A'[P], B'[P]) is the sum
+// over k of M's coefficients k times A[P-k], B[P-k]. The lane slides a
+// window of eight values down each array, taking the next four with one
+// 16-byte LDS read, so that each value read serves four positions (with
+// consecutive lanes four words apart the reads are free of bank
+// conflicts). k runs to S + 1 rounded up to 8: M's coefficients above S are
+// zero. Words down to index x - 64 must be readable (zeros below position
+// 0), and words up to x + 3 (those above the caller's top only feed sums it
+// does not store).
+__device__ __forceinline__ void apply_m_window4(const uint32_t* la, const uint32_t* lb, int x, int S,
+                                                const uint32_t* M, const Field& F, uint32_t (&outA)[4],
+                                                uint32_t (&outB)[4]) {
+    uint64_t accA[4] = {0, 0, 0, 0}, accB[4] = {0, 0, 0, 0};
+    // wa[4 + i] = A[x - k0 + i] and wa[i] = A[x - k0 - 4 + i], i < 4
+    uint32_t wa[8], wb[8];
+    {
+        const uint4 a4 = *(const uint4*)(la + x), b4 = *(const uint4*)(lb + x);
+        wa[4] = a4.x; wa[5] = a4.y; wa[6] = a4.z; wa[7] = a4.w;
+        wb[4] = b4.x; wb[5] = b4.y; wb[6] = b4.z; wb[7] = b4.w;
+    }
+    const int kend = (uni(S) + 8) & ~7;
+    uint32_t cnt = 0;
+    const uint32_t half = F.fold_every / 2;
+    for (int k0 = 0; k0 < kend; k0 += 4) {
+        {
+            const uint4 a4 = *(const uint4*)(la + x - k0 - 4), b4 = *(const uint4*)(lb + x - k0 - 4);
+            wa[0] = a4.x; wa[1] = a4.y; wa[2] = a4.z; wa[3] = a4.w;
+            wb[0] = b4.x; wb[1] = b4.y; wb[2] = b4.z; wb[3] = b4.w;
+        }
+#pragma unroll
+        for (int kk = 0; kk < 4; kk++) {
+            const int k = k0 + kk;
+            const uint32_t ma = M[k], mb = M[64 + k], mc = M[128 + k], md = M[192 + k];
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const uint32_t a = wa[4 + j - kk], b = wb[4 + j - kk];
+                accA[j] += (uint64_t)ma * a;
+                accA[j] += (uint64_t)mb * b;
+                accB[j] += (uint64_t)mc * a;
+                accB[j] += (uint64_t)md * b;
+            }
+            if (++cnt == half) {
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    accA[j] = fold(accA[j], F.c32);
+                    accB[j] = fold(accB[j], F.c32);
+                }
+                cnt = 0;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            wa[4 + i] = wa[i];
+            wb[4 + i] = wb[i];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        outA[j] = reduce64(accA[j], F);
+        outB[j] = reduce64(accB[j], F);
+    }
+}
+
 // One wave copies src[base + x] (0 below position 0) into l[x] for x < len,
 // for two arrays at once; all of a lane's loads of a 256-word block are
 // issued before the first is waited for.
