@@ -28,6 +28,12 @@ struct pm_gcd_batch {
     pm::GcdJob* d_jobs = nullptr;
     int32_t* d_order = nullptr;
     pm::GcdResult* d_res = nullptr;
+    // With both shapes, the 256-thread blocks run on a second stream beside
+    // the 1024-thread ones, so that they take each CU a large instance
+    // leaves instead of waiting for the longest one; side joins the
+    // caller's stream through the two events, so a capture takes both.
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 struct pm_mul_batch {
@@ -1104,6 +1110,13 @@ pm_status pm_gcd_batch_create(const pm_gcd_item* items, int32_t count, int32_t s
         pm_gcd_batch_destroy(B);
         return fail(PM_EDEVICE, "cannot upload the batch");
     }
+    if (B->n_large > 0 && B->n_small > 0 &&
+        (hipStreamCreateWithFlags(&B->side, hipStreamNonBlocking) != hipSuccess ||
+         hipEventCreateWithFlags(&B->ev_fork, hipEventDisableTiming) != hipSuccess ||
+         hipEventCreateWithFlags(&B->ev_join, hipEventDisableTiming) != hipSuccess)) {
+        pm_gcd_batch_destroy(B);
+        return fail(PM_EDEVICE, "cannot create the batch's second stream");
+    }
     *out = B;
     return PM_OK;
 }
@@ -1111,6 +1124,16 @@ pm_status pm_gcd_batch_create(const pm_gcd_item* items, int32_t count, int32_t s
 pm_status pm_gcd_batch_run(pm_gcd_batch* B, void* stream) {
     if (!B) return fail(PM_EINVAL, "null batch");
     hipStream_t hs = (hipStream_t)stream;
+    if (B->side) {
+        HIP_TRY(hipEventRecord(B->ev_fork, hs), "gcd batch fork");
+        HIP_TRY(hipStreamWaitEvent(B->side, B->ev_fork, 0), "gcd batch fork");
+        HIP_TRY(pm::gcd_batch_launch(B->d_jobs, B->d_order, B->n_large, 1, B->s, hs), "gcd batch launch");
+        HIP_TRY(pm::gcd_batch_launch(B->d_jobs, B->d_order + B->n_large, B->n_small, 0, B->s, B->side),
+                "gcd batch launch");
+        HIP_TRY(hipEventRecord(B->ev_join, B->side), "gcd batch join");
+        HIP_TRY(hipStreamWaitEvent(hs, B->ev_join, 0), "gcd batch join");
+        return PM_OK;
+    }
     if (B->n_large > 0)
         HIP_TRY(pm::gcd_batch_launch(B->d_jobs, B->d_order, B->n_large, 1, B->s, hs), "gcd batch launch");
     if (B->n_small > 0)
@@ -1138,6 +1161,9 @@ void pm_gcd_batch_destroy(pm_gcd_batch* B) {
     if (B->d_jobs) (void)hipFree(B->d_jobs);
     if (B->d_order) (void)hipFree(B->d_order);
     if (B->d_res) (void)hipFree(B->d_res);
+    if (B->ev_fork) (void)hipEventDestroy(B->ev_fork);
+    if (B->ev_join) (void)hipEventDestroy(B->ev_join);
+    if (B->side) (void)hipStreamDestroy(B->side);
     (void)hipSetDevice(cur);
     delete B;
 }
