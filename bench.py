@@ -367,12 +367,14 @@ def bench_batched_gcd(reqs, one_call_sample: int = 256, reps: int = 3, served=No
     # the same requests one call each (the single-instance cooperative path),
     # on a sample; the sampled gcds must equal the batch's
     k = min(one_call_sample, len(items))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    singles = [pm.gcd(a, b, p) for a, b, p in items[:k]]
-    torch.cuda.synchronize()
-    t_one = (time.perf_counter() - t0) / k
-    same = all(torch.equal(g1, res[i][0]) for i, g1 in enumerate(singles))
+    t_one = same = None
+    if k > 0:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        singles = [pm.gcd(a, b, p) for a, b, p in items[:k]]
+        torch.cuda.synchronize()
+        t_one = (time.perf_counter() - t0) / k
+        same = all(torch.equal(g1, res[i][0]) for i, g1 in enumerate(singles))
     # every gcd the server returned for the same requests equals the batch's
     served_same = None
     if served is not None:
@@ -384,8 +386,8 @@ def bench_batched_gcd(reqs, one_call_sample: int = 256, reps: int = 3, served=No
                         "in one prepared batch replayed from a CUDA graph" % len(items),
             "s": t["s"], "tune_trials": t["trials"], "model_s_star": t["model_s_star"], "ms": round(ms, 3),
             "gcds_per_s": round(len(items) / (ms * 1e-3), 1), "updates_per_s": round(updates / (ms * 1e-3), 1),
-            "one_call_per_instance_gcds_per_s": round(1.0 / t_one, 1), "one_call_sample": k,
-            "speedup_vs_one_call_per_instance": round((len(items) / (ms * 1e-3)) * t_one, 1),
+            "one_call_per_instance_gcds_per_s": round(1.0 / t_one, 1) if t_one else None, "one_call_sample": k,
+            "speedup_vs_one_call_per_instance": round((len(items) / (ms * 1e-3)) * t_one, 1) if t_one else None,
             "all_ok": ok, "sample_equals_one_call": same, "served_results_equal_batch": served_same}
 
 
@@ -688,6 +690,8 @@ def main() -> int:
     ap.add_argument("--no-div", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-batched-gcd", action="store_true", help="skip the prepared gcd batch")
+    ap.add_argument("--one-call-sample", type=int, default=256,
+                    help="gcd batch: requests also run as one poly_gcd_modp call each (0: none)")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--served-requests", type=int, default=2048)
     ap.add_argument("--no-served-baseline", action="store_true")
@@ -806,6 +810,7 @@ def main() -> int:
         # the served measurement's requests (after its warm-up ones), so the
         # server's results can be compared one by one
         out["batched_gcd"] = bench_batched_gcd(served_inputs(args.served_requests + 128)[128:],
+                                               one_call_sample=args.one_call_sample,
                                                served=out.get("served", {}).pop("_results", None))
     if "served" in out:
         out["served"].pop("_results", None)
