@@ -391,13 +391,21 @@ def bench_batched_gcd(reqs, one_call_sample: int = 256, reps: int = 3, served=No
             "all_ok": ok, "sample_equals_one_call": same, "served_results_equal_batch": served_same}
 
 
-def run_server_trace(reqs, scale: float, keep: bool = False, **opts):
+def _round_or_none(x, nd: int = 1):
+    return None if x is None else round(x, nd)
+
+
+def run_server_trace(reqs, scale: float, keep: bool = False, stats=None, **opts):
     """Submit each request at arrival * scale seconds (the requests that have
     arrived by each pass of the loop go in one submit_many call); returns
     latencies (ms, in completion order, with each one's op), the span from
     the first arrival to the last completion, and with `keep` the
     completions by request index. A request is (a, b, p, arrival, D, k) for
-    a gcd, with a seventh element True for a division."""
+    a gcd, with a seventh element True for a division. `stats` (a dict)
+    receives the completion rate over the arrival window: the requests done
+    between the first and the last submission over that time, which a short
+    trace's n / span understates (its span ends with the drain of the
+    largest requests, each one CU's step chain)."""
     import paper_1402_0264_amd as pm
     srv = pm.Server(**opts)
     t0 = time.perf_counter()
@@ -405,6 +413,7 @@ def run_server_trace(reqs, scale: float, keep: bool = False, **opts):
     lat = []
     first = last = None
     kept = {}
+    marks = []
     deadline = time.perf_counter() + 600.0
     while done < len(reqs):
         now = time.perf_counter() - t0
@@ -420,12 +429,19 @@ def run_server_trace(reqs, scale: float, keep: bool = False, **opts):
             if c["status"] != 0:
                 raise RuntimeError("served request %d failed: %d" % (c["tag"], c["status"]))
             lat.append((c["t_done_ms"] - c["t_submit_ms"], c["op"]))
+            marks.append((c["t_submit_ms"], c["t_done_ms"]))
             first = c["t_submit_ms"] if first is None else min(first, c["t_submit_ms"])
             last = c["t_done_ms"] if last is None else max(last, c["t_done_ms"])
             if keep:
                 kept[c["tag"]] = c
             done += 1
     srv.close()
+    if stats is not None:
+        s0 = min(m[0] for m in marks)
+        s1 = max(m[0] for m in marks)
+        n_in = sum(1 for m in marks if m[1] <= s1)
+        stats["window_ms"] = s1 - s0
+        stats["window_rate"] = n_in / ((s1 - s0) / 1e3) if s1 > s0 else None
     return lat, (last - first) / 1e3, kept
 
 
@@ -461,7 +477,8 @@ def bench_served(n_req: int, warm: int, load: float, baseline: bool, loads=(0.5,
     mean_gap = reqs[-1][3] / max(len(reqs) - 1, 1)         # of the rate-1 trace
     rate = load * sat
     scale = 1.0 / (rate * mean_gap)
-    lat, span, _ = run_server_trace(reqs, scale)
+    st = {}
+    lat, span, _ = run_server_trace(reqs, scale, stats=st)
     lat = [x for x, _ in lat]
     out = {"workload": "%d gcd requests, D log-uniform in [64, 16384], deg b = D-1, planted gcd degree "
                        "uniform in [0, D/4], p in {469762049, 998244353, 167772161}" % len(reqs),
@@ -469,15 +486,21 @@ def bench_served(n_req: int, warm: int, load: float, baseline: bool, loads=(0.5,
            "saturated_gcds_per_s_inputs_in_host_memory": round(len(reqs) / span_host, 1),
            "offered_rate_per_s": round(rate, 1), "load": load,
            "gcds_per_s": round(len(reqs) / span, 1),
+           "gcds_per_s_in_arrival_window": _round_or_none(st["window_rate"]),
+           "arrival_window_ms": round(st["window_ms"], 2),
            "p50_ms": round(_pct(lat, 0.50), 3), "p99_ms": round(_pct(lat, 0.99), 3),
            "max_ms": round(max(lat), 3)}
-    sweep = [{"load": load, "gcds_per_s": out["gcds_per_s"], "p50_ms": out["p50_ms"], "p99_ms": out["p99_ms"]}]
+    sweep = [{"load": load, "gcds_per_s": out["gcds_per_s"],
+              "gcds_per_s_in_arrival_window": out["gcds_per_s_in_arrival_window"],
+              "p50_ms": out["p50_ms"], "p99_ms": out["p99_ms"]}]
     for ld in loads:
         sc = 1.0 / (ld * sat * mean_gap)
-        l2, sp2, _ = run_server_trace(reqs, sc)
+        st2 = {}
+        l2, sp2, _ = run_server_trace(reqs, sc, stats=st2)
         l2 = [x for x, _ in l2]
-        sweep.append({"load": ld, "gcds_per_s": round(len(reqs) / sp2, 1), "p50_ms": round(_pct(l2, 0.50), 3),
-                      "p99_ms": round(_pct(l2, 0.99), 3)})
+        sweep.append({"load": ld, "gcds_per_s": round(len(reqs) / sp2, 1),
+                      "gcds_per_s_in_arrival_window": _round_or_none(st2["window_rate"]),
+                      "p50_ms": round(_pct(l2, 0.50), 3), "p99_ms": round(_pct(l2, 0.99), 3)})
     out["loads"] = sorted(sweep, key=lambda x: x["load"])
     if baseline:
         run_one_call_trace(warm_reqs[:16], 0.0)
@@ -531,7 +554,8 @@ def bench_served_mixed(n_req: int, warm: int, load: float) -> dict:
     lat_sat, span_sat, kept = run_server_trace(reqs, 0.0, keep=True)
     sat = len(reqs) / span_sat
     mean_gap = reqs[-1][3] / max(len(reqs) - 1, 1)
-    lat, span, _ = run_server_trace(reqs, 1.0 / (load * sat * mean_gap))
+    st = {}
+    lat, span, _ = run_server_trace(reqs, 1.0 / (load * sat * mean_gap), stats=st)
     gl = [x for x, op in lat if op != pm.PM_OP_DIVREM]
     dl = [x for x, op in lat if op == pm.PM_OP_DIVREM]
     # checks: divisions against the oracle, gcds against the prepared batch
@@ -548,6 +572,7 @@ def bench_served_mixed(n_req: int, warm: int, load: float) -> dict:
             "divisions": len(divs), "gcds": len(gcds),
             "saturated_requests_per_s": round(sat, 1), "load": load,
             "requests_per_s": round(len(reqs) / span, 1),
+            "requests_per_s_in_arrival_window": _round_or_none(st["window_rate"]),
             "gcd_p50_ms": round(_pct(gl, 0.50), 3), "gcd_p99_ms": round(_pct(gl, 0.99), 3),
             "divrem_p50_ms": round(_pct(dl, 0.50), 3), "divrem_p99_ms": round(_pct(dl, 0.99), 3),
             "divisions_equal_oracle": bool(div_ok), "gcds_equal_batch": bool(gcd_ok)}
