@@ -400,6 +400,9 @@ hipEvent_t take_event() {
 
 namespace pm {
 
+int32_t api_exception(bool out_of_memory) {
+    return out_of_memory ? fail(PM_ENOMEM, "out of host memory") : fail(PM_EDEVICE, "internal error (exception)");
+}
 pm_status server_field(uint32_t p, Field* out) { return field_for(p, out); }
 pm_status server_fail(pm_status st, const char* msg) { return fail(st, "%s", msg); }
 int server_num_cus() { return num_cus(); }
@@ -422,9 +425,10 @@ TimingScope::~TimingScope() {
 
 extern "C" {
 
-void pm_timing_enable(int on) { g_timing_on.store(on ? 1 : 0); }
+void pm_timing_enable(int on) { PM_API_BEGIN g_timing_on.store(on ? 1 : 0); PM_API_END_VOID }
 
 void pm_timing_reset(void) {
+    PM_API_BEGIN
     std::lock_guard<std::mutex> lk(g_timing_mu);
     for (auto& t : g_timed) {
         (void)hipEventSynchronize(t.stop);
@@ -432,9 +436,11 @@ void pm_timing_reset(void) {
         g_event_pool.push_back(t.stop);
     }
     g_timed.clear();
+    PM_API_END_VOID
 }
 
 pm_status pm_timing_read(const char* kernel, int64_t* launches, double* total_ms) {
+    PM_API_BEGIN
     if (!kernel || !launches || !total_ms) return fail(PM_EINVAL, "null argument");
     std::lock_guard<std::mutex> lk(g_timing_mu);
     int64_t n = 0;
@@ -450,16 +456,20 @@ pm_status pm_timing_read(const char* kernel, int64_t* launches, double* total_ms
     *launches = n;
     *total_ms = ms;
     return PM_OK;
+    PM_API_END
 }
 
 
 const char* pm_last_error(void) { return g_err; }
 
 void pm_last_gcd_stats(pm_gcd_stats* out) {
+    PM_API_BEGIN
     if (out) *out = g_gcd_stats;
+    PM_API_END_VOID
 }
 
 pm_status pm_set_params(const pm_params* params) {
+    PM_API_BEGIN
     if (!params) return fail(PM_EINVAL, "null params");
     const pm_params& q = *params;
     if (q.mul_r != 0 && q.mul_r != 1 && q.mul_r != 2 && q.mul_r != 4 && q.mul_r != 8 && q.mul_r != 16 &&
@@ -472,13 +482,17 @@ pm_status pm_set_params(const pm_params* params) {
     std::lock_guard<std::mutex> lk(g_param_mu);
     g_params = q;
     return PM_OK;
+    PM_API_END
 }
 
 void pm_get_params(pm_params* params) {
+    PM_API_BEGIN
     if (params) *params = params_now();
+    PM_API_END_VOID
 }
 
 void pm_release(void) {
+    PM_API_BEGIN
     std::lock_guard<std::mutex> lk(g_pool_mu);
     int cur = 0;
     (void)hipGetDevice(&cur);
@@ -499,9 +513,11 @@ void pm_release(void) {
     g_aux.clear();
     (void)hipSetDevice(cur);
     g_pools.clear();
+    PM_API_END_VOID
 }
 
 pm_status pm_set_workspace(void* stream, void* d_words, int64_t words) {
+    PM_API_BEGIN
     if (words < 0 || (words > 0 && !d_words)) return fail(PM_EINVAL, "null workspace or negative size");
     if (words > 0 && words < INFO_WORDS)
         return fail(PM_EINVAL, "a workspace needs at least %lld words", (long long)INFO_WORDS);
@@ -529,10 +545,12 @@ pm_status pm_set_workspace(void* stream, void* d_words, int64_t words) {
     S.view.words = (uint32_t*)d_words + INFO_WORDS;
     S.view.cap = words - INFO_WORDS;
     return PM_OK;
+    PM_API_END
 }
 
 pm_status poly_mul_modp_async(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, uint32_t p,
                               uint32_t* f, int64_t f_cap, int64_t* d_nf, int32_t* d_status, void* stream) {
+    PM_API_BEGIN
     if (bad_len(a, na) || bad_len(b, nb)) return fail(PM_EINVAL, "null input or negative length");
     int64_t need = (na > 0 && nb > 0) ? na + nb - 1 : 0;
     if (need > 0 && (f == nullptr || f_cap < need))
@@ -542,6 +560,7 @@ pm_status poly_mul_modp_async(const uint32_t* a, int64_t na, const uint32_t* b, 
     pm_status st = field_for(p, &F);
     if (st) return st;
     return mul_enqueue(a, na, b, nb, F, f, d_nf, d_status, (hipStream_t)stream);
+    PM_API_END
 }
 
 }  // extern "C"
@@ -579,6 +598,7 @@ extern "C" {
 
 pm_status poly_mul_modp_noalloc(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, uint32_t p,
                                 uint32_t* f, int64_t f_cap, int64_t* d_nf, int32_t* d_status, void* stream) {
+    PM_API_BEGIN
     if (bad_len(a, na) || bad_len(b, nb)) return fail(PM_EINVAL, "null input or negative length");
     int64_t need = (na > 0 && nb > 0) ? na + nb - 1 : 0;
     if (need > 0 && (f == nullptr || f_cap < need))
@@ -608,9 +628,11 @@ pm_status poly_mul_modp_noalloc(const uint32_t* a, int64_t na, const uint32_t* b
     HIP_TRY(pm::mul_launch(a, na, b, nb, F, f, plan, words > 0 ? ws : nullptr, d_nf, d_status, nullptr, -1, s),
             "mul launch");
     return PM_OK;
+    PM_API_END
 }
 
 void pm_mul_batch_destroy(pm_mul_batch* B) {
+    PM_API_BEGIN
     if (!B) return;
     int cur = 0;
     (void)hipGetDevice(&cur);
@@ -625,6 +647,7 @@ void pm_mul_batch_destroy(pm_mul_batch* B) {
     if (B->side) (void)hipStreamDestroy(B->side);
     (void)hipSetDevice(cur);
     delete B;
+    PM_API_END_VOID
 }
 
 // Which engine a batch item goes to: the matrix cores when the estimated
@@ -641,6 +664,7 @@ bool batch_on_matrix_cores(const pm::MxItem& it, int64_t nkr, int engine) {
 }
 
 pm_status pm_mul_batch_create(const pm_mul_item* items, int32_t count, int32_t r, int32_t kc, pm_mul_batch** out) {
+    PM_API_BEGIN
     if (!out || count < 0 || (count > 0 && !items)) return fail(PM_EINVAL, "bad arguments");
     if (r == 0) r = 8;
     if (r != 4 && r != 8 && r != 16) return fail(PM_EINVAL, "r must be 4, 8 or 16");
@@ -736,9 +760,11 @@ pm_status pm_mul_batch_create(const pm_mul_item* items, int32_t count, int32_t r
     }
     *out = B;
     return PM_OK;
+    PM_API_END
 }
 
 pm_status pm_mul_batch_run(pm_mul_batch* B, int32_t* d_status, void* stream) {
+    PM_API_BEGIN
     if (!B) return fail(PM_EINVAL, "null batch");
     hipStream_t s = (hipStream_t)stream;
     if (d_status) HIP_TRY(pm::mul_batch_check_launch(B->d_items, B->count, d_status, s), "batch check launch");
@@ -759,9 +785,11 @@ pm_status pm_mul_batch_run(pm_mul_batch* B, int32_t* d_status, void* stream) {
     HIP_TRY(pm::mul_batch_launch(B->d_items, B->d_tasks, B->ntasks, B->r, B->kc, B->fold_min, num_cus(), s),
             "batch launch");
     return PM_OK;
+    PM_API_END
 }
 
 pm_status poly_mul_modp_batch(const pm_mul_item* items, int32_t count, int32_t* d_status, void* stream) {
+    PM_API_BEGIN
     pm_mul_batch* B = nullptr;
     pm_params pp = params_now();
     int r = pp.mul_r == 4 || pp.mul_r == 8 || pp.mul_r == 16 ? pp.mul_r : 0;
@@ -771,10 +799,12 @@ pm_status poly_mul_modp_batch(const pm_mul_item* items, int32_t count, int32_t* 
     if (st == PM_OK && hipStreamSynchronize((hipStream_t)stream) != hipSuccess) st = fail(PM_EDEVICE, "sync");
     pm_mul_batch_destroy(B);
     return st;
+    PM_API_END
 }
 
 pm_status poly_mul_modp(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, uint32_t p, uint32_t* f,
                         int64_t f_cap, int64_t* nf, void* stream) {
+    PM_API_BEGIN
     if (!nf) return fail(PM_EINVAL, "null nf");
     if (bad_len(a, na) || bad_len(b, nb)) return fail(PM_EINVAL, "null input or negative length");
     int64_t need = (na > 0 && nb > 0) ? na + nb - 1 : 0;
@@ -792,6 +822,7 @@ pm_status poly_mul_modp(const uint32_t* a, int64_t na, const uint32_t* b, int64_
     *nf = P->h_info->n0;
     if (P->h_info->status) return fail(P->h_info->status, "%s", status_text(P->h_info->status));
     return PM_OK;
+    PM_API_END
 }
 
 }  // extern "C"
@@ -899,12 +930,15 @@ extern "C" {
 
 pm_status poly_divrem_modp(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, uint32_t p, uint32_t* q,
                            int64_t q_cap, int64_t* nq, uint32_t* r, int64_t r_cap, int64_t* nr, void* stream) {
+    PM_API_BEGIN
     return divrem_impl(a, na, b, nb, p, q, q_cap, nq, r, r_cap, nr, stream, nullptr);
+    PM_API_END
 }
 
 pm_status poly_divrem_modp_naive(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, uint32_t p,
                                  uint32_t* q, int64_t q_cap, int64_t* nq, uint32_t* r, int64_t r_cap, int64_t* nr,
                                  void* stream) {
+    PM_API_BEGIN
     if (!nq || !nr) return fail(PM_EINVAL, "null nq or nr");
     if (bad_len(a, na) || bad_len(b, nb)) return fail(PM_EINVAL, "null input or negative length");
     if (q_cap < 0 || r_cap < 0 || (q_cap > 0 && !q) || (r_cap > 0 && !r))
@@ -951,10 +985,12 @@ pm_status poly_divrem_modp_naive(const uint32_t* a, int64_t na, const uint32_t* 
     if ((st = read_info(P, s))) return st;
     *nr = P->h_info->n1;
     return PM_OK;
+    PM_API_END
 }
 
 pm_status poly_gcd_modp_naive(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, uint32_t p, uint32_t* g,
                               int64_t g_cap, int64_t* ng, void* stream) {
+    PM_API_BEGIN
     if (!ng) return fail(PM_EINVAL, "null ng");
     if (bad_len(a, na) || bad_len(b, nb)) return fail(PM_EINVAL, "null input or negative length");
     if (g_cap < 0 || (g_cap > 0 && !g)) return fail(PM_EINVAL, "bad output buffer");
@@ -992,6 +1028,7 @@ pm_status poly_gcd_modp_naive(const uint32_t* a, int64_t na, const uint32_t* b, 
     HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
     *ng = dR + 1;
     return PM_OK;
+    PM_API_END
 }
 
 static_assert(sizeof(pm_gcd_result) == sizeof(pm::GcdResult), "result layouts differ");
@@ -1037,6 +1074,7 @@ pm_status gcd_batch_jobs(const pm_gcd_item* items, int32_t count, std::vector<pm
 extern "C" {
 
 pm_status poly_gcd_modp_batch(const pm_gcd_item* items, int32_t count, pm_gcd_result* results, void* stream) {
+    PM_API_BEGIN
     if (count < 0 || (count > 0 && (!items || !results))) return fail(PM_EINVAL, "bad item or result array");
     if (count == 0) return PM_OK;
     hipStream_t s = (hipStream_t)stream;
@@ -1075,9 +1113,11 @@ pm_status poly_gcd_modp_batch(const pm_gcd_item* items, int32_t count, pm_gcd_re
             "copy results");
     HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
     return PM_OK;
+    PM_API_END
 }
 
 pm_status pm_gcd_batch_create(const pm_gcd_item* items, int32_t count, int32_t s, pm_gcd_batch** out) {
+    PM_API_BEGIN
     if (!out || count < 0 || (count > 0 && !items)) return fail(PM_EINVAL, "bad arguments");
     if (s < 0 || s > 256) return fail(PM_EINVAL, "s must be in [0, 256]");
     *out = nullptr;
@@ -1119,9 +1159,11 @@ pm_status pm_gcd_batch_create(const pm_gcd_item* items, int32_t count, int32_t s
     }
     *out = B;
     return PM_OK;
+    PM_API_END
 }
 
 pm_status pm_gcd_batch_run(pm_gcd_batch* B, void* stream) {
+    PM_API_BEGIN
     if (!B) return fail(PM_EINVAL, "null batch");
     hipStream_t hs = (hipStream_t)stream;
     if (B->side) {
@@ -1140,9 +1182,11 @@ pm_status pm_gcd_batch_run(pm_gcd_batch* B, void* stream) {
         HIP_TRY(pm::gcd_batch_launch(B->d_jobs, B->d_order + B->n_large, B->n_small, 0, B->s, hs),
                 "gcd batch launch");
     return PM_OK;
+    PM_API_END
 }
 
 pm_status pm_gcd_batch_results(pm_gcd_batch* B, pm_gcd_result* results, void* stream) {
+    PM_API_BEGIN
     if (!B || (B->count > 0 && !results)) return fail(PM_EINVAL, "null argument");
     if (B->count == 0) return PM_OK;
     hipStream_t hs = (hipStream_t)stream;
@@ -1150,9 +1194,11 @@ pm_status pm_gcd_batch_results(pm_gcd_batch* B, pm_gcd_result* results, void* st
             "copy results");
     HIP_TRY(hipStreamSynchronize(hs), "hipStreamSynchronize");
     return PM_OK;
+    PM_API_END
 }
 
 void pm_gcd_batch_destroy(pm_gcd_batch* B) {
+    PM_API_BEGIN
     if (!B) return;
     int cur = 0;
     (void)hipGetDevice(&cur);
@@ -1166,6 +1212,7 @@ void pm_gcd_batch_destroy(pm_gcd_batch* B) {
     if (B->side) (void)hipStreamDestroy(B->side);
     (void)hipSetDevice(cur);
     delete B;
+    PM_API_END_VOID
 }
 
 }  // extern "C"
@@ -1320,6 +1367,7 @@ extern "C" {
 
 pm_status poly_gcd_modp(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, uint32_t p, uint32_t* g,
                         int64_t g_cap, int64_t* ng, void* stream) {
+    PM_API_BEGIN
     if (!ng) return fail(PM_EINVAL, "null ng");
     if (bad_len(a, na) || bad_len(b, nb)) return fail(PM_EINVAL, "null input or negative length");
     if (g_cap < 0 || (g_cap > 0 && !g)) return fail(PM_EINVAL, "bad output buffer");
@@ -1332,11 +1380,13 @@ pm_status poly_gcd_modp(const uint32_t* a, int64_t na, const uint32_t* b, int64_
     const int64_t gap = na > nb ? na - nb : nb - na;
     if (na > 0 && nb > 0 && gap >= GCD_LEAD_GAP) return gcd_lead_division(a, na, b, nb, p, F, g, g_cap, ng, s);
     return gcd_run(a, na, b, nb, F, g, g_cap, ng, s);
+    PM_API_END
 }
 
 pm_status poly_gcd_modp_degrees(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, uint32_t p,
                                 uint32_t* g, int64_t g_cap, int64_t* ng, int64_t* degs, int64_t degs_cap,
                                 int64_t* n_degs, void* stream) {
+    PM_API_BEGIN
     if (!ng || !n_degs || degs_cap < 0 || (degs_cap > 0 && !degs)) return fail(PM_EINVAL, "null ng, n_degs or degs");
     if (bad_len(a, na) || bad_len(b, nb)) return fail(PM_EINVAL, "null input or negative length");
     if (g_cap < 0 || (g_cap > 0 && !g)) return fail(PM_EINVAL, "bad output buffer");
@@ -1367,11 +1417,13 @@ pm_status poly_gcd_modp_degrees(const uint32_t* a, int64_t na, const uint32_t* b
     *n_degs = (int64_t)seq.size();
     for (int64_t i = 0; i < (int64_t)seq.size() && i < degs_cap; i++) degs[i] = seq[(size_t)i];
     return PM_OK;
+    PM_API_END
 }
 
 pm_status poly_euclid_steps_modp(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, uint32_t p,
                                  int64_t k, uint32_t* x, int64_t x_cap, int64_t* nx, uint32_t* y, int64_t y_cap,
                                  int64_t* ny, int64_t* taken, void* stream) {
+    PM_API_BEGIN
     if (!nx || !ny || !taken) return fail(PM_EINVAL, "null nx, ny or taken");
     if (k < 0) return fail(PM_EINVAL, "negative step count");
     if (bad_len(a, na) || bad_len(b, nb)) return fail(PM_EINVAL, "null input or negative length");
@@ -1395,6 +1447,7 @@ pm_status poly_euclid_steps_modp(const uint32_t* a, int64_t na, const uint32_t* 
     *ny = I.n1;
     *taken = I.run_steps;
     return PM_OK;
+    PM_API_END
 }
 
 }  // extern "C"
@@ -1431,6 +1484,7 @@ extern "C" {
 pm_status poly_xgcd_modp(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, uint32_t p, uint32_t* g,
                          int64_t g_cap, int64_t* ng, uint32_t* s_out, int64_t s_cap, int64_t* ns, uint32_t* t_out,
                          int64_t t_cap, int64_t* nt, void* stream) {
+    PM_API_BEGIN
     if (!ng || !ns || !nt) return fail(PM_EINVAL, "null ng, ns or nt");
     if (bad_len(a, na) || bad_len(b, nb)) return fail(PM_EINVAL, "null input or negative length");
     if (g_cap < 0 || (g_cap > 0 && !g) || s_cap < 0 || (s_cap > 0 && !s_out) || t_cap < 0 || (t_cap > 0 && !t_out))
@@ -1565,11 +1619,13 @@ pm_status poly_xgcd_modp(const uint32_t* a, int64_t na, const uint32_t* b, int64
     *ns = nsf;
     *nt = ntf;
     return PM_OK;
+    PM_API_END
 }
 
 pm_status poly_divrem_modp_async(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, uint32_t p,
                                  uint32_t* q, int64_t q_cap, int64_t* d_nq, uint32_t* r, int64_t r_cap,
                                  int64_t* d_nr, int32_t* d_status, void* stream) {
+    PM_API_BEGIN
     if (bad_len(a, na) || bad_len(b, nb)) return fail(PM_EINVAL, "null input or negative length");
     if (q_cap < 0 || r_cap < 0 || (q_cap > 0 && !q) || (r_cap > 0 && !r))
         return fail(PM_EINVAL, "bad output buffer");
@@ -1609,10 +1665,12 @@ pm_status poly_divrem_modp_async(const uint32_t* a, int64_t na, const uint32_t* 
     }
     HIP_TRY(pm::info_export_launch(info, d_nq, d_nr, d_status, s), "export launch");
     return PM_OK;
+    PM_API_END
 }
 
 pm_status poly_gcd_modp_async(const uint32_t* a, int64_t na, const uint32_t* b, int64_t nb, uint32_t p, uint32_t* g,
                               int64_t g_cap, int64_t* d_ng, int32_t* d_status, void* stream) {
+    PM_API_BEGIN
     if (bad_len(a, na) || bad_len(b, nb)) return fail(PM_EINVAL, "null input or negative length");
     if (g_cap < 0 || (g_cap > 0 && !g)) return fail(PM_EINVAL, "bad output buffer");
     if (check_aliasing({{g, g_cap}}, {{a, na}, {b, nb}})) return PM_EINVAL;
@@ -1627,9 +1685,11 @@ pm_status poly_gcd_modp_async(const uint32_t* a, int64_t na, const uint32_t* b, 
     HIP_TRY(pm::gcd_launch(a, na, b, nb, F, g, g_cap, P->words, P->d_info, plan, s), "gcd launch");
     HIP_TRY(pm::info_export_launch(P->d_info, d_ng, nullptr, d_status, s), "export launch");
     return PM_OK;
+    PM_API_END
 }
 
 pm_status pm_workspace_size(int32_t op, int64_t na, int64_t nb, int64_t* words) {
+    PM_API_BEGIN
     if (!words || na < 0 || nb < 0) return fail(PM_EINVAL, "null words or negative length");
     int64_t w = 0;
     if (op == PM_OP_MUL) {
@@ -1651,9 +1711,11 @@ pm_status pm_workspace_size(int32_t op, int64_t na, int64_t nb, int64_t* words) 
     }
     *words = INFO_WORDS + w;
     return PM_OK;
+    PM_API_END
 }
 
 pm_status pm_mul_plan(int64_t na, int64_t nb, pm_mul_plan_info* out) {
+    PM_API_BEGIN
     if (!out || na < 0 || nb < 0) return fail(PM_EINVAL, "null out or negative length");
     *out = pm_mul_plan_info{0, 0, 0, 0, 0, 0};
     const uint32_t *x = nullptr, *y = nullptr;
@@ -1675,9 +1737,11 @@ pm_status pm_mul_plan(int64_t na, int64_t nb, pm_mul_plan_info* out) {
     out->s = plan.kc;
     out->scratch_words = pm::mul_scratch_words(nx, ny, plan);
     return PM_OK;
+    PM_API_END
 }
 
 pm_status pm_autotune_load(const char* path) {
+    PM_API_BEGIN
     if (!path) return fail(PM_EINVAL, "null path");
     FILE* fh = fopen(path, "r");
     if (!fh) return fail(PM_EINVAL, "cannot open %s", path);
@@ -1707,10 +1771,12 @@ pm_status pm_autotune_load(const char* path) {
     fclose(fh);
     if (st) return st;
     return pm_set_params(&q);  // checks every value; nothing changes on an error
+    PM_API_END
 }
 
 pm_status pm_radix_sort_u32(const uint32_t* keys, const uint32_t* vals, int64_t n, int32_t key_bits, int32_t s,
                             uint32_t* keys_out, uint32_t* vals_out, void* stream) {
+    PM_API_BEGIN
     if (n < 0 || n > (int64_t)0xFFFFFFFFLL) return fail(PM_EINVAL, "n must be in [0, 2^32 - 1]");
     if (key_bits < 1 || key_bits > 32) return fail(PM_EINVAL, "key_bits must be in [1, 32]");
     if (s < 0 || s > 10) return fail(PM_EINVAL, "s must be in [0, 10]");
@@ -1729,6 +1795,7 @@ pm_status pm_radix_sort_u32(const uint32_t* keys, const uint32_t* vals, int64_t 
     HIP_TRY(pm::radix_sort_launch(keys, vals, n, key_bits, sd, keys_out, vals ? vals_out : nullptr, P->words, hs),
             "radix sort launch");
     return PM_OK;
+    PM_API_END
 }
 
 }  // extern "C"

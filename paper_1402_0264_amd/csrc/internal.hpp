@@ -9,6 +9,32 @@
 
 #include "common.hpp"
 
+#include <new>
+
+namespace pm {
+// The status a function of the C interface returns for a C++ exception that
+// reached it (sets the message of pm_last_error): PM_ENOMEM for host memory
+// exhaustion, PM_EDEVICE for anything else.
+int32_t api_exception(bool out_of_memory);
+}  // namespace pm
+
+// Every function of the C interface runs its body between PM_API_BEGIN and
+// PM_API_END (PM_API_END_VOID for those that return nothing), so that no
+// C++ exception crosses the interface.
+#define PM_API_BEGIN try {
+#define PM_API_END                                   \
+    }                                                \
+    catch (const std::bad_alloc&) {                  \
+        return pm::api_exception(true);              \
+    }                                                \
+    catch (...) {                                    \
+        return pm::api_exception(false);             \
+    }
+#define PM_API_END_VOID \
+    }                   \
+    catch (...) {       \
+    }
+
 namespace pm {
 
 // Kernel timing for diagnostics (pm_timing_enable in the C ABI): when on,

@@ -427,12 +427,18 @@ void prefault(void* p, size_t bytes) {
     const size_t pages = (bytes + PAGE - 1) / PAGE;
     const unsigned hc = std::thread::hardware_concurrency();
     const size_t nt = std::min<size_t>(pages / 1024 + 1, std::min(8u, hc > 1 ? hc : 1u));
-    auto touch = [=](size_t t) {
-        for (size_t i = t; i < pages; i += nt) base[i * PAGE] = 0;
+    auto touch = [=](size_t t, size_t step) {
+        for (size_t i = t; i < pages; i += step) base[i * PAGE] = 0;
     };
     std::vector<std::thread> th;
-    for (size_t t = 1; t < nt; t++) th.emplace_back(touch, t);
-    touch(0);
+    try {
+        for (size_t t = 1; t < nt; t++) th.emplace_back(touch, t, nt);
+    } catch (...) {
+        // no more threads: the calling thread takes the pages of those
+        // that did not start (no exception crosses the C interface)
+        for (size_t t = th.size() + 1; t < nt; t++) touch(t, nt);
+    }
+    touch(0, nt);
     for (auto& x : th) x.join();
 }
 
@@ -667,6 +673,7 @@ pm_status enqueue(pm_server* S, const pm_gcd_request* r, uint64_t* ticket) {
 extern "C" {
 
 pm_status pm_server_create(const pm_server_opts* opts, pm_server** out) {
+    PM_API_BEGIN
     if (!out) return pm::server_fail(PM_EINVAL, "null output");
     *out = nullptr;
     pm_server_opts o{};
@@ -766,18 +773,22 @@ pm_status pm_server_create(const pm_server_opts* opts, pm_server** out) {
     for (int i = (int)M - 1; i >= 0; i--) S->free_slots.push_back(i);
     *out = S;
     return PM_OK;
+    PM_API_END
 }
 
-void pm_server_destroy(pm_server* S) { destroy(S); }
+void pm_server_destroy(pm_server* S) { PM_API_BEGIN destroy(S); PM_API_END_VOID }
 
 pm_status pm_server_submit(pm_server* S, const pm_gcd_request* r, uint64_t* ticket) {
+    PM_API_BEGIN
     if (!S || !r) return pm::server_fail(PM_EINVAL, "null argument");
     pm_status st = enqueue(S, r, ticket);
     if (st) return st;
     return admit(S);  // on the GPU as soon as its copy is done, when a slot is free
+    PM_API_END
 }
 
 pm_status pm_server_submit_batch(pm_server* S, const pm_gcd_request* reqs, int32_t count, uint64_t* tickets) {
+    PM_API_BEGIN
     if (!S || count < 0 || (count > 0 && !reqs)) return pm::server_fail(PM_EINVAL, "null argument");
     // every request is checked before any is queued: a bad one queues none
     for (int32_t i = 0; i < count; i++) {
@@ -808,11 +819,13 @@ pm_status pm_server_submit_batch(pm_server* S, const pm_gcd_request* reqs, int32
         }
     }
     return admit(S);
+    PM_API_END
 }
 
 int64_t pm_server_pending(pm_server* S) { return S ? (int64_t)S->queue.size() + S->inflight : 0; }
 
 pm_status pm_server_poll(pm_server* S, pm_completion* out, int32_t max, int32_t* n) {
+    PM_API_BEGIN
     if (!S || !n || (max > 0 && !out)) return pm::server_fail(PM_EINVAL, "null argument");
     *n = 0;
     publish_ready(S);
@@ -848,6 +861,7 @@ pm_status pm_server_poll(pm_server* S, pm_completion* out, int32_t max, int32_t*
         S->free_slots.push_back(si);
     }
     return admit(S);
+    PM_API_END
 }
 
 }  // extern "C"
