@@ -51,9 +51,13 @@ enum {
     PM_EMODULUS = -2,  /* p not prime, or p >= 2^30                          */
     PM_ERANGE = -3,    /* an input coefficient is >= p                       */
     PM_EDIVZERO = -4,  /* division by the zero polynomial                    */
-    PM_ENOMEM = -5,    /* device memory for scratch could not be allocated   */
+    PM_ENOMEM = -5,    /* device or host memory could not be allocated       */
     PM_EDEVICE = -6    /* a HIP runtime error or a broken device invariant   */
 };
+/* No C++ exception leaves a function of this interface: one raised inside
+ * (host memory exhaustion, a thread that cannot start) becomes PM_ENOMEM or
+ * PM_EDEVICE, with its message in pm_last_error(); the functions that
+ * return nothing swallow it. */
 
 /*
  * Product f = a * b (Sec. 5, plain multiplication: every coefficient of a
