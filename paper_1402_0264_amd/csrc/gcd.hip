@@ -572,7 +572,10 @@ __device__ void gcd_instance(const GcdJob& J, int s, int64_t cap, uint32_t* smem
     constexpr int PPA = WIN ? 4 * NP : (NT * PPT + NA - 1) / NA;
 
     const int64_t n = J.na > J.nb ? J.na : J.nb;
-    int bad = n > cap;
+    // (the window apply reads B in 16-byte pieces: B's offset, cap + PADLO
+    // words past A, must be a multiple of 4, as the capacities are)
+    const bool badcap = WIN && (cap & 3) != 0;
+    int bad = n > cap || badcap;
     if (tid < PADLO) { A[tid - PADLO] = 0u; B[tid - PADLO] = 0u; }
     if (tid == 0) steplog_reset(&s_log);
     if (J.fresh) {
@@ -595,7 +598,7 @@ __device__ void gcd_instance(const GcdJob& J, int s, int64_t cap, uint32_t* smem
     bad = __syncthreads_or(bad);
     if (bad) {
         if (tid == 0) {
-            J.out->status = n > cap ? -1 : -3;
+            J.out->status = (n > cap || badcap) ? -1 : -3;
             J.out->ng = 0;
             J.out->steps = J.out->updates = J.out->chunks = 0;
             __threadfence_system();
