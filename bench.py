@@ -788,7 +788,11 @@ def main() -> int:
                 "peak": round(PEAK_INT8_OPS_PER_S / 1e12, 1), "unit": "TOP/s",
                 "frac": round(ops / (tile_avg_ms * 1e-3) / PEAK_INT8_OPS_PER_S, 4),
                 "mfma_digit_utilisation": round(2.0 * DIGIT_PRODUCTS * work / (tile_avg_ms * 1e-3)
-                                                / PEAK_INT8_OPS_PER_S, 4)}
+                                                / PEAK_INT8_OPS_PER_S, 4),
+                # the kernel's coefficient products per second over the VALU's
+                # (one 32x32->64 multiply-add per lane per clock): above 1, the
+                # matrix cores beat any VALU mulmod kernel
+                "kernel_over_valu_mulmod_peak": round(achieved / PEAK_MULMOD_PER_S, 3)}
     else:
         roof = {"bound": "alu", "achieved": round(achieved / 1e12, 3),
                 "peak": round(PEAK_MULMOD_PER_S / 1e12, 3), "unit": "Tmulmod/s",
