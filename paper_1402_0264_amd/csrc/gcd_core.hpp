@@ -407,8 +407,13 @@ __device__ void head_run_log(const uint32_t (&hA)[E], const uint32_t (&hB)[E], i
     int VA = H, VB = H, base = 0;
     uint32_t lcA = (uint32_t)__builtin_amdgcn_readfirstlane((int)hA[0]);
     uint32_t lcB = (uint32_t)__builtin_amdgcn_readfirstlane((int)hB[0]);
+    // The helpers below are lambdas over the run's state, all forced inline:
+    // one left as a call-like closure keeps the windows (rA, rB) addressable,
+    // and the compiler then mirrors them in scratch memory, storing them on
+    // every round of the tie loop and reloading them (a wait on memory) each
+    // time the loop is entered.
     // desc[j] for flushed <= j < upto, from lane j mod 64, then published
-    auto flush = [&](int upto) {
+    auto flush = [&](int upto) __attribute__((always_inline)) {
         const int j = flushed + ((lane - flushed) & 63);
         if (j < upto) {
             const uint32_t kind = wm1 >> 30;
@@ -436,7 +441,7 @@ __device__ void head_run_log(const uint32_t (&hA)[E], const uint32_t (&hB)[E], i
         // (it vanished, or it is not exact): the first non-zero exact entry
         // below the old leading one, X = 0, or an unknown degree (the run
         // ends). Sets dX, lcX and the zero-multiplier steps.
-        auto resolve = [&](auto role, int dXo, int dY, int VX, int kX) {
+        auto resolve = [&](auto role, int dXo, int dY, int VX, int kX) __attribute__((always_inline)) {
             constexpr bool XA = decltype(role)::value;
             uint32_t(&X)[E] = XA ? rA : rB;
 #pragma unroll
@@ -467,14 +472,14 @@ __device__ void head_run_log(const uint32_t (&hA)[E], const uint32_t (&hB)[E], i
             (XA ? lcA : lcB) = nlc;
         };
         // The step's descriptor into lane n mod 64 (d only for kinds 0, 1).
-        auto record = [&](uint32_t m1, uint32_t m2, uint32_t kind) {
+        auto record = [&](uint32_t m1, uint32_t m2, uint32_t kind) __attribute__((always_inline)) {
             const int l = n & 63;
             wm1 = writelane(wm1, m1 | (kind << 30), l);
             wm2 = writelane(wm2, m2, l);
         };
         // One step with X = A (XA) or X = B; d >= 0. Each role has its own
         // copy of the step, so a step moves no data between the operands.
-        auto step = [&](auto role) {
+        auto step = [&](auto role) __attribute__((always_inline)) {
             constexpr bool XA = decltype(role)::value;
             uint32_t(&X)[E] = XA ? rA : rB;
             const uint32_t(&Y)[E] = XA ? rB : rA;
