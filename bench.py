@@ -8,7 +8,8 @@ Headline (value, ms_per_step): mulmods/s of the plain product of two dense
 polynomials of degree 65535 over p = 469762049 (4,294,967,296 products of
 coefficients per step), inputs resident in HBM, one step = one complete
 product (all kernels of the call), timed with events on the launch stream
-over K steps after W warm-up steps.
+over K steps after W warm-up steps (defaults 200 and 1000: the shader clock
+takes tens of milliseconds of sustained load to reach its steady rate).
 
 Beside it, in the same line:
   roofline      the dominant kernel of the engine that ran (matrix cores:
@@ -706,8 +707,12 @@ def bench_divrem(reps: int) -> dict:
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    # the shader clock ramps up over the first tens of milliseconds of
+    # sustained matrix-core load (per-step time of the degree-65535 product
+    # over consecutive 200-step windows from a cold start: 64.4, 61.0, 60.0,
+    # 59.8 us); 1000 warm-up steps (about 60 ms) reach the steady rate
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=1000)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gcd", action="store_true")

@@ -512,57 +512,64 @@ __global__ __launch_bounds__(MX_THREADS, 1) void mulx_batch_kernel(const MxItem*
     }
 }
 
-// Addition phase: work-group (kr, c) adds, for outputs 1024c .. 1024c+1023
-// of range kr (four consecutive outputs per thread, 16-byte loads), the
-// partial sums of the work-groups whose shares touched kr. The last
-// work-group checks the flags and the degrees.
-constexpr int MX_RED_BLOCKS = MX_RANGE / 1024;   // reduce work-groups per range
+// Addition phase: work-group (kr, c), one wave, adds for outputs
+// 256c .. 256c+255 of range kr (four consecutive outputs per lane, 16-byte
+// loads) the partial sums of the work-groups whose shares touched kr. The
+// phase moves a few MB and is bound by the latency of its loads, not by
+// bandwidth: every lane issues the loads of up to MX_RED_BATCH rows before
+// its first add, and the small work-groups spread the ranges over the CUs.
+// The last work-group checks the flags and the degrees.
+constexpr int MX_RED_OUT = 256;                       // outputs per work-group
+constexpr int MX_RED_THREADS = MX_RED_OUT / 4;        // one wave
+constexpr int MX_RED_BLOCKS = MX_RANGE / MX_RED_OUT;  // work-groups per range
+constexpr int MX_RED_BATCH = 16;                      // rows in flight per lane
+static_assert(MX_RED_THREADS == 64, "the addition phase's work-groups are single waves");
 
 __device__ __forceinline__ void add4(uint64_t s[4], const uint4 v) {
     s[0] += v.x; s[1] += v.y; s[2] += v.z; s[3] += v.w;
 }
 
-__global__ __launch_bounds__(256) void mulx_reduce_kernel(MxArgs A) {
+__global__ __launch_bounds__(MX_RED_THREADS) void mulx_reduce_kernel(MxArgs A) {
     const MxGeom& G = A.g;
     const int tid = threadIdx.x;
     if ((int64_t)blockIdx.x == G.nkr * MX_RED_BLOCKS) {
         if (!A.out_len && !A.out_status) return;
-        __shared__ int64_t s_deg[2];
         uint32_t bad = 0;
-        for (int64_t w = tid; w < G.G; w += 256) bad |= A.flags[w];
-        bad = __syncthreads_or(bad);
-        const int wave = tid >> 6;
-        if (wave < 2) {
-            int64_t d = top_nonzero_wave(wave == 0 ? A.a : A.b, wave == 0 ? G.na : G.nb);
-            if ((tid & 63) == 0) s_deg[wave] = d;
-        }
-        __syncthreads();
+        for (int64_t w = tid; w < G.G; w += MX_RED_THREADS) bad |= A.flags[w];
+        const bool any_bad = __ballot(bad != 0) != 0;
+        const int64_t da = top_nonzero_wave(A.a, G.na);
+        const int64_t db = top_nonzero_wave(A.b, G.nb);
         if (tid == 0) {
-            if (A.out_len) *A.out_len = (s_deg[0] >= 0 && s_deg[1] >= 0) ? s_deg[0] + s_deg[1] + 1 : 0;
-            if (A.out_status) *A.out_status = bad ? -3 /* PM_ERANGE */ : 0;
+            if (A.out_len) *A.out_len = (da >= 0 && db >= 0) ? da + db + 1 : 0;
+            if (A.out_status) *A.out_status = any_bad ? -3 /* PM_ERANGE */ : 0;
         }
         return;
     }
     const int64_t kr = blockIdx.x / MX_RED_BLOCKS;
-    const int x = (int)(blockIdx.x % MX_RED_BLOCKS) * 1024 + 4 * tid;
+    const int x = (int)(blockIdx.x % MX_RED_BLOCKS) * MX_RED_OUT + 4 * tid;
     const int64_t k = kr * MX_RANGE + x;
     if (k >= A.nf) return;
     const int64_t S0 = mx_prefix(G, kr), S1 = S0 + mx_groups(G, kr);
     const int64_t wf = mx_group_of(G, S0), wl = mx_group_of(G, S1 - 1);
     const int64_t seg0 = kr - mx_range_of(G, mx_share_begin(G, wf));
+    const int64_t nrow = wl - wf + 1;
+    // row 0 is segment seg0 of share wf; row r > 0 is the first segment of
+    // share wf + r, which starts inside range kr
     const uint32_t* part = A.part + x;
     const int64_t stride = G.maxseg * MX_RANGE;   // one work-group's rows
+    const uint32_t* row0 = part + (wf * G.maxseg + seg0) * MX_RANGE;
     uint64_t s[4] = {0, 0, 0, 0};
-    add4(s, *(const uint4*)(part + (wf * G.maxseg + seg0) * MX_RANGE));
-    int64_t w = wf + 1;
-    for (; w + 3 <= wl; w += 4) {
-        const uint4 v0 = *(const uint4*)(part + w * stride);
-        const uint4 v1 = *(const uint4*)(part + (w + 1) * stride);
-        const uint4 v2 = *(const uint4*)(part + (w + 2) * stride);
-        const uint4 v3 = *(const uint4*)(part + (w + 3) * stride);
-        add4(s, v0); add4(s, v1); add4(s, v2); add4(s, v3);
+    for (int64_t r0 = 0; r0 < nrow; r0 += MX_RED_BATCH) {
+        uint4 v[MX_RED_BATCH];
+#pragma unroll
+        for (int i = 0; i < MX_RED_BATCH; i++) {
+            const int64_t r = r0 + i < nrow ? r0 + i : nrow - 1;  // past the end: a valid row, not added
+            v[i] = *(const uint4*)(r == 0 ? row0 : part + (wf + r) * stride);
+        }
+#pragma unroll
+        for (int i = 0; i < MX_RED_BATCH; i++)
+            if (r0 + i < nrow) add4(s, v[i]);
     }
-    for (; w <= wl; w++) add4(s, *(const uint4*)(part + w * stride));
     uint32_t r[4] = {reduce64(s[0], A.F), reduce64(s[1], A.F), reduce64(s[2], A.F), reduce64(s[3], A.F)};
     if (A.sub) {
 #pragma unroll
@@ -731,7 +738,8 @@ hipError_t mulx_launch(const uint32_t* a, int64_t na, const uint32_t* b, int64_t
     }
     // no timing events around the addition phase: events between the two
     // kernels put a gap of several microseconds into every product
-    hipLaunchKernelGGL(mulx_reduce_kernel, dim3((unsigned)(g.nkr * MX_RED_BLOCKS + 1)), dim3(256), 0, stream, A);
+    hipLaunchKernelGGL(mulx_reduce_kernel, dim3((unsigned)(g.nkr * MX_RED_BLOCKS + 1)), dim3(MX_RED_THREADS), 0, stream,
+                       A);
     return hipGetLastError();
 }
 
