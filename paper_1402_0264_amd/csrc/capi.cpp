@@ -421,6 +421,29 @@ TimingScope::~TimingScope() {
     g_timed.push_back(TimedLaunch{kernel_, start_, stop});
 }
 
+TimedLaunchEvents::TimedLaunchEvents(const char* kernel) : kernel_(kernel) {
+    if (!g_timing_on.load(std::memory_order_relaxed)) return;
+    start_ = take_event();
+    stop_ = take_event();
+    if (!start_ || !stop_) {
+        std::lock_guard<std::mutex> lk(g_timing_mu);
+        if (start_) g_event_pool.push_back(start_);
+        if (stop_) g_event_pool.push_back(stop_);
+        start_ = stop_ = nullptr;
+    }
+}
+
+TimedLaunchEvents::~TimedLaunchEvents() {
+    if (!start_) return;
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    if (ok_) {
+        g_timed.push_back(TimedLaunch{kernel_, start_, stop_});
+    } else {
+        g_event_pool.push_back(start_);
+        g_event_pool.push_back(stop_);
+    }
+}
+
 }  // namespace pm
 
 extern "C" {

@@ -53,6 +53,27 @@ private:
     hipEvent_t start_ = nullptr;
 };
 
+// The same timing carried by the launch itself: start() and stop() go to
+// hipExtLaunchKernel, which sets them from the dispatch's own start and end,
+// with no marker packets on the stream around it. Both are null when timing
+// is off (then launch as usual). After a successful launch, launched()
+// registers the pair for pm_timing_read; otherwise the events are returned.
+class TimedLaunchEvents {
+public:
+    explicit TimedLaunchEvents(const char* kernel);
+    ~TimedLaunchEvents();
+    hipEvent_t start() const { return start_; }
+    hipEvent_t stop() const { return stop_; }
+    void launched() { ok_ = true; }
+    TimedLaunchEvents(const TimedLaunchEvents&) = delete;
+    TimedLaunchEvents& operator=(const TimedLaunchEvents&) = delete;
+
+private:
+    const char* kernel_;
+    hipEvent_t start_ = nullptr, stop_ = nullptr;
+    bool ok_ = false;
+};
+
 // ------------------------------------------------------------------ product
 // Tiling of one product f = a*b (Sec. 5). The b operand is cut into chunks
 // of `kc` coefficients (the paper's s: b-coefficients handled per

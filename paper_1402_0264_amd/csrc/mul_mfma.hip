@@ -52,6 +52,8 @@
 // chunk here: JC offsets, i.e. 64*JC = 4096 coefficients of b per LDS stage.
 #include "internal.hpp"
 
+#include <hip/hip_ext.h>
+
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -731,10 +733,20 @@ hipError_t mulx_launch(const uint32_t* a, int64_t na, const uint32_t* b, int64_t
     A.a_vec = ((uintptr_t)a & 15) == 0;
     A.b_vec = ((uintptr_t)b & 15) == 0;
     {
-        TimingScope ts("mulx_kernel", stream);
-        hipLaunchKernelGGL(mulx_kernel, dim3((unsigned)g.G), dim3(MX_THREADS), 0, stream, A);
+        // timed by the launch's own events (hipExtLaunchKernel): separate
+        // event records around the kernel cost about 2 us per product
+        TimedLaunchEvents te("mulx_kernel");
+        if (te.start()) {
+            void* args[] = {&A};
+            hipError_t e = hipExtLaunchKernel((const void*)mulx_kernel, dim3((unsigned)g.G), dim3(MX_THREADS), args, 0,
+                                              stream, te.start(), te.stop(), 0);
+            if (e != hipSuccess) return e;
+        } else {
+            hipLaunchKernelGGL(mulx_kernel, dim3((unsigned)g.G), dim3(MX_THREADS), 0, stream, A);
+        }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
+        te.launched();
     }
     // no timing events around the addition phase: events between the two
     // kernels put a gap of several microseconds into every product
