@@ -278,3 +278,42 @@ def test_pool_growth_keeps_a_captured_graph_valid():
         with torch.cuda.stream(side):
             pm.mul(dev(large[0]), dev(large[1]), p, stream=side)
         side.synchronize()
+
+
+def test_kernel_timing_records_launches_and_leaves_results_unchanged():
+    """pm_timing_*: with timing on, every matrix-core product records one
+    mulx_kernel launch (events carried by the launch itself) and a division
+    its flow kernel (events recorded around it), each with a positive
+    duration; the timed results equal the oracle's, and with timing off
+    nothing more is recorded."""
+    import torch
+    p = gen.P_A
+    st = gen.Stream(gen.SEED_BASE + 409)
+    a, b = st.uniform_poly(9000, p), st.uniform_poly(7001, p)
+    da, db = dev(a), dev(b)
+    want = oracle.mul(a, b, p)
+    try:
+        pm.timing_reset()
+        pm.timing_enable(True)
+        try:
+            q, r = pm.divrem(da, db, p)  # default engine: its remainder product takes the VALU tiles
+            pm.set_params(mul_engine=pm.MUL_MFMA)
+            outs = [pm.mul(da, db, p) for _ in range(3)]
+        finally:
+            pm.timing_enable(False)
+        torch.cuda.synchronize()
+        n, ms = pm.timing_read("mulx_kernel")
+        assert n == 3 and ms > 0.0, (n, ms)
+        n_div, ms_div = pm.timing_read("divrem_flow_kernel")
+        assert n_div == 1 and ms_div > 0.0, (n_div, ms_div)
+        for f in outs:
+            assert same(host(f), want)
+        wq, wr = oracle.divrem(a, b, p)
+        assert same(host(q), wq) and same(host(r), wr)
+        pm.mul(da, db, p)  # timing off: not recorded
+        torch.cuda.synchronize()
+        assert pm.timing_read("mulx_kernel")[0] == 3
+        pm.timing_reset()
+        assert pm.timing_read("mulx_kernel") == (0, 0.0)
+    finally:
+        pm.set_params()
